@@ -1,0 +1,314 @@
+"""Python access to the FP64 CPU oracle (oracle.c) through ctypes.
+
+TEST INFRASTRUCTURE ONLY: imported by the tests, by the package smoke check
+and by the CPU-baseline leg of the benchmark.  The GPU library and its
+Python binding never import this package, and this package never imports
+them.
+
+Systems are the dicts produced by `reservoir_inputs` (keys rowptr, col,
+val, and bs for block systems).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SO = os.path.join(_HERE, "liboracle.so")
+_SRC = os.path.join(_HERE, "oracle.c")
+
+OK, NOT_CONVERGED, ERR_ARG, ERR_ZERO_PIVOT, ERR_BREAKDOWN = 0, 1, -1, -4, -5
+PREC = {"f64": 0, "f32": 1, "bf16": 2}
+PC_KIND = {"none": 0, "bilu0": 1, "ilu0": 1, "cpr_pf": 2, "cpr_fp": 3}
+
+
+def build(force: bool = True) -> str:
+    """Compile oracle.c into liboracle.so (plain -O2, no fast-math, no FMA
+    contraction)."""
+    if force or not os.path.exists(_SO):
+        tmp = _SO + ".tmp"
+        subprocess.check_call(
+            ["gcc", "-O2", "-std=c99", "-fPIC", "-shared", "-ffp-contract=off",
+             "-fno-fast-math", "-Wall", "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _SO)
+    return _SO
+
+
+_lib = None
+
+
+def load(path: str):
+    """Open a compiled oracle library and declare its signatures."""
+    L = C.CDLL(path)
+    P, D, I = C.c_void_p, C.c_double, C.c_int
+    L.or_bsr_spmv.argtypes = [I, I, P, P, P, P, P]
+    L.or_bsr_amxpby.argtypes = [I, I, P, P, P, D, P, D, P]
+    L.or_bilu0.argtypes = [I, I, P, P, P, P]
+    L.or_bilu0.restype = I
+    L.or_bilu0_solve.argtypes = [I, I, P, P, P, P, P]
+    L.or_bilu0_solve_lower.argtypes = [I, I, P, P, P, P, P]
+    L.or_bilu0_solve_upper.argtypes = [I, I, P, P, P, P, P]
+    L.or_pc_create.argtypes = [I, I, I, P, P, P, I, I, C.POINTER(I)]
+    L.or_pc_create.restype = P
+    L.or_pc_create_learned.argtypes = [P, I, I, I, P, P, I]
+    L.or_pc_create_learned.restype = P
+    L.or_pc_apply.argtypes = [P, P, P]
+    L.or_pc_destroy.argtypes = [P]
+    L.or_pc_learned_stats.argtypes = [P, C.POINTER(C.c_long), C.POINTER(C.c_long)]
+    L.or_cpr_weights.argtypes = [I, P, P, P, P]
+    L.or_cpr_weights.restype = I
+    L.or_cpr_extract_pressure.argtypes = [I, P, P, P, P, P]
+    L.or_gmres.argtypes = [I, I, P, P, P, P, P, P, P, P, P]
+    L.or_gmres.restype = I
+    L.or_bicgstab.argtypes = [I, I, P, P, P, P, P, P, P, P, P]
+    L.or_bicgstab.restype = I
+    L.or_conv_nparams.restype = I
+    L.or_conv_forward.argtypes = [I, I, I, P, P, P, I]
+    L.or_conv_loss_grad.argtypes = [I, I, I, P, P, P, P, P, I]
+    L.or_conv_loss_grad.restype = D
+    L.or_adam_step.argtypes = [I, P, P, P, P, I, D, D, D, D]
+    L.or_gelu.argtypes = [D]
+    L.or_gelu.restype = D
+    L.or_bf16_round.argtypes = [C.c_float]
+    L.or_bf16_round.restype = C.c_float
+    return L
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_SO):
+            build()
+        _lib = load(_SO)
+    return _lib
+
+
+def compile_variant(src_text: str, out_path: str) -> str:
+    """Compile a modified copy of oracle.c (used by the tests that plant a
+    mistake in the oracle and check that a pin catches it)."""
+    d = os.path.dirname(out_path)
+    cpath = os.path.join(d, "oracle_variant.c")
+    with open(cpath, "w") as f:
+        f.write(src_text)
+    subprocess.check_call(
+        ["gcc", "-O1", "-std=c99", "-fPIC", "-shared", "-ffp-contract=off",
+         "-I", _HERE, "-o", out_path, cpath, "-lm"])
+    return out_path
+
+
+def source() -> str:
+    with open(_SRC) as f:
+        return f.read()
+
+
+class KrylovOpts(C.Structure):
+    _fields_ = [("restart", C.c_int), ("maxit", C.c_int), ("rtol", C.c_double),
+                ("atol", C.c_double), ("flexible", C.c_int), ("left", C.c_int),
+                ("check_at_cycle_end", C.c_int), ("fixed_iters", C.c_int)]
+
+
+class KrylovResult(C.Structure):
+    _fields_ = [("iters", C.c_int), ("true_relres", C.c_double),
+                ("restarts", C.c_int)]
+
+
+def _p(a):
+    return a.ctypes.data_as(C.c_void_p)
+
+
+def _i32(a):
+    return np.ascontiguousarray(a, dtype=np.int32)
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+class Matrix:
+    """Block-CSR view of a generated system (bs = 1 for CSR)."""
+
+    def __init__(self, rowptr, col, val, bs=1):
+        self.rowptr = _i32(rowptr)
+        self.col = _i32(col)
+        self.bs = int(bs)
+        self.val = _f64(val).reshape(-1)
+        self.nb = self.rowptr.size - 1
+        self.n = self.nb * self.bs
+
+    @classmethod
+    def from_system(cls, s):
+        return cls(s["rowptr"], s["col"], s["val"], s.get("bs", 1))
+
+    def args(self):
+        return (self.nb, self.bs, _p(self.rowptr), _p(self.col), _p(self.val))
+
+
+def spmv(A: Matrix, x):
+    x = _f64(x)
+    y = np.empty(A.n)
+    lib().or_bsr_spmv(*A.args(), _p(x), _p(y))
+    return y
+
+
+def amxpby(A: Matrix, alpha, x, beta, y):
+    x = _f64(x)
+    y = _f64(y).copy()
+    lib().or_bsr_amxpby(A.nb, A.bs, _p(A.rowptr), _p(A.col), _p(A.val),
+                        alpha, _p(x), beta, _p(y))
+    return y
+
+
+def bilu0(A: Matrix):
+    lu = np.empty_like(A.val)
+    rc = lib().or_bilu0(*A.args(), _p(lu))
+    return rc, lu
+
+
+def bilu0_solve(A: Matrix, lu, b, part="both"):
+    b = _f64(b)
+    x = np.empty(A.n)
+    lu = _f64(lu)
+    f = {"both": lib().or_bilu0_solve, "lower": lib().or_bilu0_solve_lower,
+         "upper": lib().or_bilu0_solve_upper}[part]
+    f(A.nb, A.bs, _p(A.rowptr), _p(A.col), _p(lu), _p(b), _p(x))
+    return x
+
+
+def cpr_weights(A: Matrix):
+    w = np.empty(3 * A.nb)
+    rc = lib().or_cpr_weights(A.nb, _p(A.rowptr), _p(A.col), _p(A.val), _p(w))
+    return rc, w
+
+
+def cpr_pressure_matrix(A: Matrix, w):
+    app = np.empty(A.rowptr[-1])
+    w = _f64(w)
+    lib().or_cpr_extract_pressure(A.nb, _p(A.rowptr), _p(A.col), _p(A.val),
+                                  _p(w), _p(app))
+    return app
+
+
+class PC:
+    """Oracle preconditioner: kind in none/bilu0/cpr_pf/cpr_fp, precision
+    f64/f32/bf16, p_sweeps = ILU(0) sweeps of the CPR pressure stage."""
+
+    def __init__(self, A: Matrix, kind="bilu0", prec="f64", p_sweeps=4):
+        self.A = A
+        err = C.c_int(0)
+        self.h = lib().or_pc_create(PC_KIND[kind], *A.args(), PREC[prec],
+                                    int(p_sweeps), C.byref(err))
+        self.err = err.value
+        if not self.h:
+            raise RuntimeError(f"oracle PC setup failed: {self.err}")
+
+    @classmethod
+    def learned(cls, base: "PC", grid, params, lnk, bf16=True):
+        obj = cls.__new__(cls)
+        obj.A = base.A
+        obj.err = 0
+        params = _f64(params)
+        lnk = _f64(lnk)
+        nx, ny, nz = grid
+        obj.h = lib().or_pc_create_learned(base.h, nx, ny, nz, _p(params),
+                                           _p(lnk), int(bf16))
+        base.h = None      # ownership moved
+        return obj
+
+    def apply(self, v):
+        v = _f64(v)
+        z = np.empty(self.A.n)
+        lib().or_pc_apply(self.h, _p(v), _p(z))
+        return z
+
+    def learned_stats(self):
+        a, f = C.c_long(0), C.c_long(0)
+        lib().or_pc_learned_stats(self.h, C.byref(a), C.byref(f))
+        return a.value, f.value
+
+    def __del__(self):
+        if getattr(self, "h", None):
+            lib().or_pc_destroy(self.h)
+            self.h = None
+
+
+def _solve(fn, A, pc, b, x0, restart, maxit, rtol, atol, flexible, left,
+           check_at_cycle_end, fixed_iters, hist):
+    b = _f64(b)
+    x = np.zeros(A.n) if x0 is None else _f64(x0).copy()
+    o = KrylovOpts(int(restart), int(maxit), float(rtol), float(atol),
+                   int(flexible), int(left), int(check_at_cycle_end),
+                   int(fixed_iters))
+    r = KrylovResult()
+    h = np.zeros(int(maxit) + 2) if hist else None
+    rc = fn(*A.args(), C.c_void_p(pc.h), _p(b), _p(x), C.byref(o), C.byref(r),
+            _p(h) if hist else None)
+    out = dict(status=rc, x=x, iters=r.iters, relres=r.true_relres,
+               restarts=r.restarts)
+    if hist:
+        out["hist"] = h[:r.iters + 1]
+    return out
+
+
+def gmres(A, pc, b, x0=None, restart=30, maxit=500, rtol=1e-6, atol=0.0,
+          flexible=False, left=False, check_at_cycle_end=False,
+          fixed_iters=False, hist=False):
+    return _solve(lib().or_gmres, A, pc, b, x0, restart, maxit, rtol, atol,
+                  flexible, left, check_at_cycle_end, fixed_iters, hist)
+
+
+def bicgstab(A, pc, b, x0=None, maxit=500, rtol=1e-6, atol=0.0,
+             fixed_iters=False, hist=False):
+    return _solve(lib().or_bicgstab, A, pc, b, x0, 0, maxit, rtol, atol,
+                  False, False, False, fixed_iters, hist)
+
+
+# ---- learned-stage network -------------------------------------------------
+CONV_CH = (4, 32, 32, 32, 3)
+
+
+def conv_nparams():
+    return lib().or_conv_nparams()
+
+
+def conv_forward(grid, params, inp, bf16=False):
+    nx, ny, nz = grid
+    params = _f64(params)
+    inp = _f64(inp)
+    out = np.empty(3 * nx * ny * nz)
+    lib().or_conv_forward(nx, ny, nz, _p(params), _p(inp), _p(out), int(bf16))
+    return out
+
+
+def conv_loss_grad(grid, params, inp, target, bf16=False, want_dinput=False):
+    nx, ny, nz = grid
+    params = _f64(params)
+    inp = _f64(inp)
+    target = _f64(target)
+    grad = np.empty(params.size)
+    din = np.empty(inp.size) if want_dinput else None
+    loss = lib().or_conv_loss_grad(nx, ny, nz, _p(params), _p(inp), _p(target),
+                                   _p(grad), _p(din) if want_dinput else None,
+                                   int(bf16))
+    return (loss, grad, din) if want_dinput else (loss, grad)
+
+
+def adam_step(params, grad, m, v, t, lr=1e-3, beta1=0.9, beta2=0.999,
+              eps=1e-8):
+    params = _f64(params).copy()
+    m = _f64(m).copy()
+    v = _f64(v).copy()
+    grad = _f64(grad)
+    lib().or_adam_step(params.size, _p(params), _p(grad), _p(m), _p(v), int(t),
+                       lr, beta1, beta2, eps)
+    return params, m, v
+
+
+def gelu(x):
+    return lib().or_gelu(float(x))
+
+
+def bf16_round(x):
+    return float(lib().or_bf16_round(float(x)))

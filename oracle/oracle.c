@@ -1,0 +1,1074 @@
+/*
+ * FP64 CPU oracle -- TEST INFRASTRUCTURE ONLY (see oracle.h).
+ *
+ * Liu & Chen, arXiv 1701.05913.  Each function names the passage it
+ * follows.  Nothing here is blocked, fused or reordered beyond what the
+ * definition states; loops run in row order, sums in column order.
+ * Compile without -ffast-math and without FMA contraction.
+ */
+#include "oracle.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+/* ======================================================================
+ * Small dense helpers for bs x bs blocks (row-major)
+ * ====================================================================== */
+
+/* y -= A x */
+static void blk_sub_mv(int bs, const double *A, const double *x, double *y)
+{
+    for (int r = 0; r < bs; r++) {
+        double s = 0.0;
+        for (int c = 0; c < bs; c++) s += A[r * bs + c] * x[c];
+        y[r] -= s;
+    }
+}
+
+/* C = A B */
+static void blk_mm(int bs, const double *A, const double *B, double *C)
+{
+    for (int r = 0; r < bs; r++)
+        for (int c = 0; c < bs; c++) {
+            double s = 0.0;
+            for (int k = 0; k < bs; k++) s += A[r * bs + k] * B[k * bs + c];
+            C[r * bs + c] = s;
+        }
+}
+
+static double blk_norm_inf(int bs, const double *A)
+{
+    double m = 0.0;
+    for (int r = 0; r < bs; r++) {
+        double s = 0.0;
+        for (int c = 0; c < bs; c++) s += fabs(A[r * bs + c]);
+        if (s > m) m = s;
+    }
+    return m;
+}
+
+/* Solve A X = B for X (bs x nrhs, row-major, nrhs columns) by Gaussian
+ * elimination with partial pivoting (first maximal pivot on ties).
+ * Zero pivot: |pivot| < 1e-14 ||A||_inf for bs > 1, |a| < 1e-300 for
+ * bs = 1, or a non-finite pivot.  Returns 0 or OR_ERR_ZERO_PIVOT. */
+static int blk_solve(int bs, const double *A, double *X, int nrhs)
+{
+    double M[64], R[64 * 64];
+    double anorm = blk_norm_inf(bs, A);
+    memcpy(M, A, sizeof(double) * bs * bs);
+    memcpy(R, X, sizeof(double) * bs * nrhs);
+    for (int k = 0; k < bs; k++) {
+        int piv = k;
+        double best = fabs(M[k * bs + k]);
+        for (int r = k + 1; r < bs; r++)
+            if (fabs(M[r * bs + k]) > best) { best = fabs(M[r * bs + k]); piv = r; }
+        if (!isfinite(best)) return OR_ERR_ZERO_PIVOT;
+        if (bs == 1 ? best < 1e-300 : best < 1e-14 * anorm) return OR_ERR_ZERO_PIVOT;
+        if (piv != k) {
+            for (int c = 0; c < bs; c++) {
+                double t = M[k * bs + c]; M[k * bs + c] = M[piv * bs + c]; M[piv * bs + c] = t;
+            }
+            for (int c = 0; c < nrhs; c++) {
+                double t = R[k * nrhs + c]; R[k * nrhs + c] = R[piv * nrhs + c]; R[piv * nrhs + c] = t;
+            }
+        }
+        for (int r = k + 1; r < bs; r++) {
+            double f = M[r * bs + k] / M[k * bs + k];
+            for (int c = k; c < bs; c++) M[r * bs + c] -= f * M[k * bs + c];
+            for (int c = 0; c < nrhs; c++) R[r * nrhs + c] -= f * R[k * nrhs + c];
+        }
+    }
+    for (int k = bs - 1; k >= 0; k--)
+        for (int c = 0; c < nrhs; c++) {
+            double s = R[k * nrhs + c];
+            for (int j = k + 1; j < bs; j++) s -= M[k * bs + j] * R[j * nrhs + c];
+            R[k * nrhs + c] = s / M[k * bs + k];
+        }
+    memcpy(X, R, sizeof(double) * bs * nrhs);
+    return 0;
+}
+
+static int blk_inverse(int bs, const double *A, double *Ainv)
+{
+    for (int r = 0; r < bs; r++)
+        for (int c = 0; c < bs; c++) Ainv[r * bs + c] = (r == c) ? 1.0 : 0.0;
+    return blk_solve(bs, A, Ainv, bs);
+}
+
+static double dot(int n, const double *x, const double *y)
+{
+    double s = 0.0;
+    for (int i = 0; i < n; i++) s += x[i] * y[i];
+    return s;
+}
+
+static double nrm2(int n, const double *x) { return sqrt(dot(n, x, x)); }
+
+static int diag_pos(const int *rp, const int *ci, int i)
+{
+    for (int p = rp[i]; p < rp[i + 1]; p++)
+        if (ci[p] == i) return p;
+    return -1;
+}
+
+/* ======================================================================
+ * Precision emulation
+ * ====================================================================== */
+float or_bf16_round(float f)
+{
+    uint32_t u;
+    memcpy(&u, &f, 4);
+    if ((u & 0x7f800000u) == 0x7f800000u) {          /* inf / nan */
+        if (u & 0x007fffffu) u |= 0x00400000u;
+        u &= 0xffff0000u;
+    } else {
+        u += 0x7fffu + ((u >> 16) & 1u);              /* nearest, ties to even */
+        u &= 0xffff0000u;
+    }
+    memcpy(&f, &u, 4);
+    return f;
+}
+
+static double bf16d(double x) { return (double)or_bf16_round((float)x); }
+
+/* ======================================================================
+ * C1. SpMV -- Figures 20 and 21: y_i = sum_j a_ij x_j row by row.
+ * ====================================================================== */
+void or_bsr_spmv(int nb, int bs, const int *rp, const int *ci,
+                 const double *a, const double *x, double *y)
+{
+    for (int i = 0; i < nb; i++) {
+        for (int r = 0; r < bs; r++) {
+            double t = 0.0;
+            for (int p = rp[i]; p < rp[i + 1]; p++) {
+                const double *blk = a + (size_t)p * bs * bs;
+                const double *xj = x + (size_t)ci[p] * bs;
+                for (int c = 0; c < bs; c++) t += blk[r * bs + c] * xj[c];
+            }
+            y[(size_t)i * bs + r] = t;
+        }
+    }
+}
+
+/* y = alpha A x + beta y  (Figure 21) */
+void or_bsr_amxpby(int nb, int bs, const int *rp, const int *ci,
+                   const double *a, double alpha, const double *x,
+                   double beta, double *y)
+{
+    for (int i = 0; i < nb; i++) {
+        for (int r = 0; r < bs; r++) {
+            double t = 0.0;
+            for (int p = rp[i]; p < rp[i + 1]; p++) {
+                const double *blk = a + (size_t)p * bs * bs;
+                const double *xj = x + (size_t)ci[p] * bs;
+                for (int c = 0; c < bs; c++) t += blk[r * bs + c] * xj[c];
+            }
+            y[(size_t)i * bs + r] = alpha * t + beta * y[(size_t)i * bs + r];
+        }
+    }
+}
+
+/* ======================================================================
+ * C2/C3. ILU(0) and block ILU(0): incomplete LU restricted to the pattern
+ * of A, row-oriented (IKJ) elimination, no pivoting across rows.
+ *   for each row i, for each k < i in row i (ascending):
+ *       a_ik <- a_ik * a_kk^{-1}
+ *       for each j > k in row k with (i, j) in the pattern:
+ *           a_ij <- a_ij - a_ik * a_kj
+ * Output lu: strictly-lower blocks hold L (unit block diagonal implied),
+ * diagonal and upper blocks hold U.
+ * ====================================================================== */
+int or_bilu0(int nb, int bs, const int *rp, const int *ci,
+             const double *a, double *lu)
+{
+    const int b2 = bs * bs;
+    memcpy(lu, a, sizeof(double) * (size_t)rp[nb] * b2);
+    double inv[64], tmp[64];
+    for (int i = 0; i < nb; i++) {
+        int di = diag_pos(rp, ci, i);
+        if (di < 0) return OR_ERR_ARG;
+        for (int p = rp[i]; p < rp[i + 1]; p++) {
+            int k = ci[p];
+            if (k >= i) break;
+            int dk = diag_pos(rp, ci, k);
+            if (blk_inverse(bs, lu + (size_t)dk * b2, inv)) return OR_ERR_ZERO_PIVOT;
+            blk_mm(bs, lu + (size_t)p * b2, inv, tmp);
+            memcpy(lu + (size_t)p * b2, tmp, sizeof(double) * b2);
+            for (int q = dk + 1; q < rp[k + 1]; q++) {
+                int j = ci[q];
+                for (int s = rp[i]; s < rp[i + 1]; s++) {
+                    if (ci[s] == j) {
+                        blk_mm(bs, lu + (size_t)p * b2, lu + (size_t)q * b2, tmp);
+                        for (int e = 0; e < b2; e++) lu[(size_t)s * b2 + e] -= tmp[e];
+                        break;
+                    }
+                }
+            }
+        }
+        if (blk_inverse(bs, lu + (size_t)di * b2, inv)) return OR_ERR_ZERO_PIVOT;
+    }
+    return OR_OK;
+}
+
+/* C4, eq. (3): L y = b row by row (unit lower) */
+void or_bilu0_solve_lower(int nb, int bs, const int *rp, const int *ci,
+                          const double *lu, const double *b, double *y)
+{
+    const int b2 = bs * bs;
+    for (int i = 0; i < nb; i++) {
+        double t[8];
+        for (int r = 0; r < bs; r++) t[r] = b[(size_t)i * bs + r];
+        for (int p = rp[i]; p < rp[i + 1] && ci[p] < i; p++)
+            blk_sub_mv(bs, lu + (size_t)p * b2, y + (size_t)ci[p] * bs, t);
+        for (int r = 0; r < bs; r++) y[(size_t)i * bs + r] = t[r];
+    }
+}
+
+/* C4, eq. (3): U x = y from the last row up; U_ii solved by elimination */
+void or_bilu0_solve_upper(int nb, int bs, const int *rp, const int *ci,
+                          const double *lu, const double *y, double *x)
+{
+    const int b2 = bs * bs;
+    for (int i = nb - 1; i >= 0; i--) {
+        double t[8];
+        int di = -1;
+        for (int r = 0; r < bs; r++) t[r] = y[(size_t)i * bs + r];
+        for (int p = rp[i]; p < rp[i + 1]; p++) {
+            if (ci[p] == i) di = p;
+            if (ci[p] > i) blk_sub_mv(bs, lu + (size_t)p * b2, x + (size_t)ci[p] * bs, t);
+        }
+        if (blk_solve(bs, lu + (size_t)di * b2, t, 1)) {
+            for (int r = 0; r < bs; r++) t[r] = NAN;
+        }
+        for (int r = 0; r < bs; r++) x[(size_t)i * bs + r] = t[r];
+    }
+}
+
+void or_bilu0_solve(int nb, int bs, const int *rp, const int *ci,
+                    const double *lu, const double *b, double *x)
+{
+    double *y = (double *)malloc(sizeof(double) * (size_t)nb * bs);
+    or_bilu0_solve_lower(nb, bs, rp, ci, lu, b, y);
+    or_bilu0_solve_upper(nb, bs, rp, ci, lu, y, x);
+    free(y);
+}
+
+/* ----------------------------------------------------------------------
+ * Reduced-precision ILU(0) apply (mixed-precision extension).
+ * Factor computed in FP64 (or_bilu0), then stored rounded: off-diagonal
+ * L and U blocks to float (or to bfloat16 held in a float), the inverse of
+ * each diagonal U block computed in FP64 and rounded to float.  The apply
+ * is the same two sweeps as eq. (3), in float arithmetic, with the
+ * backward step x_i = U_ii^{-1} (y_i - sum_j U_ij x_j).
+ * ---------------------------------------------------------------------- */
+typedef struct {
+    int nb, bs;
+    const int *rp, *ci;
+    float *f;    /* nnzb*b2: off-diagonal blocks rounded; diagonal -> U_ii^-1 */
+    float *y, *x;
+} lowp_lu;
+
+static int lowp_init(lowp_lu *L, int nb, int bs, const int *rp,
+                     const int *ci, const double *lu, int prec)
+{
+    const int b2 = bs * bs;
+    size_t nnzb = (size_t)rp[nb];
+    L->nb = nb; L->bs = bs; L->rp = rp; L->ci = ci;
+    L->f = (float *)malloc(sizeof(float) * nnzb * b2);
+    L->y = (float *)malloc(sizeof(float) * (size_t)nb * bs);
+    L->x = (float *)malloc(sizeof(float) * (size_t)nb * bs);
+    double inv[64];
+    for (int i = 0; i < nb; i++)
+        for (int p = rp[i]; p < rp[i + 1]; p++) {
+            if (ci[p] == i) {
+                if (blk_inverse(bs, lu + (size_t)p * b2, inv)) return OR_ERR_ZERO_PIVOT;
+                for (int e = 0; e < b2; e++) L->f[(size_t)p * b2 + e] = (float)inv[e];
+            } else {
+                for (int e = 0; e < b2; e++) {
+                    float v = (float)lu[(size_t)p * b2 + e];
+                    L->f[(size_t)p * b2 + e] = (prec == OR_PREC_BF16) ? or_bf16_round(v) : v;
+                }
+            }
+        }
+    return OR_OK;
+}
+
+static void lowp_free(lowp_lu *L)
+{
+    free(L->f); free(L->y); free(L->x);
+    memset(L, 0, sizeof(*L));
+}
+
+/* x = (LU)^-1 b in float; b and x given as float arrays */
+static void lowp_apply(lowp_lu *L, const float *b, float *x)
+{
+    const int bs = L->bs, b2 = bs * bs;
+    const int *rp = L->rp, *ci = L->ci;
+    for (int i = 0; i < L->nb; i++) {
+        float t[8];
+        for (int r = 0; r < bs; r++) t[r] = b[(size_t)i * bs + r];
+        for (int p = rp[i]; p < rp[i + 1] && ci[p] < i; p++) {
+            const float *blk = L->f + (size_t)p * b2;
+            const float *yk = L->y + (size_t)ci[p] * bs;
+            for (int r = 0; r < bs; r++) {
+                float s = 0.0f;
+                for (int c = 0; c < bs; c++) s += blk[r * bs + c] * yk[c];
+                t[r] -= s;
+            }
+        }
+        for (int r = 0; r < bs; r++) L->y[(size_t)i * bs + r] = t[r];
+    }
+    for (int i = L->nb - 1; i >= 0; i--) {
+        float t[8], u[8];
+        int di = -1;
+        for (int r = 0; r < bs; r++) t[r] = L->y[(size_t)i * bs + r];
+        for (int p = rp[i]; p < rp[i + 1]; p++) {
+            if (ci[p] == i) { di = p; continue; }
+            if (ci[p] < i) continue;
+            const float *blk = L->f + (size_t)p * b2;
+            const float *xj = x + (size_t)ci[p] * bs;
+            for (int r = 0; r < bs; r++) {
+                float s = 0.0f;
+                for (int c = 0; c < bs; c++) s += blk[r * bs + c] * xj[c];
+                t[r] -= s;
+            }
+        }
+        const float *dinv = L->f + (size_t)di * b2;
+        for (int r = 0; r < bs; r++) {
+            float s = 0.0f;
+            for (int c = 0; c < bs; c++) s += dinv[r * bs + c] * t[c];
+            u[r] = s;
+        }
+        for (int r = 0; r < bs; r++) x[(size_t)i * bs + r] = u[r];
+    }
+}
+
+/* ======================================================================
+ * C8. CPR with quasi-IMPES decoupling (eqs. (5)-(9), Algorithms 5-6).
+ * Block unknown 0 is the pressure; Pi_r picks it, Pi_p injects it.
+ * Quasi-IMPES weight of cell i from its diagonal block
+ *   D_i = [[d_pp, d_ps^T], [d_sp, D_ss]]:  w_i^T = [1, -d_ps^T D_ss^{-1}],
+ * so that w_i^T D_i has zeros in the secondary columns.
+ * Pressure matrix: (A_pp)_ij = w_i^T A_ij e_0, on the block pattern of A.
+ * ====================================================================== */
+int or_cpr_weights(int nb, const int *rp, const int *ci, const double *a,
+                   double *w)
+{
+    for (int i = 0; i < nb; i++) {
+        int d = diag_pos(rp, ci, i);
+        if (d < 0) return OR_ERR_ARG;
+        const double *D = a + (size_t)d * 9;
+        /* solve D_ss^T y = d_ps  ->  w_s = -y */
+        double Dss_T[4] = { D[4], D[7], D[5], D[8] };
+        double y[2] = { D[1], D[2] };
+        if (blk_solve(2, Dss_T, y, 1)) return OR_ERR_ZERO_PIVOT;
+        w[3 * i + 0] = 1.0;
+        w[3 * i + 1] = -y[0];
+        w[3 * i + 2] = -y[1];
+    }
+    return OR_OK;
+}
+
+void or_cpr_extract_pressure(int nb, const int *rp, const int *ci,
+                             const double *a, const double *w, double *app)
+{
+    for (int i = 0; i < nb; i++)
+        for (int p = rp[i]; p < rp[i + 1]; p++) {
+            const double *B = a + (size_t)p * 9;
+            app[p] = w[3 * i] * B[0] + w[3 * i + 1] * B[3] + w[3 * i + 2] * B[6];
+        }
+}
+
+/* ======================================================================
+ * Preconditioner objects (Figure 29)
+ * ====================================================================== */
+struct or_pc {
+    int kind, nb, bs, prec, p_sweeps;
+    const int *rp, *ci;
+    const double *a;
+    double *lu;                 /* FP64 (block) ILU(0) factor of A        */
+    lowp_lu lp;                 /* rounded copy for F32 / BF16            */
+    /* CPR */
+    double *w, *app, *applu;
+    lowp_lu lpp;                /* rounded pressure factor                */
+    float *appf, *af;           /* rounded A_pp values, rounded A values  */
+    /* learned stage */
+    or_pc *base;
+    int nx, ny, nz, bf16;
+    double *params, *lnk;
+    long applies, fallbacks;
+};
+
+or_pc *or_pc_create(int kind, int nb, int bs, const int *rp, const int *ci,
+                    const double *a, int prec, int p_sweeps, int *err)
+{
+    or_pc *pc = (or_pc *)calloc(1, sizeof(or_pc));
+    size_t nnzb = (size_t)rp[nb];
+    int b2 = bs * bs, e = OR_OK;
+    pc->kind = kind; pc->nb = nb; pc->bs = bs; pc->prec = prec;
+    pc->p_sweeps = p_sweeps; pc->rp = rp; pc->ci = ci; pc->a = a;
+    if (kind == OR_PC_BILU0 || kind == OR_PC_CPR_PF || kind == OR_PC_CPR_FP) {
+        pc->lu = (double *)malloc(sizeof(double) * nnzb * b2);
+        e = or_bilu0(nb, bs, rp, ci, a, pc->lu);
+        if (!e && prec != OR_PREC_F64) e = lowp_init(&pc->lp, nb, bs, rp, ci, pc->lu, prec);
+    }
+    if (!e && (kind == OR_PC_CPR_PF || kind == OR_PC_CPR_FP)) {
+        if (bs != 3) e = OR_ERR_ARG;
+        if (!e) {
+            pc->w = (double *)malloc(sizeof(double) * 3 * (size_t)nb);
+            pc->app = (double *)malloc(sizeof(double) * nnzb);
+            pc->applu = (double *)malloc(sizeof(double) * nnzb);
+            e = or_cpr_weights(nb, rp, ci, a, pc->w);
+        }
+        if (!e) {
+            or_cpr_extract_pressure(nb, rp, ci, a, pc->w, pc->app);
+            e = or_bilu0(nb, 1, rp, ci, pc->app, pc->applu);
+        }
+        if (!e && prec != OR_PREC_F64) {
+            /* the pressure factor is rounded to float in both reduced
+             * variants; only the block factor is held in bfloat16 */
+            e = lowp_init(&pc->lpp, nb, 1, rp, ci, pc->applu, OR_PREC_F32);
+            pc->appf = (float *)malloc(sizeof(float) * nnzb);
+            pc->af = (float *)malloc(sizeof(float) * nnzb * 9);
+            for (size_t p = 0; p < nnzb; p++) pc->appf[p] = (float)pc->app[p];
+            for (size_t p = 0; p < nnzb * 9; p++) pc->af[p] = (float)a[p];
+        }
+    }
+    if (err) *err = e;
+    if (e) { or_pc_destroy(pc); return NULL; }
+    return pc;
+}
+
+or_pc *or_pc_create_learned(or_pc *base, int nx, int ny, int nz,
+                            const double *params, const double *lnk,
+                            int bf16_emul)
+{
+    or_pc *pc = (or_pc *)calloc(1, sizeof(or_pc));
+    int np = or_conv_nparams();
+    size_t cells = (size_t)nx * ny * nz;
+    pc->kind = OR_PC_LEARNED;
+    pc->base = base;
+    pc->nb = base->nb; pc->bs = base->bs; pc->rp = base->rp; pc->ci = base->ci;
+    pc->a = base->a;
+    pc->nx = nx; pc->ny = ny; pc->nz = nz; pc->bf16 = bf16_emul;
+    pc->params = (double *)malloc(sizeof(double) * np);
+    memcpy(pc->params, params, sizeof(double) * np);
+    pc->lnk = (double *)malloc(sizeof(double) * cells);
+    memcpy(pc->lnk, lnk, sizeof(double) * cells);
+    return pc;
+}
+
+void or_pc_destroy(or_pc *pc)
+{
+    if (!pc) return;
+    free(pc->lu); free(pc->w); free(pc->app); free(pc->applu);
+    free(pc->appf); free(pc->af);
+    if (pc->lp.f) lowp_free(&pc->lp);
+    if (pc->lpp.f) lowp_free(&pc->lpp);
+    if (pc->base) or_pc_destroy(pc->base);
+    free(pc->params); free(pc->lnk);
+    free(pc);
+}
+
+void or_pc_learned_stats(const or_pc *pc, long *applies, long *fallbacks)
+{
+    if (applies) *applies = pc->applies;
+    if (fallbacks) *fallbacks = pc->fallbacks;
+}
+
+/* FP64 pressure stage: p = 0, then s sweeps p <- p + (LU)^-1 (r_p - A_pp p) */
+static void pstage_f64(or_pc *pc, const double *rpv, double *p)
+{
+    int nb = pc->nb;
+    double *res = (double *)malloc(sizeof(double) * nb);
+    double *d = (double *)malloc(sizeof(double) * nb);
+    for (int i = 0; i < nb; i++) p[i] = 0.0;
+    for (int s = 0; s < pc->p_sweeps; s++) {
+        memcpy(res, rpv, sizeof(double) * nb);
+        or_bsr_amxpby(nb, 1, pc->rp, pc->ci, pc->app, -1.0, p, 1.0, res);
+        or_bilu0_solve(nb, 1, pc->rp, pc->ci, pc->applu, res, d);
+        for (int i = 0; i < nb; i++) p[i] += d[i];
+    }
+    free(res); free(d);
+}
+
+/* float pressure stage, same steps in float arithmetic */
+static void pstage_f32(or_pc *pc, const float *rpv, float *p)
+{
+    int nb = pc->nb;
+    float *res = (float *)malloc(sizeof(float) * nb);
+    float *d = (float *)malloc(sizeof(float) * nb);
+    for (int i = 0; i < nb; i++) p[i] = 0.0f;
+    for (int s = 0; s < pc->p_sweeps; s++) {
+        for (int i = 0; i < nb; i++) {
+            float t = 0.0f;
+            for (int q = pc->rp[i]; q < pc->rp[i + 1]; q++) t += pc->appf[q] * p[pc->ci[q]];
+            res[i] = rpv[i] - t;
+        }
+        lowp_apply(&pc->lpp, res, d);
+        for (int i = 0; i < nb; i++) p[i] += d[i];
+    }
+    free(res); free(d);
+}
+
+static void conv_apply_learned(or_pc *pc, const double *v, double *z);
+
+void or_pc_apply(or_pc *pc, const double *v, double *z)
+{
+    const int nb = pc->nb, bs = pc->bs;
+    const size_t n = (size_t)nb * bs;
+    if (pc->kind == OR_PC_NONE) {
+        memcpy(z, v, sizeof(double) * n);
+        return;
+    }
+    if (pc->kind == OR_PC_LEARNED) {
+        conv_apply_learned(pc, v, z);
+        return;
+    }
+    if (pc->prec == OR_PREC_F64) {
+        if (pc->kind == OR_PC_BILU0) {
+            or_bilu0_solve(nb, bs, pc->rp, pc->ci, pc->lu, v, z);
+            return;
+        }
+        double *rpv = (double *)calloc((size_t)nb + 1, sizeof(double));
+        double *p = (double *)malloc(sizeof(double) * nb);
+        double *r = (double *)malloc(sizeof(double) * n);
+        double *t = (double *)malloc(sizeof(double) * n);
+        if (pc->kind == OR_PC_CPR_PF) {
+            /* Algorithm 6 read as: z1 = Pi_p(P-stage(Pi_r W v));
+             * r = v - A z1; z = z1 + BILU^-1 r */
+            for (int i = 0; i < nb; i++)
+                rpv[i] = pc->w[3 * i] * v[3 * i] + pc->w[3 * i + 1] * v[3 * i + 1]
+                       + pc->w[3 * i + 2] * v[3 * i + 2];
+            pstage_f64(pc, rpv, p);
+            for (int i = 0; i < nb; i++) { z[3 * i] = p[i]; z[3 * i + 1] = 0.0; z[3 * i + 2] = 0.0; }
+            memcpy(r, v, sizeof(double) * n);
+            or_bsr_amxpby(nb, 3, pc->rp, pc->ci, pc->a, -1.0, z, 1.0, r);
+            or_bilu0_solve(nb, 3, pc->rp, pc->ci, pc->lu, r, t);
+            for (size_t i = 0; i < n; i++) z[i] += t[i];
+        } else {
+            /* Algorithm 5: z1 = BILU^-1 v; r = v - A z1;
+             * z = z1 + Pi_p(P-stage(Pi_r W r)) */
+            or_bilu0_solve(nb, 3, pc->rp, pc->ci, pc->lu, v, z);
+            memcpy(r, v, sizeof(double) * n);
+            or_bsr_amxpby(nb, 3, pc->rp, pc->ci, pc->a, -1.0, z, 1.0, r);
+            for (int i = 0; i < nb; i++)
+                rpv[i] = pc->w[3 * i] * r[3 * i] + pc->w[3 * i + 1] * r[3 * i + 1]
+                       + pc->w[3 * i + 2] * r[3 * i + 2];
+            pstage_f64(pc, rpv, p);
+            for (int i = 0; i < nb; i++) z[3 * i] += p[i];
+        }
+        free(rpv); free(p); free(r); free(t);
+        return;
+    }
+    /* reduced precision: input rounded to float, float arithmetic,
+     * output widened to double */
+    float *vf = (float *)malloc(sizeof(float) * n);
+    float *zf = (float *)malloc(sizeof(float) * n);
+    for (size_t i = 0; i < n; i++) vf[i] = (float)v[i];
+    if (pc->kind == OR_PC_BILU0) {
+        lowp_apply(&pc->lp, vf, zf);
+    } else {
+        float *rpv = (float *)calloc((size_t)nb + 1, sizeof(float));
+        float *p = (float *)malloc(sizeof(float) * nb);
+        float *r = (float *)malloc(sizeof(float) * n);
+        float *t = (float *)malloc(sizeof(float) * n);
+        if (pc->kind == OR_PC_CPR_PF) {
+            for (int i = 0; i < nb; i++)
+                rpv[i] = (float)pc->w[3 * i] * vf[3 * i] + (float)pc->w[3 * i + 1] * vf[3 * i + 1]
+                       + (float)pc->w[3 * i + 2] * vf[3 * i + 2];
+            pstage_f32(pc, rpv, p);
+            /* r = v - A Pi_p p: only column 0 of each block meets p */
+            for (int i = 0; i < nb; i++)
+                for (int rr = 0; rr < 3; rr++) {
+                    float s = 0.0f;
+                    for (int q = pc->rp[i]; q < pc->rp[i + 1]; q++)
+                        s += pc->af[(size_t)q * 9 + rr * 3] * p[pc->ci[q]];
+                    r[3 * i + rr] = vf[3 * i + rr] - s;
+                }
+            lowp_apply(&pc->lp, r, t);
+            for (int i = 0; i < nb; i++) {
+                zf[3 * i] = p[i] + t[3 * i];
+                zf[3 * i + 1] = t[3 * i + 1];
+                zf[3 * i + 2] = t[3 * i + 2];
+            }
+        } else {
+            lowp_apply(&pc->lp, vf, zf);
+            for (int i = 0; i < nb; i++)
+                for (int rr = 0; rr < 3; rr++) {
+                    float s = 0.0f;
+                    for (int q = pc->rp[i]; q < pc->rp[i + 1]; q++) {
+                        const float *B = pc->af + (size_t)q * 9;
+                        const float *zj = zf + (size_t)pc->ci[q] * 3;
+                        s += B[rr * 3] * zj[0] + B[rr * 3 + 1] * zj[1] + B[rr * 3 + 2] * zj[2];
+                    }
+                    r[3 * i + rr] = vf[3 * i + rr] - s;
+                }
+            for (int i = 0; i < nb; i++)
+                rpv[i] = (float)pc->w[3 * i] * r[3 * i] + (float)pc->w[3 * i + 1] * r[3 * i + 1]
+                       + (float)pc->w[3 * i + 2] * r[3 * i + 2];
+            pstage_f32(pc, rpv, p);
+            for (int i = 0; i < nb; i++) zf[3 * i] += p[i];
+        }
+        free(rpv); free(p); free(r); free(t);
+    }
+    for (size_t i = 0; i < n; i++) z[i] = (double)zf[i];
+    free(vf); free(zf);
+}
+
+/* ======================================================================
+ * C5/C6. Restarted GMRES(m) (Algorithm 1) and FGMRES(m).
+ * Default reading: right preconditioning (A M^-1 u = b, x = M^-1 u) so the
+ * Arnoldi estimate |g_{j+1}| is the unpreconditioned residual; modified
+ * Gram-Schmidt as in Algorithm 1 lines 7-10; Givens rotations
+ * c = h_jj / r, s = h_{j+1,j} / r, r = hypot(h_jj, h_{j+1,j}); the
+ * estimate is checked after every Arnoldi step; the true residual
+ * b - A x decides convergence at each restart.  `left` runs Algorithm 1
+ * as printed (M r = b - A x0, M w = A v).
+ * Converged iff ||b - A x|| <= max(rtol ||b||, atol).
+ * ====================================================================== */
+int or_gmres(int nb, int bs, const int *rp, const int *ci, const double *a,
+             or_pc *pc, const double *b, double *x, const or_krylov_opts *o,
+             or_krylov_result *res, double *hist)
+{
+    const size_t n = (size_t)nb * bs;
+    const int m = o->restart;
+    if (m < 1 || o->maxit < 0) return OR_ERR_ARG;
+    double *V = (double *)malloc(sizeof(double) * n * (m + 1));
+    double *Z = o->flexible ? (double *)malloc(sizeof(double) * n * m) : NULL;
+    double *H = (double *)calloc((size_t)(m + 1) * m, sizeof(double));
+    double *cs = (double *)malloc(sizeof(double) * m);
+    double *sn = (double *)malloc(sizeof(double) * m);
+    double *g = (double *)malloc(sizeof(double) * (m + 1));
+    double *y = (double *)malloc(sizeof(double) * m);
+    double *r = (double *)malloc(sizeof(double) * n);
+    double *w = (double *)malloc(sizeof(double) * n);
+    double *z = (double *)malloc(sizeof(double) * n);
+    const double bnorm = nrm2((int)n, b);
+    double ref = bnorm;
+    if (o->left) {                 /* tolerance on ||M^-1 b|| */
+        or_pc_apply(pc, b, z);
+        ref = nrm2((int)n, z);
+    }
+    const double tol_true = fmax(o->rtol * bnorm, o->atol);
+    const double tol_est = fmax(o->rtol * ref, o->atol);
+    int nits = 0, cycles = 0, status = OR_NOT_CONVERGED;
+    double relres = 0.0;
+#define HH(i, j) H[(size_t)(i) * m + (j)]
+    for (;;) {
+        /* true residual r = b - A x */
+        memcpy(r, b, sizeof(double) * n);
+        or_bsr_amxpby(nb, bs, rp, ci, a, -1.0, x, 1.0, r);
+        double tnorm = nrm2((int)n, r);
+        relres = bnorm > 0 ? tnorm / bnorm : tnorm;
+        if (hist && nits == 0) hist[0] = tnorm;
+        if (!o->fixed_iters && tnorm <= tol_true) { status = OR_OK; break; }
+        if (nits >= o->maxit) break;
+        if (o->left) { or_pc_apply(pc, r, w); memcpy(r, w, sizeof(double) * n); }
+        double beta = nrm2((int)n, r);
+        if (beta == 0.0 || !isfinite(beta)) { status = isfinite(beta) ? OR_OK : OR_ERR_BREAKDOWN; break; }
+        for (size_t i = 0; i < n; i++) V[i] = r[i] / beta;
+        for (int i = 0; i <= m; i++) g[i] = 0.0;
+        g[0] = beta;
+        int jend = 0;
+        cycles++;
+        for (int j = 0; j < m; j++) {
+            double *vj = V + n * j;
+            if (o->left) {
+                or_bsr_spmv(nb, bs, rp, ci, a, vj, z);
+                or_pc_apply(pc, z, w);
+            } else {
+                double *zj = o->flexible ? Z + n * j : z;
+                or_pc_apply(pc, vj, zj);
+                or_bsr_spmv(nb, bs, rp, ci, a, zj, w);
+            }
+            for (int k = 0; k <= j; k++) {           /* MGS */
+                double h = dot((int)n, w, V + n * k);
+                HH(k, j) = h;
+                for (size_t i = 0; i < n; i++) w[i] -= h * V[n * k + i];
+            }
+            double hn = nrm2((int)n, w);
+            HH(j + 1, j) = hn;
+            if (hn != 0.0)
+                for (size_t i = 0; i < n; i++) V[n * (j + 1) + i] = w[i] / hn;
+            for (int k = 0; k < j; k++) {            /* old rotations */
+                double t = cs[k] * HH(k, j) + sn[k] * HH(k + 1, j);
+                HH(k + 1, j) = -sn[k] * HH(k, j) + cs[k] * HH(k + 1, j);
+                HH(k, j) = t;
+            }
+            double rr = hypot(HH(j, j), HH(j + 1, j));
+            if (rr == 0.0) { cs[j] = 1.0; sn[j] = 0.0; }
+            else { cs[j] = HH(j, j) / rr; sn[j] = HH(j + 1, j) / rr; }
+            HH(j, j) = rr;
+            HH(j + 1, j) = 0.0;
+            g[j + 1] = -sn[j] * g[j];
+            g[j] = cs[j] * g[j];
+            nits++;
+            jend = j + 1;
+            if (hist) hist[nits] = fabs(g[j + 1]);
+            if (nits >= o->maxit) break;
+            if (hn == 0.0) break;                     /* lucky breakdown */
+            if (!o->fixed_iters && !o->check_at_cycle_end && fabs(g[j + 1]) <= tol_est) break;
+        }
+        /* R y = g(0:jend) by back substitution */
+        for (int i = jend - 1; i >= 0; i--) {
+            double s = g[i];
+            for (int k = i + 1; k < jend; k++) s -= HH(i, k) * y[k];
+            y[i] = HH(i, i) != 0.0 ? s / HH(i, i) : 0.0;
+        }
+        if (o->flexible && !o->left) {
+            for (int k = 0; k < jend; k++)
+                for (size_t i = 0; i < n; i++) x[i] += y[k] * Z[n * k + i];
+        } else {
+            for (size_t i = 0; i < n; i++) w[i] = 0.0;
+            for (int k = 0; k < jend; k++)
+                for (size_t i = 0; i < n; i++) w[i] += y[k] * V[n * k + i];
+            if (o->left) {
+                for (size_t i = 0; i < n; i++) x[i] += w[i];
+            } else {
+                or_pc_apply(pc, w, z);
+                for (size_t i = 0; i < n; i++) x[i] += z[i];
+            }
+        }
+        for (size_t i = 0; i < (size_t)(m + 1) * m; i++) H[i] = 0.0;
+    }
+#undef HH
+    if (o->fixed_iters && nits >= o->maxit) status = relres <= o->rtol ? OR_OK : OR_NOT_CONVERGED;
+    if (res) { res->iters = nits; res->true_relres = relres; res->restarts = cycles; }
+    free(V); free(Z); free(H); free(cs); free(sn); free(g); free(y);
+    free(r); free(w); free(z);
+    return status;
+}
+
+/* ======================================================================
+ * C7. BiCGSTAB (van der Vorst 1992), right-preconditioned.  The paper
+ * names the method (Section 3) without printing it.  Breakdown
+ * (|rho| < 1e-300 ||rhat|| ||r||, <rhat, v> = 0, or omega = 0) restarts
+ * from the true residual.  Convergence at a half step (||s||) or a full
+ * step (||r||) is confirmed with the true residual; if that fails the
+ * iteration restarts from it.
+ * ====================================================================== */
+int or_bicgstab(int nb, int bs, const int *rp, const int *ci,
+                const double *a, or_pc *pc, const double *b, double *x,
+                const or_krylov_opts *o, or_krylov_result *res, double *hist)
+{
+    const size_t n = (size_t)nb * bs;
+    double *r = (double *)malloc(sizeof(double) * n);
+    double *rh = (double *)malloc(sizeof(double) * n);
+    double *p = (double *)malloc(sizeof(double) * n);
+    double *v = (double *)malloc(sizeof(double) * n);
+    double *ph = (double *)malloc(sizeof(double) * n);
+    double *s = (double *)malloc(sizeof(double) * n);
+    double *sh = (double *)malloc(sizeof(double) * n);
+    double *t = (double *)malloc(sizeof(double) * n);
+    const double bnorm = nrm2((int)n, b);
+    const double tol = fmax(o->rtol * bnorm, o->atol);
+    int nits = 0, restarts = 0, status = OR_NOT_CONVERGED;
+    double relres = 0.0, rho0 = 1.0, alpha = 1.0, omega = 1.0;
+    int fresh = 1;
+    for (;;) {
+        if (fresh) {
+            memcpy(r, b, sizeof(double) * n);
+            or_bsr_amxpby(nb, bs, rp, ci, a, -1.0, x, 1.0, r);
+            double tn = nrm2((int)n, r);
+            relres = bnorm > 0 ? tn / bnorm : tn;
+            if (hist && nits == 0) hist[0] = tn;
+            if (!o->fixed_iters && tn <= tol) { status = OR_OK; break; }
+            if (!isfinite(tn)) { status = OR_ERR_BREAKDOWN; break; }
+            memcpy(rh, r, sizeof(double) * n);
+            rho0 = alpha = omega = 1.0;
+            for (size_t i = 0; i < n; i++) { v[i] = 0.0; p[i] = 0.0; }
+            fresh = 0;
+        }
+        if (nits >= o->maxit) break;
+        double rho = dot((int)n, rh, r);
+        if (fabs(rho) < 1e-300 * nrm2((int)n, rh) * nrm2((int)n, r) || rho == 0.0) {
+            fresh = 1; restarts++;
+            continue;
+        }
+        double beta = (rho / rho0) * (alpha / omega);
+        for (size_t i = 0; i < n; i++) p[i] = r[i] + beta * (p[i] - omega * v[i]);
+        or_pc_apply(pc, p, ph);
+        or_bsr_spmv(nb, bs, rp, ci, a, ph, v);
+        double rv = dot((int)n, rh, v);
+        nits++;
+        if (rv == 0.0 || !isfinite(rv)) { fresh = 1; restarts++; continue; }
+        alpha = rho / rv;
+        for (size_t i = 0; i < n; i++) s[i] = r[i] - alpha * v[i];
+        double sn = nrm2((int)n, s);
+        if (!o->fixed_iters && sn <= tol) {
+            for (size_t i = 0; i < n; i++) x[i] += alpha * ph[i];
+            if (hist) hist[nits] = sn;
+            fresh = 1;                       /* confirm with true residual */
+            continue;
+        }
+        or_pc_apply(pc, s, sh);
+        or_bsr_spmv(nb, bs, rp, ci, a, sh, t);
+        double tt = dot((int)n, t, t);
+        double ts = dot((int)n, t, s);
+        omega = tt != 0.0 ? ts / tt : 0.0;
+        for (size_t i = 0; i < n; i++) x[i] += alpha * ph[i] + omega * sh[i];
+        for (size_t i = 0; i < n; i++) r[i] = s[i] - omega * t[i];
+        double rn = nrm2((int)n, r);
+        if (hist) hist[nits] = rn;
+        rho0 = rho;
+        if (!o->fixed_iters && rn <= tol) { fresh = 1; continue; }
+        if (omega == 0.0 || !isfinite(rn)) { fresh = 1; restarts++; continue; }
+    }
+    if (o->fixed_iters) {
+        memcpy(r, b, sizeof(double) * n);
+        or_bsr_amxpby(nb, bs, rp, ci, a, -1.0, x, 1.0, r);
+        double tn = nrm2((int)n, r);
+        relres = bnorm > 0 ? tn / bnorm : tn;
+        status = relres <= o->rtol ? OR_OK : OR_NOT_CONVERGED;
+    }
+    if (res) { res->iters = nits; res->true_relres = relres; res->restarts = restarts; }
+    free(r); free(rh); free(p); free(v); free(ph); free(s); free(sh); free(t);
+    return status;
+}
+
+/* ======================================================================
+ * C10. Learned stage network: 4 conv layers 4 -> 32 -> 32 -> 32 -> 3,
+ * 3x3x3 cross-correlation, stride 1, zero padding 1, bias, exact GELU
+ * x * Phi(x) (Phi via erf) after layers 1-3, linear output.
+ * bf16_emul rounds every conv operand (activations and weights, and the
+ * upstream gradient in the backward pass) to bfloat16; sums stay FP64.
+ * ====================================================================== */
+static const int CONV_C[5] = { 4, 32, 32, 32, 3 };
+
+int or_conv_nparams(void)
+{
+    int np = 0;
+    for (int l = 0; l < 4; l++) np += CONV_C[l + 1] * CONV_C[l] * 27 + CONV_C[l + 1];
+    return np;
+}
+
+double or_gelu(double x) { return 0.5 * x * (1.0 + erf(x / sqrt(2.0))); }
+
+static double gelu_grad(double x)
+{
+    const double pi = 3.14159265358979323846;
+    return 0.5 * (1.0 + erf(x / sqrt(2.0))) + x * exp(-0.5 * x * x) / sqrt(2.0 * pi);
+}
+
+/* out[co][cell] = b[co] + sum_ci sum_tap W[co][ci][tap] in[ci][cell+tap] */
+static void conv3d(int nx, int ny, int nz, int cin, int cout, const double *W,
+                   const double *bias, const double *in, double *out)
+{
+    size_t cells = (size_t)nx * ny * nz;
+    for (int co = 0; co < cout; co++)
+        for (int k = 0; k < nz; k++)
+            for (int j = 0; j < ny; j++)
+                for (int i = 0; i < nx; i++) {
+                    double s = bias[co];
+                    for (int ci = 0; ci < cin; ci++)
+                        for (int dz = -1; dz <= 1; dz++)
+                            for (int dy = -1; dy <= 1; dy++)
+                                for (int dx = -1; dx <= 1; dx++) {
+                                    int kk = k + dz, jj = j + dy, ii = i + dx;
+                                    if (kk < 0 || kk >= nz || jj < 0 || jj >= ny || ii < 0 || ii >= nx) continue;
+                                    double wv = W[(((size_t)co * cin + ci) * 27) + (dz + 1) * 9 + (dy + 1) * 3 + (dx + 1)];
+                                    s += wv * in[ci * cells + ((size_t)kk * ny + jj) * nx + ii];
+                                }
+                    out[co * cells + ((size_t)k * ny + j) * nx + i] = s;
+                }
+}
+
+static void round_copy(size_t n, const double *src, double *dst, int bf16)
+{
+    for (size_t i = 0; i < n; i++) dst[i] = bf16 ? bf16d(src[i]) : src[i];
+}
+
+/* forward pass keeping pre-activations z_l and operand copies h_l */
+static void conv_forward_full(int nx, int ny, int nz, const double *params,
+                              const double *in, int bf16, double **h,
+                              double **zpre, double *out)
+{
+    size_t cells = (size_t)nx * ny * nz;
+    const double *pp = params;
+    round_copy(cells * CONV_C[0], in, h[0], bf16);
+    for (int l = 0; l < 4; l++) {
+        int cin = CONV_C[l], cout = CONV_C[l + 1];
+        size_t nw = (size_t)cout * cin * 27;
+        double *W = (double *)malloc(sizeof(double) * nw);
+        round_copy(nw, pp, W, bf16);
+        conv3d(nx, ny, nz, cin, cout, W, pp + nw, h[l], zpre[l]);
+        free(W);
+        pp += nw + cout;
+        if (l < 3) {
+            double *act = (double *)malloc(sizeof(double) * cells * cout);
+            for (size_t q = 0; q < cells * cout; q++) act[q] = or_gelu(zpre[l][q]);
+            round_copy(cells * cout, act, h[l + 1], bf16);
+            free(act);
+        } else {
+            memcpy(out, zpre[l], sizeof(double) * cells * cout);
+        }
+    }
+}
+
+void or_conv_forward(int nx, int ny, int nz, const double *params,
+                     const double *in, double *out, int bf16_emul)
+{
+    size_t cells = (size_t)nx * ny * nz;
+    double *h[4], *zp[4];
+    for (int l = 0; l < 4; l++) {
+        h[l] = (double *)malloc(sizeof(double) * cells * CONV_C[l]);
+        zp[l] = (double *)malloc(sizeof(double) * cells * CONV_C[l + 1]);
+    }
+    conv_forward_full(nx, ny, nz, params, in, bf16_emul, h, zp, out);
+    for (int l = 0; l < 4; l++) { free(h[l]); free(zp[l]); }
+}
+
+double or_conv_loss_grad(int nx, int ny, int nz, const double *params,
+                         const double *in, const double *target,
+                         double *grad, double *dinput, int bf16_emul)
+{
+    size_t cells = (size_t)nx * ny * nz;
+    double *h[4], *zp[4];
+    for (int l = 0; l < 4; l++) {
+        h[l] = (double *)malloc(sizeof(double) * cells * CONV_C[l]);
+        zp[l] = (double *)malloc(sizeof(double) * cells * CONV_C[l + 1]);
+    }
+    double *out = (double *)malloc(sizeof(double) * cells * 3);
+    conv_forward_full(nx, ny, nz, params, in, bf16_emul, h, zp, out);
+    size_t nout = cells * 3;
+    double loss = 0.0;
+    for (size_t q = 0; q < nout; q++) {
+        double d = out[q] - target[q];
+        loss += d * d;
+    }
+    loss /= (double)nout;
+    /* g = dL/d(out) */
+    double *g = (double *)malloc(sizeof(double) * nout);
+    for (size_t q = 0; q < nout; q++) g[q] = 2.0 * (out[q] - target[q]) / (double)nout;
+    /* parameter offsets */
+    size_t off[4], acc = 0;
+    for (int l = 0; l < 4; l++) {
+        off[l] = acc;
+        acc += (size_t)CONV_C[l + 1] * CONV_C[l] * 27 + CONV_C[l + 1];
+    }
+    for (int l = 3; l >= 0; l--) {
+        int cin = CONV_C[l], cout = CONV_C[l + 1];
+        size_t nw = (size_t)cout * cin * 27;
+        /* dz = g * act'(z) */
+        double *dz = (double *)malloc(sizeof(double) * cells * cout);
+        for (size_t q = 0; q < cells * cout; q++)
+            dz[q] = (l < 3) ? g[q] * gelu_grad(zp[l][q]) : g[q];
+        /* bias gradient from the unrounded dz */
+        for (int co = 0; co < cout; co++) {
+            double s = 0.0;
+            for (size_t c = 0; c < cells; c++) s += dz[co * cells + c];
+            grad[off[l] + nw + co] = s;
+        }
+        double *dzr = (double *)malloc(sizeof(double) * cells * cout);
+        round_copy(cells * cout, dz, dzr, bf16_emul);
+        /* weight gradient: dW[co][ci][tap] = sum_cell dz[co][cell] h[ci][cell+tap] */
+        for (int co = 0; co < cout; co++)
+            for (int ci = 0; ci < cin; ci++)
+                for (int dzz = -1; dzz <= 1; dzz++)
+                    for (int dy = -1; dy <= 1; dy++)
+                        for (int dx = -1; dx <= 1; dx++) {
+                            double s = 0.0;
+                            for (int k = 0; k < nz; k++)
+                                for (int j = 0; j < ny; j++)
+                                    for (int i = 0; i < nx; i++) {
+                                        int kk = k + dzz, jj = j + dy, ii = i + dx;
+                                        if (kk < 0 || kk >= nz || jj < 0 || jj >= ny || ii < 0 || ii >= nx) continue;
+                                        s += dzr[co * cells + ((size_t)k * ny + j) * nx + i]
+                                           * h[l][ci * cells + ((size_t)kk * ny + jj) * nx + ii];
+                                    }
+                            grad[off[l] + (((size_t)co * cin + ci) * 27) + (dzz + 1) * 9 + (dy + 1) * 3 + (dx + 1)] = s;
+                        }
+        /* input gradient: gin[ci][cell] = sum_co sum_tap W[co][ci][tap] dz[co][cell - tap] */
+        if (l > 0 || dinput) {
+            double *W = (double *)malloc(sizeof(double) * nw);
+            round_copy(nw, params + off[l], W, bf16_emul);
+            double *gin = (double *)calloc(cells * cin, sizeof(double));
+            for (int ci = 0; ci < cin; ci++)
+                for (int k = 0; k < nz; k++)
+                    for (int j = 0; j < ny; j++)
+                        for (int i = 0; i < nx; i++) {
+                            double s = 0.0;
+                            for (int co = 0; co < cout; co++)
+                                for (int dzz = -1; dzz <= 1; dzz++)
+                                    for (int dy = -1; dy <= 1; dy++)
+                                        for (int dx = -1; dx <= 1; dx++) {
+                                            int kk = k - dzz, jj = j - dy, ii = i - dx;
+                                            if (kk < 0 || kk >= nz || jj < 0 || jj >= ny || ii < 0 || ii >= nx) continue;
+                                            s += W[(((size_t)co * cin + ci) * 27) + (dzz + 1) * 9 + (dy + 1) * 3 + (dx + 1)]
+                                               * dzr[co * cells + ((size_t)kk * ny + jj) * nx + ii];
+                                        }
+                            gin[ci * cells + ((size_t)k * ny + j) * nx + i] = s;
+                        }
+            free(W);
+            free(g);
+            g = gin;
+            if (l == 0 && dinput) memcpy(dinput, gin, sizeof(double) * cells * cin);
+        }
+        free(dz); free(dzr);
+    }
+    free(g); free(out);
+    for (int l = 0; l < 4; l++) { free(h[l]); free(zp[l]); }
+    return loss;
+}
+
+/* Adam (Kingma & Ba 2015), bias-corrected, step t >= 1 */
+void or_adam_step(int n, double *params, const double *grad, double *m,
+                  double *v, int t, double lr, double beta1, double beta2,
+                  double eps)
+{
+    double c1 = 1.0 - pow(beta1, t), c2 = 1.0 - pow(beta2, t);
+    for (int i = 0; i < n; i++) {
+        m[i] = beta1 * m[i] + (1.0 - beta1) * grad[i];
+        v[i] = beta2 * v[i] + (1.0 - beta2) * grad[i] * grad[i];
+        double mh = m[i] / c1, vh = v[i] / c2;
+        params[i] -= lr * mh / (sqrt(vh) + eps);
+    }
+}
+
+/* ======================================================================
+ * C11. Learned stage apply with fallback:
+ *   z1 = M_base^-1 v;  r1 = v - A z1;  s = rms(r1);
+ *   e  = s * N([r1 / s, ln k]);  z2 = z1 + e;
+ *   z  = z2 if ||v - A z2|| < ||r1||, else z1 (fallback).
+ * ====================================================================== */
+static void conv_apply_learned(or_pc *pc, const double *v, double *z)
+{
+    const int nb = pc->nb;
+    const size_t n = (size_t)nb * 3, cells = (size_t)nb;
+    double *r1 = (double *)malloc(sizeof(double) * n);
+    double *z2 = (double *)malloc(sizeof(double) * n);
+    double *r2 = (double *)malloc(sizeof(double) * n);
+    double *in = (double *)malloc(sizeof(double) * cells * 4);
+    double *out = (double *)malloc(sizeof(double) * cells * 3);
+    pc->applies++;
+    or_pc_apply(pc->base, v, z);
+    memcpy(r1, v, sizeof(double) * n);
+    or_bsr_amxpby(nb, 3, pc->rp, pc->ci, pc->a, -1.0, z, 1.0, r1);
+    double n1 = nrm2((int)n, r1);
+    double s = n1 / sqrt((double)n);
+    int accept = 0;
+    if (s > 0.0 && isfinite(s)) {
+        for (size_t c = 0; c < cells; c++) {
+            for (int ch = 0; ch < 3; ch++) in[ch * cells + c] = r1[3 * c + ch] / s;
+            in[3 * cells + c] = pc->lnk[c];
+        }
+        or_conv_forward(pc->nx, pc->ny, pc->nz, pc->params, in, out, pc->bf16);
+        int finite = 1;
+        for (size_t c = 0; c < cells; c++)
+            for (int ch = 0; ch < 3; ch++) {
+                z2[3 * c + ch] = z[3 * c + ch] + s * out[ch * cells + c];
+                if (!isfinite(z2[3 * c + ch])) finite = 0;
+            }
+        if (finite) {
+            memcpy(r2, v, sizeof(double) * n);
+            or_bsr_amxpby(nb, 3, pc->rp, pc->ci, pc->a, -1.0, z2, 1.0, r2);
+            double n2 = nrm2((int)n, r2);
+            if (n2 < n1) accept = 1;
+        }
+    }
+    if (accept) memcpy(z, z2, sizeof(double) * n);
+    else pc->fallbacks++;
+    free(r1); free(z2); free(r2); free(in); free(out);
+}

@@ -1,0 +1,131 @@
+/*
+ * FP64 CPU oracle for the preconditioned Krylov solve of Liu & Chen,
+ * "Scalable linear solvers for sparse linear systems from large-scale
+ * numerical simulations" (arXiv 1701.05913).
+ *
+ * TEST INFRASTRUCTURE ONLY.  This header and oracle.c are used by the test
+ * suite, by the package's smoke check and by the CPU-baseline leg of the
+ * benchmark.  The GPU library never includes, links or calls anything here,
+ * and nothing here includes or calls the GPU library.
+ *
+ * Plain, slow, obviously-correct C99 in double precision (the paper's FLOAT
+ * is never fixed; double is its most likely meaning).  Single precision and
+ * bfloat16 are emulated only where the mixed-precision preconditioner asks
+ * for them (float arithmetic, bf16 = round-to-nearest-even of the float bit
+ * pattern to its top 16 bits).
+ *
+ * Matrices are block-CSR with block size bs (bs = 1 is plain CSR), blocks
+ * row-major, columns ascending within a row, every row holding its
+ * diagonal block.  Vectors of a bs-block system are interleaved per block
+ * row: (p, s1, s2) of cell 0, then cell 1, ...
+ *
+ * Parity status: every function here is pinned by the CPU tests (dense
+ * solves, closed forms, invariants, finite differences) except the gain of
+ * the learned preconditioner stage, which is measured, not pinned.
+ */
+#ifndef KRYLOV_ORACLE_H
+#define KRYLOV_ORACLE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum { OR_OK = 0, OR_NOT_CONVERGED = 1, OR_ERR_ARG = -1,
+       OR_ERR_ZERO_PIVOT = -4, OR_ERR_BREAKDOWN = -5 };
+
+enum { OR_PREC_F64 = 0, OR_PREC_F32 = 1, OR_PREC_BF16 = 2 };
+
+/* ---- sparse matrix-vector products (Figures 20-21) -------------------- */
+void or_bsr_spmv(int nb, int bs, const int *rp, const int *ci,
+                 const double *a, const double *x, double *y);
+void or_bsr_amxpby(int nb, int bs, const int *rp, const int *ci,
+                   const double *a, double alpha, const double *x,
+                   double beta, double *y);
+
+/* ---- ILU(0) / block ILU(0) (Section 1 "point-wise and block-wise
+ *      incomplete factorization", eq. (3) for the solve) ---------------- */
+int  or_bilu0(int nb, int bs, const int *rp, const int *ci,
+              const double *a, double *lu);
+void or_bilu0_solve(int nb, int bs, const int *rp, const int *ci,
+                    const double *lu, const double *b, double *x);
+void or_bilu0_solve_lower(int nb, int bs, const int *rp, const int *ci,
+                          const double *lu, const double *b, double *y);
+void or_bilu0_solve_upper(int nb, int bs, const int *rp, const int *ci,
+                          const double *lu, const double *y, double *x);
+
+/* ---- preconditioner objects (Figure 29: setup / solve / destroy) ------- */
+typedef struct or_pc or_pc;
+enum { OR_PC_NONE = 0, OR_PC_BILU0 = 1, OR_PC_CPR_PF = 2, OR_PC_CPR_FP = 3,
+       OR_PC_LEARNED = 4 };
+
+or_pc *or_pc_create(int kind, int nb, int bs, const int *rp, const int *ci,
+                    const double *a, int prec, int p_sweeps, int *err);
+/* Learned stage on top of an existing BILU(0)/CPR preconditioner `base`
+ * (ownership of base passes to the new object).  w/b are the conv-net
+ * parameters (layout of or_conv_forward), lnk per cell, grid nx,ny,nz.
+ * bf16_emul != 0 rounds the network's operands to bfloat16. */
+or_pc *or_pc_create_learned(or_pc *base, int nx, int ny, int nz,
+                            const double *params, const double *lnk,
+                            int bf16_emul);
+void or_pc_apply(or_pc *pc, const double *v, double *z);
+void or_pc_destroy(or_pc *pc);
+/* counters of the learned stage: applications and fallbacks */
+void or_pc_learned_stats(const or_pc *pc, long *applies, long *fallbacks);
+/* CPR internals, exposed for pins */
+int  or_cpr_weights(int nb, const int *rp, const int *ci, const double *a,
+                    double *w /* nb*3 */);
+void or_cpr_extract_pressure(int nb, const int *rp, const int *ci,
+                             const double *a, const double *w,
+                             double *app /* nnzb values, pattern of A */);
+
+/* ---- Krylov solvers (Algorithm 1; BiCGSTAB named in Section 3) -------- */
+typedef struct {
+    int    restart;      /* m of GMRES(m) */
+    int    maxit;        /* total iterations (Arnoldi steps / BiCGSTAB its) */
+    double rtol, atol;
+    int    flexible;     /* FGMRES: store Z = M^-1 V */
+    int    left;         /* Algorithm 1 as printed: left preconditioning */
+    int    check_at_cycle_end; /* Algorithm 1 line 15 literally */
+    int    fixed_iters;  /* run exactly maxit iterations, ignore tolerance */
+} or_krylov_opts;
+
+typedef struct {
+    int    iters;
+    double true_relres;  /* ||b - A x|| / ||b|| at exit, FP64 */
+    int    restarts;     /* GMRES cycles / BiCGSTAB breakdown restarts */
+} or_krylov_result;
+
+int or_gmres(int nb, int bs, const int *rp, const int *ci, const double *a,
+             or_pc *pc, const double *b, double *x, const or_krylov_opts *o,
+             or_krylov_result *res, double *hist /* maxit+1 or NULL */);
+int or_bicgstab(int nb, int bs, const int *rp, const int *ci,
+                const double *a, or_pc *pc, const double *b, double *x,
+                const or_krylov_opts *o, or_krylov_result *res,
+                double *hist /* maxit+1 or NULL */);
+
+/* ---- learned stage: 4-layer 3D conv net (4 -> 32 -> 32 -> 32 -> 3) ----
+ * params: for each layer l, W_l[co][ci][kz][ky][kx] then b_l[co].
+ * Activations channel-major: x[c][k][j][i] (i fastest, cell order).      */
+int  or_conv_nparams(void);
+void or_conv_forward(int nx, int ny, int nz, const double *params,
+                     const double *in /* 4*cells */, double *out /* 3*cells */,
+                     int bf16_emul);
+/* loss = mean((out - target)^2); returns loss and fills grad (nparams) and
+ * optionally dinput (4*cells). */
+double or_conv_loss_grad(int nx, int ny, int nz, const double *params,
+                         const double *in, const double *target,
+                         double *grad, double *dinput, int bf16_emul);
+void or_adam_step(int n, double *params, const double *grad, double *m,
+                  double *v, int t, double lr, double beta1, double beta2,
+                  double eps);
+double or_gelu(double x);
+
+/* ---- precision helpers ------------------------------------------------ */
+float or_bf16_round(float f);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,126 @@
+"""Plant plausible mistakes in a copy of the oracle and check that the pins
+catch each one.  The mutated source is compiled to a temporary library and
+swapped in for the duration of one pin; the committed oracle is untouched.
+"""
+import contextlib
+
+import pytest
+
+import oracle
+from tests import test_oracle_cpr_conv as tc
+from tests import test_oracle_krylov as tk
+from tests import test_oracle_linalg as tl
+
+# (name, exact text in oracle.c, replacement, pins expected to fail)
+MUTANTS = [
+    ("spmv_transposed_block",
+     "for (int c = 0; c < bs; c++) t += blk[r * bs + c] * xj[c];\n            }\n            y[(size_t)i * bs + r] = t;",
+     "for (int c = 0; c < bs; c++) t += blk[c * bs + r] * xj[c];\n            }\n            y[(size_t)i * bs + r] = t;",
+     [lambda: tl.test_spmv_matches_dense(1)]),
+    ("spmv_dropped_last_term",
+     "for (int p = rp[i]; p < rp[i + 1]; p++) {\n                const double *blk = a + (size_t)p * bs * bs;\n                const double *xj = x + (size_t)ci[p] * bs;\n                for (int c = 0; c < bs; c++) t += blk[r * bs + c] * xj[c];\n            }\n            y[(size_t)i * bs + r] = t;",
+     "for (int p = rp[i]; p < rp[i + 1] - 1; p++) {\n                const double *blk = a + (size_t)p * bs * bs;\n                const double *xj = x + (size_t)ci[p] * bs;\n                for (int c = 0; c < bs; c++) t += blk[r * bs + c] * xj[c];\n            }\n            y[(size_t)i * bs + r] = t;",
+     [lambda: tl.test_spmv_matches_dense(0)]),
+    ("ilu_update_sign",
+     "for (int e = 0; e < b2; e++) lu[(size_t)s * b2 + e] -= tmp[e];",
+     "for (int e = 0; e < b2; e++) lu[(size_t)s * b2 + e] += tmp[e];",
+     [lambda: tl.test_ilu_product_equals_a_on_pattern(0),
+      lambda: tl.test_ilu_exact_on_tridiagonal(1)]),
+    ("ilu_multiplier_order",
+     "blk_mm(bs, lu + (size_t)p * b2, inv, tmp);",
+     "blk_mm(bs, inv, lu + (size_t)p * b2, tmp);",
+     [lambda: tl.test_ilu_product_equals_a_on_pattern(1)]),
+    ("lower_solve_skips_dependencies",
+     "for (int p = rp[i]; p < rp[i + 1] && ci[p] < i; p++)\n            blk_sub_mv(",
+     "for (int p = rp[i]; p < rp[i + 1] && ci[p] < i - 1; p++)\n            blk_sub_mv(",
+     [lambda: tl.test_triangular_solves_match_dense(1)]),
+    ("givens_sign",
+     "g[j + 1] = -sn[j] * g[j];",
+     "g[j + 1] = sn[j] * g[j];",
+     [lambda: tk.test_gmres_estimate_equals_true_residual_right_preconditioned()]),
+    ("mgs_sign",
+     "for (size_t i = 0; i < n; i++) w[i] -= h * V[n * k + i];",
+     "for (size_t i = 0; i < n; i++) w[i] += h * V[n * k + i];",
+     [lambda: tk.test_solution_matches_dense_solve("gmres")]),
+    ("bicgstab_omega_sign",
+     "omega = tt != 0.0 ? ts / tt : 0.0;",
+     "omega = tt != 0.0 ? -ts / tt : 0.0;",
+     [lambda: tk.test_solution_matches_dense_solve("bicgstab")]),
+    ("bicgstab_beta_inverted",
+     "double beta = (rho / rho0) * (alpha / omega);",
+     "double beta = (rho0 / rho) * (alpha / omega);",
+     [lambda: tk.test_solution_matches_dense_solve("bicgstab")]),
+    ("fgmres_updates_with_v",
+     "for (size_t i = 0; i < n; i++) x[i] += y[k] * Z[n * k + i];",
+     "for (size_t i = 0; i < n; i++) x[i] += y[k] * V[n * k + i];",
+     [lambda: tk.test_fgmres_equals_right_gmres_with_fixed_preconditioner()]),
+    ("qimpes_weight_sign",
+     "w[3 * i + 1] = -y[0];",
+     "w[3 * i + 1] = y[0];",
+     [lambda: tc.test_quasi_impes_weights_zero_secondary_columns()]),
+    ("cpr_pressure_uses_wrong_column",
+     "app[p] = w[3 * i] * B[0] + w[3 * i + 1] * B[3] + w[3 * i + 2] * B[6];",
+     "app[p] = w[3 * i] * B[0] + w[3 * i + 1] * B[1] + w[3 * i + 2] * B[2];",
+     [lambda: tc.test_pressure_matrix_is_decoupled_operator_on_pressure_vectors()]),
+    ("cpr_pf_second_stage_on_v",
+     "or_bsr_amxpby(nb, 3, pc->rp, pc->ci, pc->a, -1.0, z, 1.0, r);\n            or_bilu0_solve(nb, 3, pc->rp, pc->ci, pc->lu, r, t);",
+     "or_bilu0_solve(nb, 3, pc->rp, pc->ci, pc->lu, r, t);",
+     [lambda: tc.test_cpr_exact_when_stages_are_exact("cpr_pf")]),
+    ("gelu_grad_missing_density_term",
+     "return 0.5 * (1.0 + erf(x / sqrt(2.0))) + x * exp(-0.5 * x * x) / sqrt(2.0 * pi);",
+     "return 0.5 * (1.0 + erf(x / sqrt(2.0)));",
+     [lambda: tc.test_conv_finite_differences()]),
+    ("conv_input_grad_tap_flip",
+     "int kk = k - dzz, jj = j - dy, ii = i - dx;",
+     "int kk = k + dzz, jj = j + dy, ii = i + dx;",
+     [lambda: tc.test_conv_finite_differences()]),
+    ("conv_cross_correlation_as_convolution",
+     "int kk = k + dz, jj = j + dy, ii = i + dx;\n                                    if (kk < 0",
+     "int kk = k - dz, jj = j - dy, ii = i - dx;\n                                    if (kk < 0",
+     [lambda: tc.test_conv_finite_differences()]),
+    ("adam_no_bias_correction",
+     "double mh = m[i] / c1, vh = v[i] / c2;",
+     "double mh = m[i], vh = v[i];",
+     [lambda: tc.test_adam_first_step_closed_form()]),
+    ("bf16_truncation",
+     "u += 0x7fffu + ((u >> 16) & 1u);",
+     "u += 0u;",
+     [lambda: tl.test_bf16_rounding_closed_forms()]),
+    ("learned_accepts_ties",
+     "if (n2 < n1) accept = 1;",
+     "if (n2 <= n1) accept = 1;",
+     [lambda: tc.test_learned_stage_zero_net_falls_back_bit_exactly()]),
+]
+
+
+@contextlib.contextmanager
+def _swapped(lib):
+    saved = oracle._lib
+    oracle._lib = lib
+    try:
+        yield
+    finally:
+        oracle._lib = saved
+
+
+def test_mutant_texts_present():
+    src = oracle.source()
+    for name, old, new, _ in MUTANTS:
+        assert src.count(old) >= 1, name
+
+
+@pytest.mark.parametrize("mut", MUTANTS, ids=[m[0] for m in MUTANTS])
+def test_pins_catch_planted_mistake(mut, tmp_path):
+    name, old, new, pins = mut
+    src = oracle.source()
+    assert old in src
+    so = oracle.compile_variant(src.replace(old, new, 1), str(tmp_path / f"lib_{name}.so"))
+    lib = oracle.load(so)
+    caught = 0
+    with _swapped(lib):
+        for pin in pins:
+            try:
+                pin()
+            except (AssertionError, RuntimeError):
+                caught += 1
+    assert caught >= 1, f"no pin caught mutant {name}"
