@@ -1,0 +1,269 @@
+"""Benchmark: time to a true FP64 relative residual of 1e-8 on the 64^3
+black-oil system, plain FP64 block-ILU(0) against the mixed-precision and
+CPR variants, with per-kernel HBM roofline figures and the CPU oracle
+timed on the host.
+
+One step = one full pass of the solve path for every configuration in
+CONFIGS (preconditioner setup + solve from x0 = 0 each time, inputs
+resident in HBM).  `value` is the mean time-to-solution of the plain
+FP64 GMRES(30) + BILU(0) solve; every configuration's time, iterations and
+true residual are reported under "variants".
+
+    python bench.py [--steps K] [--warmup W] [--workload NAME] [--no-cpu]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = ("time-to-1e-8 residual (s) + iters, plain vs mixed/learned; "
+          "SpMV HBM GB/s")
+HBM_PEAK_GBS = 8000.0
+
+WORKLOADS = {
+    "blackoil64": dict(grid=(64, 64, 64), perm="layered", sigma2=2.0,
+                       desc="64x64x64 3x3-block black-oil system (786,432 unknowns, "
+                            "1,810,432 blocks), layered log-normal permeability, seed 0"),
+    "blackoil128x128x64": dict(grid=(128, 128, 64), perm="layered", sigma2=2.0,
+                               desc="128x128x64 3x3-block black-oil system "
+                                    "(3,145,728 unknowns), seed 0"),
+    "blackoil32": dict(grid=(32, 32, 32), perm="layered", sigma2=2.0,
+                       desc="32^3 3x3-block black-oil system (quick check)"),
+}
+
+# name, solver, pc, precision, cpr (variant, sweeps)
+CONFIGS = [
+    ("gmres30_bilu0_f64", "GMRES", "BILU0", "F64", None),
+    ("bicgstab_bilu0_f64", "BICGSTAB", "BILU0", "F64", None),
+    ("fgmres30_bilu0_f32", "FGMRES", "BILU0", "F32", None),
+    ("fgmres30_bilu0_bf16", "FGMRES", "BILU0", "BF16_FACTORS", None),
+    ("fgmres30_cpr_f64", "FGMRES", "CPR", "F64", ("PF", 4)),
+    ("fgmres30_cpr_f32", "FGMRES", "CPR", "F32", ("PF", 4)),
+]
+HEADLINE = "gmres30_bilu0_f64"
+
+
+def algorithmic_bytes(nb, nnzb):
+    """Minimum HBM bytes per launch of each timed kernel family (each matrix
+    byte once, each vector once): 3x3 blocks with int32 column indices."""
+    nl = (nnzb - nb) // 2          # strictly lower blocks (= upper) of a 7-point stencil
+    ptr = 4 * (nb + 1)
+    return {
+        "spmv_bsr3": 76 * nnzb + ptr + 48 * nb,
+        "ilu_fwd_bsr3_f64": 76 * nl + ptr + 48 * nb,
+        "ilu_bwd_bsr3_f64": 76 * nl + 72 * nb + ptr + 48 * nb,
+        # FP32 factors: 40 B per block, FP32 intermediate, FP64 in/out
+        "ilu_fwd_bsr3_f32": 40 * nl + ptr + 24 * nb + 12 * nb,
+        "ilu_bwd_bsr3_f32": 40 * nl + 36 * nb + ptr + 12 * nb + 24 * nb,
+        # BF16 factors: 22 B per block, FP32 diagonal inverses
+        "ilu_fwd_bsr3_bf16": 22 * nl + ptr + 24 * nb + 12 * nb,
+        "ilu_bwd_bsr3_bf16": 22 * nl + 36 * nb + ptr + 12 * nb + 24 * nb,
+    }
+
+
+def traffic_from_profiles(kernel):
+    """HBM bytes per launch measured with rocprofv3 FETCH_SIZE/WRITE_SIZE,
+    if a summary exists for this kernel and its source has not changed."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        data = json.load(open(path))
+        ent = data.get(kernel)
+        if not ent:
+            return None
+        src = os.path.join(ROOT, ent["source"])
+        h = hashlib.sha256(open(src, "rb").read()).hexdigest()
+        if h != ent["source_sha256"]:
+            return None
+        return float(ent["bytes_per_launch"])
+    except Exception:
+        return None
+
+
+def cpu_baseline(s, rtol, budget_s=40.0):
+    """The FP64 oracle (single-threaded C, as written) on the same system:
+    BILU(0) setup + GMRES(30) to rtol.  If the solve would take longer than
+    the budget, a prefix of iterations is timed and scaled to the oracle's
+    per-iteration cost times the GPU-measured iteration count."""
+    import oracle
+    A = oracle.Matrix.from_system(s)
+    t0 = time.perf_counter()
+    pc = oracle.PC(A, "bilu0")
+    t_setup = time.perf_counter() - t0
+    # prefix timing to size the run
+    t0 = time.perf_counter()
+    oracle.gmres(A, pc, s["b"], restart=30, maxit=10, rtol=0.0, fixed_iters=True)
+    per_it = (time.perf_counter() - t0) / 10
+    if per_it * 1000 < budget_s:
+        t0 = time.perf_counter()
+        r = oracle.gmres(A, pc, s["b"], restart=30, maxit=1000, rtol=rtol)
+        t_solve = time.perf_counter() - t0
+        return dict(value=t_setup + t_solve, unit="s", cores=1, kind="oracle",
+                    iters=r["iters"], true_relres=r["relres"],
+                    sample="full BILU(0) setup + GMRES(30) solve to the same rtol, "
+                           "single-threaded oracle")
+    return dict(value=None, unit="s", cores=1, kind="oracle",
+                sample=f"not run: estimated {per_it:.3f} s per iteration exceeds the budget")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="blackoil64", choices=sorted(WORKLOADS))
+    ap.add_argument("--rtol", type=float, default=1e-8)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--configs", default="all")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py: this build measures one GPU holding one rank's share; "
+              "multi-GPU runs are not supported (use --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import paper_1701_05913_amd as K
+    import reservoir_inputs as ri
+
+    wl = WORKLOADS[args.workload]
+    t0 = time.perf_counter()
+    s = ri.blackoil_system(*wl["grid"], seed=0, perm=wl["perm"], sigma2=wl["sigma2"])
+    t_gen = time.perf_counter() - t0
+    nb = len(s["rowptr"]) - 1
+    n = 3 * nb
+    nnzb = int(s["rowptr"][-1])
+    dev = torch.device("cuda:0")
+    rp = torch.from_numpy(np.ascontiguousarray(s["rowptr"], dtype=np.int32)).to(dev)
+    ci = torch.from_numpy(np.ascontiguousarray(s["col"], dtype=np.int32)).to(dev)
+    va = torch.from_numpy(np.ascontiguousarray(s["val"].reshape(-1))).to(dev)
+    b = torch.from_numpy(s["b"]).to(dev)
+    x = torch.zeros(n, dtype=torch.float64, device=dev)
+    stream = torch.cuda.current_stream()
+    K.KrylovSetStream(stream)
+    m = K.MapCreateLocal(n)
+    t0 = time.perf_counter()
+    A = K.MatCreateBSR(m, nb, 3, rp, ci, va)
+    torch.cuda.synchronize()
+    t_upload = time.perf_counter() - t0
+    bh, xh = K.VecWrap(m, b), K.VecWrap(m, x)
+
+    configs = CONFIGS if args.configs == "all" else [c for c in CONFIGS if c[0] in args.configs.split(",")]
+    solvers = {}
+    for name, st, pc, prec, cpr in configs:
+        S = K.SolverCreate(getattr(K, f"KRY_{st}"), getattr(K, f"KRY_PC_{pc}"), m)
+        K.SolverSetMat(S, A)
+        K.SolverSetRtol(S, args.rtol)
+        K.SolverSetMaxit(S, 5000)
+        K.SolverSetRestart(S, 30)
+        K.SolverSetPrecision(S, getattr(K, f"KRY_PREC_{prec}"))
+        if cpr:
+            K.SolverSetCPR(S, getattr(K, f"KRY_CPR_{cpr[0]}"), cpr[1])
+        K.SolverSetStream(S, stream)
+        solvers[name] = S
+
+    def run_one(name):
+        S = solvers[name]
+        x.zero_()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        K.SolverAssemble(S)
+        rc = K.SolverSolve(S, bh, xh)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        st, ss = K.SolverGetTimes(S)
+        return dict(time_s=dt, setup_s=st, solve_s=ss, iters=K.SolverGetIters(S),
+                    true_relres=K.SolverGetResidual(S), status=rc)
+
+    for _ in range(args.warmup):
+        for name, *_ in configs:
+            run_one(name)
+
+    K.KernelTimingReset()
+    K.KernelTimingEnable(True)
+    results = {name: [] for name, *_ in configs}
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    for _ in range(args.steps):
+        for name, *_ in configs:
+            results[name].append(run_one(name))
+    torch.cuda.synchronize()
+    t_total = time.perf_counter() - t_start
+    K.KernelTimingEnable(False)
+
+    # per-kernel figures over the timed region
+    abytes = algorithmic_bytes(nb, nnzb)
+    kernels = {}
+    for kname in list(abytes) + ["cgs2", "ilu_fwd_csr_f64", "ilu_bwd_csr_f64",
+                                 "ilu_fwd_csr_f32", "ilu_bwd_csr_f32", "spmv_csr"]:
+        cnt, ms = K.KernelTimingQuery(kname)
+        if cnt == 0:
+            continue
+        ent = dict(launches=cnt, total_ms=round(ms, 4), avg_us=round(1000 * ms / cnt, 3))
+        if kname in abytes:
+            gbs = abytes[kname] / (ms / cnt * 1e-3) / 1e9
+            ent.update(bytes_per_launch=abytes[kname], gbs=round(gbs, 1),
+                       frac_hbm=round(gbs / HBM_PEAK_GBS, 4))
+        kernels[kname] = ent
+    # dominant kernel of the headline configuration's families
+    cand = {k: v for k, v in kernels.items() if k in abytes}
+    dom = max(cand, key=lambda k: cand[k]["total_ms"]) if cand else None
+    roof = None
+    if dom:
+        ach = cand[dom]["gbs"]
+        roof = dict(kernel=dom, bound="hbm", achieved=ach, peak=HBM_PEAK_GBS, unit="GB/s",
+                    frac=round(ach / HBM_PEAK_GBS, 4), traffic=traffic_from_profiles(dom),
+                    bytes_per_launch=abytes[dom], avg_launch_us=cand[dom]["avg_us"])
+
+    variants = {}
+    for name, *_ in configs:
+        rs = results[name]
+        variants[name] = dict(
+            time_s=round(float(np.mean([r["time_s"] for r in rs])), 5),
+            setup_s=round(float(np.mean([r["setup_s"] for r in rs])), 5),
+            solve_s=round(float(np.mean([r["solve_s"] for r in rs])), 5),
+            iters=rs[-1]["iters"], true_relres=rs[-1]["true_relres"],
+            converged=all(r["status"] == 0 for r in rs))
+    head = variants.get(HEADLINE) or next(iter(variants.values()))
+
+    for S in solvers.values():
+        K.SolverDestroy(S)
+    K.VecDestroy(bh)
+    K.VecDestroy(xh)
+    K.MatDestroy(A)
+    K.MapDestroy(m)
+
+    cpu = None
+    if not args.no_cpu:
+        cpu = cpu_baseline(s, args.rtol)
+
+    out = {
+        "metric": METRIC, "value": head["time_s"], "unit": "s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(1000 * t_total / args.steps, 3),
+        "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"{args.workload}: {wl['desc']}; GMRES(30) + block ILU(0), "
+                               f"FP64, rtol {args.rtol:g}, x0 = 0",
+                   "headline": HEADLINE, "rtol": args.rtol, "restart": 30,
+                   "step": "assemble + solve of every configuration in variants"},
+        "iters": head["iters"], "true_relres": head["true_relres"],
+        "variants": variants, "kernels": kernels, "roofline": roof,
+        "cpu_baseline": cpu,
+        "setup_host": {"generate_s": round(t_gen, 3), "upload_s": round(t_upload, 3)},
+    }
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,205 @@
+/*
+ * krylov.h -- C ABI of the MI355X-native preconditioned Krylov solver.
+ *
+ * Liu & Chen, "Scalable linear solvers for sparse linear systems from
+ * large-scale numerical simulations" (arXiv 1701.05913), re-designed for
+ * one gfx950 GPU holding one rank's share of the system.  The object model
+ * mirrors the paper's MAP (Section 2.1, Figures 1-5), VEC (Section 2.2,
+ * Figures 6-13), MAT (Section 2.3, Figures 15-21), SOLVER (Section 3,
+ * Figures 22-28) and preconditioner (Figure 29) interfaces.
+ *
+ * Conventions
+ *  - One rank: a MAP is the trivial row distribution offset = {0, n}
+ *    (eq. (1) with N_p = 1); there is no communication.
+ *  - Scalars at the boundary are double (the paper's FLOAT); global sizes
+ *    int64_t (the paper's INT); matrix index arrays int32_t.
+ *  - Every pointer argument marked "device" must point to GPU memory
+ *    (hipMalloc, or a PyTorch CUDA tensor); "host" to CPU memory.  The
+ *    `where` argument (KRY_HOST / KRY_DEVICE) says which, where both are
+ *    accepted.
+ *  - Vectors of a block system are interleaved per block row:
+ *    (p, s1, s2) of block row 0, then block row 1, ...
+ *  - Functions returning int return KRY_OK (0), KRY_NOT_CONVERGED (1) or a
+ *    negative error code; functions returning a pointer return NULL on
+ *    error.  LastError() describes the most recent error of the calling
+ *    thread.
+ *  - Work is issued on the solver's stream (SolverSetStream) or, for the
+ *    VEC / MAT calls, on the stream set by KrylovSetStream (default: the
+ *    null stream).  Calls that return a scalar to the host (VecDot,
+ *    VecNorm2, VecGetEntry) synchronize that stream.
+ *  - Objects are not thread-safe; distinct objects may be used from
+ *    distinct threads.
+ */
+#ifndef KRYLOV_H
+#define KRYLOV_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ------------------------------------------------------ */
+#define KRY_OK               0
+#define KRY_NOT_CONVERGED    1   /* results (residual, iterations) valid   */
+#define KRY_ERR_ARG         -1   /* invalid argument / malformed matrix    */
+#define KRY_ERR_DIM         -2   /* size mismatch (the paper's asserts)    */
+#define KRY_ERR_ALLOC       -3   /* device or host allocation failed       */
+#define KRY_ERR_ZERO_PIVOT  -4   /* ILU pivot block singular              */
+#define KRY_ERR_BREAKDOWN   -5   /* Krylov breakdown / non-finite values   */
+#define KRY_ERR_HIP         -6   /* HIP runtime error                      */
+#define KRY_ERR_UNSUPPORTED -7   /* option not implemented                 */
+#define KRY_ERR_STALL       -8   /* a level-scheduled sweep waited longer
+                                    than its bound (inconsistent schedule) */
+
+/* ---- enumerations -------------------------------------------------------- */
+enum { KRY_HOST = 0, KRY_DEVICE = 1 };
+enum { KRY_F64 = 0 };                         /* VEC data type             */
+enum { KRY_GMRES = 0, KRY_FGMRES = 1, KRY_BICGSTAB = 2 };
+enum { KRY_PC_NONE = 0, KRY_PC_ILU0 = 1, KRY_PC_BILU0 = 1, KRY_PC_CPR = 2,
+       KRY_PC_CUSTOM = 3 };
+/* precision of the preconditioner apply (mixed-precision extension) */
+enum { KRY_PREC_F64 = 0, KRY_PREC_F32 = 1, KRY_PREC_BF16_FACTORS = 2 };
+/* CPR stage order: PF = pressure then full (Algorithm 6, corrected);
+ * FP = full then pressure (Algorithm 5) */
+enum { KRY_CPR_PF = 0, KRY_CPR_FP = 1 };
+
+typedef struct MAP_ MAP;
+typedef struct VEC_ VEC;
+typedef struct MAT_ MAT;
+typedef struct SOLVER_ SOLVER;
+
+/* ---- MAP: row distribution (Section 2.1, eq. (1)-(2)) --------------------
+ * MapCreate requires ilower < iupper (eq. (2)); NULL otherwise.  With one
+ * rank the map owns rows [0, iupper - ilower) locally.  MapCreateLocal is
+ * the C name of the second creator (Figure 3).  The caller destroys every
+ * VEC, MAT and SOLVER built on a map before destroying the map (Figure 4). */
+MAP    *MapCreate(int64_t ilower, int64_t iupper);
+MAP    *MapCreateLocal(int64_t nlocal);
+void    MapDestroy(MAP *map);
+int64_t MapGetNlocal(const MAP *map);
+
+/* ---- VEC: device vector (Section 2.2, Figures 6-13) ----------------------
+ * VecCreate allocates nlocal doubles on the device (owned, zeroed).
+ * VecWrap borrows caller-owned device memory of nlocal doubles; the
+ * library never frees it.  VecDestroy frees owned memory and sets *vec to
+ * NULL; NULL is a no-op.  Entry access uses local indices and is a slow,
+ * synchronous host path meant for tests.  The algebraic calls return
+ * KRY_ERR_DIM where the paper asserts equal sizes. */
+VEC    *VecCreate(MAP *map, int dtype);
+VEC    *VecWrap(MAP *map, void *device_ptr, int dtype);
+void    VecDestroy(VEC **vec);
+void   *VecGetData(VEC *vec);
+int     VecAddEntry(VEC *vec, int64_t idx, double value);    /* Figure 9  */
+double  VecGetEntry(VEC *vec, int64_t idx);                  /* Figure 9  */
+int     VecSetValue(VEC *x, double v);                       /* Figure 13 */
+int     VecAXPBY(double alpha, VEC *x, double beta, VEC *y); /* Figure 10: y = a x + b y */
+int     VecAXPBYZ(double alpha, VEC *x, double beta, VEC *y, VEC *z); /* Figure 11 */
+double  VecDot(VEC *x, VEC *y);                              /* Figure 12 (NaN on error) */
+double  VecNorm2(VEC *x);
+
+/* ---- MAT: sparse matrix (Section 2.3, Figures 15-21) ---------------------
+ * Built in one call from CSR (bs = 1) or block CSR with bs x bs row-major
+ * blocks (bs = 1 or 3).  The arrays are copied into library-owned device
+ * storage; `where` says whether they are host or device pointers.
+ * Requirements (KRY_ERR_ARG otherwise): rowptr non-decreasing from 0,
+ * column indices in [0, n) strictly ascending within a row, every row
+ * holding its diagonal.  MatVecMXY: y = A x (Figure 20).  MatVecAMXPBY:
+ * y = alpha A x + beta y (Figure 21).  x and y must not alias. */
+MAT *MatCreateCSR(MAP *map, int32_t n, const int32_t *rowptr,
+                  const int32_t *col, const double *val, int where);
+MAT *MatCreateBSR(MAP *map, int32_t nb, int32_t bs, const int32_t *browptr,
+                  const int32_t *bcol, const double *bval, int where);
+void MatDestroy(MAT **mat);
+int  MatVecMXY(MAT *A, VEC *x, VEC *y);
+int  MatVecAMXPBY(double alpha, MAT *A, VEC *x, double beta, VEC *y);
+int64_t MatGetNnzBlocks(const MAT *A);
+
+/* ---- SOLVER (Section 3, Figures 22-28) -----------------------------------
+ * SolverCreate(type, pc_type, map) as in Figure 23.  SolverSetMat borrows
+ * the matrix, which must outlive the solver (replaces the entry-adding
+ * calls of Figure 27).  SolverAssemble builds the preconditioner
+ * (Figure 25): level sets, ILU(0)/block ILU(0) factor, CPR pressure
+ * matrix, reduced-precision copies.  SolverSolve(solver, b, x) solves
+ * A x = b (Figure 26 plus an explicit right-hand side); x holds the
+ * initial guess on entry.  Convergence: ||b - A x||_2 <= max(rtol ||b||_2,
+ * atol), judged by the true FP64 residual; btol is stored, unused.
+ * Iterations: Arnoldi steps for GMRES/FGMRES, one per BiCGSTAB pass.
+ * Returns KRY_OK, KRY_NOT_CONVERGED (maxit reached, results filled) or an
+ * error.  SolverPCApply applies the assembled preconditioner once:
+ * z = M^-1 v (z and v distinct). */
+SOLVER *SolverCreate(int solver_type, int pc_type, MAP *map);
+int     SolverDestroy(SOLVER **solver);
+int     SolverSetMat(SOLVER *s, MAT *A);
+int     SolverAssemble(SOLVER *s);
+int     SolverSolve(SOLVER *s, VEC *b, VEC *x);
+int     SolverPCApply(SOLVER *s, VEC *v, VEC *z);
+
+void SolverSetDefaultMaxit(int64_t it);
+void SolverSetDefaultRtol(double tol);
+void SolverSetDefaultAtol(double tol);
+void SolverSetDefaultBtol(double tol);
+void SolverSetDefaultRestart(int64_t m);
+void SolverSetDefaultAugk(int64_t k);
+int  SolverSetMaxit(SOLVER *s, int64_t it);
+int  SolverSetRtol(SOLVER *s, double tol);
+int  SolverSetAtol(SOLVER *s, double tol);
+int  SolverSetBtol(SOLVER *s, double tol);
+int  SolverSetRestart(SOLVER *s, int64_t m);    /* 1 <= m <= 64 */
+int  SolverSetAugk(SOLVER *s, int64_t k);       /* LGMRES: only k = 0 */
+
+/* Extensions beyond the paper:
+ * SolverSetPrecision: precision of the preconditioner apply (FP64, FP32
+ *   factors and arithmetic, or BF16-stored off-diagonal factor blocks with
+ *   FP32 diagonal inverses and FP32 arithmetic); requires FGMRES for
+ *   anything but FP64.  Outer iteration, orthogonalization, Givens and
+ *   true residuals stay FP64.
+ * SolverSetCPR: stage order and number of ILU(0) sweeps of the pressure
+ *   stage (default PF, 4).
+ * SolverSetStream: HIP stream (hipStream_t) for all work of the solver. */
+int SolverSetPrecision(SOLVER *s, int prec);
+int SolverSetCPR(SOLVER *s, int variant, int p_sweeps);
+int SolverSetStream(SOLVER *s, void *hip_stream);
+
+/* results (Figure 22: residual, nits) */
+double SolverGetResidual(const SOLVER *s);   /* final true relative residual */
+int    SolverGetIters(const SOLVER *s);
+int    SolverGetTimes(const SOLVER *s, double *setup_s, double *solve_s);
+/* residual history: entry 0 is ||r0||, entry k the estimate (GMRES) or
+ * the recurrence residual norm (BiCGSTAB) after iteration k; returns the
+ * number of entries written (at most cap). */
+int    SolverGetHistory(const SOLVER *s, double *hist, int cap);
+
+/* Custom preconditioner (Figure 29): setup(data, A) once in
+ * SolverAssemble, solve(data, x, b) computes x = M^-1 b on the solver's
+ * stream, destroy(data) in SolverDestroy.  pc_type must be
+ * KRY_PC_CUSTOM.  Only FGMRES may use a preconditioner that varies. */
+typedef int  (*PC_SETUP)(void *data, MAT *A);
+typedef int  (*PC_SOLVE)(void *data, VEC *x, VEC *b);
+typedef void (*PC_DESTROY)(void *data);
+int SolverSetPC(SOLVER *s, PC_SETUP setup, PC_SOLVE solve,
+                PC_DESTROY destroy, void *data);
+
+/* ---- per-kernel timing (measurement only) ----------------------------------
+ * When enabled, the library brackets every launch of the kernels it times
+ * (SpMV, ILU sweeps, CGS2 passes) with HIP events on the launch stream.
+ * KernelTimingQuery synchronizes and returns the launch count and the
+ * summed duration in milliseconds of the named kernel family: "spmv_bsr3"
+ * and "spmv_csr" (FP64 SpMV), "ilu_fwd_<fmt>_<prec>" and
+ * "ilu_bwd_<fmt>_<prec>" (forward / backward sweep, fmt = bsr3 or csr,
+ * prec = f64, f32 or bf16 factor storage), "cgs2" (one orthogonalization
+ * step: both Gram-Schmidt passes, the norm and the Givens update). */
+int KernelTimingEnable(int on);
+int KernelTimingReset(void);
+int KernelTimingQuery(const char *name, int64_t *launches, double *total_ms);
+
+/* stream for VEC / MAT calls (hipStream_t; NULL = null stream) */
+int KrylovSetStream(void *hip_stream);
+
+const char *LastError(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* KRYLOV_H */

@@ -1,0 +1,134 @@
+// Device-side helpers shared by the gfx950 kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace kry {
+
+constexpr int WAVE = 64;
+
+// ---- wavefront and block reductions (fixed order -> reproducible) --------
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, WAVE);
+    return v;
+}
+
+__device__ __forceinline__ float wave_sum(float v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, WAVE);
+    return v;
+}
+
+// sum over a block of NT threads; result valid in thread 0
+template <int NT>
+__device__ __forceinline__ double block_sum(double v, double *lds /* NT/64 */) {
+    v = wave_sum(v);
+    const int w = threadIdx.x / WAVE, l = threadIdx.x % WAVE;
+    if (l == 0) lds[w] = v;
+    __syncthreads();
+    double r = 0.0;
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int i = 0; i < NT / WAVE; i++) r += lds[i];
+    }
+    __syncthreads();
+    return r;
+}
+
+// ---- bfloat16 storage ---------------------------------------------------
+__device__ __forceinline__ float bf16_to_f32(uint16_t h) {
+    return __uint_as_float(static_cast<uint32_t>(h) << 16);
+}
+
+__host__ __device__ inline uint16_t f32_to_bf16_rne(float f) {
+    uint32_t u;
+    memcpy(&u, &f, 4);
+    if ((u & 0x7f800000u) == 0x7f800000u) {
+        if (u & 0x007fffffu) u |= 0x00400000u;
+        return static_cast<uint16_t>(u >> 16);
+    }
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return static_cast<uint16_t>(u >> 16);
+}
+
+template <typename T>
+__device__ __forceinline__ float to_f32(T v) { return static_cast<float>(v); }
+template <>
+__device__ __forceinline__ float to_f32<uint16_t>(uint16_t v) { return bf16_to_f32(v); }
+
+template <typename TC, typename T>
+__device__ __forceinline__ TC load_as(const T *p) { return static_cast<TC>(*p); }
+template <>
+__device__ __forceinline__ float load_as<float, uint16_t>(const uint16_t *p) {
+    return bf16_to_f32(*p);
+}
+
+// ---- self-validating values for the sync-free sweeps ----------------------
+// A sweep output slot holds a reserved quiet-NaN payload ("not yet
+// written") until its row publishes the value.  Producers store with
+// relaxed agent-scope atomics, consumers poll with relaxed agent-scope
+// atomic loads; every value validates itself, so no fence is needed.
+template <typename T> struct Bits;
+template <> struct Bits<double> {
+    using U = uint64_t;
+    static constexpr U sentinel = 0x7FFDEAD00BEEF001ull;
+    static constexpr U qnan = 0x7FF8000000000000ull;
+    __device__ static U to(double v) { return __double_as_longlong(v); }
+    __device__ static double from(U u) { return __longlong_as_double(static_cast<long long>(u)); }
+};
+template <> struct Bits<float> {
+    using U = uint32_t;
+    static constexpr U sentinel = 0x7FC0DEADu;
+    static constexpr U qnan = 0x7FC00000u;
+    __device__ static U to(float v) { return __float_as_uint(v); }
+    __device__ static float from(U u) { return __uint_as_float(u); }
+};
+
+template <typename T>
+__device__ __forceinline__ T sentinel_value() { return Bits<T>::from(Bits<T>::sentinel); }
+
+template <typename T>
+__device__ __forceinline__ void publish(T *p, T v) {
+    using U = typename Bits<T>::U;
+    U u = Bits<T>::to(v);
+    if (u == Bits<T>::sentinel) u = Bits<T>::qnan;
+    __hip_atomic_store(reinterpret_cast<U *>(p), u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+constexpr uint32_t SPIN_LIMIT = 1u << 22;
+constexpr int ERR_STALL_FLAG = 2;
+
+// Wait until BS consecutive values at p are published.  Returns false
+// (values NaN) when the error flag is raised or the spin bound is hit, so
+// that every wave drains instead of hanging.
+template <typename T, int BS>
+__device__ __forceinline__ bool wait_values(const T *p, T *out, int *err) {
+    using U = typename Bits<T>::U;
+    U *q = const_cast<U *>(reinterpret_cast<const U *>(p));
+    for (uint32_t it = 0;; ++it) {
+        bool ready = true;
+#pragma unroll
+        for (int r = 0; r < BS; r++) {
+            U u = __hip_atomic_load(q + r, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            out[r] = Bits<T>::from(u);
+            ready = ready && (u != Bits<T>::sentinel);
+        }
+        if (ready) return true;
+        if ((it & 63u) == 63u) {
+            int e = __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (e != 0 || it > SPIN_LIMIT) {
+                if (e == 0)
+                    __hip_atomic_store(err, ERR_STALL_FLAG, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+#pragma unroll
+                for (int r = 0; r < BS; r++) out[r] = Bits<T>::from(Bits<T>::qnan);
+                return false;
+            }
+        }
+        __builtin_amdgcn_s_sleep(1);
+    }
+}
+
+}  // namespace kry

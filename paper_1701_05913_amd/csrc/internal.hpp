@@ -1,0 +1,275 @@
+// Internal declarations of the gfx950 Krylov library (not installed).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdarg>
+#include <cstdint>
+#include <cstdio>
+#include <cstring>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "krylov.h"
+
+namespace kry {
+
+// ---------------------------------------------------------------------------
+// errors
+// ---------------------------------------------------------------------------
+int set_error(int code, const char *fmt, ...);
+
+#define KRY_HIP(call)                                                          \
+    do {                                                                       \
+        hipError_t e_ = (call);                                                \
+        if (e_ != hipSuccess)                                                  \
+            return ::kry::set_error(KRY_ERR_HIP, "%s: %s (%s:%d)", #call,      \
+                                    hipGetErrorString(e_), __FILE__, __LINE__); \
+    } while (0)
+
+#define KRY_TRY(expr)                                                          \
+    do {                                                                       \
+        int rc_ = (expr);                                                      \
+        if (rc_ < 0) return rc_;                                               \
+    } while (0)
+
+// ---------------------------------------------------------------------------
+// device buffers (library-owned memory)
+// ---------------------------------------------------------------------------
+template <typename T>
+struct DBuf {
+    T *p = nullptr;
+    size_t n = 0;
+    DBuf() = default;
+    DBuf(const DBuf &) = delete;
+    DBuf &operator=(const DBuf &) = delete;
+    ~DBuf() { release(); }
+    int alloc(size_t count) {
+        release();
+        if (count == 0) count = 1;
+        if (hipMalloc(reinterpret_cast<void **>(&p), count * sizeof(T)) != hipSuccess) {
+            p = nullptr;
+            return set_error(KRY_ERR_ALLOC, "hipMalloc of %zu bytes failed", count * sizeof(T));
+        }
+        n = count;
+        return KRY_OK;
+    }
+    void release() {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        n = 0;
+    }
+    size_t bytes() const { return n * sizeof(T); }
+};
+
+// ---------------------------------------------------------------------------
+// sliced ELLPACK with 64-row slices (one wavefront per slice) and
+// entry-major value planes: value e of slot t of lane l sits at
+// val[(t * b2 + e) * 64 + l].  A slot is one nonzero block position of all
+// 64 rows of a slice; col = -1 marks padding.  perm maps slice lanes to
+// matrix rows (-1: padding row); empty perm means natural order.
+// ---------------------------------------------------------------------------
+struct Sell {
+    int bs = 1;
+    int nslices = 0;
+    int64_t nslots = 0;
+    int maxw = 0;
+    DBuf<int> off;       // nslices + 1
+    DBuf<int> col;       // nslots * 64
+    DBuf<double> val;    // nslots * b2 * 64
+    DBuf<float> valf;    // optional FP32 copy
+    DBuf<uint16_t> valh; // optional BF16 copy
+    DBuf<int> perm;      // nslices * 64 (optional)
+    std::vector<int> h_off;
+};
+
+}  // namespace kry
+
+// ---------------------------------------------------------------------------
+// C ABI objects
+// ---------------------------------------------------------------------------
+struct MAP_ {
+    int64_t ilower = 0, iupper = 0, nlocal = 0, nglobal = 0;
+    int64_t offset[2] = {0, 0};
+    int rank = 0, nprocs = 1;
+};
+
+struct VEC_ {
+    MAP *map = nullptr;
+    int64_t n = 0;
+    int dtype = KRY_F64;
+    double *data = nullptr;
+    bool owned = false;
+};
+
+struct MAT_ {
+    MAP *map = nullptr;
+    int nb = 0, bs = 1;
+    int64_t nnzb = 0;
+    std::vector<int> h_rowptr, h_col, h_diag;   // host copy of the pattern
+    kry::DBuf<int> rowptr, col, diag;
+    kry::DBuf<double> val;                      // block CSR values (FP64)
+    kry::Sell sell;                             // natural-order SpMV layout
+    kry::DBuf<float> col0f;                     // FP32 column-0 planes (bs=3)
+};
+
+namespace kry {
+
+hipStream_t global_stream();
+
+// ---------------------------------------------------------------------------
+// kernel timing registry (HIP events around selected launches)
+// ---------------------------------------------------------------------------
+bool timing_on();
+void timing_begin(const char *name, hipStream_t s);
+void timing_end(const char *name, hipStream_t s);
+
+struct TimedScope {
+    const char *name;
+    hipStream_t s;
+    bool on;
+    TimedScope(const char *n, hipStream_t st) : name(n), s(st), on(timing_on()) {
+        if (on) timing_begin(name, s);
+    }
+    ~TimedScope() {
+        if (on) timing_end(name, s);
+    }
+};
+
+// ---------------------------------------------------------------------------
+// reductions: fixed-size grids and a fixed summation order, so results
+// are bitwise reproducible run to run
+// ---------------------------------------------------------------------------
+constexpr int RED_BLOCKS = 512;   // partial sums per reduction
+constexpr int RED_THREADS = 256;
+
+// vector kernels (vec.hip)
+struct Coef {
+    const double *p;  // device scalar, or nullptr
+    double v;         // host value (p == nullptr) or multiplier of *p
+};
+inline Coef hc(double v) { return Coef{nullptr, v}; }
+inline Coef dc(const double *p, double mul = 1.0) { return Coef{p, mul}; }
+
+int vec_fill(hipStream_t s, int64_t n, double *x, double v);
+// z = a x + b y (y may be null when b is a host zero); z may alias x or y
+int vec_axpbyz(hipStream_t s, int64_t n, Coef a, const double *x, Coef b,
+               const double *y, double *z);
+int vec_axpbypcz(hipStream_t s, int64_t n, Coef a, const double *x, Coef b,
+                 const double *y, Coef c, double *z);   // z = a x + b y + c z
+int vec_scale_copy(hipStream_t s, int64_t n, Coef a, const double *x, double *y);
+// partial dots of up to 2 pairs: partial[b*2+k] = sum x_k . y_k
+int vec_dot_partial(hipStream_t s, int64_t n, const double *x0, const double *y0,
+                    const double *x1, const double *y1, double *partial);
+// out[k] = sum_b partial[b*stride + k], k < nk, one block, fixed order
+int sum_partials(hipStream_t s, const double *partial, int nparts, int stride,
+                 int nk, double *out, int op);
+enum { SUM_PLAIN = 0, SUM_SQRT = 1 };
+int vec_copy_f64_to_f32(hipStream_t s, int64_t n, const double *x, float *y);
+
+// SpMV (spmv.hip)
+int sell_build(hipStream_t s, MAT_ *A);
+int sell_build_perm_free(hipStream_t s, int nrows, int bs, const int *d_rowptr,
+                         const int *d_col, const double *d_val, Sell &out,
+                         const std::vector<int> &h_rowptr);
+// y = alpha A x + beta z (z may be y or another vector; beta = 0: z unused)
+// ndot fused partial dots of y with u0 / u1 (nullptr = y itself)
+int spmv_f64(hipStream_t s, const MAT_ *A, double alpha, const double *x,
+             double beta, const double *z, double *y, int ndot,
+             const double *u0, const double *u1, double *partial);
+int spmv_sell_f32(hipStream_t s, const Sell &S, int nrows, float alpha,
+                  const float *x, float beta, const float *z, float *y);
+int spmv_sell_f64(hipStream_t s, const Sell &S, int nrows, double alpha,
+                  const double *x, double beta, const double *z, double *y);
+// r = v - A(:, col 0 of each block) p  (bs = 3), in T
+int spmv_col0_residual_f32(hipStream_t s, const MAT_ *A, const float *v,
+                           const float *p, float *r);
+int spmv_col0_residual_f64(hipStream_t s, const MAT_ *A, const double *v,
+                           const double *p, double *r);
+int ensure_sell_f32(hipStream_t s, Sell &S);
+int ensure_col0_f32(hipStream_t s, MAT_ *A);
+
+// ---------------------------------------------------------------------------
+// ILU(0) / block ILU(0) factor in level-scheduled layout (ilu.hip)
+// ---------------------------------------------------------------------------
+struct IluFactor {
+    int bs = 1, nb = 0;
+    int prec = KRY_PREC_F64;
+    int nlev_f = 0, nlev_b = 0;
+    Sell L;                 // forward order, strictly lower blocks
+    Sell U;                 // backward order, strictly upper blocks
+    DBuf<double> dinv;      // U_ii^-1 in U slice layout
+    DBuf<float> dinvf;
+    DBuf<double> y64;       // forward result (sentinel between sweeps)
+    DBuf<float> y32;
+    DBuf<int> ctr;          // [0] forward, [1] backward slice counters
+    int grid_waves = 0;     // waves launched per sweep
+};
+
+// factor A (FP64), pack for prec; err = device int flag
+int ilu_setup(hipStream_t s, const MAT_ *A, const double *d_val, IluFactor &F,
+              int prec, int *d_err);
+// x = (LU)^-1 b.  in/out element types: 0 = double, 1 = float.
+// add_mode 0: out = x; 1: add_out = add_in + x (full vector, out type);
+// 2: add_out[i*bs + r] = (r == 0 ? add_in[i] : 0) + x (pressure injection)
+// xscr: output of the solve itself (dependency source); when add_mode == 0
+// it is the result.
+int ilu_apply(hipStream_t s, IluFactor &F, const void *b, int in_type,
+              void *xscr, int out_type, int add_mode, const void *add_in,
+              void *add_out, int *d_err);
+
+// ---------------------------------------------------------------------------
+// CPR two-stage preconditioner (cpr.hip)
+// ---------------------------------------------------------------------------
+struct CprPC {
+    int variant = KRY_CPR_PF, sweeps = 4, prec = KRY_PREC_F64;
+    int nb = 0;
+    DBuf<double> w;         // quasi-IMPES weights nb*3
+    MAT_ app;               // pressure matrix (CSR, pattern of A's blocks)
+    IluFactor ilu_p;        // ILU(0) of A_pp
+    IluFactor ilu_a;        // block ILU(0) of A
+    DBuf<char> work;        // scratch vectors
+};
+int cpr_setup(hipStream_t s, MAT_ *A, CprPC &C, int variant, int sweeps,
+              int prec, int *d_err);
+int cpr_apply(hipStream_t s, MAT_ *A, CprPC &C, const double *v, double *z,
+              int *d_err);
+
+}  // namespace kry
+
+// ---------------------------------------------------------------------------
+// solver object
+// ---------------------------------------------------------------------------
+struct SOLVER_ {
+    int type = KRY_GMRES, pc_type = KRY_PC_NONE;
+    MAP *map = nullptr;
+    MAT_ *A = nullptr;
+    double rtol = 1e-6, atol = 0.0, btol = 0.0;
+    int64_t maxit = 500, augk = 0;
+    int restart = 30;
+    int prec = KRY_PREC_F64;
+    int cpr_variant = KRY_CPR_PF, cpr_sweeps = 4;
+    hipStream_t stream = nullptr;
+    PC_SETUP csetup = nullptr;
+    PC_SOLVE csolve = nullptr;
+    PC_DESTROY cdestroy = nullptr;
+    void *cdata = nullptr;
+    std::unique_ptr<kry::IluFactor> ilu;
+    std::unique_ptr<kry::CprPC> cpr;
+    bool assembled = false;
+    double residual = 0.0;
+    int nits = 0;
+    double t_setup = 0.0, t_solve = 0.0;
+    std::vector<double> hist;
+    kry::DBuf<int> err;          // device error flag
+    // Krylov workspace
+    int64_t ldv = 0;
+    kry::DBuf<double> V, Z, wrk, H, small, partial;
+    double *h_pinned = nullptr;  // host-visible readback slots
+};
+
+namespace kry {
+int pc_apply(SOLVER_ *S, const double *v, double *z);
+int check_device_error(SOLVER_ *S);
+}  // namespace kry

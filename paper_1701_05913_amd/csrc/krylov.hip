@@ -1,0 +1,807 @@
+// Krylov solvers and the SOLVER object (Section 3, Figures 22-28;
+// preconditioner interface of Figure 29).
+//
+// GMRES(m) follows Algorithm 1 with right preconditioning (the Arnoldi
+// estimate is then the true unpreconditioned residual); FGMRES keeps
+// Z = [M^-1 v_1 ... M^-1 v_m] so the preconditioner may vary (mixed
+// precision, learned stage).  BiCGSTAB is van der Vorst's method, which the
+// paper names without printing.
+//
+// gfx950 design: the Gram-Schmidt of Algorithm 1 lines 7-10 (modified,
+// j dependent dot products per step) becomes classical Gram-Schmidt with
+// one reorthogonalization (CGS2): two passes of h = V^T w, w -= V h, each a
+// tall-skinny GEMV that streams V once.  All scalars (Hessenberg column,
+// Givens rotations, residual estimate) stay in device memory; the host
+// reads back one estimate per step, which is the only per-step sync.
+// Reductions use fixed grids and fixed summation order, so two runs give
+// bitwise identical iterates.
+#include <chrono>
+#include <cmath>
+
+#include "device.hpp"
+#include "internal.hpp"
+
+namespace kry {
+
+constexpr int MAXCOL = 64;   // restart length limit (columns of V)
+
+// slots of the small scalar area
+enum {
+    SC_BETA = 0, SC_INVBETA, SC_HN, SC_INVHN, SC_EST, SC_BREAK,
+    SC_RHO, SC_RHO0, SC_ALPHA, SC_OMEGA, SC_BETAB, SC_RV, SC_TT, SC_TS,
+    SC_SNORM, SC_RNORM, SC_FLAGS, SC_RHN, SC_NONE, SC_COUNT = 32
+};
+
+struct SmallLayout {
+    int m;
+    size_t H, cs, sn, g, y, h1, h2, sc, total;
+    explicit SmallLayout(int m_) : m(m_) {
+        H = 0;
+        cs = H + (size_t)(m + 1) * m;
+        sn = cs + m;
+        g = sn + m;
+        y = g + (m + 1);
+        h1 = y + m;
+        h2 = h1 + MAXCOL;
+        sc = h2 + MAXCOL;
+        total = sc + SC_COUNT;
+    }
+};
+
+// ---------------------------------------------------------------------------
+// CGS2 kernels: V column-major with leading dimension ldv
+// ---------------------------------------------------------------------------
+template <int MAXC>
+__device__ __forceinline__ void block_reduce_cols(double *acc, int nc, double *lds /*4*MAXC*/,
+                                                  double *out /*MAXC*/) {
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+#pragma unroll
+    for (int k = 0; k < MAXC; k++) {
+        if (k < nc) {
+            double v = wave_sum(acc[k]);
+            if (l == 0) lds[w * MAXC + k] = v;
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x < nc) {
+        const int k = threadIdx.x;
+        out[k] = lds[k] + lds[MAXC + k] + lds[2 * MAXC + k] + lds[3 * MAXC + k];
+    }
+}
+
+// pass 1: partial[b * MAXCOL + k] = sum_i V[k][i] w[i]
+template <int MAXC>
+__global__ __launch_bounds__(256) void k_gemvt(int64_t n, const double *__restrict__ V,
+                                               int64_t ldv, int nc, const double *__restrict__ w,
+                                               double *__restrict__ partial) {
+    __shared__ double lds[4 * MAXC];
+    double acc[MAXC];
+#pragma unroll
+    for (int k = 0; k < MAXC; k++) acc[k] = 0.0;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const double wi = w[i];
+#pragma unroll
+        for (int k = 0; k < MAXC; k++)
+            if (k < nc) acc[k] += V[k * ldv + i] * wi;
+    }
+    block_reduce_cols<MAXC>(acc, nc, lds, partial + (size_t)blockIdx.x * MAXCOL);
+}
+
+// w -= V h, then (NORM = 0) partial dots V^T w or (NORM = 1) partial ||w||^2
+template <int MAXC, int NORM>
+__global__ __launch_bounds__(256) void k_gemvn_update(int64_t n, const double *__restrict__ V,
+                                                      int64_t ldv, int nc,
+                                                      const double *__restrict__ h, double *w,
+                                                      double *__restrict__ partial) {
+    __shared__ double lds[4 * MAXC];
+    __shared__ double hs[MAXC];
+    if (threadIdx.x < nc) hs[threadIdx.x] = h[threadIdx.x];
+    __syncthreads();
+    double acc[NORM ? 1 : MAXC];
+#pragma unroll
+    for (int k = 0; k < (NORM ? 1 : MAXC); k++) acc[k] = 0.0;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        double v[MAXC];
+        double t = w[i];
+#pragma unroll
+        for (int k = 0; k < MAXC; k++)
+            if (k < nc) {
+                v[k] = V[k * ldv + i];
+                t -= v[k] * hs[k];
+            }
+        w[i] = t;
+        if (NORM) {
+            acc[0] += t * t;
+        } else {
+#pragma unroll
+            for (int k = 0; k < MAXC; k++)
+                if (k < nc) acc[k] += v[k] * t;
+        }
+    }
+    block_reduce_cols<NORM ? 1 : MAXC>(acc, NORM ? 1 : nc, lds, partial + (size_t)blockIdx.x * MAXCOL);
+}
+
+// out[k] = sum over blocks of partial[b * MAXCOL + k]
+__global__ __launch_bounds__(256) void k_sum_cols(const double *__restrict__ partial, int nblocks,
+                                                  int nc, double *__restrict__ out) {
+    __shared__ double lds[4];
+    for (int k = 0; k < nc; k++) {
+        double s = 0.0;
+        for (int b = threadIdx.x; b < nblocks; b += blockDim.x) s += partial[(size_t)b * MAXCOL + k];
+        s = block_sum<256>(s, lds);
+        if (threadIdx.x == 0) out[k] = s;
+    }
+}
+
+// Finish Arnoldi step j: column j of H = h1 + h2, h_{j+1,j} = ||w||, apply
+// the previous Givens rotations, form rotation j, update g and the
+// residual estimate |g_{j+1}|.
+__global__ __launch_bounds__(256) void k_arnoldi_finish(const double *__restrict__ partial,
+                                                        int nblocks, int j, int m, double *small,
+                                                        SmallLayout L) {
+    __shared__ double lds[4];
+    double s = 0.0;
+    for (int b = threadIdx.x; b < nblocks; b += blockDim.x) s += partial[(size_t)b * MAXCOL];
+    s = block_sum<256>(s, lds);
+    if (threadIdx.x != 0) return;
+    double *col = small + L.H + (size_t)j * (m + 1);
+    double *cs = small + L.cs, *sn = small + L.sn, *g = small + L.g, *sc = small + L.sc;
+    const double *h1 = small + L.h1, *h2 = small + L.h2;
+    const double hn = sqrt(s);
+    for (int k = 0; k <= j; k++) col[k] = h1[k] + h2[k];
+    col[j + 1] = hn;
+    sc[SC_HN] = hn;
+    sc[SC_INVHN] = hn != 0.0 ? 1.0 / hn : 0.0;
+    sc[SC_BREAK] = hn == 0.0 ? 1.0 : 0.0;
+    for (int k = 0; k < j; k++) {
+        const double t = cs[k] * col[k] + sn[k] * col[k + 1];
+        col[k + 1] = -sn[k] * col[k] + cs[k] * col[k + 1];
+        col[k] = t;
+    }
+    const double r = hypot(col[j], col[j + 1]);
+    double c = 1.0, sv = 0.0;
+    if (r != 0.0) {
+        c = col[j] / r;
+        sv = col[j + 1] / r;
+    }
+    cs[j] = c;
+    sn[j] = sv;
+    col[j] = r;
+    col[j + 1] = 0.0;
+    g[j + 1] = -sv * g[j];
+    g[j] = c * g[j];
+    sc[SC_EST] = fabs(g[j + 1]);
+}
+
+// g = beta e_1 and the first basis vector scale factor
+__global__ void k_cycle_start(double *small, SmallLayout L) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    double *g = small + L.g, *sc = small + L.sc;
+    const double beta = sc[SC_BETA];
+    for (int k = 0; k <= L.m; k++) g[k] = 0.0;
+    g[0] = beta;
+    sc[SC_INVBETA] = beta != 0.0 ? 1.0 / beta : 0.0;
+}
+
+// R y = g(0:jend) by back substitution
+__global__ void k_ls_solve(double *small, SmallLayout L, int jend) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    const int m = L.m;
+    const double *H = small + L.H, *g = small + L.g;
+    double *y = small + L.y;
+    for (int i = jend - 1; i >= 0; i--) {
+        double s = g[i];
+        for (int k = i + 1; k < jend; k++) s -= H[(size_t)k * (m + 1) + i] * y[k];
+        const double d = H[(size_t)i * (m + 1) + i];
+        y[i] = d != 0.0 ? s / d : 0.0;
+    }
+}
+
+// x = beta x + sum_k Z[k] y[k]
+template <int MAXC>
+__global__ __launch_bounds__(256) void k_gemvn_acc(int64_t n, const double *__restrict__ Z,
+                                                   int64_t ldz, int nc, const double *__restrict__ y,
+                                                   double beta, double *x) {
+    __shared__ double ys[MAXC];
+    if (threadIdx.x < nc) ys[threadIdx.x] = y[threadIdx.x];
+    __syncthreads();
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        double t = beta != 0.0 ? beta * x[i] : 0.0;
+#pragma unroll
+        for (int k = 0; k < MAXC; k++)
+            if (k < nc) t += Z[k * ldz + i] * ys[k];
+        x[i] = t;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// BiCGSTAB fused kernels (scalars in device memory)
+// ---------------------------------------------------------------------------
+// rho = <rhat, r>; breakdown test; beta = (rho / rho0)(alpha / omega)
+__global__ void k_bicg_rho(const double *__restrict__ partial, int nblocks, double *sc) {
+    __shared__ double lds[4];
+    double s = 0.0;
+    for (int b = threadIdx.x; b < nblocks; b += blockDim.x) s += partial[(size_t)b * 2];
+    s = block_sum<256>(s, lds);
+    if (threadIdx.x != 0) return;
+    const double rho = s;
+    sc[SC_RHO] = rho;
+    const bool brk = fabs(rho) < 1e-300 * sc[SC_RHN] * sc[SC_RNORM] || rho == 0.0;
+    sc[SC_FLAGS] = brk ? 1.0 : 0.0;
+    sc[SC_BETAB] = brk ? 0.0 : (rho / sc[SC_RHO0]) * (sc[SC_ALPHA] / sc[SC_OMEGA]);
+}
+
+// p = r + beta (p - omega v)
+__global__ void k_bicg_p(int64_t n, const double *__restrict__ r, double *__restrict__ p,
+                         const double *__restrict__ v, const double *__restrict__ sc) {
+    const double beta = sc[SC_BETAB], omega = sc[SC_OMEGA];
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = r[i] + beta * (p[i] - omega * v[i]);
+}
+
+// alpha = rho / <rhat, v>
+__global__ void k_bicg_alpha(const double *__restrict__ partial, int nblocks, double *sc) {
+    __shared__ double lds[4];
+    double s = 0.0;
+    for (int b = threadIdx.x; b < nblocks; b += blockDim.x) s += partial[(size_t)b * 2];
+    s = block_sum<256>(s, lds);
+    if (threadIdx.x != 0) return;
+    sc[SC_RV] = s;
+    const bool brk = s == 0.0 || !isfinite(s);
+    if (brk) sc[SC_FLAGS] = 2.0;
+    sc[SC_ALPHA] = brk ? 0.0 : sc[SC_RHO] / s;
+}
+
+// s = r - alpha v, partial ||s||^2
+__global__ __launch_bounds__(256) void k_bicg_s(int64_t n, const double *__restrict__ r,
+                                                const double *__restrict__ v,
+                                                double *__restrict__ s_,
+                                                const double *__restrict__ sc,
+                                                double *__restrict__ partial) {
+    __shared__ double lds[4];
+    const double alpha = sc[SC_ALPHA];
+    double acc = 0.0;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const double t = r[i] - alpha * v[i];
+        s_[i] = t;
+        acc += t * t;
+    }
+    acc = block_sum<256>(acc, lds);
+    if (threadIdx.x == 0) partial[blockIdx.x * 2] = acc;
+}
+
+// omega = <t, s> / <t, t> from the SpMV's fused partials (tt, ts)
+__global__ void k_bicg_omega(const double *__restrict__ partial, int nblocks, double *sc) {
+    __shared__ double lds[4];
+    double tt = 0.0, ts = 0.0;
+    for (int b = threadIdx.x; b < nblocks; b += blockDim.x) {
+        tt += partial[(size_t)b * 2];
+        ts += partial[(size_t)b * 2 + 1];
+    }
+    tt = block_sum<256>(tt, lds);
+    ts = block_sum<256>(ts, lds);
+    if (threadIdx.x != 0) return;
+    sc[SC_TT] = tt;
+    sc[SC_TS] = ts;
+    sc[SC_OMEGA] = tt != 0.0 ? ts / tt : 0.0;
+}
+
+// x += alpha ph + omega sh; r = s - omega t; partial ||r||^2
+__global__ __launch_bounds__(256) void k_bicg_update(int64_t n, double *__restrict__ x,
+                                                     const double *__restrict__ ph,
+                                                     const double *__restrict__ sh,
+                                                     const double *__restrict__ s_,
+                                                     const double *__restrict__ t,
+                                                     double *__restrict__ r,
+                                                     const double *__restrict__ sc,
+                                                     double *__restrict__ partial) {
+    __shared__ double lds[4];
+    const double alpha = sc[SC_ALPHA], omega = sc[SC_OMEGA];
+    double acc = 0.0;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        x[i] += alpha * ph[i] + omega * sh[i];
+        const double ri = s_[i] - omega * t[i];
+        r[i] = ri;
+        acc += ri * ri;
+    }
+    acc = block_sum<256>(acc, lds);
+    if (threadIdx.x == 0) partial[blockIdx.x * 2] = acc;
+}
+
+__global__ void k_bicg_restart_scalars(double *sc) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    sc[SC_RHO0] = 1.0;
+    sc[SC_ALPHA] = 1.0;
+    sc[SC_OMEGA] = 1.0;
+    sc[SC_RHN] = sc[SC_BETA];
+    sc[SC_RNORM] = sc[SC_BETA];
+    sc[SC_FLAGS] = 0.0;
+}
+
+__global__ void k_bicg_next(double *sc) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    sc[SC_RHO0] = sc[SC_RHO];
+}
+
+__global__ void k_zero_int(int *p) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) *p = 0;
+}
+
+// ---------------------------------------------------------------------------
+// host helpers
+// ---------------------------------------------------------------------------
+static int spmv_blocks(const MAT_ *A) { return (A->sell.nslices * 64 + 255) / 256; }
+
+static int ensure_workspace(SOLVER_ *S) {
+    const int64_t n = (int64_t)S->A->nb * S->A->bs;
+    const int64_t ldv = (n + 63) / 64 * 64;
+    const int m = S->restart;
+    if (S->ldv == ldv && S->V.p && (int64_t)S->V.n >= (m + 1) * ldv &&
+        (S->type != KRY_FGMRES || (int64_t)S->Z.n >= m * ldv))
+        return KRY_OK;
+    S->ldv = ldv;
+    KRY_TRY(S->V.alloc((size_t)(m + 1) * ldv));
+    if (S->type == KRY_FGMRES) KRY_TRY(S->Z.alloc((size_t)m * ldv));
+    KRY_TRY(S->wrk.alloc((size_t)8 * ldv));
+    SmallLayout L(m);
+    KRY_TRY(S->small.alloc(L.total));
+    const size_t np = std::max<size_t>((size_t)RED_BLOCKS * MAXCOL, (size_t)spmv_blocks(S->A) * 2);
+    KRY_TRY(S->partial.alloc(np));
+    if (!S->h_pinned) KRY_HIP(hipHostMalloc(reinterpret_cast<void **>(&S->h_pinned), 64 * sizeof(double)));
+    KRY_HIP(hipMemsetAsync(S->small.p, 0, S->small.bytes(), S->stream));
+    return KRY_OK;
+}
+
+// read n scalars from device memory (synchronizes the solver stream)
+static int readback(SOLVER_ *S, const double *d, int n, double *h) {
+    KRY_HIP(hipMemcpyAsync(S->h_pinned, d, sizeof(double) * n, hipMemcpyDeviceToHost, S->stream));
+    KRY_HIP(hipStreamSynchronize(S->stream));
+    memcpy(h, S->h_pinned, sizeof(double) * n);
+    return KRY_OK;
+}
+
+template <int MAXC>
+static void launch_cgs(hipStream_t st, int64_t n, const double *V, int64_t ldv, int nc,
+                       double *w, double *small, SmallLayout L, double *partial, int j, int m) {
+    const dim3 g(RED_BLOCKS), b(256);
+    hipLaunchKernelGGL(k_gemvt<MAXC>, g, b, 0, st, n, V, ldv, nc, w, partial);
+    hipLaunchKernelGGL(k_sum_cols, dim3(1), b, 0, st, partial, RED_BLOCKS, nc, small + L.h1);
+    hipLaunchKernelGGL((k_gemvn_update<MAXC, 0>), g, b, 0, st, n, V, ldv, nc, small + L.h1, w, partial);
+    hipLaunchKernelGGL(k_sum_cols, dim3(1), b, 0, st, partial, RED_BLOCKS, nc, small + L.h2);
+    hipLaunchKernelGGL((k_gemvn_update<MAXC, 1>), g, b, 0, st, n, V, ldv, nc, small + L.h2, w, partial);
+    hipLaunchKernelGGL(k_arnoldi_finish, dim3(1), b, 0, st, partial, RED_BLOCKS, j, m, small, L);
+}
+
+static int cgs2_step(SOLVER_ *S, int j, double *w) {
+    const int64_t n = (int64_t)S->A->nb * S->A->bs;
+    const int nc = j + 1;
+    SmallLayout L(S->restart);
+    TimedScope ts("cgs2", S->stream);
+    if (nc <= 8) launch_cgs<8>(S->stream, n, S->V.p, S->ldv, nc, w, S->small.p, L, S->partial.p, j, S->restart);
+    else if (nc <= 16) launch_cgs<16>(S->stream, n, S->V.p, S->ldv, nc, w, S->small.p, L, S->partial.p, j, S->restart);
+    else if (nc <= 32) launch_cgs<32>(S->stream, n, S->V.p, S->ldv, nc, w, S->small.p, L, S->partial.p, j, S->restart);
+    else launch_cgs<64>(S->stream, n, S->V.p, S->ldv, nc, w, S->small.p, L, S->partial.p, j, S->restart);
+    KRY_HIP(hipGetLastError());
+    return KRY_OK;
+}
+
+static int gemvn_acc(SOLVER_ *S, const double *Z, int nc, const double *y, double beta, double *x) {
+    const int64_t n = (int64_t)S->A->nb * S->A->bs;
+    const dim3 g(2048), b(256);
+    if (nc <= 8) hipLaunchKernelGGL(k_gemvn_acc<8>, g, b, 0, S->stream, n, Z, S->ldv, nc, y, beta, x);
+    else if (nc <= 16) hipLaunchKernelGGL(k_gemvn_acc<16>, g, b, 0, S->stream, n, Z, S->ldv, nc, y, beta, x);
+    else if (nc <= 32) hipLaunchKernelGGL(k_gemvn_acc<32>, g, b, 0, S->stream, n, Z, S->ldv, nc, y, beta, x);
+    else hipLaunchKernelGGL(k_gemvn_acc<64>, g, b, 0, S->stream, n, Z, S->ldv, nc, y, beta, x);
+    KRY_HIP(hipGetLastError());
+    return KRY_OK;
+}
+
+// r = b - A x with ||r|| into sc[SC_BETA]; returns it on the host
+static int true_residual(SOLVER_ *S, const double *b, const double *x, double *r, double *beta) {
+    SmallLayout L(S->restart);
+    double *sc = S->small.p + L.sc;
+    KRY_TRY(spmv_f64(S->stream, S->A, -1.0, x, 1.0, b, r, 1, nullptr, nullptr, S->partial.p));
+    KRY_TRY(sum_partials(S->stream, S->partial.p, spmv_blocks(S->A), 2, 1, sc + SC_BETA, SUM_SQRT));
+    return readback(S, sc + SC_BETA, 1, beta);
+}
+
+static double host_norm(SOLVER_ *S, const double *b) {
+    const int64_t n = (int64_t)S->A->nb * S->A->bs;
+    SmallLayout L(S->restart);
+    double *sc = S->small.p + L.sc;
+    double v = NAN;
+    if (vec_dot_partial(S->stream, n, b, b, nullptr, nullptr, S->partial.p) ||
+        sum_partials(S->stream, S->partial.p, RED_BLOCKS, 2, 1, sc + SC_NONE, SUM_SQRT) ||
+        readback(S, sc + SC_NONE, 1, &v))
+        return NAN;
+    return v;
+}
+
+}  // namespace kry
+
+// ---------------------------------------------------------------------------
+// preconditioner dispatch
+// ---------------------------------------------------------------------------
+namespace kry {
+
+int pc_apply(SOLVER_ *S, const double *v, double *z) {
+    const int64_t n = (int64_t)S->A->nb * S->A->bs;
+    switch (S->pc_type) {
+    case KRY_PC_NONE:
+        KRY_HIP(hipMemcpyAsync(z, v, sizeof(double) * n, hipMemcpyDeviceToDevice, S->stream));
+        return KRY_OK;
+    case KRY_PC_ILU0:
+        return ilu_apply(S->stream, *S->ilu, v, 0, z, 0, 0, nullptr, nullptr, S->err.p);
+    case KRY_PC_CPR:
+        return cpr_apply(S->stream, S->A, *S->cpr, v, z, S->err.p);
+    case KRY_PC_CUSTOM: {
+        VEC_ vv, zz;
+        vv.map = zz.map = S->map;
+        vv.n = zz.n = n;
+        vv.data = const_cast<double *>(v);
+        zz.data = z;
+        const int rc = S->csolve(S->cdata, &zz, &vv);
+        return rc < 0 ? set_error(rc, "custom preconditioner solve failed (%d)", rc) : KRY_OK;
+    }
+    default:
+        return set_error(KRY_ERR_ARG, "unknown preconditioner type %d", S->pc_type);
+    }
+}
+
+int check_device_error(SOLVER_ *S) {
+    int e = 0;
+    KRY_HIP(hipMemcpyAsync(&e, S->err.p, sizeof(int), hipMemcpyDeviceToHost, S->stream));
+    KRY_HIP(hipStreamSynchronize(S->stream));
+    if (e == 1) return set_error(KRY_ERR_ZERO_PIVOT, "singular pivot block in the factorization");
+    if (e == ERR_STALL_FLAG)
+        return set_error(KRY_ERR_STALL, "a level-scheduled sweep exceeded its wait bound");
+    if (e != 0) return set_error(KRY_ERR_HIP, "device error flag %d", e);
+    return KRY_OK;
+}
+
+// ---------------------------------------------------------------------------
+// GMRES(m) / FGMRES(m)
+// ---------------------------------------------------------------------------
+static int gmres_solve(SOLVER_ *S, const double *b, double *x) {
+    const int64_t n = (int64_t)S->A->nb * S->A->bs;
+    const int m = S->restart;
+    const bool flexible = S->type == KRY_FGMRES;
+    KRY_TRY(ensure_workspace(S));
+    SmallLayout L(m);
+    double *small = S->small.p, *sc = small + L.sc;
+    double *ztmp = S->wrk.p, *utmp = S->wrk.p + S->ldv;
+    const double bnorm = host_norm(S, b);
+    if (!std::isfinite(bnorm)) return set_error(KRY_ERR_BREAKDOWN, "non-finite right-hand side");
+    const double tol = std::max(S->rtol * bnorm, S->atol);
+    int nits = 0;
+    S->hist.clear();
+    int status = KRY_NOT_CONVERGED;
+    double relres = 0.0;
+    for (;;) {
+        double beta = 0.0;
+        KRY_TRY(true_residual(S, b, x, S->V.p, &beta));
+        relres = bnorm > 0 ? beta / bnorm : beta;
+        if (nits == 0) S->hist.push_back(beta);
+        if (beta <= tol) { status = KRY_OK; break; }
+        if (!std::isfinite(beta)) return set_error(KRY_ERR_BREAKDOWN, "non-finite residual");
+        if (nits >= S->maxit) break;
+        hipLaunchKernelGGL(k_cycle_start, dim3(1), dim3(64), 0, S->stream, small, L);
+        KRY_TRY(vec_scale_copy(S->stream, n, dc(sc + SC_INVBETA), S->V.p, S->V.p));
+        int jend = 0;
+        for (int j = 0; j < m; j++) {
+            double *vj = S->V.p + (size_t)j * S->ldv;
+            double *zj = flexible ? S->Z.p + (size_t)j * S->ldv : ztmp;
+            double *w = S->V.p + (size_t)(j + 1) * S->ldv;
+            KRY_TRY(pc_apply(S, vj, zj));
+            KRY_TRY(spmv_f64(S->stream, S->A, 1.0, zj, 0.0, nullptr, w, 0, nullptr, nullptr, nullptr));
+            KRY_TRY(cgs2_step(S, j, w));
+            double hv[3];                                  // SC_HN, SC_INVHN, SC_EST
+            KRY_TRY(readback(S, sc + SC_HN, 3, hv));
+            const double est = hv[2];
+            nits++;
+            jend = j + 1;
+            S->hist.push_back(est);
+            if (nits >= S->maxit) break;
+            if (hv[0] == 0.0) break;                      // lucky breakdown
+            if (est <= tol) break;
+            KRY_TRY(vec_scale_copy(S->stream, n, dc(sc + SC_INVHN), w, w));
+        }
+        hipLaunchKernelGGL(k_ls_solve, dim3(1), dim3(64), 0, S->stream, small, L, jend);
+        if (flexible) {
+            KRY_TRY(gemvn_acc(S, S->Z.p, jend, small + L.y, 1.0, x));
+        } else {
+            KRY_TRY(gemvn_acc(S, S->V.p, jend, small + L.y, 0.0, utmp));
+            KRY_TRY(pc_apply(S, utmp, ztmp));
+            KRY_TRY(vec_axpbyz(S->stream, n, hc(1.0), ztmp, hc(1.0), x, x));
+        }
+    }
+    S->nits = nits;
+    S->residual = relres;
+    return status;
+}
+
+// ---------------------------------------------------------------------------
+// BiCGSTAB
+// ---------------------------------------------------------------------------
+static int bicgstab_solve(SOLVER_ *S, const double *b, double *x) {
+    const int64_t n = (int64_t)S->A->nb * S->A->bs;
+    KRY_TRY(ensure_workspace(S));
+    SmallLayout L(S->restart);
+    double *sc = S->small.p + L.sc;
+    const int64_t ld = S->ldv;
+    double *r = S->wrk.p, *rh = r + ld, *p = rh + ld, *v = p + ld, *ph = v + ld;
+    double *sv = ph + ld, *sh = sv + ld, *t = sh + ld;
+    double *part = S->partial.p;
+    const int nsb = spmv_blocks(S->A);
+    const dim3 gv(2048), bv(256);
+    const double bnorm = host_norm(S, b);
+    if (!std::isfinite(bnorm)) return set_error(KRY_ERR_BREAKDOWN, "non-finite right-hand side");
+    const double tol = std::max(S->rtol * bnorm, S->atol);
+    int nits = 0, status = KRY_NOT_CONVERGED;
+    double relres = 0.0;
+    bool fresh = true;
+    S->hist.clear();
+    for (;;) {
+        if (fresh) {
+            double tn = 0.0;
+            KRY_TRY(true_residual(S, b, x, r, &tn));
+            relres = bnorm > 0 ? tn / bnorm : tn;
+            if (nits == 0) S->hist.push_back(tn);
+            if (tn <= tol) { status = KRY_OK; break; }
+            if (!std::isfinite(tn)) return set_error(KRY_ERR_BREAKDOWN, "non-finite residual");
+            KRY_HIP(hipMemcpyAsync(rh, r, sizeof(double) * n, hipMemcpyDeviceToDevice, S->stream));
+            KRY_TRY(vec_fill(S->stream, n, v, 0.0));
+            KRY_TRY(vec_fill(S->stream, n, p, 0.0));
+            hipLaunchKernelGGL(k_bicg_restart_scalars, dim3(1), dim3(64), 0, S->stream, sc);
+            fresh = false;
+        }
+        if (nits >= S->maxit) break;
+        // rho, beta, p
+        KRY_TRY(vec_dot_partial(S->stream, n, rh, r, nullptr, nullptr, part));
+        hipLaunchKernelGGL(k_bicg_rho, dim3(1), dim3(256), 0, S->stream, part, RED_BLOCKS, sc);
+        hipLaunchKernelGGL(k_bicg_p, gv, bv, 0, S->stream, n, r, p, v, sc);
+        KRY_TRY(pc_apply(S, p, ph));
+        KRY_TRY(spmv_f64(S->stream, S->A, 1.0, ph, 0.0, nullptr, v, 1, rh, nullptr, part));
+        hipLaunchKernelGGL(k_bicg_alpha, dim3(1), dim3(256), 0, S->stream, part, nsb, sc);
+        hipLaunchKernelGGL(k_bicg_s, dim3(RED_BLOCKS), bv, 0, S->stream, n, r, v, sv, sc, part);
+        KRY_TRY(sum_partials(S->stream, part, RED_BLOCKS, 2, 1, sc + SC_SNORM, SUM_SQRT));
+        double sdata[SC_RHN + 1];
+        KRY_TRY(readback(S, sc, SC_RHN + 1, sdata));
+        const int flags = static_cast<int>(sdata[SC_FLAGS]);
+        if (flags == 1) { fresh = true; continue; }       // rho breakdown: not counted
+        nits++;
+        if (flags == 2) { fresh = true; continue; }       // <rhat, v> = 0
+        const double snorm = sdata[SC_SNORM];
+        if (snorm <= tol) {
+            KRY_TRY(vec_axpbyz(S->stream, n, dc(sc + SC_ALPHA), ph, hc(1.0), x, x));
+            S->hist.push_back(snorm);
+            fresh = true;
+            continue;
+        }
+        KRY_TRY(pc_apply(S, sv, sh));
+        KRY_TRY(spmv_f64(S->stream, S->A, 1.0, sh, 0.0, nullptr, t, 2, nullptr, sv, part));
+        hipLaunchKernelGGL(k_bicg_omega, dim3(1), dim3(256), 0, S->stream, part, nsb, sc);
+        hipLaunchKernelGGL(k_bicg_update, dim3(RED_BLOCKS), bv, 0, S->stream, n, x, ph, sh, sv, t, r,
+                           sc, part);
+        KRY_TRY(sum_partials(S->stream, part, RED_BLOCKS, 2, 1, sc + SC_RNORM, SUM_SQRT));
+        hipLaunchKernelGGL(k_bicg_next, dim3(1), dim3(64), 0, S->stream, sc);
+        double rv[SC_RNORM + 1];
+        KRY_TRY(readback(S, sc, SC_RNORM + 1, rv));
+        const double rn = rv[SC_RNORM], omega = rv[SC_OMEGA];
+        S->hist.push_back(rn);
+        if (rn <= tol) { fresh = true; continue; }
+        if (omega == 0.0 || !std::isfinite(rn)) { fresh = true; continue; }
+    }
+    S->nits = nits;
+    S->residual = relres;
+    return status;
+}
+
+}  // namespace kry
+
+using namespace kry;
+
+// ===========================================================================
+// C ABI: SOLVER
+// ===========================================================================
+static int64_t g_def_maxit = 500;
+static double g_def_rtol = 1e-6, g_def_atol = 0.0, g_def_btol = 0.0;
+static int64_t g_def_restart = 30, g_def_augk = 0;
+
+extern "C" void SolverSetDefaultMaxit(int64_t it) { g_def_maxit = it; }
+extern "C" void SolverSetDefaultRtol(double tol) { g_def_rtol = tol; }
+extern "C" void SolverSetDefaultAtol(double tol) { g_def_atol = tol; }
+extern "C" void SolverSetDefaultBtol(double tol) { g_def_btol = tol; }
+extern "C" void SolverSetDefaultRestart(int64_t m) { g_def_restart = m; }
+extern "C" void SolverSetDefaultAugk(int64_t k) { g_def_augk = k; }
+
+extern "C" SOLVER *SolverCreate(int solver_type, int pc_type, MAP *map) {
+    if (!map) { set_error(KRY_ERR_ARG, "SolverCreate: map is NULL"); return nullptr; }
+    if (solver_type != KRY_GMRES && solver_type != KRY_FGMRES && solver_type != KRY_BICGSTAB) {
+        set_error(KRY_ERR_UNSUPPORTED, "SolverCreate: solver type %d", solver_type);
+        return nullptr;
+    }
+    if (pc_type < KRY_PC_NONE || pc_type > KRY_PC_CUSTOM) {
+        set_error(KRY_ERR_UNSUPPORTED, "SolverCreate: preconditioner type %d", pc_type);
+        return nullptr;
+    }
+    SOLVER *s = new SOLVER_();
+    s->type = solver_type;
+    s->pc_type = pc_type;
+    s->map = map;
+    s->maxit = g_def_maxit;
+    s->rtol = g_def_rtol;
+    s->atol = g_def_atol;
+    s->btol = g_def_btol;
+    s->restart = static_cast<int>(std::min<int64_t>(std::max<int64_t>(g_def_restart, 1), MAXCOL - 1));
+    s->augk = g_def_augk;
+    return s;
+}
+
+extern "C" int SolverDestroy(SOLVER **sp) {
+    if (!sp || !*sp) return KRY_OK;
+    SOLVER *s = *sp;
+    if (s->pc_type == KRY_PC_CUSTOM && s->cdestroy) s->cdestroy(s->cdata);
+    if (s->h_pinned) (void)hipHostFree(s->h_pinned);
+    delete s;
+    *sp = nullptr;
+    return KRY_OK;
+}
+
+extern "C" int SolverSetMat(SOLVER *s, MAT *A) {
+    if (!s || !A) return set_error(KRY_ERR_ARG, "SolverSetMat: NULL argument");
+    if ((int64_t)A->nb * A->bs != s->map->nlocal) return set_error(KRY_ERR_DIM, "SolverSetMat: size mismatch");
+    s->A = A;
+    s->assembled = false;
+    return KRY_OK;
+}
+
+extern "C" int SolverSetMaxit(SOLVER *s, int64_t it) {
+    if (!s || it < 0) return set_error(KRY_ERR_ARG, "SolverSetMaxit: bad argument");
+    s->maxit = it;
+    return KRY_OK;
+}
+extern "C" int SolverSetRtol(SOLVER *s, double t) {
+    if (!s || !(t >= 0)) return set_error(KRY_ERR_ARG, "SolverSetRtol: bad argument");
+    s->rtol = t;
+    return KRY_OK;
+}
+extern "C" int SolverSetAtol(SOLVER *s, double t) {
+    if (!s || !(t >= 0)) return set_error(KRY_ERR_ARG, "SolverSetAtol: bad argument");
+    s->atol = t;
+    return KRY_OK;
+}
+extern "C" int SolverSetBtol(SOLVER *s, double t) {
+    if (!s || !(t >= 0)) return set_error(KRY_ERR_ARG, "SolverSetBtol: bad argument");
+    s->btol = t;
+    return KRY_OK;
+}
+extern "C" int SolverSetRestart(SOLVER *s, int64_t m) {
+    if (!s || m < 1 || m > MAXCOL - 1) return set_error(KRY_ERR_ARG, "SolverSetRestart: need 1 <= m <= %d", MAXCOL - 1);
+    s->restart = static_cast<int>(m);
+    s->ldv = 0;
+    return KRY_OK;
+}
+extern "C" int SolverSetAugk(SOLVER *s, int64_t k) {
+    if (!s) return set_error(KRY_ERR_ARG, "SolverSetAugk: NULL solver");
+    if (k != 0) return set_error(KRY_ERR_UNSUPPORTED, "SolverSetAugk: LGMRES augmentation is not implemented");
+    s->augk = 0;
+    return KRY_OK;
+}
+extern "C" int SolverSetPrecision(SOLVER *s, int prec) {
+    if (!s || prec < KRY_PREC_F64 || prec > KRY_PREC_BF16_FACTORS)
+        return set_error(KRY_ERR_ARG, "SolverSetPrecision: bad argument");
+    s->prec = prec;
+    s->assembled = false;
+    return KRY_OK;
+}
+extern "C" int SolverSetCPR(SOLVER *s, int variant, int p_sweeps) {
+    if (!s || (variant != KRY_CPR_PF && variant != KRY_CPR_FP) || p_sweeps < 1)
+        return set_error(KRY_ERR_ARG, "SolverSetCPR: bad argument");
+    s->cpr_variant = variant;
+    s->cpr_sweeps = p_sweeps;
+    s->assembled = false;
+    return KRY_OK;
+}
+extern "C" int SolverSetStream(SOLVER *s, void *stream) {
+    if (!s) return set_error(KRY_ERR_ARG, "SolverSetStream: NULL solver");
+    s->stream = static_cast<hipStream_t>(stream);
+    return KRY_OK;
+}
+extern "C" int SolverSetPC(SOLVER *s, PC_SETUP setup, PC_SOLVE solve, PC_DESTROY destroy, void *data) {
+    if (!s || !solve) return set_error(KRY_ERR_ARG, "SolverSetPC: NULL solver or solve callback");
+    if (s->pc_type != KRY_PC_CUSTOM) return set_error(KRY_ERR_ARG, "SolverSetPC: solver was not created with KRY_PC_CUSTOM");
+    s->csetup = setup;
+    s->csolve = solve;
+    s->cdestroy = destroy;
+    s->cdata = data;
+    s->assembled = false;
+    return KRY_OK;
+}
+
+extern "C" int SolverAssemble(SOLVER *s) {
+    if (!s || !s->A) return set_error(KRY_ERR_ARG, "SolverAssemble: no matrix");
+    if (s->prec != KRY_PREC_F64 && s->type != KRY_FGMRES)
+        return set_error(KRY_ERR_ARG, "reduced-precision preconditioning needs FGMRES");
+    if (s->prec != KRY_PREC_F64 && s->pc_type != KRY_PC_ILU0 && s->pc_type != KRY_PC_CPR)
+        return set_error(KRY_ERR_ARG, "reduced precision applies to ILU and CPR preconditioners");
+    const auto t0 = std::chrono::steady_clock::now();
+    if (!s->err.p) KRY_TRY(s->err.alloc(1));
+    hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(64), 0, s->stream, s->err.p);
+    s->ilu.reset();
+    s->cpr.reset();
+    switch (s->pc_type) {
+    case KRY_PC_NONE:
+        break;
+    case KRY_PC_ILU0:
+        s->ilu.reset(new IluFactor());
+        KRY_TRY(ilu_setup(s->stream, s->A, s->A->val.p, *s->ilu, s->prec, s->err.p));
+        break;
+    case KRY_PC_CPR:
+        s->cpr.reset(new CprPC());
+        KRY_TRY(cpr_setup(s->stream, s->A, *s->cpr, s->cpr_variant, s->cpr_sweeps, s->prec, s->err.p));
+        break;
+    case KRY_PC_CUSTOM:
+        if (!s->csolve) return set_error(KRY_ERR_ARG, "custom preconditioner not set");
+        if (s->csetup) {
+            const int rc = s->csetup(s->cdata, s->A);
+            if (rc < 0) return set_error(rc, "custom preconditioner setup failed (%d)", rc);
+        }
+        break;
+    }
+    KRY_TRY(check_device_error(s));
+    KRY_TRY(ensure_workspace(s));
+    KRY_HIP(hipStreamSynchronize(s->stream));
+    s->t_setup = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    s->assembled = true;
+    return KRY_OK;
+}
+
+extern "C" int SolverSolve(SOLVER *s, VEC *b, VEC *x) {
+    if (!s || !b || !x) return set_error(KRY_ERR_ARG, "SolverSolve: NULL argument");
+    if (!s->A) return set_error(KRY_ERR_ARG, "SolverSolve: no matrix");
+    if (!s->assembled) return set_error(KRY_ERR_ARG, "SolverSolve: call SolverAssemble first");
+    const int64_t n = (int64_t)s->A->nb * s->A->bs;
+    if (b->n != n || x->n != n) return set_error(KRY_ERR_DIM, "SolverSolve: vector sizes differ from the matrix");
+    if (b->data == x->data) return set_error(KRY_ERR_ARG, "SolverSolve: b and x alias");
+    const auto t0 = std::chrono::steady_clock::now();
+    int rc = (s->type == KRY_BICGSTAB) ? bicgstab_solve(s, b->data, x->data) : gmres_solve(s, b->data, x->data);
+    const int erc = check_device_error(s);
+    if (hipStreamSynchronize(s->stream) != hipSuccess && rc >= 0) rc = set_error(KRY_ERR_HIP, "SolverSolve: stream error");
+    s->t_solve = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    if (erc < 0) return erc;
+    return rc;
+}
+
+extern "C" int SolverPCApply(SOLVER *s, VEC *v, VEC *z) {
+    if (!s || !v || !z) return set_error(KRY_ERR_ARG, "SolverPCApply: NULL argument");
+    if (!s->assembled) return set_error(KRY_ERR_ARG, "SolverPCApply: call SolverAssemble first");
+    const int64_t n = (int64_t)s->A->nb * s->A->bs;
+    if (v->n != n || z->n != n) return set_error(KRY_ERR_DIM, "SolverPCApply: sizes differ");
+    if (v->data == z->data) return set_error(KRY_ERR_ARG, "SolverPCApply: v and z alias");
+    KRY_TRY(pc_apply(s, v->data, z->data));
+    return check_device_error(s);
+}
+
+extern "C" double SolverGetResidual(const SOLVER *s) { return s ? s->residual : NAN; }
+extern "C" int SolverGetIters(const SOLVER *s) { return s ? s->nits : -1; }
+
+extern "C" int SolverGetTimes(const SOLVER *s, double *setup_s, double *solve_s) {
+    if (!s) return set_error(KRY_ERR_ARG, "SolverGetTimes: NULL solver");
+    if (setup_s) *setup_s = s->t_setup;
+    if (solve_s) *solve_s = s->t_solve;
+    return KRY_OK;
+}
+
+extern "C" int SolverGetHistory(const SOLVER *s, double *hist, int cap) {
+    if (!s || (!hist && cap > 0)) return set_error(KRY_ERR_ARG, "SolverGetHistory: bad argument");
+    const int k = std::min<int>(cap, static_cast<int>(s->hist.size()));
+    for (int i = 0; i < k; i++) hist[i] = s->hist[i];
+    return k;
+}

@@ -1,0 +1,251 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 oracle on the
+same seeded inputs.
+
+Bars (from the method's pass criteria): FP64 SpMV within 1e-12 relative
+(normwise); FP64 preconditioner applies within 1e-10 (rounding order and
+FMA contraction differ, the factor is the same); every solve reaches a
+true FP64 residual <= rtol; iteration counts within 10% of the oracle's;
+||x - x_oracle|| / ||x_oracle|| <= 1e-6, compared at the oracle's run of
+exactly the GPU's iteration count when the counts differ (a one-step
+difference can move x by up to kappa * rtol)."""
+import numpy as np
+import pytest
+
+import oracle
+import reservoir_inputs as ri
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+import paper_1701_05913_amd as K  # noqa: E402
+from tests.gpu_helpers import GpuSystem, pc_apply, relerr, solve  # noqa: E402
+
+SMALL_SCALAR = (37, 29, 23)     # 24 679 rows: many slices, ragged tail
+SMALL_BLOCK = (13, 11, 9)       # 1 287 block rows, ragged tail
+
+
+def _sys(kind, grid, seed=0):
+    if kind == "scalar":
+        return ri.scalar_system(*grid, seed=seed)
+    return ri.blackoil_system(*grid, seed=seed)
+
+
+# ---- SpMV ------------------------------------------------------------------
+@pytest.mark.parametrize("kind,grid", [("scalar", SMALL_SCALAR), ("scalar", (32, 32, 32)),
+                                       ("block", SMALL_BLOCK), ("block", (64, 64, 64)),
+                                       ("block", (1, 1, 1)), ("scalar", (3, 1, 1))])
+def test_spmv_parity(kind, grid):
+    s = _sys(kind, grid, seed=1)
+    A = oracle.Matrix.from_system(s)
+    x = np.random.default_rng(2).standard_normal(A.n)
+    y0 = np.random.default_rng(3).standard_normal(A.n)
+    ref = oracle.spmv(A, x)
+    ref2 = oracle.amxpby(A, -0.5, x, 2.0, y0)
+    g = GpuSystem(s)
+    try:
+        xt, xh = g.vec(x)
+        yt, yh = g.vec()
+        K.MatVecMXY(g.A, xh, yh)
+        assert relerr(yt.cpu().numpy(), ref) <= 1e-12
+        zt, zh = g.vec(y0)
+        K.MatVecAMXPBY(-0.5, g.A, xh, 2.0, zh)
+        assert relerr(zt.cpu().numpy(), ref2) <= 1e-12
+    finally:
+        g.close()
+
+
+def test_spmv_integer_exact_bitwise():
+    rng = np.random.default_rng(0)
+    s = ri.blackoil_system(17, 9, 5, seed=4)
+    s["val"] = rng.integers(-8, 9, size=s["val"].shape).astype(np.float64)
+    A = oracle.Matrix.from_system(s)
+    x = rng.integers(-5, 6, size=A.n).astype(np.float64)
+    g = GpuSystem(s, where="device")
+    try:
+        xt, xh = g.vec(x)
+        yt, yh = g.vec()
+        K.MatVecMXY(g.A, xh, yh)
+        assert np.array_equal(yt.cpu().numpy(), oracle.spmv(A, x))
+    finally:
+        g.close()
+
+
+# ---- vector kernels (Figures 10-13) ------------------------------------------
+def test_vector_kernels():
+    s = ri.scalar_system(*SMALL_SCALAR, seed=1)
+    g = GpuSystem(s)
+    rng = np.random.default_rng(5)
+    a = rng.standard_normal(g.n)
+    b = rng.standard_normal(g.n)
+    try:
+        at, ah = g.vec(a)
+        bt, bh = g.vec(b)
+        ct, ch = g.vec()
+        assert abs(K.VecDot(ah, bh) - a @ b) <= 1e-12 * np.abs(a) @ np.abs(b)
+        assert abs(K.VecNorm2(ah) - np.linalg.norm(a)) <= 1e-13 * np.linalg.norm(a)
+        # one rounding (FMA) against numpy's two: bound by the magnitudes
+        K.VecAXPBYZ(2.0, ah, -3.0, bh, ch)
+        assert np.all(np.abs(ct.cpu().numpy() - (2 * a - 3 * b)) <= 4e-16 * (2 * np.abs(a) + 3 * np.abs(b)))
+        K.VecAXPBY(0.5, ah, 2.0, bh)
+        assert np.all(np.abs(bt.cpu().numpy() - (0.5 * a + 2 * b)) <= 4e-16 * (0.5 * np.abs(a) + 2 * np.abs(b)))
+        K.VecSetValue(ch, 7.0)
+        assert np.all(ct.cpu().numpy() == 7.0)
+        K.VecAddEntry(ch, 5, 1.5)
+        assert K.VecGetEntry(ch, 5) == 8.5
+    finally:
+        g.close()
+
+
+# ---- ILU(0) / block ILU(0) apply --------------------------------------------
+@pytest.mark.parametrize("kind,grid", [("scalar", SMALL_SCALAR), ("scalar", (32, 32, 32)),
+                                       ("block", SMALL_BLOCK), ("block", (64, 64, 64)),
+                                       ("block", (40, 1, 1)), ("block", (1, 1, 1))])
+def test_ilu_apply_parity_fp64(kind, grid):
+    s = _sys(kind, grid, seed=2)
+    A = oracle.Matrix.from_system(s)
+    v = np.random.default_rng(6).standard_normal(A.n)
+    ref = oracle.PC(A, "bilu0").apply(v)
+    g = GpuSystem(s)
+    try:
+        z = pc_apply(g, K.KRY_PC_ILU0, v)
+    finally:
+        g.close()
+    assert relerr(z, ref) <= 1e-10
+
+
+@pytest.mark.parametrize("prec,tol", [(K.KRY_PREC_F32, 1e-5), (K.KRY_PREC_BF16_FACTORS, 1e-4)])
+@pytest.mark.parametrize("kind,grid", [("scalar", SMALL_SCALAR), ("block", SMALL_BLOCK),
+                                       ("block", (64, 64, 64))])
+def test_ilu_apply_parity_reduced(kind, grid, prec, tol):
+    s = _sys(kind, grid, seed=3)
+    A = oracle.Matrix.from_system(s)
+    v = np.random.default_rng(7).standard_normal(A.n)
+    name = "f32" if prec == K.KRY_PREC_F32 else "bf16"
+    ref = oracle.PC(A, "bilu0", name).apply(v)
+    ref64 = oracle.PC(A, "bilu0").apply(v)
+    g = GpuSystem(s)
+    try:
+        z = pc_apply(g, K.KRY_PC_ILU0, v, prec=prec)
+    finally:
+        g.close()
+    # against the oracle's emulation of the same rounding
+    assert relerr(z, ref) <= tol
+    # and the reduced apply really is reduced
+    assert relerr(z, ref64) > 1e-9
+
+
+# ---- CPR two-stage -----------------------------------------------------------------
+@pytest.mark.parametrize("variant", [K.KRY_CPR_PF, K.KRY_CPR_FP])
+@pytest.mark.parametrize("prec,tol", [(K.KRY_PREC_F64, 1e-10), (K.KRY_PREC_F32, 1e-5),
+                                      (K.KRY_PREC_BF16_FACTORS, 1e-4)])
+@pytest.mark.parametrize("grid", [SMALL_BLOCK, (32, 32, 16)])
+def test_cpr_apply_parity(grid, variant, prec, tol):
+    s = ri.blackoil_system(*grid, seed=4)
+    A = oracle.Matrix.from_system(s)
+    v = np.random.default_rng(8).standard_normal(A.n)
+    name = {K.KRY_PREC_F64: "f64", K.KRY_PREC_F32: "f32", K.KRY_PREC_BF16_FACTORS: "bf16"}[prec]
+    kind = "cpr_pf" if variant == K.KRY_CPR_PF else "cpr_fp"
+    ref = oracle.PC(A, kind, name, p_sweeps=4).apply(v)
+    g = GpuSystem(s)
+    try:
+        z = pc_apply(g, K.KRY_PC_CPR, v, prec=prec, cpr=(variant, 4))
+    finally:
+        g.close()
+    assert relerr(z, ref) <= tol
+
+
+# ---- solves ------------------------------------------------------------------
+def _bicgstab_envelope(A, pc, b, rtol, maxit, nperturb=4):
+    """BiCGSTAB has no minimization property: one-ulp changes of b move its
+    iteration count and iterate far more than the reduction order of a GPU
+    does to GMRES.  The oracle's own spread under such perturbations is the
+    parity envelope (iterations range, largest x deviation)."""
+    base = oracle.bicgstab(A, pc, b, rtol=rtol, maxit=maxit)
+    its, dev = [base["iters"]], [0.0]
+    rng = np.random.default_rng(12345)
+    for _ in range(nperturb):
+        b2 = b * (1 + 2.0**-52 * rng.choice([-1.0, 0.0, 1.0], size=b.size))
+        r = oracle.bicgstab(A, pc, b2, rtol=rtol, maxit=maxit)
+        its.append(r["iters"])
+        dev.append(relerr(r["x"], base["x"]))
+    return base, min(its), max(its), max(dev)
+
+
+def _check_bicgstab(s, gpu, A, pc, rtol, maxit):
+    assert gpu["status"] == K.KRY_OK, gpu
+    r = s["b"] - oracle.spmv(A, gpu["x"])
+    assert np.linalg.norm(r) <= rtol * np.linalg.norm(s["b"]) * (1 + 1e-9)
+    base, lo, hi, dev = _bicgstab_envelope(A, pc, s["b"], rtol, maxit)
+    assert 0.9 * lo - 1 <= gpu["iters"] <= 1.1 * hi + 1, (gpu["iters"], lo, hi)
+    assert relerr(gpu["x"], base["x"]) <= max(1e-6, 2.0 * dev), (relerr(gpu["x"], base["x"]), dev)
+
+
+def _check_solve(s, gpu, A, pc_ref, rtol, oracle_fn, **okw):
+    ref = oracle_fn(A, pc_ref, s["b"], rtol=rtol, **okw)
+    assert ref["status"] == 0
+    assert gpu["status"] == K.KRY_OK, gpu
+    # true FP64 residual of the GPU's x, recomputed by the oracle
+    r = s["b"] - oracle.spmv(A, gpu["x"])
+    assert np.linalg.norm(r) <= rtol * np.linalg.norm(s["b"]) * (1 + 1e-9)
+    assert abs(gpu["relres"] - np.linalg.norm(r) / np.linalg.norm(s["b"])) <= 1e-3 * rtol
+    it_g, it_o = gpu["iters"], ref["iters"]
+    assert abs(it_g - it_o) <= max(1, 0.1 * it_o), (it_g, it_o)
+    if it_g == it_o:
+        xo = ref["x"]
+    else:
+        fixed = dict(okw)
+        fixed["maxit"] = it_g
+        xo = oracle_fn(A, pc_ref, s["b"], rtol=rtol, fixed_iters=True, **fixed)["x"]
+    assert relerr(gpu["x"], xo) <= 1e-6
+    return ref
+
+
+def test_scalar32_gmres_ilu0():
+    # the 32^3 scalar finite-volume system: GMRES(30) + ILU(0), rtol 1e-6
+    s = ri.scalar_system(32, 32, 32, seed=0)
+    A = oracle.Matrix.from_system(s)
+    g = GpuSystem(s)
+    try:
+        gpu = solve(g, K.KRY_GMRES, K.KRY_PC_ILU0, rtol=1e-6, maxit=500)
+    finally:
+        g.close()
+    _check_solve(s, gpu, A, oracle.PC(A, "bilu0"), 1e-6, oracle.gmres, restart=30, maxit=500)
+
+
+@pytest.mark.parametrize("solver", ["gmres", "fgmres", "bicgstab"])
+def test_small_block_solves(solver):
+    s = ri.blackoil_system(*SMALL_BLOCK, seed=5)
+    A = oracle.Matrix.from_system(s)
+    st = {"gmres": K.KRY_GMRES, "fgmres": K.KRY_FGMRES, "bicgstab": K.KRY_BICGSTAB}[solver]
+    g = GpuSystem(s)
+    try:
+        gpu = solve(g, st, K.KRY_PC_BILU0, rtol=1e-8, maxit=2000)
+    finally:
+        g.close()
+    pc = oracle.PC(A, "bilu0")
+    if solver == "bicgstab":
+        _check_bicgstab(s, gpu, A, pc, 1e-8, 2000)
+    else:
+        _check_solve(s, gpu, A, pc, 1e-8, oracle.gmres, restart=30, maxit=2000,
+                     flexible=solver == "fgmres")
+
+
+@pytest.mark.parametrize("solver", ["gmres", "bicgstab"])
+def test_blackoil64_bilu0(solver):
+    # the 64^3 black-oil system: BiCGSTAB and GMRES(30) with block ILU(0), rtol 1e-8
+    s = ri.blackoil_system(64, 64, 64, seed=0)
+    A = oracle.Matrix.from_system(s)
+    st = K.KRY_GMRES if solver == "gmres" else K.KRY_BICGSTAB
+    g = GpuSystem(s)
+    try:
+        gpu = solve(g, st, K.KRY_PC_BILU0, rtol=1e-8, maxit=5000)
+    finally:
+        g.close()
+    pc = oracle.PC(A, "bilu0")
+    if solver == "gmres":
+        _check_solve(s, gpu, A, pc, 1e-8, oracle.gmres, restart=30, maxit=5000)
+    else:
+        _check_bicgstab(s, gpu, A, pc, 1e-8, 5000)
