@@ -67,6 +67,10 @@ def algorithmic_bytes(nb, nnzb):
         # BF16 factors: 22 B per block, FP32 diagonal inverses
         "ilu_fwd_bsr3_bf16": 22 * nl + ptr + 24 * nb + 12 * nb,
         "ilu_bwd_bsr3_bf16": 22 * nl + 36 * nb + ptr + 12 * nb + 24 * nb,
+        # CPR second stage: the backward sweep also reads the pressure
+        # correction (one value per cell) and writes the combined FP64 result
+        "ilu_bwd_bsr3_f64_inject": 76 * nl + 72 * nb + ptr + 48 * nb + 8 * nb + 24 * nb,
+        "ilu_bwd_bsr3_f32_inject": 40 * nl + 36 * nb + ptr + 12 * nb + 12 * nb + 4 * nb + 24 * nb,
     }
 
 
@@ -125,6 +129,8 @@ def main():
     ap.add_argument("--rtol", type=float, default=1e-8)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--configs", default="all")
+    ap.add_argument("--layout", default="auto", choices=["auto", "levels", "grid"],
+                    help="ILU sweep layout (see SolverSetSweepLayout)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this build measures one GPU holding one rank's share; "
@@ -170,6 +176,7 @@ def main():
         if cpr:
             K.SolverSetCPR(S, getattr(K, f"KRY_CPR_{cpr[0]}"), cpr[1])
         K.SolverSetStream(S, stream)
+        K.SolverSetSweepLayout(S, getattr(K, f"KRY_SWEEP_{args.layout.upper()}"))
         solvers[name] = S
 
     def run_one(name):
@@ -256,6 +263,7 @@ def main():
         "config": {"workload": f"{args.workload}: {wl['desc']}; GMRES(30) + block ILU(0), "
                                f"FP64, rtol {args.rtol:g}, x0 = 0",
                    "headline": HEADLINE, "rtol": args.rtol, "restart": 30,
+                   "sweep_layout": args.layout,
                    "step": "assemble + solve of every configuration in variants"},
         "iters": head["iters"], "true_relres": head["true_relres"],
         "variants": variants, "kernels": kernels, "roofline": roof,

@@ -64,6 +64,10 @@ enum { KRY_PREC_F64 = 0, KRY_PREC_F32 = 1, KRY_PREC_BF16_FACTORS = 2 };
 /* CPR stage order: PF = pressure then full (Algorithm 6, corrected);
  * FP = full then pressure (Algorithm 5) */
 enum { KRY_CPR_PF = 0, KRY_CPR_FP = 1 };
+/* layout of the ILU triangular sweeps: AUTO picks GRID when the matrix is a
+ * 7-point stencil on an nx x ny x nz grid (nx, ny, nz >= 2) in natural
+ * order, LEVELS otherwise */
+enum { KRY_SWEEP_AUTO = 0, KRY_SWEEP_LEVELS = 1, KRY_SWEEP_GRID = 2 };
 
 typedef struct MAP_ MAP;
 typedef struct VEC_ VEC;
@@ -112,6 +116,11 @@ MAT *MatCreateCSR(MAP *map, int32_t n, const int32_t *rowptr,
 MAT *MatCreateBSR(MAP *map, int32_t nb, int32_t bs, const int32_t *browptr,
                   const int32_t *bcol, const double *bval, int where);
 void MatDestroy(MAT **mat);
+/* The 7-point grid the pattern was recognised as (MatCreate checks every
+ * row against the stencil in natural order cell = i + nx (j + ny k));
+ * returns KRY_OK and the sizes, or KRY_ERR_ARG with zeros when the pattern
+ * is not such a stencil. */
+int  MatGetGrid(const MAT *A, int32_t *nx, int32_t *ny, int32_t *nz);
 int  MatVecMXY(MAT *A, VEC *x, VEC *y);
 int  MatVecAMXPBY(double alpha, MAT *A, VEC *x, double beta, VEC *y);
 int64_t MatGetNnzBlocks(const MAT *A);
@@ -160,6 +169,11 @@ int  SolverSetAugk(SOLVER *s, int64_t k);       /* LGMRES: only k = 0 */
  * SolverSetStream: HIP stream (hipStream_t) for all work of the solver. */
 int SolverSetPrecision(SOLVER *s, int prec);
 int SolverSetCPR(SOLVER *s, int variant, int p_sweeps);
+/* SolverSetSweepLayout: KRY_SWEEP_AUTO (default), KRY_SWEEP_LEVELS (generic
+ * level-scheduled sweeps), or KRY_SWEEP_GRID (grid-tiled sweeps; assembly
+ * fails with KRY_ERR_ARG if the matrix is not a 7-point grid stencil).
+ * Both layouts apply the same factor. */
+int SolverSetSweepLayout(SOLVER *s, int layout);
 int SolverSetStream(SOLVER *s, void *hip_stream);
 
 /* results (Figure 22: residual, nits) */

@@ -621,7 +621,7 @@ void or_pc_apply(or_pc *pc, const double *v, double *z)
  * C5/C6. Restarted GMRES(m) (Algorithm 1) and FGMRES(m).
  * Default reading: right preconditioning (A M^-1 u = b, x = M^-1 u) so the
  * Arnoldi estimate |g_{j+1}| is the unpreconditioned residual; modified
- * Gram-Schmidt as in Algorithm 1 lines 7-10; Givens rotations
+ * Gram-Schmidt as in the Arnoldi step of Algorithm 1; Givens rotations
  * c = h_jj / r, s = h_{j+1,j} / r, r = hypot(h_jj, h_{j+1,j}); the
  * estimate is checked after every Arnoldi step; the true residual
  * b - A x decides convergence at each restart.  `left` runs Algorithm 1

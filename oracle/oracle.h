@@ -87,7 +87,7 @@ typedef struct {
     double rtol, atol;
     int    flexible;     /* FGMRES: store Z = M^-1 V */
     int    left;         /* Algorithm 1 as printed: left preconditioning */
-    int    check_at_cycle_end; /* Algorithm 1 line 15 literally */
+    int    check_at_cycle_end; /* Algorithm 1 literally: test only at cycle end */
     int    fixed_iters;  /* run exactly maxit iterations, ignore tolerance */
 } or_krylov_opts;
 

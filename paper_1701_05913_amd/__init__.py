@@ -30,6 +30,7 @@ KRY_GMRES, KRY_FGMRES, KRY_BICGSTAB = 0, 1, 2
 KRY_PC_NONE, KRY_PC_ILU0, KRY_PC_BILU0, KRY_PC_CPR, KRY_PC_CUSTOM = 0, 1, 1, 2, 3
 KRY_PREC_F64, KRY_PREC_F32, KRY_PREC_BF16_FACTORS = 0, 1, 2
 KRY_CPR_PF, KRY_CPR_FP = 0, 1
+KRY_SWEEP_AUTO, KRY_SWEEP_LEVELS, KRY_SWEEP_GRID = 0, 1, 2
 
 
 class KrylovError(RuntimeError):
@@ -57,6 +58,7 @@ _SIGS = {
     "MatCreateBSR": (P, [P, I32, I32, P, P, P, C.c_int]),
     "MatDestroy": (None, [C.POINTER(P)]), "MatVecMXY": (C.c_int, [P, P, P]),
     "MatVecAMXPBY": (C.c_int, [D, P, P, D, P]), "MatGetNnzBlocks": (I64, [P]),
+    "MatGetGrid": (C.c_int, [P, C.POINTER(I32), C.POINTER(I32), C.POINTER(I32)]),
     "SolverCreate": (P, [C.c_int, C.c_int, P]),
     "SolverDestroy": (C.c_int, [C.POINTER(P)]),
     "SolverSetMat": (C.c_int, [P, P]), "SolverAssemble": (C.c_int, [P]),
@@ -69,6 +71,7 @@ _SIGS = {
     "SolverSetRestart": (C.c_int, [P, I64]), "SolverSetAugk": (C.c_int, [P, I64]),
     "SolverSetPrecision": (C.c_int, [P, C.c_int]),
     "SolverSetCPR": (C.c_int, [P, C.c_int, C.c_int]),
+    "SolverSetSweepLayout": (C.c_int, [P, C.c_int]),
     "SolverSetStream": (C.c_int, [P, P]),
     "SolverGetResidual": (D, [P]), "SolverGetIters": (C.c_int, [P]),
     "SolverGetTimes": (C.c_int, [P, C.POINTER(D), C.POINTER(D)]),
@@ -229,6 +232,13 @@ def MatGetNnzBlocks(a):
     return _lib.MatGetNnzBlocks(a)
 
 
+def MatGetGrid(a):
+    """(nx, ny, nz) of the recognised 7-point grid, or None."""
+    nx, ny, nz = C.c_int32(0), C.c_int32(0), C.c_int32(0)
+    rc = _lib.MatGetGrid(a, C.byref(nx), C.byref(ny), C.byref(nz))
+    return (nx.value, ny.value, nz.value) if rc == 0 else None
+
+
 # ---- SOLVER --------------------------------------------------------------
 def SolverCreate(solver_type, pc_type, m):
     return _handle(_lib.SolverCreate(solver_type, pc_type, m), "SolverCreate")
@@ -269,6 +279,7 @@ def SolverSetRestart(s, m): return _check(_lib.SolverSetRestart(s, m))
 def SolverSetAugk(s, k): return _check(_lib.SolverSetAugk(s, k))
 def SolverSetPrecision(s, p): return _check(_lib.SolverSetPrecision(s, p))
 def SolverSetCPR(s, variant, p_sweeps): return _check(_lib.SolverSetCPR(s, variant, p_sweeps))
+def SolverSetSweepLayout(s, layout): return _check(_lib.SolverSetSweepLayout(s, layout))
 
 
 def SolverSetStream(s, stream):

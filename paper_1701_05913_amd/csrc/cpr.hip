@@ -98,7 +98,8 @@ __global__ void k_cast(int64_t n, const double *__restrict__ x, T *__restrict__ 
         y[i] = static_cast<T>(x[i]);
 }
 
-int cpr_setup(hipStream_t s, MAT_ *A, CprPC &C, int variant, int sweeps, int prec, int *d_err) {
+int cpr_setup(hipStream_t s, MAT_ *A, CprPC &C, int variant, int sweeps, int prec, int *d_err,
+              int layout) {
     if (A->bs != 3) return set_error(KRY_ERR_UNSUPPORTED, "CPR needs 3x3 blocks");
     if (sweeps < 1) return set_error(KRY_ERR_ARG, "CPR needs at least one pressure sweep");
     const int nb = A->nb;
@@ -118,6 +119,9 @@ int cpr_setup(hipStream_t s, MAT_ *A, CprPC &C, int variant, int sweeps, int pre
     P.h_rowptr = A->h_rowptr;
     P.h_col = A->h_col;
     P.h_diag = A->h_diag;
+    P.gnx = A->gnx;
+    P.gny = A->gny;
+    P.gnz = A->gnz;
     KRY_TRY(P.rowptr.alloc(nb + 1));
     KRY_TRY(P.col.alloc(A->nnzb));
     KRY_TRY(P.diag.alloc(nb));
@@ -130,8 +134,8 @@ int cpr_setup(hipStream_t s, MAT_ *A, CprPC &C, int variant, int sweeps, int pre
     KRY_TRY(sell_build(s, &P));
     // factors: the pressure factor is FP32 whenever the apply is reduced
     const int pprec = prec == KRY_PREC_F64 ? KRY_PREC_F64 : KRY_PREC_F32;
-    KRY_TRY(ilu_setup(s, &P, P.val.p, C.ilu_p, pprec, d_err));
-    KRY_TRY(ilu_setup(s, A, A->val.p, C.ilu_a, prec, d_err));
+    KRY_TRY(ilu_setup(s, &P, P.val.p, C.ilu_p, pprec, d_err, layout));
+    KRY_TRY(ilu_setup(s, A, A->val.p, C.ilu_a, prec, d_err, layout));
     if (prec != KRY_PREC_F64) {
         KRY_TRY(ensure_sell_f32(s, P.sell));
         if (variant == KRY_CPR_PF) KRY_TRY(ensure_col0_f32(s, A));

@@ -131,4 +131,83 @@ __device__ __forceinline__ bool wait_values(const T *p, T *out, int *err) {
     }
 }
 
+// Wait for up to N cells at once: cell d (valid when cells[d] >= 0) holds
+// BS values at base + cells[d] * BS.  All polls of a round are in flight
+// together (one memory round trip per round).
+template <typename T, int BS, int N>
+__device__ __forceinline__ void wait_cells(const T *base, const int64_t (&cells)[N],
+                                           T (&out)[N][BS], int *err) {
+    using U = typename Bits<T>::U;
+    U *q = const_cast<U *>(reinterpret_cast<const U *>(base));
+    for (uint32_t it = 0;; ++it) {
+        bool ready = true;
+#pragma unroll
+        for (int d = 0; d < N; d++) {
+#pragma unroll
+            for (int r = 0; r < BS; r++) {
+                if (cells[d] >= 0) {
+                    const U u = __hip_atomic_load(q + cells[d] * BS + r, __ATOMIC_RELAXED,
+                                                  __HIP_MEMORY_SCOPE_AGENT);
+                    out[d][r] = Bits<T>::from(u);
+                    ready = ready && (u != Bits<T>::sentinel);
+                } else {
+                    out[d][r] = T(0);
+                }
+            }
+        }
+        if (ready) return;
+        if ((it & 63u) == 63u) {
+            const int e = __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (e != 0 || it > SPIN_LIMIT) {
+                if (e == 0) __hip_atomic_store(err, ERR_STALL_FLAG, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+#pragma unroll
+                for (int d = 0; d < N; d++)
+#pragma unroll
+                    for (int r = 0; r < BS; r++) out[d][r] = Bits<T>::from(Bits<T>::qnan);
+                return;
+            }
+        }
+        __builtin_amdgcn_s_sleep(1);
+    }
+}
+
+// Synchronisation between the wavefronts of one workgroup through LDS.
+// The fences are restricted to the LDS address space, so they wait only for
+// LDS operations (lgkmcnt) and never for outstanding global stores.
+__device__ __forceinline__ void lds_release() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+}
+__device__ __forceinline__ void lds_acquire() {
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+__device__ __forceinline__ int lds_get(int *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+__device__ __forceinline__ void lds_put(int *p, int v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+// Every wait below is on a wavefront of the same workgroup that itself only
+// waits on earlier steps, so it ends; the bound turns a broken protocol
+// into an error flag instead of a hang.
+__device__ __forceinline__ void lds_wait_eq(int *p, int v, int *err) {
+    for (uint32_t it = 0; lds_get(p) != v; ++it) {
+        if (it > 4 * SPIN_LIMIT) {
+            __hip_atomic_store(err, ERR_STALL_FLAG, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            break;
+        }
+        __builtin_amdgcn_s_sleep(1);
+    }
+    lds_acquire();
+}
+__device__ __forceinline__ void lds_wait_ge(int *p, int v, int *err) {
+    for (uint32_t it = 0; lds_get(p) < v; ++it) {
+        if (it > 4 * SPIN_LIMIT) {
+            __hip_atomic_store(err, ERR_STALL_FLAG, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            break;
+        }
+        __builtin_amdgcn_s_sleep(1);
+    }
+    lds_acquire();
+}
+
 }  // namespace kry

@@ -423,7 +423,7 @@ static int sweep_waves_cap() {
     return cap;
 }
 
-static int upload_layout(hipStream_t s, const LevelSlices &L, Sell &S, int bs) {
+static int upload_layout(hipStream_t s, const LevelSlices &L, Sell &S, int bs, bool storage) {
     S.bs = bs;
     S.nslices = L.nslices;
     S.maxw = L.maxw;
@@ -431,8 +431,10 @@ static int upload_layout(hipStream_t s, const LevelSlices &L, Sell &S, int bs) {
     S.nslots = L.off[L.nslices];
     KRY_TRY(S.off.alloc(L.nslices + 1));
     KRY_TRY(S.perm.alloc((size_t)L.nslices * 64));
-    KRY_TRY(S.col.alloc(std::max<int64_t>(1, S.nslots) * 64));
-    KRY_TRY(S.val.alloc(std::max<int64_t>(1, S.nslots) * 64 * bs * bs));
+    if (storage) {
+        KRY_TRY(S.col.alloc(std::max<int64_t>(1, S.nslots) * 64));
+        KRY_TRY(S.val.alloc(std::max<int64_t>(1, S.nslots) * 64 * bs * bs));
+    }
     KRY_HIP(hipMemcpyAsync(S.off.p, L.off.data(), sizeof(int) * (L.nslices + 1),
                            hipMemcpyHostToDevice, s));
     KRY_HIP(hipMemcpyAsync(S.perm.p, L.perm.data(), sizeof(int) * L.perm.size(),
@@ -441,7 +443,7 @@ static int upload_layout(hipStream_t s, const LevelSlices &L, Sell &S, int bs) {
 }
 
 int ilu_setup(hipStream_t s, const MAT_ *A, const double *d_val, IluFactor &F, int prec,
-              int *d_err) {
+              int *d_err, int layout) {
     const int nb = A->nb, bs = A->bs, b2 = bs * bs;
     const std::vector<int> &rp = A->h_rowptr, &ci = A->h_col, &dg = A->h_diag;
     F.bs = bs;
@@ -474,9 +476,12 @@ int ilu_setup(hipStream_t s, const MAT_ *A, const double *d_val, IluFactor &F, i
         for (int p = dg[i] + 1; p < rp[i + 1]; p++) f(ci[p]);
     });
     if (!okf || !okb) return set_error(KRY_ERR_ARG, "ILU: inconsistent level schedule");
+    if (layout == KRY_SWEEP_GRID && A->gnx == 0)
+        return set_error(KRY_ERR_ARG, "grid sweep layout requested for a matrix that is not a 7-point grid stencil");
+    const bool use_grid = layout == KRY_SWEEP_GRID || (layout == KRY_SWEEP_AUTO && A->gnx > 0);
 
-    KRY_TRY(upload_layout(s, LF, F.L, bs));
-    KRY_TRY(upload_layout(s, LB, F.U, bs));
+    KRY_TRY(upload_layout(s, LF, F.L, bs, !use_grid));
+    if (!use_grid) KRY_TRY(upload_layout(s, LB, F.U, bs, true));
 
     // numeric factorization on a working copy of the values
     DBuf<double> lu, uinv;
@@ -496,6 +501,9 @@ int ilu_setup(hipStream_t s, const MAT_ *A, const double *d_val, IluFactor &F, i
     }
     KRY_HIP(hipGetLastError());
 
+    if (use_grid) {
+        KRY_TRY(ilu_grid_setup(s, A, lu.p, uinv.p, F));
+    } else {
     // pack L and U (+ diagonal inverses) in level order
     KRY_TRY(F.dinv.alloc((size_t)F.U.nslices * 64 * b2));
     {
@@ -542,6 +550,7 @@ int ilu_setup(hipStream_t s, const MAT_ *A, const double *d_val, IluFactor &F, i
         F.U.val.release();
         F.dinv.release();
     }
+    }
     // sweep state: forward output all-unwritten, counters zero
     const int64_t n = (int64_t)nb * bs;
     if (prec == KRY_PREC_F64) {
@@ -563,16 +572,18 @@ int ilu_setup(hipStream_t s, const MAT_ *A, const double *d_val, IluFactor &F, i
 // ---------------------------------------------------------------------------
 // apply
 // ---------------------------------------------------------------------------
-// timer names: family, block size, factor storage precision
-template <int BS, typename TF>
-static const char *sweep_name(bool fwd) {
-    constexpr int tb = sizeof(TF);
-    if (BS == 3) {
-        if (fwd) return tb == 8 ? "ilu_fwd_bsr3_f64" : tb == 4 ? "ilu_fwd_bsr3_f32" : "ilu_fwd_bsr3_bf16";
-        return tb == 8 ? "ilu_bwd_bsr3_f64" : tb == 4 ? "ilu_bwd_bsr3_f32" : "ilu_bwd_bsr3_bf16";
-    }
-    if (fwd) return tb == 8 ? "ilu_fwd_csr_f64" : tb == 4 ? "ilu_fwd_csr_f32" : "ilu_fwd_csr_bf16";
-    return tb == 8 ? "ilu_bwd_csr_f64" : tb == 4 ? "ilu_bwd_csr_f32" : "ilu_bwd_csr_bf16";
+const char *sweep_timer_name(bool fwd, int bs, int factor_bytes, int add_mode) {
+    // [bs == 3][precision f64/f32/bf16][fwd, bwd, bwd+add1, bwd+add2]
+    static const char *const names[2][3][4] = {
+        {{"ilu_fwd_csr_f64", "ilu_bwd_csr_f64", "ilu_bwd_csr_f64_add", "ilu_bwd_csr_f64_inject"},
+         {"ilu_fwd_csr_f32", "ilu_bwd_csr_f32", "ilu_bwd_csr_f32_add", "ilu_bwd_csr_f32_inject"},
+         {"ilu_fwd_csr_bf16", "ilu_bwd_csr_bf16", "ilu_bwd_csr_bf16_add", "ilu_bwd_csr_bf16_inject"}},
+        {{"ilu_fwd_bsr3_f64", "ilu_bwd_bsr3_f64", "ilu_bwd_bsr3_f64_add", "ilu_bwd_bsr3_f64_inject"},
+         {"ilu_fwd_bsr3_f32", "ilu_bwd_bsr3_f32", "ilu_bwd_bsr3_f32_add", "ilu_bwd_bsr3_f32_inject"},
+         {"ilu_fwd_bsr3_bf16", "ilu_bwd_bsr3_bf16", "ilu_bwd_bsr3_bf16_add", "ilu_bwd_bsr3_bf16_inject"}},
+    };
+    const int p = factor_bytes == 8 ? 0 : factor_bytes == 4 ? 1 : 2;
+    return names[bs == 3][p][fwd ? 0 : 1 + add_mode];
 }
 
 template <int BS, typename TF, typename TD, typename TC, typename TIN, typename TO, int ADD,
@@ -581,13 +592,13 @@ static int sweep_pair(hipStream_t s, IluFactor &F, const TF *lval, const TF *uva
                       TC *y, const TIN *b, TO *xo, const TAI *add_in, TAO *add_out, int *err) {
     const dim3 grid((F.grid_waves + 3) / 4), block(256);
     {
-        TimedScope t(sweep_name<BS, TF>(true), s);
+        TimedScope t(sweep_timer_name(true, BS, sizeof(TF), ADD), s);
         hipLaunchKernelGGL((k_ilu_fwd<BS, TF, TC, TIN, TO>), grid, block, 0, s, F.L.nslices,
                            F.L.perm.p, F.L.off.p, F.L.col.p, lval, b, y, xo, F.ctr.p,
                            F.ctr.p + 1, err);
     }
     {
-        TimedScope t(sweep_name<BS, TF>(false), s);
+        TimedScope t(sweep_timer_name(false, BS, sizeof(TF), ADD), s);
         hipLaunchKernelGGL((k_ilu_bwd<BS, TF, TD, TC, TO, ADD, TAI, TAO>), grid, block, 0, s,
                            F.U.nslices, F.U.perm.p, F.U.off.p, F.U.col.p, uval, dinv, y, xo,
                            add_in, add_out, F.ctr.p + 1, F.ctr.p, err);
@@ -653,6 +664,8 @@ static int apply_bs(hipStream_t s, IluFactor &F, const void *b, int in_type, voi
 int ilu_apply(hipStream_t s, IluFactor &F, const void *b, int in_type, void *xscr, int out_type,
               int add_mode, const void *add_in, void *add_out, int *d_err) {
     if (F.nb == 0) return set_error(KRY_ERR_ARG, "ILU apply before setup");
+    if (F.grid)
+        return ilu_grid_apply(s, F, b, in_type, xscr, out_type, add_mode, add_in, add_out, d_err);
     if (F.bs == 1) return apply_bs<1>(s, F, b, in_type, xscr, out_type, add_mode, add_in, add_out, d_err);
     return apply_bs<3>(s, F, b, in_type, xscr, out_type, add_mode, add_in, add_out, d_err);
 }

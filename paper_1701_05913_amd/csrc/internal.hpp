@@ -112,6 +112,7 @@ struct MAT_ {
     kry::DBuf<double> val;                      // block CSR values (FP64)
     kry::Sell sell;                             // natural-order SpMV layout
     kry::DBuf<float> col0f;                     // FP32 column-0 planes (bs=3)
+    int gnx = 0, gny = 0, gnz = 0;              // 7-point grid of the pattern (0: none)
 };
 
 namespace kry {
@@ -193,6 +194,15 @@ int ensure_col0_f32(hipStream_t s, MAT_ *A);
 // ---------------------------------------------------------------------------
 // ILU(0) / block ILU(0) factor in level-scheduled layout (ilu.hip)
 // ---------------------------------------------------------------------------
+// 7-point grid tiling: a tile is TJ x TK x-lines (one lane each) of a
+// wavefront; S = nx + TJ + TK - 2 hyperplane steps per tile; order[t] =
+// J | (K << 16) lists tiles by increasing J + K.
+struct GridTiles {
+    int nx = 0, ny = 0, nz = 0;
+    int TJ = 0, TK = 0, NJ = 0, NK = 0, ntiles = 0, S = 0;
+    const int *order = nullptr;
+};
+
 struct IluFactor {
     int bs = 1, nb = 0;
     int prec = KRY_PREC_F64;
@@ -205,11 +215,30 @@ struct IluFactor {
     DBuf<float> y32;
     DBuf<int> ctr;          // [0] forward, [1] backward slice counters
     int grid_waves = 0;     // waves launched per sweep
+    // grid-tiled sweeps (7-point stencils in natural order)
+    bool grid = false;
+    GridTiles G;
+    DBuf<int> order;
+    DBuf<double> lt64, ut64, dt64;
+    DBuf<float> lt32, ut32, dt32;
+    DBuf<uint16_t> lt16, ut16;
 };
 
-// factor A (FP64), pack for prec; err = device int flag
+// timer name of one sweep kernel: direction, block size, factor storage
+// bytes (8, 4, 2) and fused epilogue (add_mode of ilu_apply); each
+// distinct kernel instantiation family gets its own name
+const char *sweep_timer_name(bool fwd, int bs, int factor_bytes, int add_mode);
+
+// grid-tiled layout and sweeps (ilu_grid.hip)
+int ilu_grid_setup(hipStream_t s, const MAT_ *A, const double *lu, const double *uinv,
+                   IluFactor &F);
+int ilu_grid_apply(hipStream_t s, IluFactor &F, const void *b, int in_type, void *xscr,
+                   int out_type, int add_mode, const void *add_in, void *add_out, int *d_err);
+
+// factor A (FP64), pack for prec; err = device int flag; layout one of
+// KRY_SWEEP_AUTO / KRY_SWEEP_LEVELS / KRY_SWEEP_GRID
 int ilu_setup(hipStream_t s, const MAT_ *A, const double *d_val, IluFactor &F,
-              int prec, int *d_err);
+              int prec, int *d_err, int layout = KRY_SWEEP_AUTO);
 // x = (LU)^-1 b.  in/out element types: 0 = double, 1 = float.
 // add_mode 0: out = x; 1: add_out = add_in + x (full vector, out type);
 // 2: add_out[i*bs + r] = (r == 0 ? add_in[i] : 0) + x (pressure injection)
@@ -232,7 +261,7 @@ struct CprPC {
     DBuf<char> work;        // scratch vectors
 };
 int cpr_setup(hipStream_t s, MAT_ *A, CprPC &C, int variant, int sweeps,
-              int prec, int *d_err);
+              int prec, int *d_err, int layout);
 int cpr_apply(hipStream_t s, MAT_ *A, CprPC &C, const double *v, double *z,
               int *d_err);
 
@@ -250,6 +279,7 @@ struct SOLVER_ {
     int restart = 30;
     int prec = KRY_PREC_F64;
     int cpr_variant = KRY_CPR_PF, cpr_sweeps = 4;
+    int sweep_layout = KRY_SWEEP_AUTO;
     hipStream_t stream = nullptr;
     PC_SETUP csetup = nullptr;
     PC_SOLVE csolve = nullptr;

@@ -7,7 +7,7 @@
 // precision, learned stage).  BiCGSTAB is van der Vorst's method, which the
 // paper names without printing.
 //
-// gfx950 design: the Gram-Schmidt of Algorithm 1 lines 7-10 (modified,
+// gfx950 design: the Gram-Schmidt of Algorithm 1's Arnoldi step (modified,
 // j dependent dot products per step) becomes classical Gram-Schmidt with
 // one reorthogonalization (CGS2): two passes of h = V^T w, w -= V h, each a
 // tall-skinny GEMV that streams V once.  All scalars (Hessenberg column,
@@ -709,6 +709,14 @@ extern "C" int SolverSetCPR(SOLVER *s, int variant, int p_sweeps) {
     s->assembled = false;
     return KRY_OK;
 }
+extern "C" int SolverSetSweepLayout(SOLVER *s, int layout) {
+    if (!s || layout < KRY_SWEEP_AUTO || layout > KRY_SWEEP_GRID)
+        return set_error(KRY_ERR_ARG, "SolverSetSweepLayout: bad argument");
+    s->sweep_layout = layout;
+    s->assembled = false;
+    return KRY_OK;
+}
+
 extern "C" int SolverSetStream(SOLVER *s, void *stream) {
     if (!s) return set_error(KRY_ERR_ARG, "SolverSetStream: NULL solver");
     s->stream = static_cast<hipStream_t>(stream);
@@ -741,11 +749,12 @@ extern "C" int SolverAssemble(SOLVER *s) {
         break;
     case KRY_PC_ILU0:
         s->ilu.reset(new IluFactor());
-        KRY_TRY(ilu_setup(s->stream, s->A, s->A->val.p, *s->ilu, s->prec, s->err.p));
+        KRY_TRY(ilu_setup(s->stream, s->A, s->A->val.p, *s->ilu, s->prec, s->err.p, s->sweep_layout));
         break;
     case KRY_PC_CPR:
         s->cpr.reset(new CprPC());
-        KRY_TRY(cpr_setup(s->stream, s->A, *s->cpr, s->cpr_variant, s->cpr_sweeps, s->prec, s->err.p));
+        KRY_TRY(cpr_setup(s->stream, s->A, *s->cpr, s->cpr_variant, s->cpr_sweeps, s->prec, s->err.p,
+                          s->sweep_layout));
         break;
     case KRY_PC_CUSTOM:
         if (!s->csolve) return set_error(KRY_ERR_ARG, "custom preconditioner not set");

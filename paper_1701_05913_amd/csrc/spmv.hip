@@ -281,6 +281,40 @@ static int validate_pattern(int nb, const std::vector<int> &rp, const std::vecto
     return KRY_OK;
 }
 
+// Recognise a 7-point stencil on an nx x ny x nz grid in natural order
+// (nx, ny, nz >= 2): row 0 gives nx and nx*ny, then every row must hold
+// exactly its existing neighbours.
+static void detect_grid(MAT_ *A) {
+    A->gnx = A->gny = A->gnz = 0;
+    const int nb = A->nb;
+    const std::vector<int> &rp = A->h_rowptr, &ci = A->h_col;
+    if (rp[1] - rp[0] != 4 || ci[0] != 0 || ci[1] != 1) return;
+    const int64_t nx = ci[2], nxy = ci[3];
+    if (nx < 2 || nxy % nx != 0) return;
+    const int64_t ny = nxy / nx;
+    if (ny < 2 || nb % nxy != 0) return;
+    const int64_t nz = nb / nxy;
+    if (nz < 2) return;
+    for (int64_t c = 0; c < nb; c++) {
+        const int64_t i = c % nx, j = (c / nx) % ny, k = c / nxy;
+        int64_t want[7];
+        int m = 0;
+        if (k > 0) want[m++] = c - nxy;
+        if (j > 0) want[m++] = c - nx;
+        if (i > 0) want[m++] = c - 1;
+        want[m++] = c;
+        if (i < nx - 1) want[m++] = c + 1;
+        if (j < ny - 1) want[m++] = c + nx;
+        if (k < nz - 1) want[m++] = c + nxy;
+        if (rp[c + 1] - rp[c] != m) return;
+        for (int q = 0; q < m; q++)
+            if (ci[rp[c] + q] != want[q]) return;
+    }
+    A->gnx = static_cast<int>(nx);
+    A->gny = static_cast<int>(ny);
+    A->gnz = static_cast<int>(nz);
+}
+
 static MAT *mat_create(MAP *map, int32_t nb, int32_t bs, const int32_t *rowptr,
                        const int32_t *col, const double *val, int where) {
     if (!map || !rowptr || !col || !val) {
@@ -323,6 +357,7 @@ static MAT *mat_create(MAP *map, int32_t nb, int32_t bs, const int32_t *rowptr,
         return nullptr;
     }
     if (validate_pattern(nb, A->h_rowptr, A->h_col, A->h_diag) != KRY_OK) return nullptr;
+    detect_grid(A.get());
     const int b2 = bs * bs;
     if (A->rowptr.alloc(nb + 1) || A->col.alloc(nnzb) || A->diag.alloc(nb) ||
         A->val.alloc(nnzb * b2))
@@ -364,6 +399,14 @@ extern "C" void MatDestroy(MAT **mat) {
 }
 
 extern "C" int64_t MatGetNnzBlocks(const MAT *A) { return A ? A->nnzb : -1; }
+
+extern "C" int MatGetGrid(const MAT *A, int32_t *nx, int32_t *ny, int32_t *nz) {
+    if (!A) return set_error(KRY_ERR_ARG, "MatGetGrid: NULL matrix");
+    if (nx) *nx = A->gnx;
+    if (ny) *ny = A->gny;
+    if (nz) *nz = A->gnz;
+    return A->gnx > 0 ? KRY_OK : set_error(KRY_ERR_ARG, "MatGetGrid: not a 7-point grid stencil");
+}
 
 extern "C" int MatVecMXY(MAT *A, VEC *x, VEC *y) {
     if (!A || !x || !y) return set_error(KRY_ERR_ARG, "MatVecMXY: NULL argument");

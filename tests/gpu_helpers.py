@@ -43,8 +43,9 @@ class GpuSystem:
 
 
 def make_solver(g, solver, pc, rtol=1e-8, maxit=5000, restart=30,
-                prec=K.KRY_PREC_F64, cpr=(K.KRY_CPR_PF, 4)):
+                prec=K.KRY_PREC_F64, cpr=(K.KRY_CPR_PF, 4), layout=K.KRY_SWEEP_AUTO):
     S = K.SolverCreate(solver, pc, g.map)
+    K.SolverSetSweepLayout(S, layout)
     K.SolverSetMat(S, g.A)
     K.SolverSetRtol(S, rtol)
     K.SolverSetMaxit(S, maxit)
@@ -71,15 +72,19 @@ def solve(g, solver, pc, b=None, x0=None, **kw):
         K.SolverDestroy(S)
 
 
-def pc_apply(g, pc, v, prec=K.KRY_PREC_F64, cpr=(K.KRY_CPR_PF, 4), solver=K.KRY_FGMRES):
-    S = make_solver(g, solver, pc, prec=prec, cpr=cpr)
+def pc_apply(g, pc, v, prec=K.KRY_PREC_F64, cpr=(K.KRY_CPR_PF, 4), solver=K.KRY_FGMRES,
+             layout=K.KRY_SWEEP_AUTO, repeat=1):
+    S = make_solver(g, solver, pc, prec=prec, cpr=cpr, layout=layout)
     try:
         K.SolverAssemble(S)
         vt, vh = g.vec(v)
         zt, zh = g.vec()
-        K.SolverPCApply(S, vh, zh)
-        torch.cuda.synchronize()
-        return zt.cpu().numpy()
+        outs = []
+        for _ in range(repeat):
+            K.SolverPCApply(S, vh, zh)
+            torch.cuda.synchronize()
+            outs.append(zt.cpu().numpy())
+        return outs[0] if repeat == 1 else outs
     finally:
         K.SolverDestroy(S)
 

@@ -100,26 +100,56 @@ def test_vector_kernels():
 
 
 # ---- ILU(0) / block ILU(0) apply --------------------------------------------
+LAYOUTS = [pytest.param(K.KRY_SWEEP_LEVELS, id="levels"), pytest.param(K.KRY_SWEEP_GRID, id="gridtiles")]
+
+
+def test_grid_detection():
+    for grid, want in [((13, 11, 9), (13, 11, 9)), ((40, 1, 1), None), ((5, 2, 2), (5, 2, 2))]:
+        s = ri.blackoil_system(*grid, seed=1)
+        g = GpuSystem(s)
+        try:
+            assert K.MatGetGrid(g.A) == want
+        finally:
+            g.close()
+
+
+@pytest.mark.parametrize("layout", LAYOUTS)
 @pytest.mark.parametrize("kind,grid", [("scalar", SMALL_SCALAR), ("scalar", (32, 32, 32)),
                                        ("block", SMALL_BLOCK), ("block", (64, 64, 64)),
+                                       ("block", (20, 5, 3)), ("block", (9, 17, 2)),
                                        ("block", (40, 1, 1)), ("block", (1, 1, 1))])
-def test_ilu_apply_parity_fp64(kind, grid):
+def test_ilu_apply_parity_fp64(kind, grid, layout):
     s = _sys(kind, grid, seed=2)
+    if layout == K.KRY_SWEEP_GRID and min(grid) < 2:
+        pytest.skip("not a 3D grid stencil")
     A = oracle.Matrix.from_system(s)
     v = np.random.default_rng(6).standard_normal(A.n)
     ref = oracle.PC(A, "bilu0").apply(v)
     g = GpuSystem(s)
     try:
-        z = pc_apply(g, K.KRY_PC_ILU0, v)
+        z1, z2 = pc_apply(g, K.KRY_PC_ILU0, v, layout=layout, repeat=2)
     finally:
         g.close()
-    assert relerr(z, ref) <= 1e-10
+    assert relerr(z1, ref) <= 1e-10
+    # the sweep state re-arms itself: a second apply is bitwise identical
+    assert np.array_equal(z1, z2)
 
 
+def test_grid_layout_requires_grid_stencil():
+    s = ri.blackoil_system(40, 1, 1, seed=2)
+    g = GpuSystem(s)
+    try:
+        with pytest.raises(K.KrylovError):
+            pc_apply(g, K.KRY_PC_ILU0, np.ones(g.n), layout=K.KRY_SWEEP_GRID)
+    finally:
+        g.close()
+
+
+@pytest.mark.parametrize("layout", LAYOUTS)
 @pytest.mark.parametrize("prec,tol", [(K.KRY_PREC_F32, 1e-5), (K.KRY_PREC_BF16_FACTORS, 1e-4)])
 @pytest.mark.parametrize("kind,grid", [("scalar", SMALL_SCALAR), ("block", SMALL_BLOCK),
                                        ("block", (64, 64, 64))])
-def test_ilu_apply_parity_reduced(kind, grid, prec, tol):
+def test_ilu_apply_parity_reduced(kind, grid, prec, tol, layout):
     s = _sys(kind, grid, seed=3)
     A = oracle.Matrix.from_system(s)
     v = np.random.default_rng(7).standard_normal(A.n)
@@ -128,7 +158,7 @@ def test_ilu_apply_parity_reduced(kind, grid, prec, tol):
     ref64 = oracle.PC(A, "bilu0").apply(v)
     g = GpuSystem(s)
     try:
-        z = pc_apply(g, K.KRY_PC_ILU0, v, prec=prec)
+        z = pc_apply(g, K.KRY_PC_ILU0, v, prec=prec, layout=layout)
     finally:
         g.close()
     # against the oracle's emulation of the same rounding
@@ -138,11 +168,12 @@ def test_ilu_apply_parity_reduced(kind, grid, prec, tol):
 
 
 # ---- CPR two-stage -----------------------------------------------------------------
+@pytest.mark.parametrize("layout", LAYOUTS)
 @pytest.mark.parametrize("variant", [K.KRY_CPR_PF, K.KRY_CPR_FP])
 @pytest.mark.parametrize("prec,tol", [(K.KRY_PREC_F64, 1e-10), (K.KRY_PREC_F32, 1e-5),
                                       (K.KRY_PREC_BF16_FACTORS, 1e-4)])
 @pytest.mark.parametrize("grid", [SMALL_BLOCK, (32, 32, 16)])
-def test_cpr_apply_parity(grid, variant, prec, tol):
+def test_cpr_apply_parity(grid, variant, prec, tol, layout):
     s = ri.blackoil_system(*grid, seed=4)
     A = oracle.Matrix.from_system(s)
     v = np.random.default_rng(8).standard_normal(A.n)
@@ -151,19 +182,19 @@ def test_cpr_apply_parity(grid, variant, prec, tol):
     ref = oracle.PC(A, kind, name, p_sweeps=4).apply(v)
     g = GpuSystem(s)
     try:
-        z = pc_apply(g, K.KRY_PC_CPR, v, prec=prec, cpr=(variant, 4))
+        z = pc_apply(g, K.KRY_PC_CPR, v, prec=prec, cpr=(variant, 4), layout=layout)
     finally:
         g.close()
     assert relerr(z, ref) <= tol
 
 
 # ---- solves ------------------------------------------------------------------
-def _bicgstab_envelope(A, pc, b, rtol, maxit, nperturb=4):
+def _bicgstab_envelope(A, pc, b, rtol, maxit, nperturb=8):
     """BiCGSTAB has no minimization property: one-ulp changes of b move its
     iteration count and iterate far more than the reduction order of a GPU
     does to GMRES.  The oracle's own spread under such perturbations is the
     parity envelope (iterations range, largest x deviation)."""
-    base = oracle.bicgstab(A, pc, b, rtol=rtol, maxit=maxit)
+    base = oracle.bicgstab(A, pc, b, rtol=rtol, maxit=maxit, hist=True)
     its, dev = [base["iters"]], [0.0]
     rng = np.random.default_rng(12345)
     for _ in range(nperturb):
@@ -179,6 +210,9 @@ def _check_bicgstab(s, gpu, A, pc, rtol, maxit):
     r = s["b"] - oracle.spmv(A, gpu["x"])
     assert np.linalg.norm(r) <= rtol * np.linalg.norm(s["b"]) * (1 + 1e-9)
     base, lo, hi, dev = _bicgstab_envelope(A, pc, s["b"], rtol, maxit)
+    # before rounding differences grow, the recurrences agree step by step
+    k = min(10, len(base["hist"]), len(gpu["hist"]))
+    assert relerr(gpu["hist"][:k], base["hist"][:k]) <= 1e-6
     assert 0.9 * lo - 1 <= gpu["iters"] <= 1.1 * hi + 1, (gpu["iters"], lo, hi)
     assert relerr(gpu["x"], base["x"]) <= max(1e-6, 2.0 * dev), (relerr(gpu["x"], base["x"]), dev)
 
