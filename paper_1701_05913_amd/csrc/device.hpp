@@ -210,4 +210,19 @@ __device__ __forceinline__ void lds_wait_ge(int *p, int v, int *err) {
     lds_acquire();
 }
 
+// wait for *p == v and, when w >= 0, *q == w: both flags in one poll
+__device__ __forceinline__ void lds_wait_pair(int *p, int v, int *q, int w, int *err) {
+    for (uint32_t it = 0;; ++it) {
+        const int a = lds_get(p);
+        const int b = w >= 0 ? lds_get(q) : w;
+        if (a == v && b == w) break;
+        if (it > 4 * SPIN_LIMIT) {
+            __hip_atomic_store(err, ERR_STALL_FLAG, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            break;
+        }
+        __builtin_amdgcn_s_sleep(1);
+    }
+    lds_acquire();
+}
+
 }  // namespace kry

@@ -9,22 +9,32 @@
 // processes i = t - jj - kk, so
 //   * (i-1) is the lane's own result of the previous step (a register),
 //   * (j-1) and (k-1) are the results of lanes jj-1 and kk-1 of the
-//     previous step (cross-lane shuffles),
-//   * only lanes on the tile's low faces read values of neighbouring
-//     tiles from memory, GC cells at a time, polling the same
-//     self-validating slots as the generic sweep.
+//     previous step (cross-lane moves),
+//   * only lanes on the tile's low faces need values of neighbouring
+//     tiles, which those tiles publish into small per-step face buffers.
 // A dependency chain therefore crosses memory only when it crosses a tile
 // face: NJ + NK hops per sweep instead of nx + ny + nz levels.  Tiles are
-// handed to wavefronts in the order of J + K from an atomic counter, so a
+// handed to workgroups in the order of J + K from an atomic counter, so a
 // tile's producers are always running already (no deadlock).
 //
-// Factor layout: step-major per tile, entry-major planes of 64 lanes:
-// forward block b (0: k-1, 1: j-1, 2: i-1) entry e of lane l at step t of
-// tile T sits at Lt[(((T * S + t) * 3 + b) * bs^2 + e) * 64 + l];
-// backward blocks (0: i+1, 1: j+1, 2: k+1) likewise in Ut, indexed by the
-// backward step, and the diagonal-block inverse in Dt.  Missing
-// neighbours and idle lanes hold zeros, so every load is in bounds and
-// unconditional.
+// Layouts (all step-major per tile in 64-lane planes, so every wavefront
+// access of the sweeps is one contiguous row):
+//   factors  forward block b (0: k-1, 1: j-1, 2: i-1) entry e of lane l at
+//            step t of tile T at Lt[(((T * S + t) * 3 + b) * bs^2 + e) * 64 + l];
+//            backward blocks (0: i+1, 1: j+1, 2: k+1) likewise in Ut,
+//            indexed by the backward step, diagonal-block inverses in Dt;
+//   result   yt[((T * S + t) * bs + r) * 64 + l]: the forward result of
+//            the cell of lane l at forward step t; the backward sweep
+//            reads it and overwrites it with the backward result of the
+//            same cell (its step S - 1 - t), and a last kernel copies it
+//            to the caller's vector in natural order;
+//   faces    face entry f of step t of tile T at ((T * S + t) * NF + f) * bs:
+//            f < TK the j-face cell of lane kk = f, f = TK + q the k-face
+//            cell of lane jj = q.
+// Missing neighbours, idle lanes and steps outside the line hold zero
+// factors and zero right-hand sides.  Such lanes only ever see zeros, so
+// they compute exact zeros, and a real cell multiplies a zero block only
+// by an exact zero: the sweeps need no per-lane predication.
 #include <algorithm>
 #include <type_traits>
 
@@ -32,6 +42,11 @@
 #include "internal.hpp"
 
 namespace kry {
+
+constexpr int NLOAD = 4;       // factor loader wavefronts per workgroup
+constexpr int GWG = 64 * (2 + NLOAD);
+constexpr int NFACE = 40;      // >= TJ + TK for every tiling used
+constexpr int DB = 16;         // boundary ring depth (steps)
 
 // ---------------------------------------------------------------------------
 // setup
@@ -98,6 +113,13 @@ __global__ void k_grid_round_bf16(int64_t n, const double *__restrict__ x, uint1
         y[i] = f32_to_bf16_rne(static_cast<float>(x[i]));
 }
 
+template <typename T>
+__global__ void k_grid_fill_sentinel(int64_t n, T *__restrict__ y) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        y[i] = sentinel_value<T>();
+}
+
 int ilu_grid_setup(hipStream_t s, const MAT_ *A, const double *lu, const double *uinv,
                    IluFactor &F) {
     GridTiles &G = F.G;
@@ -105,25 +127,33 @@ int ilu_grid_setup(hipStream_t s, const MAT_ *A, const double *lu, const double 
     G.ny = A->gny;
     G.nz = A->gnz;
     G.TJ = std::min(8, G.ny);
-    G.TK = std::min(64 / G.TJ, G.nz);
+    G.TK = std::min(std::min(64 / G.TJ, G.nz), NFACE - G.TJ);
+    G.NF = G.TJ + G.TK;
     G.NJ = (G.ny + G.TJ - 1) / G.TJ;
     G.NK = (G.nz + G.TK - 1) / G.TK;
     G.ntiles = G.NJ * G.NK;
     G.S = G.nx + G.TJ + G.TK - 2;
     if (G.NJ > 0xffff || G.NK > 0x7fff) return set_error(KRY_ERR_UNSUPPORTED, "grid too large for tiling");
-    std::vector<int> ord;
+    std::vector<int> ord, tid(G.ntiles);
     ord.reserve(G.ntiles);
     for (int d = 0; d <= G.NJ + G.NK - 2; d++)
         for (int J = 0; J < G.NJ; J++) {
             const int K = d - J;
-            if (K >= 0 && K < G.NK) ord.push_back(J | (K << 16));
+            if (K >= 0 && K < G.NK) {
+                tid[J * G.NK + K] = static_cast<int>(ord.size());
+                ord.push_back(J | (K << 16));
+            }
         }
     KRY_TRY(F.order.alloc(G.ntiles));
+    KRY_TRY(F.tidx.alloc(G.ntiles));
     KRY_HIP(hipMemcpy(F.order.p, ord.data(), sizeof(int) * G.ntiles, hipMemcpyHostToDevice));
+    KRY_HIP(hipMemcpy(F.tidx.p, tid.data(), sizeof(int) * G.ntiles, hipMemcpyHostToDevice));
     G.order = F.order.p;
+    G.tidx = F.tidx.p;
     const int bs = A->bs, b2 = bs * bs;
     const int64_t steps = (int64_t)G.ntiles * G.S;
     const int64_t nlu = steps * 3 * b2 * 64, nd = steps * b2 * 64;
+    const int64_t nyt = steps * bs * 64, nf = steps * G.NF * bs;
     KRY_TRY(F.lt64.alloc(nlu));
     KRY_TRY(F.ut64.alloc(nlu));
     KRY_TRY(F.dt64.alloc(nd));
@@ -154,7 +184,20 @@ int ilu_grid_setup(hipStream_t s, const MAT_ *A, const double *lu, const double 
         F.lt64.release();
         F.ut64.release();
         F.dt64.release();
+        // result and face buffers in FP32; faces start out unwritten
+        KRY_TRY(F.yt32.alloc(nyt));
+        KRY_TRY(F.ff32.alloc(nf));
+        KRY_TRY(F.fb32.alloc(nf));
+        hipLaunchKernelGGL(k_grid_fill_sentinel<float>, dim3(1024), blk, 0, s, nf, F.ff32.p);
+        hipLaunchKernelGGL(k_grid_fill_sentinel<float>, dim3(1024), blk, 0, s, nf, F.fb32.p);
+    } else {
+        KRY_TRY(F.yt64.alloc(nyt));
+        KRY_TRY(F.ff64.alloc(nf));
+        KRY_TRY(F.fb64.alloc(nf));
+        hipLaunchKernelGGL(k_grid_fill_sentinel<double>, dim3(1024), blk, 0, s, nf, F.ff64.p);
+        hipLaunchKernelGGL(k_grid_fill_sentinel<double>, dim3(1024), blk, 0, s, nf, F.fb64.p);
     }
+    KRY_HIP(hipGetLastError());
     F.grid = true;
     return KRY_OK;
 }
@@ -162,23 +205,18 @@ int ilu_grid_setup(hipStream_t s, const MAT_ *A, const double *lu, const double 
 // ---------------------------------------------------------------------------
 // sweeps: one workgroup per tile, wavefront-specialised
 //   wave 0            compute: consumes one hyperplane step at a time from
-//                     LDS, exchanges neighbour values by shuffles,
-//                     publishes results; it issues no global loads, so it
-//                     never waits on memory latency
-//   wave 1            boundary: polls the published values of the two
-//                     upstream tiles (BR steps of 2 cells per lane per
-//                     round) and stages them in LDS
-//   waves 2..         factor loaders: stream each step's factor planes and
+//                     LDS, exchanges neighbour values across lanes, stores
+//                     the step's results (one contiguous row per component)
+//                     and publishes the face cells; it issues no loads
+//   wave 1            boundary: polls the face buffers of the two upstream
+//                     tiles and stages the values in LDS
+//   waves 2..         loaders: stream each step's factor planes and
 //                     right-hand side into an LDS ring, two steps in flight
-//                     per wavefront
+//                     per wavefront; when a tile is done they re-arm the
+//                     other sweep's face slots of that tile
 // Ring slots carry the step's stamp (a running step count of the
 // workgroup), so no slot is ever reset.
 // ---------------------------------------------------------------------------
-constexpr int NLOAD = 4;
-constexpr int GWG = 64 * (2 + NLOAD);
-constexpr int NFACE = 40;      // >= TJ + TK for every tiling used
-constexpr int DB = 16;         // boundary ring depth (steps)
-
 template <typename TC, typename TF>
 __device__ __forceinline__ TC gld(const TF *p) { return static_cast<TC>(*p); }
 template <>
@@ -200,90 +238,119 @@ __device__ __forceinline__ void block_sub(TC (&acc)[BS], const TC (&v)[NV], int 
         for (int c = 0; c < BS; c++) acc[r] -= v[b * BS * BS + r * BS + c] * y[c];
 }
 
-// Boundary role.  Face f < TK is the j-face cell of lane kk = f; face
-// TK + q the k-face cell of lane jj = q.  For step t the face cell is at
-// i = t - lag_f; `cb` is its line base (cell at i = 0) or -1 when the
-// upstream tile does not exist.  Each lane serves face f = lane % NF for
-// steps t0 + rr and t0 + rr + RS of a round of 2 RS steps.
-template <typename TV, typename TC, int BS>
-__device__ void boundary_role(int S, int nx, int base, int lane, int NF, const int64_t cb,
-                              int lag, const TV *src, TC (&bring)[DB][NFACE][BS], int *bfull,
-                              int *bcons, int *err) {
-    // a round of 2 RS steps must fit in half the ring, or it would wait
-    // for slots that only its own consumer can free
-    const int RS = (64 / NF) < (DB / 2) ? (64 / NF) : (DB / 2);
-    const int f = lane % NF, rr = lane / NF;
-    const bool lane_ok = rr < RS;
-    for (int t0 = 0; t0 < S; t0 += 2 * RS) {
-        int64_t cells[2];
-        int ts[2];
+// value held by the next lower lane (UP = false) or the next higher lane
+// (UP = true) of the wavefront, by whole-wave DPP shifts (no LDS traffic);
+// the lane at the end of the wave receives 0
+template <bool UP>
+__device__ __forceinline__ int lane_shift1(int v) {
+    return __builtin_amdgcn_update_dpp(0, v, UP ? 0x130 : 0x138, 0xF, 0xF, false);
+}
+template <bool UP>
+__device__ __forceinline__ float lane_shift1(float v) {
+    return __int_as_float(lane_shift1<UP>(__float_as_int(v)));
+}
+template <bool UP>
+__device__ __forceinline__ double lane_shift1(double v) {
+    const long long u = __double_as_longlong(v);
+    const int lo = lane_shift1<UP>(static_cast<int>(u & 0xffffffffll));
+    const int hi = lane_shift1<UP>(static_cast<int>(u >> 32));
+    return __longlong_as_double((static_cast<long long>(hi) << 32) |
+                                static_cast<unsigned int>(lo));
+}
+
+// Boundary role.  Lane f of the NF face lanes serves face entry f; `src`
+// points at that entry of the upstream tile at the step that produces the
+// value for this tile's step 0 (nullptr when the upstream tile or the
+// lane's line does not exist), consecutive steps are NF * BS values apart.
+// The face cell of step t lies at offset t - lag along the lane's line.
+//
+// The wave is cut into G = 64 / NF groups of NF lanes; group g stages
+// steps g, g + G, g + 2G, ... .  Every round polls each group's current
+// step once; a group whose NF cells are all published (and whose ring
+// slot has been consumed) stages them and moves on, the others poll again,
+// so a step is handed over one poll after its last cell appears.
+template <typename TC, int BS>
+__device__ void boundary_role(int S, int nx, int base, int lane, int NF, const TC *src, int lag,
+                              TC (&bring)[DB][NFACE][BS], int *bfull, int *bcons, int *err) {
+    using U = typename Bits<TC>::U;
+    const U *q = reinterpret_cast<const U *>(src);
+    const int G = (64 / NF) < DB ? (64 / NF) : DB;
+    const int f = lane % NF, g = lane / NF;
+    const bool lane_ok = g < G;
+    const uint64_t gmask = (NF >= 64 ? ~0ull : ((1ull << NF) - 1ull)) << (lane_ok ? g * NF : 0);
+    const int64_t stride = (int64_t)NF * BS;
+    int ts = g;
+    bool failed = false;
+    uint32_t idle = 0;
+    for (;;) {
+        const bool active = lane_ok && ts < S;
+        if (__ballot(active) == 0) break;
+        bool ready = active;
+        TC vals[BS];
 #pragma unroll
-        for (int m = 0; m < 2; m++) {
-            ts[m] = t0 + rr + m * RS;
-            const int i = ts[m] - lag;
-            cells[m] = (lane_ok && cb >= 0 && ts[m] < S && i >= 0 && i < nx) ? cb + i : -1;
+        for (int r = 0; r < BS; r++) vals[r] = TC(0);
+        if (active) {
+            const int off = ts - lag;
+            if (q != nullptr && off >= 0 && off < nx) {
+#pragma unroll
+                for (int r = 0; r < BS; r++) {
+                    const U u = failed ? Bits<TC>::qnan
+                                       : __hip_atomic_load(const_cast<U *>(q) + ts * stride + r,
+                                                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    vals[r] = Bits<TC>::from(u);
+                    ready = ready && u != Bits<TC>::sentinel;
+                }
+            }
+            // the slot of step ts held step ts - DB: it must have been read
+            ready = ready && lds_get(bcons) >= base + ts - DB + 1;
         }
-        TV vals[2][BS];
-        wait_cells<TV, BS, 2>(src, cells, vals, err);
-        // slots for steps t0 .. t0 + 2 RS - 1 must have been consumed
-        lds_wait_ge(bcons, base + t0 + 2 * RS - DB, err);
+        const bool go = active && (__ballot(ready) & gmask) == gmask;
+        lds_acquire();
+        if (go)
 #pragma unroll
-        for (int m = 0; m < 2; m++)
-            if (lane_ok && ts[m] < S)
-#pragma unroll
-                for (int r = 0; r < BS; r++) bring[ts[m] % DB][f][r] = static_cast<TC>(vals[m][r]);
+            for (int r = 0; r < BS; r++) bring[ts % DB][f][r] = vals[r];
         lds_release();
-#pragma unroll
-        for (int m = 0; m < 2; m++)
-            if (lane_ok && f == 0 && ts[m] < S) lds_put(&bfull[ts[m] % DB], base + ts[m]);
+        if (go && f == 0) lds_put(&bfull[ts % DB], base + ts);
+        if (go) ts += G;
+        if (__ballot(go) != 0) {
+            idle = 0;
+            continue;
+        }
+        // no group could stage this round
+        if ((++idle & 63u) == 0u && !failed) {
+            const int e = __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (e != 0 || idle > SPIN_LIMIT) {
+                if (e == 0 && lane == 0)
+                    __hip_atomic_store(err, ERR_STALL_FLAG, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                failed = true;   // stage NaNs from now on so the compute wave drains
+            }
+        }
+        __builtin_amdgcn_s_sleep(1);
     }
 }
 
-// as boundary_role for the backward sweep: step t reaches cell
-// i = nx - 1 - (t - lag), i.e. cbr - (t - lag) with cbr the line's last cell
-template <typename TV, typename TC, int BS>
-__device__ void boundary_role_rev(int S, int nx, int base, int lane, int NF, const int64_t cbr,
-                                  int lag, const TV *src, TC (&bring)[DB][NFACE][BS], int *bfull,
-                                  int *bcons, int *err) {
-    // a round of 2 RS steps must fit in half the ring, or it would wait
-    // for slots that only its own consumer can free
-    const int RS = (64 / NF) < (DB / 2) ? (64 / NF) : (DB / 2);
-    const int f = lane % NF, rr = lane / NF;
-    const bool lane_ok = rr < RS;
-    for (int t0 = 0; t0 < S; t0 += 2 * RS) {
-        int64_t cells[2];
-        int ts[2];
-#pragma unroll
-        for (int m = 0; m < 2; m++) {
-            ts[m] = t0 + rr + m * RS;
-            const int i = nx - 1 - (ts[m] - lag);
-            cells[m] = (lane_ok && cbr >= 0 && ts[m] < S && i >= 0 && i < nx) ? cbr - (ts[m] - lag) : -1;
-        }
-        TV vals[2][BS];
-        wait_cells<TV, BS, 2>(src, cells, vals, err);
-        lds_wait_ge(bcons, base + t0 + 2 * RS - DB, err);
-#pragma unroll
-        for (int m = 0; m < 2; m++)
-            if (lane_ok && ts[m] < S)
-#pragma unroll
-                for (int r = 0; r < BS; r++) bring[ts[m] % DB][f][r] = static_cast<TC>(vals[m][r]);
-        lds_release();
-#pragma unroll
-        for (int m = 0; m < 2; m++)
-            if (lane_ok && f == 0 && ts[m] < S) lds_put(&bfull[ts[m] % DB], base + ts[m]);
-    }
+// The next tile of this workgroup (same value in every wavefront).  Each
+// role runs its own tile loop, so every wavefront passes the two barriers
+// once per tile and once more at the end.
+__device__ __forceinline__ int next_tile(int *ctr, int *tile) {
+    __syncthreads();
+    if (threadIdx.x == 0) *tile = atomicAdd(ctr, 1);
+    __syncthreads();
+    return *tile;
 }
 
-template <int BS, typename TF, typename TC, typename TIN, typename TO>
+template <int BS, typename TF, typename TC, typename TIN>
 __global__ __launch_bounds__(GWG) void k_grid_fwd(GridTiles G, const TF *__restrict__ Lt,
-                                                  const TIN *__restrict__ b, TC *y, TO *xo,
-                                                  int *ctr, int *other_ctr, int *err) {
+                                                  const TIN *__restrict__ b, TC *yt, TC *ff,
+                                                  TC *fb, int *ctr, int *other_ctr, int *err) {
     constexpr int B2 = BS * BS, NM = 3 * B2, NV = NM + BS;
     constexpr int D = ring_depth<NV, TC>();
     __shared__ TC ring[D][NV][64];
     __shared__ TC bring[DB][NFACE][BS];
     __shared__ int full[D], bfull[DB], cons, bcons, tile;
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    // wave-uniform role index (an SGPR), so the roles are real branches
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
     if (blockIdx.x == 0 && threadIdx.x == 0) *other_ctr = 0;
     if (threadIdx.x < D) full[threadIdx.x] = -1;
     if (threadIdx.x < DB) bfull[threadIdx.x] = -1;
@@ -291,129 +358,156 @@ __global__ __launch_bounds__(GWG) void k_grid_fwd(GridTiles G, const TF *__restr
         cons = 0;
         bcons = 0;
     }
-    const int TJ = G.TJ, TK = G.TK, nx = G.nx, S = G.S;
+    const int TJ = G.TJ, TK = G.TK, NF = G.NF, nx = G.nx, S = G.S;
     const int64_t sJ = G.nx, sK = (int64_t)G.nx * G.ny;
-    int base = 0;
-    for (;;) {
-        __syncthreads();
-        if (threadIdx.x == 0) tile = atomicAdd(ctr, 1);
-        __syncthreads();
-        const int T = tile;
-        if (T >= G.ntiles) break;
-        const int JK = G.order[T];
-        const int j0 = (JK & 0xffff) * TJ, k0 = (JK >> 16) * TK;
-        if (wave == 0) {
-            // ---- compute ----
-            const int jj = lane % TJ, kk = lane / TJ;
-            const int j = j0 + jj, k = k0 + kk;
-            const bool lane_ok = lane < TJ * TK && j < G.ny && k < G.nz;
-            const int64_t cl = lane_ok ? sJ * j + sK * k : 0;
+    const int jj = lane % TJ, kk = lane / TJ;
+    if (wave == 0) {
+        // ---- compute ----
+        // face entries this lane publishes (high faces feed tiles J+1, K+1)
+        const int fj = jj == TJ - 1 && kk < TK ? kk : -1;
+        const int fk = kk == TK - 1 ? TK + jj : -1;
+        for (int base = 0;; base += S) {
+            const int T = next_tile(ctr, &tile);
+            if (T >= G.ntiles) break;
+            TC *yrow = yt + (int64_t)T * S * BS * 64 + lane;
+            TC *frow = ff + (int64_t)T * S * NF * BS;
             TC yp[BS];
 #pragma unroll
             for (int r = 0; r < BS; r++) yp[r] = TC(0);
-            for (int t = 0; t < S; t++) {
-                const int st = base + t, slot = t % D, bslot = t % DB;
-                lds_wait_eq(&full[slot], st, err);
-                TC v[NV];
-#pragma unroll
-                for (int e = 0; e < NV; e++) v[e] = ring[slot][e][lane];
-                lds_release();
-                if (lane == 0) lds_put(&cons, st + 1);
-                lds_wait_eq(&bfull[bslot], st, err);
-                TC yj[BS], yk[BS], fj[BS], fk[BS];
+            // step t computes with the planes in vc and reads the planes of
+            // step t + 1 into vn; the two arrays swap roles every step
+            auto step = [&](int t, const TC (&vc)[NV], TC (&vn)[NV]) {
+                const int st = base + t, bslot = t % DB;
+                const bool more = t + 1 < S;
+                // one poll for this step's boundary and the next step's planes
+                lds_wait_pair(&bfull[bslot], st, &full[(t + 1) % D], more ? st + 1 : -1, err);
+                TC yj[BS], yk[BS];
 #pragma unroll
                 for (int r = 0; r < BS; r++) {
-                    fj[r] = bring[bslot][kk < NFACE ? kk : 0][r];
-                    fk[r] = bring[bslot][TK + jj < NFACE ? TK + jj : 0][r];
-                }
-                lds_release();
-                if (lane == 0) lds_put(&bcons, st + 1);
-#pragma unroll
-                for (int r = 0; r < BS; r++) {
-                    yj[r] = __shfl_up(yp[r], 1, 64);
+                    const TC bj = bring[bslot][kk < TK ? kk : 0][r];
+                    const TC bk = bring[bslot][TK + jj][r];
+                    yj[r] = lane_shift1<false>(yp[r]);
                     yk[r] = __shfl_up(yp[r], TJ, 64);
-                    if (jj == 0) yj[r] = fj[r];
-                    if (kk == 0) yk[r] = fk[r];
+                    if (jj == 0) yj[r] = bj;
+                    if (kk == 0) yk[r] = bk;
                 }
-                const int i = t - jj - kk;
-                if (lane_ok && i >= 0 && i < nx) {
-                    const int64_t c = cl + i;
-                    TC acc[BS];
+                if (more) {
 #pragma unroll
-                    for (int r = 0; r < BS; r++) acc[r] = v[NM + r];
-                    if (k > 0) block_sub<BS>(acc, v, 0, yk);
-                    if (j > 0) block_sub<BS>(acc, v, 1, yj);
-                    if (i > 0) block_sub<BS>(acc, v, 2, yp);
-#pragma unroll
-                    for (int r = 0; r < BS; r++) {
-                        yp[r] = acc[r];
-                        publish<TC>(y + c * BS + r, acc[r]);
-                        xo[c * BS + r] = sentinel_value<TO>();
-                    }
+                    for (int e = 0; e < NV; e++) vn[e] = ring[(t + 1) % D][e][lane];
                 }
+                TC acc[BS];
+#pragma unroll
+                for (int r = 0; r < BS; r++) acc[r] = vc[NM + r];
+                block_sub<BS>(acc, vc, 0, yk);
+                block_sub<BS>(acc, vc, 1, yj);
+                block_sub<BS>(acc, vc, 2, yp);
+#pragma unroll
+                for (int r = 0; r < BS; r++) {
+                    yp[r] = acc[r];
+                    yrow[(t * BS + r) * 64] = acc[r];
+                }
+                if (fj >= 0)
+#pragma unroll
+                    for (int r = 0; r < BS; r++) publish<TC>(frow + ((int64_t)t * NF + fj) * BS + r, acc[r]);
+                if (fk >= 0)
+#pragma unroll
+                    for (int r = 0; r < BS; r++) publish<TC>(frow + ((int64_t)t * NF + fk) * BS + r, acc[r]);
+                // every LDS read of this step has returned: hand both slots back
+                lds_release();
+                if (lane == 0) {
+                    lds_put(&bcons, st + 1);
+                    lds_put(&cons, more ? st + 2 : st + 1);
+                }
+            };
+            TC va[NV], vb[NV];
+            lds_wait_eq(&full[0], base, err);
+#pragma unroll
+            for (int e = 0; e < NV; e++) va[e] = ring[0][e][lane];
+            int t = 0;
+            for (; t + 1 < S; t += 2) {
+                step(t, va, vb);
+                step(t + 1, vb, va);
             }
-        } else if (wave == 1) {
-            // ---- boundary: upstream values y of tiles (J-1, K) and (J, K-1) ----
-            const int NF = TJ + TK;
-            const int f = lane % NF;
-            int64_t cb = -1;
+            if (t < S) step(t, va, vb);
+        }
+    } else if (wave == 1) {
+        // ---- boundary: faces of tiles (J-1, K) and (J, K-1) ----
+        const int f = lane % NF;
+        for (int base = 0;; base += S) {
+            const int T = next_tile(ctr, &tile);
+            if (T >= G.ntiles) break;
+            const int JK = G.order[T];
+            const int J = JK & 0xffff, K = JK >> 16;
+            const TC *src = nullptr;
             int lag = 0;
-            if (f < TK) {                               // j-face, lane kk = f
-                if (j0 > 0 && k0 + f < G.nz) cb = sJ * (j0 - 1) + sK * (k0 + f);
+            if (f < TK) {                  // j-face of lane kk = f: lane (TJ-1, f) of (J-1, K)
+                if (J > 0 && K * TK + f < G.nz)
+                    src = ff + (((int64_t)G.tidx[(J - 1) * G.NK + K] * S + (TJ - 1)) * NF + f) * BS;
                 lag = f;
-            } else {                                    // k-face, lane jj = f - TK
+            } else {                       // k-face of lane jj = q: lane (q, TK-1) of (J, K-1)
                 const int q = f - TK;
-                if (k0 > 0 && j0 + q < G.ny) cb = sJ * (j0 + q) + sK * (k0 - 1);
+                if (K > 0 && J * TJ + q < G.ny)
+                    src = ff + (((int64_t)G.tidx[J * G.NK + K - 1] * S + (TK - 1)) * NF + f) * BS;
                 lag = q;
             }
-            boundary_role<TC, TC, BS>(S, nx, base, lane, NF, cb, lag, y, bring, bfull, &bcons, err);
-        } else {
-            // ---- factor loaders ----
-            const int w = wave - 2;
-            const int jj = lane % TJ, kk = lane / TJ;
-            const int j = j0 + jj, k = k0 + kk;
+            boundary_role<TC, BS>(S, nx, base, lane, NF, src, lag, bring, bfull, &bcons, err);
+        }
+    } else {
+        // ---- loaders: planes of steps w, w + NLOAD, ... ----
+        const int w = wave - 2;
+        for (int base = 0;; base += S) {
+            const int T = next_tile(ctr, &tile);
+            if (T >= G.ntiles) break;
+            const int JK = G.order[T];
+            const int j = (JK & 0xffff) * TJ + jj, k = (JK >> 16) * TK + kk;
             const bool lane_ok = lane < TJ * TK && j < G.ny && k < G.nz;
             const int64_t cl = lane_ok ? sJ * j + sK * k : 0;
             const TF *lb = Lt + (int64_t)T * S * NM * 64 + lane;
-            TC cur[NV], nxt[NV];
             auto load_step = [&](int t, TC (&v)[NV]) {
 #pragma unroll
                 for (int e = 0; e < NM; e++) v[e] = gld<TC, TF>(lb + ((int64_t)t * NM + e) * 64);
                 const int i = t - jj - kk;
-                const int64_t c = (lane_ok && i >= 0 && i < nx) ? cl + i : 0;
+                const bool ok = lane_ok && i >= 0 && i < nx;
+                const int64_t c = ok ? cl + i : 0;
 #pragma unroll
-                for (int r = 0; r < BS; r++) v[NM + r] = static_cast<TC>(b[c * BS + r]);
+                for (int r = 0; r < BS; r++) v[NM + r] = ok ? static_cast<TC>(b[c * BS + r]) : TC(0);
             };
-            if (w < S) load_step(w, cur);
-            for (int t = w; t < S; t += NLOAD) {
-                const int tn = t + NLOAD;
-                if (tn < S) load_step(tn, nxt);
+            // store step t (held in cur) while step t + NLOAD loads into nxt
+            auto put_step = [&](int t, const TC (&cur)[NV], TC (&nxt)[NV]) {
+                if (t + NLOAD < S) load_step(t + NLOAD, nxt);
                 lds_wait_ge(&cons, base + t - D + 1, err);
 #pragma unroll
                 for (int e = 0; e < NV; e++) ring[t % D][e][lane] = cur[e];
                 lds_release();
                 if (lane == 0) lds_put(&full[t % D], base + t);
-#pragma unroll
-                for (int e = 0; e < NV; e++) cur[e] = nxt[e];
+            };
+            TC ca[NV], cb[NV];
+            if (w < S) load_step(w, ca);
+            int t = w;
+            for (; t + NLOAD < S; t += 2 * NLOAD) {
+                put_step(t, ca, cb);
+                put_step(t + NLOAD, cb, ca);
             }
+            if (t < S) put_step(t, ca, cb);
+            // the backward sweep's face slots of this tile start unwritten
+            TC *fr = fb + (int64_t)T * S * NF * BS;
+            for (int64_t e = w * 64 + lane; e < (int64_t)S * NF * BS; e += NLOAD * 64)
+                fr[e] = sentinel_value<TC>();
         }
-        base += S;
     }
 }
 
-template <int BS, typename TF, typename TD, typename TC, typename TO, int ADD, typename TAI,
-          typename TAO>
+template <int BS, typename TF, typename TD, typename TC, typename TO>
 __global__ __launch_bounds__(GWG) void k_grid_bwd(GridTiles G, const TF *__restrict__ Ut,
-                                                  const TD *__restrict__ Dt, TC *y, TO *xo,
-                                                  const TAI *__restrict__ add_in,
-                                                  TAO *__restrict__ add_out, int *ctr,
-                                                  int *other_ctr, int *err) {
+                                                  const TD *__restrict__ Dt, TC *yt, TC *fb,
+                                                  TC *ff, int *ctr, int *other_ctr, int *err) {
     constexpr int B2 = BS * BS, NM = 3 * B2, NV = NM + B2 + BS;
     constexpr int D = ring_depth<NV, TC>();
     __shared__ TC ring[D][NV][64];
     __shared__ TC bring[DB][NFACE][BS];
     __shared__ int full[D], bfull[DB], cons, bcons, tile;
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
     if (blockIdx.x == 0 && threadIdx.x == 0) *other_ctr = 0;
     if (threadIdx.x < D) full[threadIdx.x] = -1;
     if (threadIdx.x < DB) bfull[threadIdx.x] = -1;
@@ -421,140 +515,177 @@ __global__ __launch_bounds__(GWG) void k_grid_bwd(GridTiles G, const TF *__restr
         cons = 0;
         bcons = 0;
     }
-    const int TJ = G.TJ, TK = G.TK, nx = G.nx, S = G.S;
-    const int64_t sJ = G.nx, sK = (int64_t)G.nx * G.ny;
-    int base = 0;
-    for (;;) {
-        __syncthreads();
-        if (threadIdx.x == 0) tile = atomicAdd(ctr, 1);
-        __syncthreads();
-        const int Tq = tile;
-        if (Tq >= G.ntiles) break;
-        const int T = G.ntiles - 1 - Tq;           // reverse tile order
-        const int JK = G.order[T];
-        const int j0 = (JK & 0xffff) * TJ, k0 = (JK >> 16) * TK;
-        if (wave == 0) {
-            // ---- compute ----
-            const int jj = lane % TJ, kk = lane / TJ;
-            const int j = j0 + jj, k = k0 + kk;
-            const bool lane_ok = lane < TJ * TK && j < G.ny && k < G.nz;
-            const int64_t cl = lane_ok ? sJ * j + sK * k : 0;
-            const int lag = (TJ - 1 - jj) + (TK - 1 - kk);
+    const int TJ = G.TJ, TK = G.TK, NF = G.NF, nx = G.nx, S = G.S;
+    const int jj = lane % TJ, kk = lane / TJ;
+    if (wave == 0) {
+        // ---- compute ----
+        // face entries this lane publishes (low faces feed tiles J-1, K-1)
+        const int fj = jj == 0 && kk < TK ? kk : -1;
+        const int fk = kk == 0 ? TK + jj : -1;
+        for (int base = 0;; base += S) {
+            const int T = G.ntiles - 1 - next_tile(ctr, &tile);   // reverse tile order
+            if (T < 0) break;
+            TC *yrow = yt + (int64_t)T * S * BS * 64 + lane;
+            TC *frow = fb + (int64_t)T * S * NF * BS;
             TC xp[BS];
 #pragma unroll
             for (int r = 0; r < BS; r++) xp[r] = TC(0);
-            for (int t = 0; t < S; t++) {
-                const int st = base + t, slot = t % D, bslot = t % DB;
-                lds_wait_eq(&full[slot], st, err);
-                TC v[NV];
-#pragma unroll
-                for (int e = 0; e < NV; e++) v[e] = ring[slot][e][lane];
-                lds_release();
-                if (lane == 0) lds_put(&cons, st + 1);
-                lds_wait_eq(&bfull[bslot], st, err);
-                TC fj[BS], fk[BS], xj[BS], xk[BS];
-                const int fjx = (TJ - 1 - jj) < 0 ? 0 : kk;
+            auto step = [&](int t, const TC (&vc)[NV], TC (&vn)[NV]) {
+                const int st = base + t, bslot = t % DB;
+                const bool more = t + 1 < S;
+                lds_wait_pair(&bfull[bslot], st, &full[(t + 1) % D], more ? st + 1 : -1, err);
+                TC xj[BS], xk[BS];
 #pragma unroll
                 for (int r = 0; r < BS; r++) {
-                    fj[r] = bring[bslot][fjx < NFACE ? fjx : 0][r];
-                    fk[r] = bring[bslot][TK + jj < NFACE ? TK + jj : 0][r];
-                }
-                lds_release();
-                if (lane == 0) lds_put(&bcons, st + 1);
-#pragma unroll
-                for (int r = 0; r < BS; r++) {
-                    xj[r] = __shfl_down(xp[r], 1, 64);
+                    const TC bj = bring[bslot][kk < TK ? kk : 0][r];
+                    const TC bk = bring[bslot][TK + jj][r];
+                    xj[r] = lane_shift1<true>(xp[r]);
                     xk[r] = __shfl_down(xp[r], TJ, 64);
-                    if (jj == TJ - 1) xj[r] = fj[r];
-                    if (kk == TK - 1) xk[r] = fk[r];
+                    if (jj == TJ - 1) xj[r] = bj;
+                    if (kk == TK - 1) xk[r] = bk;
                 }
-                const int i = nx - 1 - (t - lag);
-                if (lane_ok && i >= 0 && i < nx) {
-                    const int64_t c = cl + i;
-                    TC acc[BS];
+                if (more) {
 #pragma unroll
-                    for (int r = 0; r < BS; r++) {
-                        acc[r] = v[NM + B2 + r];
-                        y[c * BS + r] = sentinel_value<TC>();
-                    }
-                    if (i + 1 < nx) block_sub<BS>(acc, v, 0, xp);
-                    if (j + 1 < G.ny) block_sub<BS>(acc, v, 1, xj);
-                    if (k + 1 < G.nz) block_sub<BS>(acc, v, 2, xk);
-                    TC res[BS];
-#pragma unroll
-                    for (int r = 0; r < BS; r++) {
-                        TC sum = TC(0);
-#pragma unroll
-                        for (int q = 0; q < BS; q++) sum += v[NM + r * BS + q] * acc[q];
-                        res[r] = sum;
-                    }
-#pragma unroll
-                    for (int r = 0; r < BS; r++) {
-                        xp[r] = static_cast<TC>(static_cast<TO>(res[r]));
-                        publish<TO>(xo + c * BS + r, static_cast<TO>(res[r]));
-                        if (ADD == 1)
-                            add_out[c * BS + r] =
-                                static_cast<TAO>(add_in[c * BS + r]) + static_cast<TAO>(res[r]);
-                        if (ADD == 2) {
-                            const TC base0 = (r == 0) ? static_cast<TC>(add_in[c]) : TC(0);
-                            add_out[c * BS + r] = static_cast<TAO>(base0 + res[r]);
-                        }
-                    }
+                    for (int e = 0; e < NV; e++) vn[e] = ring[(t + 1) % D][e][lane];
                 }
+                TC acc[BS];
+#pragma unroll
+                for (int r = 0; r < BS; r++) acc[r] = vc[NM + B2 + r];
+                block_sub<BS>(acc, vc, 0, xp);
+                block_sub<BS>(acc, vc, 1, xj);
+                block_sub<BS>(acc, vc, 2, xk);
+                TC res[BS];
+#pragma unroll
+                for (int r = 0; r < BS; r++) {
+                    TC sum = TC(0);
+#pragma unroll
+                    for (int q = 0; q < BS; q++) sum += vc[NM + r * BS + q] * acc[q];
+                    res[r] = sum;
+                }
+                // neighbours consume the value as the caller's output type
+#pragma unroll
+                for (int r = 0; r < BS; r++) {
+                    xp[r] = static_cast<TC>(static_cast<TO>(res[r]));
+                    yrow[((S - 1 - t) * BS + r) * 64] = res[r];
+                }
+                if (fj >= 0)
+#pragma unroll
+                    for (int r = 0; r < BS; r++) publish<TC>(frow + ((int64_t)t * NF + fj) * BS + r, xp[r]);
+                if (fk >= 0)
+#pragma unroll
+                    for (int r = 0; r < BS; r++) publish<TC>(frow + ((int64_t)t * NF + fk) * BS + r, xp[r]);
+                lds_release();
+                if (lane == 0) {
+                    lds_put(&bcons, st + 1);
+                    lds_put(&cons, more ? st + 2 : st + 1);
+                }
+            };
+            TC va[NV], vb[NV];
+            lds_wait_eq(&full[0], base, err);
+#pragma unroll
+            for (int e = 0; e < NV; e++) va[e] = ring[0][e][lane];
+            int t = 0;
+            for (; t + 1 < S; t += 2) {
+                step(t, va, vb);
+                step(t + 1, vb, va);
             }
-        } else if (wave == 1) {
-            // ---- boundary: downstream values x of tiles (J+1, K) and (J, K+1) ----
-            const int NF = TJ + TK;
-            const int f = lane % NF;
-            int64_t cb = -1;
+            if (t < S) step(t, va, vb);
+        }
+    } else if (wave == 1) {
+        // ---- boundary: faces of tiles (J+1, K) and (J, K+1) ----
+        const int f = lane % NF;
+        for (int base = 0;; base += S) {
+            const int T = G.ntiles - 1 - next_tile(ctr, &tile);
+            if (T < 0) break;
+            const int JK = G.order[T];
+            const int J = JK & 0xffff, K = JK >> 16;
+            const TC *src = nullptr;
             int lag = 0;
-            if (f < TK) {                               // j-face of lane (TJ-1, kk = f)
-                if (j0 + TJ < G.ny && k0 + f < G.nz) cb = sJ * (j0 + TJ) + sK * (k0 + f);
-                lag = (TK - 1 - f);                     // lag of lane (TJ-1, f)
-            } else {                                    // k-face of lane (jj = q, TK-1)
+            if (f < TK) {                  // j-face of lane (TJ-1, f): lane (0, f) of (J+1, K)
+                if (J + 1 < G.NJ && K * TK + f < G.nz)
+                    src = fb + (((int64_t)G.tidx[(J + 1) * G.NK + K] * S + (TJ - 1)) * NF + f) * BS;
+                lag = TK - 1 - f;
+            } else {                       // k-face of lane (q, TK-1): lane (q, 0) of (J, K+1)
                 const int q = f - TK;
-                if (k0 + TK < G.nz && j0 + q < G.ny) cb = sJ * (j0 + q) + sK * (k0 + TK);
-                lag = (TJ - 1 - q);
+                if (K + 1 < G.NK && J * TJ + q < G.ny)
+                    src = fb + (((int64_t)G.tidx[J * G.NK + K + 1] * S + (TK - 1)) * NF + f) * BS;
+                lag = TJ - 1 - q;
             }
-            // the backward step t reaches i = nx - 1 - (t - lag): index the
-            // line from its far end
-            const int64_t cbr = cb >= 0 ? cb + nx - 1 : -1;
-            boundary_role_rev<TO, TC, BS>(S, nx, base, lane, NF, cbr, lag, xo, bring, bfull, &bcons, err);
-        } else {
-            // ---- loaders: U blocks, diagonal inverse, forward result ----
-            const int w = wave - 2;
-            const int jj = lane % TJ, kk = lane / TJ;
-            const int j = j0 + jj, k = k0 + kk;
-            const bool lane_ok = lane < TJ * TK && j < G.ny && k < G.nz;
-            const int64_t cl = lane_ok ? sJ * j + sK * k : 0;
-            const int lag = (TJ - 1 - jj) + (TK - 1 - kk);
+            boundary_role<TC, BS>(S, nx, base, lane, NF, src, lag, bring, bfull, &bcons, err);
+        }
+    } else {
+        // ---- loaders: U blocks, diagonal inverse, forward result ----
+        const int w = wave - 2;
+        for (int base = 0;; base += S) {
+            const int T = G.ntiles - 1 - next_tile(ctr, &tile);
+            if (T < 0) break;
             const TF *ub = Ut + (int64_t)T * S * NM * 64 + lane;
             const TD *db = Dt + (int64_t)T * S * B2 * 64 + lane;
-            TC cur[NV], nxt[NV];
+            const TC *yb = yt + (int64_t)T * S * BS * 64 + lane;
             auto load_step = [&](int t, TC (&v)[NV]) {
 #pragma unroll
                 for (int e = 0; e < NM; e++) v[e] = gld<TC, TF>(ub + ((int64_t)t * NM + e) * 64);
 #pragma unroll
                 for (int e = 0; e < B2; e++) v[NM + e] = static_cast<TC>(db[((int64_t)t * B2 + e) * 64]);
-                const int i = nx - 1 - (t - lag);
-                const int64_t c = (lane_ok && i >= 0 && i < nx) ? cl + i : 0;
+                // the forward result of the same cells: forward step S - 1 - t
 #pragma unroll
-                for (int r = 0; r < BS; r++) v[NM + B2 + r] = y[c * BS + r];
+                for (int r = 0; r < BS; r++) v[NM + B2 + r] = yb[((int64_t)(S - 1 - t) * BS + r) * 64];
             };
-            if (w < S) load_step(w, cur);
-            for (int t = w; t < S; t += NLOAD) {
-                const int tn = t + NLOAD;
-                if (tn < S) load_step(tn, nxt);
+            auto put_step = [&](int t, const TC (&cur)[NV], TC (&nxt)[NV]) {
+                if (t + NLOAD < S) load_step(t + NLOAD, nxt);
                 lds_wait_ge(&cons, base + t - D + 1, err);
 #pragma unroll
                 for (int e = 0; e < NV; e++) ring[t % D][e][lane] = cur[e];
                 lds_release();
                 if (lane == 0) lds_put(&full[t % D], base + t);
+            };
+            TC ca[NV], cb[NV];
+            if (w < S) load_step(w, ca);
+            int t = w;
+            for (; t + NLOAD < S; t += 2 * NLOAD) {
+                put_step(t, ca, cb);
+                put_step(t + NLOAD, cb, ca);
+            }
+            if (t < S) put_step(t, ca, cb);
+            // the forward sweep's face slots of this tile start unwritten
+            TC *fr = ff + (int64_t)T * S * NF * BS;
+            for (int64_t e = w * 64 + lane; e < (int64_t)S * NF * BS; e += NLOAD * 64)
+                fr[e] = sentinel_value<TC>();
+        }
+    }
+}
+
+// Copy the tile-step-major result to natural order, with the caller's
+// epilogue (the add modes of ilu_apply): one block per (tile, 8 steps),
+// reads in contiguous 64-lane rows.
+template <int BS, typename TC, typename TO, int ADD, typename TAI, typename TAO>
+__global__ __launch_bounds__(256) void k_grid_untile(GridTiles G, const TC *__restrict__ yt,
+                                                     TO *__restrict__ xo,
+                                                     const TAI *__restrict__ add_in,
+                                                     TAO *__restrict__ add_out) {
+    const int nchunk = (G.S + 7) / 8;
+    const int T = blockIdx.x / nchunk, t0 = (blockIdx.x % nchunk) * 8;
+    const int lane = threadIdx.x & 63;
+    const int JK = G.order[T];
+    const int jj = lane % G.TJ, kk = lane / G.TJ;
+    const int j = (JK & 0xffff) * G.TJ + jj, k = (JK >> 16) * G.TK + kk;
+    if (lane >= G.TJ * G.TK || j >= G.ny || k >= G.nz) return;
+    const int64_t cl = (int64_t)G.nx * j + (int64_t)G.nx * G.ny * k;
+    for (int t = t0 + (threadIdx.x >> 6); t < t0 + 8 && t < G.S; t += 4) {
+        const int i = t - jj - kk;
+        if (i < 0 || i >= G.nx) continue;
+        const int64_t c = cl + i;
+        const TC *src = yt + ((int64_t)T * G.S + t) * BS * 64 + lane;
 #pragma unroll
-                for (int e = 0; e < NV; e++) cur[e] = nxt[e];
+        for (int r = 0; r < BS; r++) {
+            const TC v = src[r * 64];
+            if (ADD == 0) xo[c * BS + r] = static_cast<TO>(v);
+            if (ADD == 1) add_out[c * BS + r] = static_cast<TAO>(add_in[c * BS + r]) + static_cast<TAO>(v);
+            if (ADD == 2) {
+                const TC base0 = (r == 0) ? static_cast<TC>(add_in[c]) : TC(0);
+                add_out[c * BS + r] = static_cast<TAO>(base0 + v);
             }
         }
-        base += S;
     }
 }
 
@@ -564,18 +695,25 @@ __global__ __launch_bounds__(GWG) void k_grid_bwd(GridTiles G, const TF *__restr
 template <int BS, typename TF, typename TD, typename TC, typename TIN, typename TO, int ADD,
           typename TAI, typename TAO>
 static int grid_pair(hipStream_t s, IluFactor &F, const TF *lt, const TF *ut, const TD *dt,
-                     TC *y, const TIN *b, TO *xo, const TAI *add_in, TAO *add_out, int *err) {
+                     TC *yt, TC *ff, TC *fb, const TIN *b, TO *xo, const TAI *add_in,
+                     TAO *add_out, int *err) {
     // one workgroup per tile in flight (LDS-bound); 256 CUs
     const int wgs = std::min(F.G.ntiles, 512);
     {
         TimedScope t(sweep_timer_name(true, BS, sizeof(TF), ADD), s);
-        hipLaunchKernelGGL((k_grid_fwd<BS, TF, TC, TIN, TO>), dim3(wgs), dim3(GWG), 0, s, F.G,
-                           lt, b, y, xo, F.ctr.p, F.ctr.p + 1, err);
+        hipLaunchKernelGGL((k_grid_fwd<BS, TF, TC, TIN>), dim3(wgs), dim3(GWG), 0, s, F.G, lt, b,
+                           yt, ff, fb, F.ctr.p, F.ctr.p + 1, err);
     }
     {
-        TimedScope t(sweep_timer_name(false, BS, sizeof(TF), ADD), s);
-        hipLaunchKernelGGL((k_grid_bwd<BS, TF, TD, TC, TO, ADD, TAI, TAO>), dim3(wgs), dim3(GWG),
-                           0, s, F.G, ut, dt, y, xo, add_in, add_out, F.ctr.p + 1, F.ctr.p, err);
+        TimedScope t(sweep_timer_name(false, BS, sizeof(TF), 0), s);
+        hipLaunchKernelGGL((k_grid_bwd<BS, TF, TD, TC, TO>), dim3(wgs), dim3(GWG), 0, s, F.G, ut,
+                           dt, yt, fb, ff, F.ctr.p + 1, F.ctr.p, err);
+    }
+    {
+        TimedScope t("ilu_grid_untile", s);
+        const int nchunk = (F.G.S + 7) / 8;
+        hipLaunchKernelGGL((k_grid_untile<BS, TC, TO, ADD, TAI, TAO>), dim3(F.G.ntiles * nchunk),
+                           dim3(256), 0, s, F.G, yt, xo, add_in, add_out);
     }
     KRY_HIP(hipGetLastError());
     return KRY_OK;
@@ -586,39 +724,41 @@ static int grid_typed(hipStream_t s, IluFactor &F, const TIN *b, TO *xo, int add
                       const void *add_in, void *add_out, int *err) {
     if (F.prec == KRY_PREC_F64) {
         using TC = double;
+        TC *yt = F.yt64.p, *ff = F.ff64.p, *fb = F.fb64.p;
         if (add_mode == 0)
             return grid_pair<BS, double, double, TC, TIN, TO, 0, double, double>(
-                s, F, F.lt64.p, F.ut64.p, F.dt64.p, F.y64.p, b, xo, nullptr, nullptr, err);
+                s, F, F.lt64.p, F.ut64.p, F.dt64.p, yt, ff, fb, b, xo, nullptr, nullptr, err);
         if (add_mode == 1)
             return grid_pair<BS, double, double, TC, TIN, TO, 1, TO, TO>(
-                s, F, F.lt64.p, F.ut64.p, F.dt64.p, F.y64.p, b, xo, (const TO *)add_in,
+                s, F, F.lt64.p, F.ut64.p, F.dt64.p, yt, ff, fb, b, xo, (const TO *)add_in,
                 (TO *)add_out, err);
         return grid_pair<BS, double, double, TC, TIN, TO, 2, TC, double>(
-            s, F, F.lt64.p, F.ut64.p, F.dt64.p, F.y64.p, b, xo, (const TC *)add_in,
+            s, F, F.lt64.p, F.ut64.p, F.dt64.p, yt, ff, fb, b, xo, (const TC *)add_in,
             (double *)add_out, err);
     }
     using TC = float;
+    TC *yt = F.yt32.p, *ff = F.ff32.p, *fb = F.fb32.p;
     if (F.prec == KRY_PREC_F32) {
         if (add_mode == 0)
             return grid_pair<BS, float, float, TC, TIN, TO, 0, float, float>(
-                s, F, F.lt32.p, F.ut32.p, F.dt32.p, F.y32.p, b, xo, nullptr, nullptr, err);
+                s, F, F.lt32.p, F.ut32.p, F.dt32.p, yt, ff, fb, b, xo, nullptr, nullptr, err);
         if (add_mode == 1)
             return grid_pair<BS, float, float, TC, TIN, TO, 1, TO, TO>(
-                s, F, F.lt32.p, F.ut32.p, F.dt32.p, F.y32.p, b, xo, (const TO *)add_in,
+                s, F, F.lt32.p, F.ut32.p, F.dt32.p, yt, ff, fb, b, xo, (const TO *)add_in,
                 (TO *)add_out, err);
         return grid_pair<BS, float, float, TC, TIN, TO, 2, TC, double>(
-            s, F, F.lt32.p, F.ut32.p, F.dt32.p, F.y32.p, b, xo, (const TC *)add_in,
+            s, F, F.lt32.p, F.ut32.p, F.dt32.p, yt, ff, fb, b, xo, (const TC *)add_in,
             (double *)add_out, err);
     }
     if (add_mode == 0)
         return grid_pair<BS, uint16_t, float, TC, TIN, TO, 0, float, float>(
-            s, F, F.lt16.p, F.ut16.p, F.dt32.p, F.y32.p, b, xo, nullptr, nullptr, err);
+            s, F, F.lt16.p, F.ut16.p, F.dt32.p, yt, ff, fb, b, xo, nullptr, nullptr, err);
     if (add_mode == 1)
         return grid_pair<BS, uint16_t, float, TC, TIN, TO, 1, TO, TO>(
-            s, F, F.lt16.p, F.ut16.p, F.dt32.p, F.y32.p, b, xo, (const TO *)add_in,
+            s, F, F.lt16.p, F.ut16.p, F.dt32.p, yt, ff, fb, b, xo, (const TO *)add_in,
             (TO *)add_out, err);
     return grid_pair<BS, uint16_t, float, TC, TIN, TO, 2, TC, double>(
-        s, F, F.lt16.p, F.ut16.p, F.dt32.p, F.y32.p, b, xo, (const TC *)add_in,
+        s, F, F.lt16.p, F.ut16.p, F.dt32.p, yt, ff, fb, b, xo, (const TC *)add_in,
         (double *)add_out, err);
 }
 

@@ -200,7 +200,9 @@ int ensure_col0_f32(hipStream_t s, MAT_ *A);
 struct GridTiles {
     int nx = 0, ny = 0, nz = 0;
     int TJ = 0, TK = 0, NJ = 0, NK = 0, ntiles = 0, S = 0;
-    const int *order = nullptr;
+    int NF = 0;                      // face cells per step: TK (j-face) + TJ (k-face)
+    const int *order = nullptr;      // tile T -> J | K << 16, in J + K order
+    const int *tidx = nullptr;       // J * NK + K -> tile T
 };
 
 struct IluFactor {
@@ -218,10 +220,15 @@ struct IluFactor {
     // grid-tiled sweeps (7-point stencils in natural order)
     bool grid = false;
     GridTiles G;
-    DBuf<int> order;
+    DBuf<int> order, tidx;
     DBuf<double> lt64, ut64, dt64;
     DBuf<float> lt32, ut32, dt32;
     DBuf<uint16_t> lt16, ut16;
+    // tile-step-major forward result (overwritten in place by the backward
+    // result) and the published face values of both sweeps, in the
+    // compute precision
+    DBuf<double> yt64, ff64, fb64;
+    DBuf<float> yt32, ff32, fb32;
 };
 
 // timer name of one sweep kernel: direction, block size, factor storage
