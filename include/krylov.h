@@ -58,7 +58,10 @@ enum { KRY_HOST = 0, KRY_DEVICE = 1 };
 enum { KRY_F64 = 0 };                         /* VEC data type             */
 enum { KRY_GMRES = 0, KRY_FGMRES = 1, KRY_BICGSTAB = 2 };
 enum { KRY_PC_NONE = 0, KRY_PC_ILU0 = 1, KRY_PC_BILU0 = 1, KRY_PC_CPR = 2,
-       KRY_PC_CUSTOM = 3 };
+       KRY_PC_CUSTOM = 3,
+       /* learned-stage extension: base preconditioner followed by the
+        * convolutional correction with its residual-test fallback */
+       KRY_PC_BILU0_LEARNED = 4, KRY_PC_CPR_LEARNED = 5 };
 /* precision of the preconditioner apply (mixed-precision extension) */
 enum { KRY_PREC_F64 = 0, KRY_PREC_F32 = 1, KRY_PREC_BF16_FACTORS = 2 };
 /* CPR stage order: PF = pressure then full (Algorithm 6, corrected);
@@ -73,6 +76,7 @@ typedef struct MAP_ MAP;
 typedef struct VEC_ VEC;
 typedef struct MAT_ MAT;
 typedef struct SOLVER_ SOLVER;
+typedef struct LEARNED_ LEARNED;
 
 /* ---- MAP: row distribution (Section 2.1, eq. (1)-(2)) --------------------
  * MapCreate requires ilower < iupper (eq. (2)); NULL otherwise.  With one
@@ -195,6 +199,56 @@ typedef void (*PC_DESTROY)(void *data);
 int SolverSetPC(SOLVER *s, PC_SETUP setup, PC_SOLVE solve,
                 PC_DESTROY destroy, void *data);
 
+/* ---- learned preconditioner stage (extension beyond the paper) -------------
+ * Network: four 3x3x3 convolutions 4 -> 32 -> 32 -> 32 -> 3 channels with
+ * zero padding and bias, exact GELU after the first three, BF16 operands
+ * with FP32 accumulation.  Parameters (LearnedNumParams() = 61443 FP32
+ * values): for each layer l, W_l[co][ci][tap] with
+ * tap = (dz+1)*9 + (dy+1)*3 + (dx+1), then b_l[co].
+ *
+ * Inside a solver (pc_type KRY_PC_BILU0_LEARNED or KRY_PC_CPR_LEARNED,
+ * FGMRES only, a 3x3-block 7-point grid matrix): z1 = M_base^-1 v,
+ * r1 = v - A z1, s = ||r1|| / sqrt(n), e = s N([r1 / s, ln k]),
+ * z2 = z1 + e; the apply returns z2 if ||v - A z2|| < ||r1|| and z1
+ * otherwise (a fallback; also when s is zero or anything is not finite).
+ *   SolverSetLearned: parameters from a checkpoint file written by
+ *     LearnedSave; ln k per cell (nb values, FP32, device).
+ *   SolverSetLearnedParams: parameters from host memory; ln k on `where`.
+ *   SolverGetLearnedStats: applications and fallbacks since assembly.
+ * Both setters copy their inputs; call them before SolverAssemble. */
+int SolverSetLearned(SOLVER *s, const char *weights_path, const float *logk_dev);
+int SolverSetLearnedParams(SOLVER *s, const float *params_host, const float *logk,
+                           int where);
+int SolverGetLearnedStats(SOLVER *s, int64_t *applies, int64_t *fallbacks);
+
+/* Training interface on an nx x ny x nz grid (the network alone).
+ * Tensors are channel-major FP32 on the device: input [4][cells]
+ * (three residual components, then ln k), output and target [3][cells],
+ * cells in natural order (x fastest).
+ *   LearnedCreate(training = 0) allocates the forward pass only;
+ *     training = 1 adds pre-activations, gradients and Adam moments.
+ *   LearnedSetParams / LearnedGetParams copy the FP32 master parameters.
+ *   LearnedForward: out = N(in).
+ *   LearnedLossGrad: loss = mean((N(in) - target)^2) (returned on the host)
+ *     and its gradient (device, LearnedNumParams() values; may be NULL:
+ *     kept internally for LearnedAdamStep).
+ *   LearnedAdamStep: one bias-corrected Adam step on the last gradient.
+ *   LearnedSave / LearnedLoad: checkpoint (parameters, Adam moments and
+ *     step count) in a little-endian binary file.
+ * All calls synchronize the object's stream (LearnedSetStream). */
+LEARNED *LearnedCreate(int nx, int ny, int nz, int training);
+int LearnedDestroy(LEARNED **L);
+int LearnedNumParams(void);
+int LearnedSetStream(LEARNED *L, void *hip_stream);
+int LearnedSetParams(LEARNED *L, const float *params, int where);
+int LearnedGetParams(LEARNED *L, float *params_host);
+int LearnedForward(LEARNED *L, const float *in, float *out);
+int LearnedLossGrad(LEARNED *L, const float *in, const float *target, float *loss_host,
+                    float *grad);
+int LearnedAdamStep(LEARNED *L, float lr, float beta1, float beta2, float eps);
+int LearnedSave(LEARNED *L, const char *path);
+int LearnedLoad(LEARNED *L, const char *path);
+
 /* ---- per-kernel timing (measurement only) ----------------------------------
  * When enabled, the library brackets every launch of the kernels it times
  * (SpMV, ILU sweeps, CGS2 passes) with HIP events on the launch stream.
@@ -203,7 +257,10 @@ int SolverSetPC(SOLVER *s, PC_SETUP setup, PC_SOLVE solve,
  * and "spmv_csr" (FP64 SpMV), "ilu_fwd_<fmt>_<prec>" and
  * "ilu_bwd_<fmt>_<prec>" (forward / backward sweep, fmt = bsr3 or csr,
  * prec = f64, f32 or bf16 factor storage), "cgs2" (one orthogonalization
- * step: both Gram-Schmidt passes, the norm and the Givens update). */
+ * step: both Gram-Schmidt passes, the norm and the Givens update),
+ * "learned_stage" (one learned-stage apply after the base preconditioner),
+ * "conv_l<k>_fwd" (layer k of the network), "conv_wgrad", "conv_dgrad"
+ * (weight and input gradients). */
 int KernelTimingEnable(int on);
 int KernelTimingReset(void);
 int KernelTimingQuery(const char *name, int64_t *launches, double *total_ms);

@@ -28,6 +28,7 @@ KRY_HOST, KRY_DEVICE = 0, 1
 KRY_F64 = 0
 KRY_GMRES, KRY_FGMRES, KRY_BICGSTAB = 0, 1, 2
 KRY_PC_NONE, KRY_PC_ILU0, KRY_PC_BILU0, KRY_PC_CPR, KRY_PC_CUSTOM = 0, 1, 1, 2, 3
+KRY_PC_BILU0_LEARNED, KRY_PC_CPR_LEARNED = 4, 5
 KRY_PREC_F64, KRY_PREC_F32, KRY_PREC_BF16_FACTORS = 0, 1, 2
 KRY_CPR_PF, KRY_CPR_FP = 0, 1
 KRY_SWEEP_AUTO, KRY_SWEEP_LEVELS, KRY_SWEEP_GRID = 0, 1, 2
@@ -80,6 +81,17 @@ _SIGS = {
     "KernelTimingEnable": (C.c_int, [C.c_int]), "KernelTimingReset": (C.c_int, []),
     "KernelTimingQuery": (C.c_int, [C.c_char_p, C.POINTER(I64), C.POINTER(D)]),
     "KrylovSetStream": (C.c_int, [P]), "LastError": (C.c_char_p, []),
+    "SolverSetLearned": (C.c_int, [P, C.c_char_p, P]),
+    "SolverSetLearnedParams": (C.c_int, [P, P, P, C.c_int]),
+    "SolverGetLearnedStats": (C.c_int, [P, C.POINTER(I64), C.POINTER(I64)]),
+    "LearnedCreate": (P, [C.c_int, C.c_int, C.c_int, C.c_int]),
+    "LearnedDestroy": (C.c_int, [C.POINTER(P)]), "LearnedNumParams": (C.c_int, []),
+    "LearnedSetStream": (C.c_int, [P, P]),
+    "LearnedSetParams": (C.c_int, [P, P, C.c_int]), "LearnedGetParams": (C.c_int, [P, P]),
+    "LearnedForward": (C.c_int, [P, P, P]),
+    "LearnedLossGrad": (C.c_int, [P, P, P, C.POINTER(C.c_float), P]),
+    "LearnedAdamStep": (C.c_int, [P, C.c_float, C.c_float, C.c_float, C.c_float]),
+    "LearnedSave": (C.c_int, [P, C.c_char_p]), "LearnedLoad": (C.c_int, [P, C.c_char_p]),
 }
 for _name, (_res, _args) in _SIGS.items():
     _f = getattr(_lib, _name)
@@ -317,6 +329,97 @@ def SolverSetPC(s, setup, solve, destroy, data=None):
     """setup/solve/destroy: PC_SETUP / PC_SOLVE / PC_DESTROY instances (the
     caller keeps them alive as long as the solver)."""
     return _check(_lib.SolverSetPC(s, setup, solve, destroy, data))
+
+
+# ---- learned stage ---------------------------------------------------------------
+def _fptr(a):
+    """(pointer, where) of a float32 torch tensor or numpy array."""
+    if hasattr(a, "data_ptr"):
+        import torch
+        if a.dtype != torch.float32 or not a.is_contiguous():
+            raise TypeError("expected a contiguous float32 tensor")
+        return C.c_void_p(a.data_ptr()), (KRY_DEVICE if a.is_cuda else KRY_HOST)
+    a = np.asarray(a)
+    if a.dtype != np.float32 or not a.flags["C_CONTIGUOUS"]:
+        raise TypeError("expected a contiguous float32 array")
+    return a.ctypes.data_as(C.c_void_p), KRY_HOST
+
+
+def _fdptr(t):
+    p, where = _fptr(t)
+    if where != KRY_DEVICE:
+        raise TypeError("expected a CUDA float32 tensor")
+    return p
+
+
+def SolverSetLearned(s, weights_path, logk_dev):
+    return _check(_lib.SolverSetLearned(s, os.fsencode(weights_path), _fdptr(logk_dev)))
+
+
+def SolverSetLearnedParams(s, params, logk):
+    pp, pw = _fptr(params)
+    if pw != KRY_HOST:
+        raise TypeError("parameters must be a host float32 array")
+    lp, lw = _fptr(logk)
+    return _check(_lib.SolverSetLearnedParams(s, pp, lp, lw))
+
+
+def SolverGetLearnedStats(s):
+    a, f = C.c_int64(0), C.c_int64(0)
+    _check(_lib.SolverGetLearnedStats(s, C.byref(a), C.byref(f)))
+    return a.value, f.value
+
+
+def LearnedCreate(nx, ny, nz, training=False):
+    return _handle(_lib.LearnedCreate(nx, ny, nz, int(bool(training))), "LearnedCreate")
+
+
+def LearnedDestroy(L):
+    h = C.c_void_p(L)
+    return _check(_lib.LearnedDestroy(C.byref(h)))
+
+
+def LearnedNumParams():
+    return _lib.LearnedNumParams()
+
+
+def LearnedSetStream(L, stream):
+    raw = getattr(stream, "cuda_stream", stream)
+    return _check(_lib.LearnedSetStream(L, C.c_void_p(raw or 0)))
+
+
+def LearnedSetParams(L, params):
+    p, where = _fptr(params)
+    return _check(_lib.LearnedSetParams(L, p, where))
+
+
+def LearnedGetParams(L):
+    out = np.zeros(LearnedNumParams(), dtype=np.float32)
+    _check(_lib.LearnedGetParams(L, out.ctypes.data_as(C.c_void_p)))
+    return out
+
+
+def LearnedForward(L, inp, out):
+    return _check(_lib.LearnedForward(L, _fdptr(inp), _fdptr(out)))
+
+
+def LearnedLossGrad(L, inp, target, grad=None):
+    loss = C.c_float(0)
+    _check(_lib.LearnedLossGrad(L, _fdptr(inp), _fdptr(target), C.byref(loss),
+                                _fdptr(grad) if grad is not None else None))
+    return loss.value
+
+
+def LearnedAdamStep(L, lr, beta1=0.9, beta2=0.999, eps=1e-8):
+    return _check(_lib.LearnedAdamStep(L, lr, beta1, beta2, eps))
+
+
+def LearnedSave(L, path):
+    return _check(_lib.LearnedSave(L, os.fsencode(path)))
+
+
+def LearnedLoad(L, path):
+    return _check(_lib.LearnedLoad(L, os.fsencode(path)))
 
 
 # ---- timing and stream ---------------------------------------------------------

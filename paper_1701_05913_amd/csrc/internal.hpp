@@ -277,6 +277,22 @@ int cpr_apply(hipStream_t s, MAT_ *A, CprPC &C, const double *v, double *z,
 // ---------------------------------------------------------------------------
 // solver object
 // ---------------------------------------------------------------------------
+namespace kry {
+// learned preconditioner stage (learned.hip)
+struct LearnedStage;
+void learned_stage_delete(LearnedStage *L);
+struct LearnedStageDeleter {
+    void operator()(LearnedStage *L) const { learned_stage_delete(L); }
+};
+int learned_stage_create(hipStream_t s, const MAT_ *A, const float *params_host,
+                         const float *lnk, int lnk_where, LearnedStage **out);
+// z holds the base preconditioner's result on entry, the stage's on exit
+int learned_stage_apply(hipStream_t s, const MAT_ *A, LearnedStage &L, const double *v, double *z);
+int learned_stage_stats(hipStream_t s, LearnedStage &L, int64_t *applies, int64_t *fallbacks);
+int learned_read_file(const char *path, std::vector<float> &p, std::vector<float> &m,
+                      std::vector<float> &v, int &adam_t);
+}  // namespace kry
+
 struct SOLVER_ {
     int type = KRY_GMRES, pc_type = KRY_PC_NONE;
     MAP *map = nullptr;
@@ -294,6 +310,9 @@ struct SOLVER_ {
     void *cdata = nullptr;
     std::unique_ptr<kry::IluFactor> ilu;
     std::unique_ptr<kry::CprPC> cpr;
+    std::unique_ptr<kry::LearnedStage, kry::LearnedStageDeleter> learned;
+    std::vector<float> learned_params;     // host copy until assembly
+    kry::DBuf<float> learned_lnk;          // ln k per cell
     bool assembled = false;
     double residual = 0.0;
     int nits = 0;

@@ -440,6 +440,12 @@ int pc_apply(SOLVER_ *S, const double *v, double *z) {
         return ilu_apply(S->stream, *S->ilu, v, 0, z, 0, 0, nullptr, nullptr, S->err.p);
     case KRY_PC_CPR:
         return cpr_apply(S->stream, S->A, *S->cpr, v, z, S->err.p);
+    case KRY_PC_BILU0_LEARNED:
+        KRY_TRY(ilu_apply(S->stream, *S->ilu, v, 0, z, 0, 0, nullptr, nullptr, S->err.p));
+        return learned_stage_apply(S->stream, S->A, *S->learned, v, z);
+    case KRY_PC_CPR_LEARNED:
+        KRY_TRY(cpr_apply(S->stream, S->A, *S->cpr, v, z, S->err.p));
+        return learned_stage_apply(S->stream, S->A, *S->learned, v, z);
     case KRY_PC_CUSTOM: {
         VEC_ vv, zz;
         vv.map = zz.map = S->map;
@@ -627,7 +633,7 @@ extern "C" SOLVER *SolverCreate(int solver_type, int pc_type, MAP *map) {
         set_error(KRY_ERR_UNSUPPORTED, "SolverCreate: solver type %d", solver_type);
         return nullptr;
     }
-    if (pc_type < KRY_PC_NONE || pc_type > KRY_PC_CUSTOM) {
+    if (pc_type < KRY_PC_NONE || pc_type > KRY_PC_CPR_LEARNED) {
         set_error(KRY_ERR_UNSUPPORTED, "SolverCreate: preconditioner type %d", pc_type);
         return nullptr;
     }
@@ -737,21 +743,29 @@ extern "C" int SolverAssemble(SOLVER *s) {
     if (!s || !s->A) return set_error(KRY_ERR_ARG, "SolverAssemble: no matrix");
     if (s->prec != KRY_PREC_F64 && s->type != KRY_FGMRES)
         return set_error(KRY_ERR_ARG, "reduced-precision preconditioning needs FGMRES");
-    if (s->prec != KRY_PREC_F64 && s->pc_type != KRY_PC_ILU0 && s->pc_type != KRY_PC_CPR)
+    if (s->prec != KRY_PREC_F64 && (s->pc_type == KRY_PC_NONE || s->pc_type == KRY_PC_CUSTOM))
         return set_error(KRY_ERR_ARG, "reduced precision applies to ILU and CPR preconditioners");
+    const bool learned = s->pc_type == KRY_PC_BILU0_LEARNED || s->pc_type == KRY_PC_CPR_LEARNED;
+    if (learned && s->type != KRY_FGMRES)
+        return set_error(KRY_ERR_ARG, "the learned stage varies between applications: it needs FGMRES");
+    if (learned && s->learned_params.empty())
+        return set_error(KRY_ERR_ARG, "learned stage: call SolverSetLearned before SolverAssemble");
     const auto t0 = std::chrono::steady_clock::now();
     if (!s->err.p) KRY_TRY(s->err.alloc(1));
     hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(64), 0, s->stream, s->err.p);
     s->ilu.reset();
     s->cpr.reset();
+    s->learned.reset();
     switch (s->pc_type) {
     case KRY_PC_NONE:
         break;
     case KRY_PC_ILU0:
+    case KRY_PC_BILU0_LEARNED:
         s->ilu.reset(new IluFactor());
         KRY_TRY(ilu_setup(s->stream, s->A, s->A->val.p, *s->ilu, s->prec, s->err.p, s->sweep_layout));
         break;
     case KRY_PC_CPR:
+    case KRY_PC_CPR_LEARNED:
         s->cpr.reset(new CprPC());
         KRY_TRY(cpr_setup(s->stream, s->A, *s->cpr, s->cpr_variant, s->cpr_sweeps, s->prec, s->err.p,
                           s->sweep_layout));
@@ -763,6 +777,12 @@ extern "C" int SolverAssemble(SOLVER *s) {
             if (rc < 0) return set_error(rc, "custom preconditioner setup failed (%d)", rc);
         }
         break;
+    }
+    if (learned) {
+        LearnedStage *L = nullptr;
+        KRY_TRY(learned_stage_create(s->stream, s->A, s->learned_params.data(), s->learned_lnk.p,
+                                     KRY_DEVICE, &L));
+        s->learned.reset(L);
     }
     KRY_TRY(check_device_error(s));
     KRY_TRY(ensure_workspace(s));
@@ -786,6 +806,41 @@ extern "C" int SolverSolve(SOLVER *s, VEC *b, VEC *x) {
     s->t_solve = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     if (erc < 0) return erc;
     return rc;
+}
+
+static int set_learned(SOLVER *s, std::vector<float> &&params, const float *logk, int where) {
+    if (s->pc_type != KRY_PC_BILU0_LEARNED && s->pc_type != KRY_PC_CPR_LEARNED)
+        return set_error(KRY_ERR_ARG, "SolverSetLearned: solver was not created with a learned preconditioner");
+    if (!logk) return set_error(KRY_ERR_ARG, "SolverSetLearned: ln k is NULL");
+    if (s->map->nlocal % 3 != 0) return set_error(KRY_ERR_DIM, "SolverSetLearned: system size is not 3 per cell");
+    const int64_t cells = s->map->nlocal / 3;
+    KRY_TRY(s->learned_lnk.alloc(cells));
+    KRY_HIP(hipMemcpyAsync(s->learned_lnk.p, logk, sizeof(float) * cells,
+                           where == KRY_HOST ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice, s->stream));
+    KRY_HIP(hipStreamSynchronize(s->stream));
+    s->learned_params = std::move(params);
+    s->assembled = false;
+    return KRY_OK;
+}
+
+extern "C" int SolverSetLearned(SOLVER *s, const char *weights_path, const float *logk_dev) {
+    if (!s || !weights_path) return set_error(KRY_ERR_ARG, "SolverSetLearned: NULL argument");
+    std::vector<float> p, m, v;
+    int t = 0;
+    KRY_TRY(learned_read_file(weights_path, p, m, v, t));
+    return set_learned(s, std::move(p), logk_dev, KRY_DEVICE);
+}
+
+extern "C" int SolverSetLearnedParams(SOLVER *s, const float *params_host, const float *logk, int where) {
+    if (!s || !params_host) return set_error(KRY_ERR_ARG, "SolverSetLearnedParams: NULL argument");
+    std::vector<float> p(params_host, params_host + LearnedNumParams());
+    return set_learned(s, std::move(p), logk, where);
+}
+
+extern "C" int SolverGetLearnedStats(SOLVER *s, int64_t *applies, int64_t *fallbacks) {
+    if (!s) return set_error(KRY_ERR_ARG, "SolverGetLearnedStats: NULL");
+    if (!s->learned) return set_error(KRY_ERR_ARG, "SolverGetLearnedStats: no learned stage assembled");
+    return learned_stage_stats(s->stream, *s->learned, applies, fallbacks);
 }
 
 extern "C" int SolverPCApply(SOLVER *s, VEC *v, VEC *z) {

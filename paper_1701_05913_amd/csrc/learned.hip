@@ -1,0 +1,868 @@
+// Learned preconditioner stage: a 4-layer 3D convolutional network
+// (4 -> 32 -> 32 -> 32 -> 3 channels, 3x3x3 kernels, zero padding, bias,
+// exact GELU after the three hidden layers) applied after the base
+// preconditioner, with forward and backward passes for training.
+//
+// gfx950 design.  Every convolution is an implicit GEMM on the BF16 matrix
+// cores (v_mfma_f32_16x16x32_bf16, FP32 accumulation): M = 16 cells along
+// x, N = 16 output channels, K = 32 input channels of one tap (or 8 taps
+// of the 4-channel first layer).  A workgroup owns a 16 x 8 x 4 brick of
+// output cells; the input brick with its one-cell halo and the layer's
+// packed weights are staged in LDS (cells padded to 80 bytes so the 16
+// lanes of a row read distinct banks).  Activations are channels-last
+// BF16 ([cell][channel]), so one lane's eight K values are one 16-byte
+// load.  The input gradient of a layer is the same kernel run with the
+// weights flipped in space and transposed in channels; the weight gradient
+// is a second MFMA kernel that contracts over cells (K = 32 cells), with
+// channel-major LDS copies of the brick shifted along x so every 8-cell
+// operand is an aligned 16-byte load.  Partial sums are reduced in a fixed
+// order (bitwise reproducible).
+//
+// Parameter layout (FP32 master copy): for each layer l, W_l[co][ci][tap]
+// with tap = (dz+1)*9 + (dy+1)*3 + (dx+1), then b_l[co].
+#include <cmath>
+#include <cstdio>
+#include <vector>
+
+#include "device.hpp"
+#include "internal.hpp"
+
+namespace kry {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+constexpr int NET_C[5] = {4, 32, 32, 32, 3};
+constexpr int NET_OFF[5] = {0, 3488, 31168, 58848, 61443};   // parameter offsets
+constexpr int HID = 32;
+constexpr int BX = 16, BY = 8, BZ = 4;                       // forward brick
+constexpr int HX = BX + 2, HY = BY + 2, HZ = BZ + 2;
+constexpr int HCELLS = HX * HY * HZ;
+constexpr int CSTRIDE32 = 40;                                // bf16 per halo cell (32 + pad)
+constexpr int DWX = 16, DWY = 4, DWZ = 2;                    // weight-gradient brick
+constexpr int DWROWX = 24;                                   // padded x extent of its halo rows
+constexpr int DW_WG = 256;                                   // persistent weight-gradient workgroups
+
+__device__ __forceinline__ uint16_t f2bf(float f) { return f32_to_bf16_rne(f); }
+__device__ __forceinline__ float gelu(float x) { return 0.5f * x * (1.0f + erff(x * 0.70710678118654752f)); }
+__device__ __forceinline__ float gelu_grad(float x) {
+    return 0.5f * (1.0f + erff(x * 0.70710678118654752f)) + x * expf(-0.5f * x * x) * 0.39894228040143268f;
+}
+
+// ---------------------------------------------------------------------------
+// weight packing: B fragments of v_mfma_f32_16x16x32_bf16.  Lane l of
+// fragment (kb, ct) holds eight K values k = kb*32 + (l/16)*8 + i of output
+// channel n = ct*16 + l%16.  K is the input channel of tap kb (CINP = 32)
+// or tap*4 + channel over all taps (CINP = 4).  `transposed` packs the
+// input-gradient convolution: output channel n of it is input channel n
+// of the layer, and taps are mirrored.
+// ---------------------------------------------------------------------------
+__global__ void k_pack_weights(const float *__restrict__ W, int cin_l, int cout_l, int cinp,
+                               int nt, int transposed, uint16_t *__restrict__ wp) {
+    const int nkb = cinp == 32 ? 27 : 4;
+    const int total = nkb * nt * 64 * 8;
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= total) return;
+    const int i = q & 7, l = (q >> 3) & 63, ct = (q >> 9) % nt, kb = (q >> 9) / nt;
+    const int k = kb * 32 + (l >> 4) * 8 + i, n = ct * 16 + (l & 15);
+    int tap, c;
+    if (cinp == 32) {
+        tap = kb;
+        c = k - kb * 32;
+    } else {
+        tap = k >> 2;
+        c = k & 3;
+    }
+    // (kernel input channel c, kernel output channel n) of this convolution
+    const int cin_k = transposed ? cout_l : cin_l, cout_k = transposed ? cin_l : cout_l;
+    float v = 0.0f;
+    if (tap < 27 && c < cin_k && n < cout_k) {
+        v = transposed ? W[((size_t)c * cin_l + n) * 27 + (26 - tap)]
+                       : W[((size_t)n * cin_l + c) * 27 + tap];
+    }
+    wp[q] = f2bf(v);
+}
+
+// ---------------------------------------------------------------------------
+// convolution forward (and input-gradient) kernel
+//   CINP   4 or 32 channels-last BF16 input
+//   NT     output tiles of 16 channels (2: 32 channels, 1: up to 16)
+//   MODE   0 hidden layer: y = bias + conv; out_h = bf16(GELU(y)), out_z = y
+//          1 output layer: out_f[cell][cout] = bias + conv (FP32)
+//          2 input gradient of the next layer: d = conv (no bias);
+//            g = d * GELU'(z_prev); out_h = bf16(g), dbpart += g (FP32)
+// ---------------------------------------------------------------------------
+template <int CINP, int NT, int MODE>
+__global__ __launch_bounds__(256) void k_conv(int nx, int ny, int nz, int cout,
+                                              const uint16_t *__restrict__ in,
+                                              const uint16_t *__restrict__ wp,
+                                              const float *__restrict__ bias,
+                                              uint16_t *__restrict__ out_h,
+                                              float *__restrict__ out_f,
+                                              const float *__restrict__ zprev,
+                                              float *__restrict__ dbpart) {
+    constexpr int NKB = CINP == 32 ? 27 : 4;
+    constexpr int CST = CINP == 32 ? CSTRIDE32 : 4;          // bf16 per halo cell
+    constexpr int NW = NKB * NT * 64 * 8;                     // packed weight bf16
+    __shared__ __attribute__((aligned(16))) uint16_t sh_in[HCELLS * CST];
+    __shared__ __attribute__((aligned(16))) uint16_t sh_w[NW];
+    __shared__ float sh_db[4][32];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int nbx = (nx + BX - 1) / BX, nby = (ny + BY - 1) / BY;
+    const int bxi = blockIdx.x % nbx, byi = (blockIdx.x / nbx) % nby, bzi = blockIdx.x / (nbx * nby);
+    const int x0 = bxi * BX, y0 = byi * BY, z0 = bzi * BZ;
+    const int64_t sy = nx, sz = (int64_t)nx * ny;
+
+    // ---- stage the input brick with halo (zeros outside the grid) ----
+    if (CINP == 32) {
+        for (int c = tid; c < HCELLS * 4; c += 256) {
+            const int hc = c >> 2, part = c & 3;
+            const int hx = hc % HX, hy = (hc / HX) % HY, hz = hc / (HX * HY);
+            const int gx = x0 + hx - 1, gy = y0 + hy - 1, gz = z0 + hz - 1;
+            uint4 v = make_uint4(0, 0, 0, 0);
+            if (gx >= 0 && gx < nx && gy >= 0 && gy < ny && gz >= 0 && gz < nz)
+                v = *reinterpret_cast<const uint4 *>(in + (gx + gy * sy + gz * sz) * 32 + part * 8);
+            *reinterpret_cast<uint4 *>(sh_in + hc * CST + part * 8) = v;
+        }
+    } else {
+        for (int hc = tid; hc < HCELLS; hc += 256) {
+            const int hx = hc % HX, hy = (hc / HX) % HY, hz = hc / (HX * HY);
+            const int gx = x0 + hx - 1, gy = y0 + hy - 1, gz = z0 + hz - 1;
+            uint2 v = make_uint2(0, 0);
+            if (gx >= 0 && gx < nx && gy >= 0 && gy < ny && gz >= 0 && gz < nz)
+                v = *reinterpret_cast<const uint2 *>(in + (gx + gy * sy + gz * sz) * 4);
+            *reinterpret_cast<uint2 *>(sh_in + hc * 4) = v;
+        }
+    }
+    for (int c = tid; c < NW / 8; c += 256)
+        *reinterpret_cast<uint4 *>(sh_w + c * 8) = *reinterpret_cast<const uint4 *>(wp + c * 8);
+    if (MODE == 2 && tid < 128) sh_db[tid >> 5][tid & 31] = 0.0f;
+    __syncthreads();
+
+    // ---- wave `wave` computes rows (y = 0..7, z = wave) of 16 cells ----
+    f32x4 acc[BY][NT];
+#pragma unroll
+    for (int r = 0; r < BY; r++)
+#pragma unroll
+        for (int t = 0; t < NT; t++) acc[r][t] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+    const int xl = lane & 15, g = lane >> 4;
+    for (int kb = 0; kb < NKB; kb++) {
+        bf16x8 bfr[NT];
+#pragma unroll
+        for (int t = 0; t < NT; t++)
+            bfr[t] = *reinterpret_cast<const bf16x8 *>(sh_w + ((kb * NT + t) * 64 + lane) * 8);
+        if (CINP == 32) {
+            const int dz = kb / 9 - 1, dy = (kb / 3) % 3 - 1, dx = kb % 3 - 1;
+            const int hbase = ((wave + 1 + dz) * HY + (1 + dy)) * HX + (xl + 1 + dx);
+#pragma unroll
+            for (int r = 0; r < BY; r++) {
+                const bf16x8 a = *reinterpret_cast<const bf16x8 *>(sh_in + (hbase + r * HX) * CST + g * 8);
+#pragma unroll
+                for (int t = 0; t < NT; t++)
+                    acc[r][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bfr[t], acc[r][t], 0, 0, 0);
+            }
+        } else {
+            // eight K values = taps 2q and 2q+1 (four channels each), q = kb*4 + g
+            const int t0 = kb * 8 + g * 2;
+            int off[2];
+#pragma unroll
+            for (int h = 0; h < 2; h++) {
+                const int tp = t0 + h < 27 ? t0 + h : 26;     // padded taps carry zero weights
+                const int dz = tp / 9 - 1, dy = (tp / 3) % 3 - 1, dx = tp % 3 - 1;
+                off[h] = ((wave + 1 + dz) * HY + (1 + dy)) * HX + (xl + 1 + dx);
+            }
+#pragma unroll
+            for (int r = 0; r < BY; r++) {
+                uint4 u;
+                const uint2 lo = *reinterpret_cast<const uint2 *>(sh_in + (off[0] + r * HX) * 4);
+                const uint2 hi = *reinterpret_cast<const uint2 *>(sh_in + (off[1] + r * HX) * 4);
+                u.x = lo.x; u.y = lo.y; u.z = hi.x; u.w = hi.y;
+                const bf16x8 a = __builtin_bit_cast(bf16x8, u);
+#pragma unroll
+                for (int t = 0; t < NT; t++)
+                    acc[r][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bfr[t], acc[r][t], 0, 0, 0);
+            }
+        }
+    }
+
+    // ---- epilogue: lane holds channel n = t*16 + lane%16 of cells x = 4g + i ----
+    const int gz = z0 + wave;
+    float dbs[NT];
+#pragma unroll
+    for (int t = 0; t < NT; t++) dbs[t] = 0.0f;
+#pragma unroll
+    for (int r = 0; r < BY; r++) {
+        const int gy = y0 + r;
+#pragma unroll
+        for (int i = 0; i < 4; i++) {
+            const int gx = x0 + 4 * g + i;
+            const bool ok = gx < nx && gy < ny && gz < nz;
+            const int64_t cell = gx + gy * sy + gz * sz;
+#pragma unroll
+            for (int t = 0; t < NT; t++) {
+                const int n = t * 16 + xl;
+                const float y = acc[r][t][i];
+                if (MODE == 0) {
+                    if (ok) {
+                        const float v = y + bias[n];
+                        out_h[cell * 32 + n] = f2bf(gelu(v));
+                        if (out_f) out_f[cell * 32 + n] = v;
+                    }
+                } else if (MODE == 1) {
+                    if (ok && n < cout) out_f[cell * cout + n] = y + bias[n];
+                } else {
+                    if (ok) {
+                        const float gv = y * gelu_grad(zprev[cell * 32 + n]);
+                        out_h[cell * 32 + n] = f2bf(gv);
+                        dbs[t] += gv;
+                    }
+                }
+            }
+        }
+    }
+    if (MODE == 2) {
+        // fixed-order block reduction of the bias gradient: lanes sharing a
+        // channel (same lane%16) first, then the four waves
+#pragma unroll
+        for (int t = 0; t < NT; t++) {
+            float v = dbs[t];
+            v += __shfl_xor(v, 16, 64);
+            v += __shfl_xor(v, 32, 64);
+            if (lane < 16) sh_db[wave][t * 16 + lane] = v;
+        }
+        __syncthreads();
+        if (tid < 32) {
+            const float v = sh_db[0][tid] + sh_db[1][tid] + sh_db[2][tid] + sh_db[3][tid];
+            dbpart[(size_t)blockIdx.x * 32 + tid] = v;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// weight gradient: part[wg][m][n] = sum over the bricks of workgroup wg of
+// dz[cell][m] * h[cell + tap][c], n = tap * CINP + c (M = MT*16 output
+// channels, N = 27*CINP columns in tiles of 16).  K runs over 32 cells at a
+// time: lane group q of a K block covers 8 consecutive x cells.
+// ---------------------------------------------------------------------------
+template <int CINP, int MT, int DZC>
+__global__ __launch_bounds__(256) void k_conv_wgrad(int nx, int ny, int nz,
+                                                    const uint16_t *__restrict__ dz,
+                                                    const uint16_t *__restrict__ h,
+                                                    float *__restrict__ part) {
+    constexpr int NNT = (27 * CINP + 15) / 16;               // column tiles
+    constexpr int TPW = (NNT + 3) / 4;                       // column tiles per wave
+    constexpr int M = MT * 16;
+    constexpr int HYd = DWY + 2, HZd = DWZ + 2;
+    constexpr int ROWS = HYd * HZd;                          // halo rows per channel
+    constexpr int CH = CINP;
+    // channel-major brick of h with halo, three copies shifted along x by
+    // 0, 1, 2 cells so that the 8-cell operand of every tap is aligned
+    __shared__ __attribute__((aligned(16))) uint16_t sh_h[3][CH * ROWS * DWROWX];
+    __shared__ __attribute__((aligned(16))) uint16_t sh_dz[M][DWX * DWY * DWZ];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int nbx = (nx + DWX - 1) / DWX, nby = (ny + DWY - 1) / DWY, nbz = (nz + DWZ - 1) / DWZ;
+    const int nbricks = nbx * nby * nbz;
+    const int64_t sy = nx, sz = (int64_t)nx * ny;
+    const int xl = lane & 15, q = lane >> 4;
+    f32x4 acc[TPW][MT];
+#pragma unroll
+    for (int j = 0; j < TPW; j++)
+#pragma unroll
+        for (int m = 0; m < MT; m++) acc[j][m] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+
+    for (int br = blockIdx.x; br < nbricks; br += gridDim.x) {
+        const int x0 = (br % nbx) * DWX, y0 = ((br / nbx) % nby) * DWY, z0 = (br / (nbx * nby)) * DWZ;
+        __syncthreads();
+        // stage h: copy s holds x index hx at position hx - s
+        for (int e = tid; e < CH * ROWS * DWROWX; e += 256) {
+            const int px = e % DWROWX, row = (e / DWROWX) % ROWS, c = e / (DWROWX * ROWS);
+            const int hy = row % HYd, hz = row / HYd;
+            const int gy = y0 + hy - 1, gz = z0 + hz - 1;
+#pragma unroll
+            for (int s = 0; s < 3; s++) {
+                const int gx = x0 + px + s - 1;
+                uint16_t v = 0;
+                if (px + s < DWX + 2 && gx >= 0 && gx < nx && gy >= 0 && gy < ny && gz >= 0 && gz < nz)
+                    v = h[(gx + gy * sy + gz * sz) * CINP + c];
+                sh_h[s][e] = v;
+            }
+        }
+        // stage dz transposed: sh_dz[m][cell of brick]
+        for (int e = tid; e < M * DWX * DWY * DWZ; e += 256) {
+            const int cb = e % (DWX * DWY * DWZ), m = e / (DWX * DWY * DWZ);
+            const int bx = cb % DWX, by = (cb / DWX) % DWY, bz = cb / (DWX * DWY);
+            const int gx = x0 + bx, gy = y0 + by, gz = z0 + bz;
+            uint16_t v = 0;
+            if (m < DZC && gx < nx && gy < ny && gz < nz) v = dz[(gx + gy * sy + gz * sz) * DZC + m];
+            sh_dz[m][cb] = v;
+        }
+        __syncthreads();
+        // K blocks: 32 cells = rows (2 kb, 2 kb + 1) of 16 x cells; lane group
+        // q covers row 2 kb + q/2, x = 8 (q%2) .. + 8
+        for (int kb = 0; kb < DWY * DWZ / 2; kb++) {
+            const int row = 2 * kb + (q >> 1), xs = 8 * (q & 1);
+            const int by = row % DWY, bz = row / DWY;
+            bf16x8 afr[MT];
+#pragma unroll
+            for (int m = 0; m < MT; m++)
+                afr[m] = *reinterpret_cast<const bf16x8 *>(&sh_dz[m * 16 + xl][row * DWX + xs]);
+#pragma unroll
+            for (int j = 0; j < TPW; j++) {
+                const int nt = wave + 4 * j;
+                if (nt < NNT) {
+                    const int n = nt * 16 + xl;
+                    const int tap = n / CINP < 27 ? n / CINP : 26, c = n % CINP;
+                    const int dzz = tap / 9 - 1, dyy = (tap / 3) % 3 - 1, dxx = tap % 3 - 1;
+                    // halo x of the first cell = xs + 1 + dxx, taken from copy
+                    // s = 1 + dxx at position xs (aligned to 8 elements)
+                    const int hrow = (bz + 1 + dzz) * HYd + (by + 1 + dyy);
+                    const uint16_t *src = &sh_h[1 + dxx][(c * ROWS + hrow) * DWROWX + xs];
+                    bf16x8 b = *reinterpret_cast<const bf16x8 *>(src);
+                    if (n >= 27 * CINP) b = bf16x8{};
+#pragma unroll
+                    for (int m = 0; m < MT; m++)
+                        acc[j][m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(afr[m], b, acc[j][m], 0, 0, 0);
+                }
+            }
+        }
+    }
+    // D[m][n]: lane holds n = nt*16 + lane%16, m = mt*16 + 4 (lane/16) + i
+    float *pw = part + (size_t)blockIdx.x * M * (NNT * 16);
+#pragma unroll
+    for (int j = 0; j < TPW; j++) {
+        const int nt = wave + 4 * j;
+        if (nt < NNT)
+#pragma unroll
+            for (int m = 0; m < MT; m++)
+#pragma unroll
+                for (int i = 0; i < 4; i++)
+                    pw[(size_t)(m * 16 + 4 * q + i) * (NNT * 16) + nt * 16 + xl] = acc[j][m][i];
+    }
+}
+
+// grad W[co][ci][tap] = sum over workgroups (fixed order) of part[wg][co][tap*CINP + ci]
+__global__ void k_wgrad_reduce(const float *__restrict__ part, int nwg, int M, int NN, int cinp,
+                               int cin, int cout, float *__restrict__ gW) {
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= cout * cin * 27) return;
+    const int tap = q % 27, ci = (q / 27) % cin, co = q / (27 * cin);
+    const int n = tap * cinp + ci;
+    float s = 0.0f;
+    for (int w = 0; w < nwg; w++) s += part[((size_t)w * M + co) * NN + n];
+    gW[q] = s;
+}
+
+// bias gradient from block partials (fixed order)
+__global__ void k_bgrad_reduce(const float *__restrict__ part, int nblk, int stride, int cout,
+                               float *__restrict__ gb) {
+    const int co = threadIdx.x;
+    if (co >= cout) return;
+    float s = 0.0f;
+    for (int b = 0; b < nblk; b++) s += part[(size_t)b * stride + co];
+    gb[co] = s;
+}
+
+// ---------------------------------------------------------------------------
+// loss and output gradient: d = out - target (target channel-major);
+// dz4[cell][c] = bf16(2 d / N) (c < 3, channel 3 zero); per-block partial
+// sums of d^2 and of the FP32 output gradient (the last layer's bias
+// gradient).  One block of 256 threads per 256 cells.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_loss(int64_t cells, const float *__restrict__ out,
+                                              const float *__restrict__ target,
+                                              uint16_t *__restrict__ dz4, float *__restrict__ part) {
+    __shared__ float sh[4][4];
+    const int64_t c = blockIdx.x * (int64_t)256 + threadIdx.x;
+    const float scale = 2.0f / (3.0f * (float)cells);
+    float l2 = 0.0f, gs[3] = {0.0f, 0.0f, 0.0f};
+    if (c < cells) {
+#pragma unroll
+        for (int k = 0; k < 3; k++) {
+            const float d = out[c * 3 + k] - target[k * cells + c];
+            l2 += d * d;
+            gs[k] = scale * d;
+            dz4[c * 4 + k] = f2bf(gs[k]);
+        }
+        dz4[c * 4 + 3] = 0;
+    }
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    float v[4] = {l2, gs[0], gs[1], gs[2]};
+#pragma unroll
+    for (int k = 0; k < 4; k++) {
+        float s = wave_sum(v[k]);
+        if (lane == 0) sh[w][k] = s;
+    }
+    __syncthreads();
+    if (threadIdx.x < 4) {
+        const int k = threadIdx.x;
+        part[(size_t)blockIdx.x * 4 + k] = sh[0][k] + sh[1][k] + sh[2][k] + sh[3][k];
+    }
+}
+
+__global__ void k_loss_final(const float *__restrict__ part, int nblk, int64_t cells,
+                             float *__restrict__ loss, float *__restrict__ gb4) {
+    const int k = threadIdx.x;
+    if (k >= 4) return;
+    double s = 0.0;
+    for (int b = 0; b < nblk; b++) s += part[(size_t)b * 4 + k];
+    if (k == 0) *loss = static_cast<float>(s / (3.0 * (double)cells));
+    else gb4[k - 1] = static_cast<float>(s);
+}
+
+// Adam with bias correction (Kingma and Ba, 2015), FP32 master weights
+__global__ void k_adam(int n, float *__restrict__ p, const float *__restrict__ g,
+                       float *__restrict__ m, float *__restrict__ v, float lr, float b1, float b2,
+                       float eps, float c1, float c2) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float gi = g[i];
+    const float mi = b1 * m[i] + (1.0f - b1) * gi;
+    const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    p[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+}
+
+// channel-major FP32 [4][cells] -> channels-last BF16 [cells][4]
+__global__ void k_input_cm(int64_t cells, const float *__restrict__ x, uint16_t *__restrict__ h0) {
+    const int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (c >= cells) return;
+#pragma unroll
+    for (int k = 0; k < 4; k++) h0[c * 4 + k] = f2bf(x[k * cells + c]);
+}
+
+// channels-last [cells][3] -> channel-major [3][cells]
+__global__ void k_output_cm(int64_t cells, const float *__restrict__ o, float *__restrict__ y) {
+    const int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (c >= cells) return;
+#pragma unroll
+    for (int k = 0; k < 3; k++) y[k * cells + c] = o[c * 3 + k];
+}
+
+// network input of the stage: [r1 / s, ln k] with s = ||r1|| / sqrt(n);
+// nrm[0] = ||r1||.  When s is zero or not finite the input is zero (the
+// correction is then rejected by the residual test).
+__global__ void k_stage_input(int64_t cells, const double *__restrict__ r1,
+                              const double *__restrict__ nrm, const float *__restrict__ lnk,
+                              uint16_t *__restrict__ h0) {
+    const int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (c >= cells) return;
+    const double s = nrm[0] / sqrt(3.0 * (double)cells);
+    const bool ok = s > 0.0 && isfinite(s);
+#pragma unroll
+    for (int k = 0; k < 3; k++)
+        h0[c * 4 + k] = f2bf(ok ? static_cast<float>(r1[c * 3 + k] / s) : 0.0f);
+    h0[c * 4 + 3] = f2bf(lnk[c]);
+}
+
+// z2 = z1 + s * out
+__global__ void k_stage_update(int64_t cells, const double *__restrict__ z1,
+                               const float *__restrict__ out, const double *__restrict__ nrm,
+                               double *__restrict__ z2) {
+    const int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (q >= cells * 3) return;
+    const double s = nrm[0] / sqrt(3.0 * (double)cells);
+    z2[q] = z1[q] + s * static_cast<double>(out[q]);
+}
+
+// accept z2 when s > 0 is finite and ||v - A z2|| < ||r1|| (any non-finite
+// value fails the comparison); counters: [0] applications, [1] fallbacks
+__global__ void k_stage_select(int64_t n, const double *__restrict__ z2,
+                               const double *__restrict__ nrm, double *__restrict__ z,
+                               unsigned long long *__restrict__ counters) {
+    const double s = nrm[0] / sqrt((double)n);
+    const bool accept = s > 0.0 && isfinite(s) && nrm[1] < nrm[0];
+    const int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (q == 0) {
+        counters[0] += 1ull;
+        if (!accept) counters[1] += 1ull;
+    }
+    if (accept && q < n) z[q] = z2[q];
+}
+
+// ---------------------------------------------------------------------------
+// host side
+// ---------------------------------------------------------------------------
+struct ConvNet {
+    int nx = 0, ny = 0, nz = 0;
+    int64_t cells = 0;
+    DBuf<float> params, grad, m, v;
+    int adam_t = 0;
+    DBuf<uint16_t> wf[4], wt[4];          // forward / input-gradient fragments
+    DBuf<uint16_t> h0, h[3], dz4, dza, dzb;
+    DBuf<float> z[3], out, part, loss, tmp_io;
+    bool training = false;
+};
+
+static int conv_blocks(const ConvNet &N) {
+    return ((N.nx + BX - 1) / BX) * ((N.ny + BY - 1) / BY) * ((N.nz + BZ - 1) / BZ);
+}
+static int wgrad_blocks(const ConvNet &N) {
+    const int nb = ((N.nx + DWX - 1) / DWX) * ((N.ny + DWY - 1) / DWY) * ((N.nz + DWZ - 1) / DWZ);
+    return std::min(nb, DW_WG);
+}
+
+static int net_alloc(ConvNet &N, int nx, int ny, int nz, bool training) {
+    if (nx <= 0 || ny <= 0 || nz <= 0) return set_error(KRY_ERR_ARG, "learned stage: grid %d x %d x %d", nx, ny, nz);
+    N.nx = nx;
+    N.ny = ny;
+    N.nz = nz;
+    N.cells = (int64_t)nx * ny * nz;
+    N.training = training;
+    const int np = NET_OFF[4];
+    KRY_TRY(N.params.alloc(np));
+    KRY_HIP(hipMemset(N.params.p, 0, sizeof(float) * np));
+    for (int l = 0; l < 4; l++) {
+        const int cinp = l == 0 ? 4 : 32, nt = l == 3 ? 1 : 2;
+        KRY_TRY(N.wf[l].alloc((cinp == 32 ? 27 : 4) * nt * 512));
+    }
+    // input-gradient convolutions: layer 4 (3 -> 32 channels, padded input of
+    // 4) and layers 3, 2 (32 -> 32)
+    KRY_TRY(N.wt[3].alloc(4 * 2 * 512));
+    KRY_TRY(N.wt[2].alloc(27 * 2 * 512));
+    KRY_TRY(N.wt[1].alloc(27 * 2 * 512));
+    KRY_TRY(N.h0.alloc(N.cells * 4));
+    for (int l = 0; l < 3; l++) KRY_TRY(N.h[l].alloc(N.cells * 32));
+    KRY_TRY(N.out.alloc(N.cells * 3));
+    KRY_TRY(N.loss.alloc(4));
+    if (training) {
+        KRY_TRY(N.grad.alloc(np));
+        KRY_TRY(N.m.alloc(np));
+        KRY_TRY(N.v.alloc(np));
+        KRY_HIP(hipMemset(N.m.p, 0, sizeof(float) * np));
+        KRY_HIP(hipMemset(N.v.p, 0, sizeof(float) * np));
+        for (int l = 0; l < 3; l++) KRY_TRY(N.z[l].alloc(N.cells * 32));
+        KRY_TRY(N.dz4.alloc(N.cells * 4));
+        KRY_TRY(N.dza.alloc(N.cells * 32));
+        KRY_TRY(N.dzb.alloc(N.cells * 32));
+        const size_t pw = (size_t)wgrad_blocks(N) * 32 * ((27 * 32 + 15) / 16 * 16);
+        const size_t pl = (size_t)((N.cells + 255) / 256) * 4;
+        const size_t pb = (size_t)conv_blocks(N) * 32;
+        KRY_TRY(N.part.alloc(std::max(pw, std::max(pl, pb))));
+    }
+    KRY_TRY(N.tmp_io.alloc(N.cells * 4));
+    return KRY_OK;
+}
+
+static int net_pack(hipStream_t s, ConvNet &N) {
+    for (int l = 0; l < 4; l++) {
+        const int cin = NET_C[l], cout = NET_C[l + 1];
+        const int cinp = l == 0 ? 4 : 32, nt = l == 3 ? 1 : 2;
+        const int tot = (cinp == 32 ? 27 : 4) * nt * 512;
+        hipLaunchKernelGGL(k_pack_weights, dim3((tot + 255) / 256), dim3(256), 0, s,
+                           N.params.p + NET_OFF[l], cin, cout, cinp, nt, 0, N.wf[l].p);
+    }
+    // transposed packs: layer 4 (kernel input = its 3 output channels, padded to 4)
+    hipLaunchKernelGGL(k_pack_weights, dim3((4 * 2 * 512 + 255) / 256), dim3(256), 0, s,
+                       N.params.p + NET_OFF[3], 32, 3, 4, 2, 1, N.wt[3].p);
+    for (int l = 1; l <= 2; l++)
+        hipLaunchKernelGGL(k_pack_weights, dim3((27 * 2 * 512 + 255) / 256), dim3(256), 0, s,
+                           N.params.p + NET_OFF[l], 32, 32, 32, 2, 1, N.wt[l].p);
+    KRY_HIP(hipGetLastError());
+    return KRY_OK;
+}
+
+// forward from N.h0; keeps pre-activations when training
+static int net_forward(hipStream_t s, ConvNet &N) {
+    const dim3 g(conv_blocks(N)), b(256);
+    const bool keep = N.training;
+    {
+        TimedScope t("conv_l1_fwd", s);
+        hipLaunchKernelGGL((k_conv<4, 2, 0>), g, b, 0, s, N.nx, N.ny, N.nz, 32, N.h0.p, N.wf[0].p,
+                           N.params.p + NET_OFF[0] + 32 * 4 * 27, N.h[0].p, keep ? N.z[0].p : nullptr,
+                           nullptr, nullptr);
+    }
+    for (int l = 1; l <= 2; l++) {
+        TimedScope t(l == 1 ? "conv_l2_fwd" : "conv_l3_fwd", s);
+        hipLaunchKernelGGL((k_conv<32, 2, 0>), g, b, 0, s, N.nx, N.ny, N.nz, 32, N.h[l - 1].p,
+                           N.wf[l].p, N.params.p + NET_OFF[l] + 32 * 32 * 27, N.h[l].p,
+                           keep ? N.z[l].p : nullptr, nullptr, nullptr);
+    }
+    {
+        TimedScope t("conv_l4_fwd", s);
+        hipLaunchKernelGGL((k_conv<32, 1, 1>), g, b, 0, s, N.nx, N.ny, N.nz, 3, N.h[2].p, N.wf[3].p,
+                           N.params.p + NET_OFF[3] + 3 * 32 * 27, nullptr, N.out.p, nullptr, nullptr);
+    }
+    KRY_HIP(hipGetLastError());
+    return KRY_OK;
+}
+
+// loss and full parameter gradient for target (channel-major [3][cells])
+static int net_backward(hipStream_t s, ConvNet &N, const float *target) {
+    const int nlb = static_cast<int>((N.cells + 255) / 256);
+    hipLaunchKernelGGL(k_loss, dim3(nlb), dim3(256), 0, s, N.cells, N.out.p, target, N.dz4.p, N.part.p);
+    hipLaunchKernelGGL(k_loss_final, dim3(1), dim3(64), 0, s, N.part.p, nlb, N.cells, N.loss.p,
+                       N.grad.p + NET_OFF[3] + 3 * 32 * 27);
+    const dim3 g(conv_blocks(N)), b(256);
+    const int nwg = wgrad_blocks(N);
+    constexpr int NN32 = (27 * 32 + 15) / 16 * 16, NN4 = (27 * 4 + 15) / 16 * 16;
+    // layer 4: weight gradient from dz4 (3 channels) and h[2]
+    {
+        TimedScope t("conv_wgrad", s);
+        hipLaunchKernelGGL((k_conv_wgrad<32, 1, 4>), dim3(nwg), b, 0, s, N.nx, N.ny, N.nz, N.dz4.p,
+                           N.h[2].p, N.part.p);
+        hipLaunchKernelGGL(k_wgrad_reduce, dim3((3 * 32 * 27 + 255) / 256), dim3(256), 0, s, N.part.p,
+                           nwg, 16, NN32, 32, 32, 3, N.grad.p + NET_OFF[3]);
+    }
+    // dz3 = conv^T(dz4) * GELU'(z3)
+    {
+        TimedScope t("conv_dgrad", s);
+        hipLaunchKernelGGL((k_conv<4, 2, 2>), g, b, 0, s, N.nx, N.ny, N.nz, 32, N.dz4.p, N.wt[3].p,
+                           nullptr, N.dza.p, nullptr, N.z[2].p, N.part.p);
+        hipLaunchKernelGGL(k_bgrad_reduce, dim3(1), dim3(64), 0, s, N.part.p, (int)g.x, 32, 32,
+                           N.grad.p + NET_OFF[2] + 32 * 32 * 27);
+    }
+    // layers 3 and 2: weight gradient, then the input gradient of the layer below
+    uint16_t *dcur = N.dza.p, *dnext = N.dzb.p;
+    for (int l = 2; l >= 1; l--) {
+        {
+            TimedScope t("conv_wgrad", s);
+            hipLaunchKernelGGL((k_conv_wgrad<32, 2, 32>), dim3(nwg), b, 0, s, N.nx, N.ny, N.nz, dcur,
+                               N.h[l - 1].p, N.part.p);
+            hipLaunchKernelGGL(k_wgrad_reduce, dim3((32 * 32 * 27 + 255) / 256), dim3(256), 0, s,
+                               N.part.p, nwg, 32, NN32, 32, 32, 32, N.grad.p + NET_OFF[l]);
+        }
+        {
+            TimedScope t("conv_dgrad", s);
+            hipLaunchKernelGGL((k_conv<32, 2, 2>), g, b, 0, s, N.nx, N.ny, N.nz, 32, dcur, N.wt[l].p,
+                               nullptr, dnext, nullptr, N.z[l - 1].p, N.part.p);
+            hipLaunchKernelGGL(k_bgrad_reduce, dim3(1), dim3(64), 0, s, N.part.p, (int)g.x, 32, 32,
+                               N.grad.p + NET_OFF[l - 1] + (l - 1 == 0 ? 32 * 4 * 27 : 32 * 32 * 27));
+        }
+        std::swap(dcur, dnext);
+    }
+    // layer 1: weight gradient from dz1 and the 4-channel input
+    {
+        TimedScope t("conv_wgrad", s);
+        hipLaunchKernelGGL((k_conv_wgrad<4, 2, 32>), dim3(nwg), b, 0, s, N.nx, N.ny, N.nz, dcur, N.h0.p,
+                           N.part.p);
+        hipLaunchKernelGGL(k_wgrad_reduce, dim3((32 * 4 * 27 + 255) / 256), dim3(256), 0, s, N.part.p,
+                           nwg, 32, NN4, 4, 4, 32, N.grad.p + NET_OFF[0]);
+    }
+    KRY_HIP(hipGetLastError());
+    return KRY_OK;
+}
+
+}  // namespace kry
+
+using namespace kry;
+
+struct LEARNED_ {
+    ConvNet net;
+    hipStream_t stream = nullptr;
+};
+
+static int copy_in(hipStream_t s, void *dst, const void *src, size_t bytes, int where) {
+    KRY_HIP(hipMemcpyAsync(dst, src, bytes, where == KRY_HOST ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice, s));
+    return KRY_OK;
+}
+
+extern "C" LEARNED *LearnedCreate(int nx, int ny, int nz, int training) {
+    LEARNED *L = new LEARNED_();
+    if (net_alloc(L->net, nx, ny, nz, training != 0) != KRY_OK) {
+        delete L;
+        return nullptr;
+    }
+    return L;
+}
+
+extern "C" int LearnedDestroy(LEARNED **Lp) {
+    if (!Lp || !*Lp) return KRY_OK;
+    delete *Lp;
+    *Lp = nullptr;
+    return KRY_OK;
+}
+
+extern "C" int LearnedNumParams(void) { return NET_OFF[4]; }
+
+extern "C" int LearnedSetStream(LEARNED *L, void *stream) {
+    if (!L) return set_error(KRY_ERR_ARG, "LearnedSetStream: NULL");
+    L->stream = static_cast<hipStream_t>(stream);
+    return KRY_OK;
+}
+
+extern "C" int LearnedSetParams(LEARNED *L, const float *params, int where) {
+    if (!L || !params) return set_error(KRY_ERR_ARG, "LearnedSetParams: NULL argument");
+    KRY_TRY(copy_in(L->stream, L->net.params.p, params, sizeof(float) * NET_OFF[4], where));
+    KRY_TRY(net_pack(L->stream, L->net));
+    KRY_HIP(hipStreamSynchronize(L->stream));
+    return KRY_OK;
+}
+
+extern "C" int LearnedGetParams(LEARNED *L, float *params_host) {
+    if (!L || !params_host) return set_error(KRY_ERR_ARG, "LearnedGetParams: NULL argument");
+    KRY_HIP(hipMemcpyAsync(params_host, L->net.params.p, sizeof(float) * NET_OFF[4], hipMemcpyDeviceToHost, L->stream));
+    KRY_HIP(hipStreamSynchronize(L->stream));
+    return KRY_OK;
+}
+
+extern "C" int LearnedForward(LEARNED *L, const float *in, float *out) {
+    if (!L || !in || !out) return set_error(KRY_ERR_ARG, "LearnedForward: NULL argument");
+    ConvNet &N = L->net;
+    const dim3 g((N.cells + 255) / 256), b(256);
+    hipLaunchKernelGGL(k_input_cm, g, b, 0, L->stream, N.cells, in, N.h0.p);
+    KRY_TRY(net_forward(L->stream, N));
+    hipLaunchKernelGGL(k_output_cm, g, b, 0, L->stream, N.cells, N.out.p, out);
+    KRY_HIP(hipGetLastError());
+    KRY_HIP(hipStreamSynchronize(L->stream));
+    return KRY_OK;
+}
+
+extern "C" int LearnedLossGrad(LEARNED *L, const float *in, const float *target, float *loss_host,
+                               float *grad) {
+    if (!L || !in || !target) return set_error(KRY_ERR_ARG, "LearnedLossGrad: NULL argument");
+    ConvNet &N = L->net;
+    if (!N.training) return set_error(KRY_ERR_ARG, "LearnedLossGrad: created without training buffers");
+    const dim3 g((N.cells + 255) / 256), b(256);
+    hipLaunchKernelGGL(k_input_cm, g, b, 0, L->stream, N.cells, in, N.h0.p);
+    KRY_TRY(net_forward(L->stream, N));
+    KRY_TRY(net_backward(L->stream, N, target));
+    if (grad)
+        KRY_HIP(hipMemcpyAsync(grad, N.grad.p, sizeof(float) * NET_OFF[4], hipMemcpyDeviceToDevice, L->stream));
+    float lh = 0.0f;
+    KRY_HIP(hipMemcpyAsync(&lh, N.loss.p, sizeof(float), hipMemcpyDeviceToHost, L->stream));
+    KRY_HIP(hipStreamSynchronize(L->stream));
+    if (loss_host) *loss_host = lh;
+    return KRY_OK;
+}
+
+extern "C" int LearnedAdamStep(LEARNED *L, float lr, float beta1, float beta2, float eps) {
+    if (!L) return set_error(KRY_ERR_ARG, "LearnedAdamStep: NULL");
+    ConvNet &N = L->net;
+    if (!N.training) return set_error(KRY_ERR_ARG, "LearnedAdamStep: created without training buffers");
+    N.adam_t += 1;
+    const float c1 = 1.0f - std::pow(beta1, (float)N.adam_t), c2 = 1.0f - std::pow(beta2, (float)N.adam_t);
+    const int np = NET_OFF[4];
+    hipLaunchKernelGGL(k_adam, dim3((np + 255) / 256), dim3(256), 0, L->stream, np, N.params.p, N.grad.p,
+                       N.m.p, N.v.p, lr, beta1, beta2, eps, c1, c2);
+    KRY_TRY(net_pack(L->stream, N));
+    KRY_HIP(hipStreamSynchronize(L->stream));
+    return KRY_OK;
+}
+
+// checkpoint: magic, version, nparams, adam step, params, m, v (FP32)
+extern "C" int LearnedSave(LEARNED *L, const char *path) {
+    if (!L || !path) return set_error(KRY_ERR_ARG, "LearnedSave: NULL argument");
+    ConvNet &N = L->net;
+    const int np = NET_OFF[4];
+    std::vector<float> p(np), m(np, 0.0f), v(np, 0.0f);
+    KRY_HIP(hipMemcpy(p.data(), N.params.p, sizeof(float) * np, hipMemcpyDeviceToHost));
+    if (N.training) {
+        KRY_HIP(hipMemcpy(m.data(), N.m.p, sizeof(float) * np, hipMemcpyDeviceToHost));
+        KRY_HIP(hipMemcpy(v.data(), N.v.p, sizeof(float) * np, hipMemcpyDeviceToHost));
+    }
+    FILE *f = std::fopen(path, "wb");
+    if (!f) return set_error(KRY_ERR_ARG, "LearnedSave: cannot open %s", path);
+    const int hdr[4] = {0x4B524C4E, 1, np, N.adam_t};
+    bool ok = std::fwrite(hdr, sizeof(int), 4, f) == 4 && std::fwrite(p.data(), sizeof(float), np, f) == (size_t)np &&
+              std::fwrite(m.data(), sizeof(float), np, f) == (size_t)np &&
+              std::fwrite(v.data(), sizeof(float), np, f) == (size_t)np;
+    ok = (std::fclose(f) == 0) && ok;
+    return ok ? KRY_OK : set_error(KRY_ERR_ARG, "LearnedSave: write failed for %s", path);
+}
+
+namespace kry {
+int learned_read_file(const char *path, std::vector<float> &p, std::vector<float> &m,
+                      std::vector<float> &v, int &adam_t) {
+    FILE *f = std::fopen(path, "rb");
+    if (!f) return set_error(KRY_ERR_ARG, "cannot open %s", path);
+    int hdr[4] = {0, 0, 0, 0};
+    const int np = NET_OFF[4];
+    bool ok = std::fread(hdr, sizeof(int), 4, f) == 4 && hdr[0] == 0x4B524C4E && hdr[1] == 1 && hdr[2] == np;
+    p.resize(np);
+    m.resize(np);
+    v.resize(np);
+    ok = ok && std::fread(p.data(), sizeof(float), np, f) == (size_t)np &&
+         std::fread(m.data(), sizeof(float), np, f) == (size_t)np &&
+         std::fread(v.data(), sizeof(float), np, f) == (size_t)np;
+    std::fclose(f);
+    if (!ok) return set_error(KRY_ERR_ARG, "%s is not a learned-stage checkpoint", path);
+    adam_t = hdr[3];
+    return KRY_OK;
+}
+}  // namespace kry
+
+extern "C" int LearnedLoad(LEARNED *L, const char *path) {
+    if (!L || !path) return set_error(KRY_ERR_ARG, "LearnedLoad: NULL argument");
+    std::vector<float> p, m, v;
+    int t = 0;
+    KRY_TRY(learned_read_file(path, p, m, v, t));
+    ConvNet &N = L->net;
+    const int np = NET_OFF[4];
+    KRY_HIP(hipMemcpy(N.params.p, p.data(), sizeof(float) * np, hipMemcpyHostToDevice));
+    if (N.training) {
+        KRY_HIP(hipMemcpy(N.m.p, m.data(), sizeof(float) * np, hipMemcpyHostToDevice));
+        KRY_HIP(hipMemcpy(N.v.p, v.data(), sizeof(float) * np, hipMemcpyHostToDevice));
+        N.adam_t = t;
+    }
+    KRY_TRY(net_pack(L->stream, N));
+    KRY_HIP(hipStreamSynchronize(L->stream));
+    return KRY_OK;
+}
+
+// ---------------------------------------------------------------------------
+// the stage inside a solver
+// ---------------------------------------------------------------------------
+namespace kry {
+
+struct LearnedStage {
+    ConvNet net;
+    DBuf<float> lnk;
+    DBuf<double> r, z2, nrm, partial;
+    DBuf<unsigned long long> counters;
+};
+
+void learned_stage_delete(LearnedStage *L) { delete L; }
+
+int learned_stage_create(hipStream_t s, const MAT_ *A, const float *params_host,
+                         const float *lnk, int lnk_where, LearnedStage **out) {
+    if (A->gnx <= 0 || A->bs != 3)
+        return set_error(KRY_ERR_ARG, "learned stage needs a 3x3-block 7-point grid matrix");
+    std::unique_ptr<LearnedStage> L(new LearnedStage());
+    KRY_TRY(net_alloc(L->net, A->gnx, A->gny, A->gnz, false));
+    const int64_t cells = L->net.cells, n = 3 * cells;
+    KRY_HIP(hipMemcpyAsync(L->net.params.p, params_host, sizeof(float) * NET_OFF[4], hipMemcpyHostToDevice, s));
+    KRY_TRY(net_pack(s, L->net));
+    KRY_TRY(L->lnk.alloc(cells));
+    KRY_TRY(copy_in(s, L->lnk.p, lnk, sizeof(float) * cells, lnk_where));
+    KRY_TRY(L->r.alloc(n));
+    KRY_TRY(L->z2.alloc(n));
+    KRY_TRY(L->nrm.alloc(2));
+    KRY_TRY(L->partial.alloc(RED_BLOCKS * 2));
+    KRY_TRY(L->counters.alloc(2));
+    KRY_HIP(hipMemsetAsync(L->counters.p, 0, 2 * sizeof(unsigned long long), s));
+    KRY_HIP(hipStreamSynchronize(s));
+    *out = L.release();
+    return KRY_OK;
+}
+
+// z holds z1 = M_base^-1 v on entry and the stage's result on exit
+int learned_stage_apply(hipStream_t s, const MAT_ *A, LearnedStage &L, const double *v, double *z) {
+    ConvNet &N = L.net;
+    const int64_t cells = N.cells, n = 3 * cells;
+    TimedScope t("learned_stage", s);
+    // r1 = v - A z1 and ||r1||
+    KRY_TRY(spmv_f64(s, A, -1.0, z, 1.0, v, L.r.p, 1, nullptr, nullptr, L.partial.p));
+    KRY_TRY(sum_partials(s, L.partial.p, RED_BLOCKS, 2, 1, L.nrm.p, SUM_SQRT));
+    const dim3 g((cells + 255) / 256), g3((n + 255) / 256), b(256);
+    hipLaunchKernelGGL(k_stage_input, g, b, 0, s, cells, L.r.p, L.nrm.p, L.lnk.p, N.h0.p);
+    KRY_TRY(net_forward(s, N));
+    hipLaunchKernelGGL(k_stage_update, g3, b, 0, s, cells, z, N.out.p, L.nrm.p, L.z2.p);
+    // ||v - A z2||
+    KRY_TRY(spmv_f64(s, A, -1.0, L.z2.p, 1.0, v, L.r.p, 1, nullptr, nullptr, L.partial.p));
+    KRY_TRY(sum_partials(s, L.partial.p, RED_BLOCKS, 2, 1, L.nrm.p + 1, SUM_SQRT));
+    hipLaunchKernelGGL(k_stage_select, g3, b, 0, s, n, L.z2.p, L.nrm.p, z, L.counters.p);
+    KRY_HIP(hipGetLastError());
+    return KRY_OK;
+}
+
+int learned_stage_stats(hipStream_t s, LearnedStage &L, int64_t *applies, int64_t *fallbacks) {
+    unsigned long long c[2] = {0, 0};
+    KRY_HIP(hipMemcpyAsync(c, L.counters.p, sizeof(c), hipMemcpyDeviceToHost, s));
+    KRY_HIP(hipStreamSynchronize(s));
+    if (applies) *applies = static_cast<int64_t>(c[0]);
+    if (fallbacks) *fallbacks = static_cast<int64_t>(c[1]);
+    return KRY_OK;
+}
+
+}  // namespace kry

@@ -1,0 +1,294 @@
+"""GPU parity of the learned preconditioner stage (network forward, loss
+gradient, Adam, checkpoints, the stage inside FGMRES) against the oracle.
+
+The oracle's BF16 emulation rounds the same operands the GPU rounds
+(activations, weights, upstream gradients) and sums in FP64; the GPU
+sums in FP32 on the matrix cores.  Activations are rounded after GELU,
+which the two evaluate in different precisions, so an operand can land
+on the other side of a BF16 rounding boundary; normwise tolerances below
+cover that (a few 1e-3)."""
+import os
+import tempfile
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_1701_05913_amd as K
+import reservoir_inputs as ri
+from gpu_helpers import DEV, GpuSystem
+from _helpers import relerr
+
+pytestmark = pytest.mark.gpu
+
+NP = 61443
+
+
+def _params(seed, scale=1.0):
+    """Uniform(-1/sqrt(fan_in), 1/sqrt(fan_in)) weights and biases, scaled."""
+    rng = np.random.default_rng(seed)
+    ch = oracle.CONV_CH
+    out = []
+    for l in range(4):
+        fan = ch[l] * 27
+        bound = 1.0 / np.sqrt(fan)
+        out.append(scale * rng.uniform(-bound, bound, ch[l + 1] * fan))
+        out.append(scale * rng.uniform(-bound, bound, ch[l + 1]))
+    return np.concatenate(out)
+
+
+def _layer_slices():
+    ch = oracle.CONV_CH
+    off, sl = 0, []
+    for l in range(4):
+        nw = ch[l + 1] * ch[l] * 27
+        sl.append((slice(off, off + nw), slice(off + nw, off + nw + ch[l + 1])))
+        off += nw + ch[l + 1]
+    return sl
+
+
+def _dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).to(DEV)
+
+
+def test_num_params():
+    assert K.LearnedNumParams() == NP == oracle.conv_nparams()
+
+
+@pytest.mark.parametrize("grid", [(16, 8, 4), (20, 18, 9), (5, 3, 2)])
+def test_forward_matches_oracle(grid):
+    nx, ny, nz = grid
+    cells = nx * ny * nz
+    prm = _params(11, scale=2.0)
+    inp = np.random.default_rng(1).standard_normal(4 * cells)
+    # the oracle sees the operands the GPU sees: FP32 parameters and inputs
+    prm32, inp32 = prm.astype(np.float32), inp.astype(np.float32)
+    ref = oracle.conv_forward(grid, prm32.astype(np.float64), inp32.astype(np.float64), bf16=True)
+    L = K.LearnedCreate(nx, ny, nz, False)
+    try:
+        K.LearnedSetParams(L, prm32)
+        out = torch.zeros(3 * cells, dtype=torch.float32, device=DEV)
+        K.LearnedForward(L, _dev(inp32), out)
+        got = out.cpu().numpy().astype(np.float64)
+    finally:
+        K.LearnedDestroy(L)
+    assert relerr(got, ref) <= 5e-3
+    # and close to the unrounded network
+    exact = oracle.conv_forward(grid, prm32.astype(np.float64), inp32.astype(np.float64))
+    assert relerr(got, exact) <= 3e-2
+
+
+def test_forward_delta_kernels_are_identity():
+    # centre-tap identity weights: GELU(x) = x to FP32 for x >= 10, and
+    # multiples of 1/16 in [10, 12) are exact in BF16
+    grid = (18, 9, 5)
+    nx, ny, nz = grid
+    cells = nx * ny * nz
+    ch = oracle.CONV_CH
+    parts = []
+    for l in range(4):
+        W = np.zeros((ch[l + 1], ch[l], 27))
+        for c in range(min(ch[l], ch[l + 1])):
+            W[c, c, 13] = 1.0
+        parts += [W.ravel(), np.zeros(ch[l + 1])]
+    prm = np.concatenate(parts).astype(np.float32)
+    rng = np.random.default_rng(2)
+    inp = (10.0 + rng.integers(0, 32, 4 * cells) / 16.0).astype(np.float32)
+    L = K.LearnedCreate(nx, ny, nz, False)
+    try:
+        K.LearnedSetParams(L, prm)
+        out = torch.zeros(3 * cells, dtype=torch.float32, device=DEV)
+        K.LearnedForward(L, _dev(inp), out)
+        got = out.cpu().numpy()
+    finally:
+        K.LearnedDestroy(L)
+    assert np.array_equal(got, inp[:3 * cells])
+
+
+@pytest.mark.parametrize("grid", [(12, 10, 6), (17, 5, 3)])
+def test_loss_gradient_matches_oracle(grid):
+    nx, ny, nz = grid
+    cells = nx * ny * nz
+    rng = np.random.default_rng(3)
+    prm = _params(12, scale=2.0).astype(np.float32)
+    inp = rng.standard_normal(4 * cells).astype(np.float32)
+    tgt = rng.standard_normal(3 * cells).astype(np.float32)
+    loss_ref, grad_ref = oracle.conv_loss_grad(grid, prm.astype(np.float64), inp.astype(np.float64),
+                                               tgt.astype(np.float64), bf16=True)
+    L = K.LearnedCreate(nx, ny, nz, True)
+    try:
+        K.LearnedSetParams(L, prm)
+        grad = torch.zeros(NP, dtype=torch.float32, device=DEV)
+        loss = K.LearnedLossGrad(L, _dev(inp), _dev(tgt), grad)
+        g = grad.cpu().numpy().astype(np.float64)
+    finally:
+        K.LearnedDestroy(L)
+    assert abs(loss - loss_ref) <= 1e-3 * abs(loss_ref)
+    for l, (ws, bs) in enumerate(_layer_slices()):
+        assert relerr(g[ws], grad_ref[ws]) <= 1e-2, f"layer {l + 1} weights"
+        assert relerr(g[bs], grad_ref[bs]) <= 1e-2, f"layer {l + 1} bias"
+
+
+def test_adam_step_matches_oracle():
+    grid = (9, 7, 5)
+    nx, ny, nz = grid
+    cells = nx * ny * nz
+    rng = np.random.default_rng(4)
+    prm = _params(13).astype(np.float32)
+    inp = rng.standard_normal(4 * cells).astype(np.float32)
+    tgt = rng.standard_normal(3 * cells).astype(np.float32)
+    L = K.LearnedCreate(nx, ny, nz, True)
+    try:
+        K.LearnedSetParams(L, prm)
+        grad = torch.zeros(NP, dtype=torch.float32, device=DEV)
+        K.LearnedLossGrad(L, _dev(inp), _dev(tgt), grad)
+        K.LearnedAdamStep(L, 1e-3, 0.9, 0.999, 1e-8)
+        p1 = K.LearnedGetParams(L).astype(np.float64)
+        g = grad.cpu().numpy().astype(np.float64)
+    finally:
+        K.LearnedDestroy(L)
+    ref, _, _ = oracle.adam_step(prm.astype(np.float64), g, np.zeros(NP), np.zeros(NP), 1, lr=1e-3)
+    assert np.max(np.abs(p1 - ref)) <= 1e-6
+
+
+def test_checkpoint_resume_reproduces_training():
+    grid = (10, 9, 6)
+    nx, ny, nz = grid
+    cells = nx * ny * nz
+    rng = np.random.default_rng(5)
+    prm = _params(14).astype(np.float32)
+    data = [(_dev(rng.standard_normal(4 * cells)), _dev(rng.standard_normal(3 * cells)))
+            for _ in range(5)]
+
+    def run(L, batches):
+        losses = []
+        for inp, tgt in batches:
+            losses.append(K.LearnedLossGrad(L, inp, tgt))
+            K.LearnedAdamStep(L, 2e-3)
+        return losses
+
+    A = K.LearnedCreate(nx, ny, nz, True)
+    B = K.LearnedCreate(nx, ny, nz, True)
+    C = K.LearnedCreate(nx, ny, nz, True)
+    try:
+        K.LearnedSetParams(A, prm)
+        straight = run(A, data)
+        K.LearnedSetParams(B, prm)
+        first = run(B, data[:3])
+        with tempfile.TemporaryDirectory() as d:
+            path = os.path.join(d, "ckpt.bin")
+            K.LearnedSave(B, path)
+            K.LearnedLoad(C, path)
+        resumed = run(C, data[3:])
+        assert first + resumed == straight
+        assert np.array_equal(K.LearnedGetParams(A), K.LearnedGetParams(C))
+    finally:
+        for h in (A, B, C):
+            K.LearnedDestroy(h)
+
+
+# ---- the stage inside the solver ------------------------------------------------
+def _stage_solver(G, s, pc_type, params, solver=K.KRY_FGMRES):
+    S = K.SolverCreate(solver, pc_type, G.map)
+    K.SolverSetMat(S, G.A)
+    K.SolverSetStream(S, torch.cuda.current_stream())
+    if params is not None:
+        K.SolverSetLearnedParams(S, np.ascontiguousarray(params, dtype=np.float32),
+                                 np.ascontiguousarray(s["lnk"], dtype=np.float32))
+    K.SolverAssemble(S)
+    return S
+
+
+def _pc_apply(G, S, v):
+    vt, vh = G.vec(v)
+    zt, zh = G.vec()
+    K.SolverPCApply(S, vh, zh)
+    torch.cuda.synchronize()
+    return zt.cpu().numpy()
+
+
+@pytest.mark.parametrize("kind", ["zero", "nan"])
+def test_stage_rejected_correction_returns_base_bit_exactly(kind):
+    s = ri.blackoil_system(13, 9, 6, seed=21)
+    G = GpuSystem(s)
+    v = np.random.default_rng(6).standard_normal(G.n)
+    prm = np.zeros(NP) if kind == "zero" else np.full(NP, np.nan)
+    Sb = _stage_solver(G, s, K.KRY_PC_BILU0, None)
+    Sl = _stage_solver(G, s, K.KRY_PC_BILU0_LEARNED, prm)
+    try:
+        zb = _pc_apply(G, Sb, v)
+        zl = _pc_apply(G, Sl, v)
+        assert np.array_equal(zl, zb)
+        assert K.SolverGetLearnedStats(Sl) == (1, 1)
+    finally:
+        K.SolverDestroy(Sb)
+        K.SolverDestroy(Sl)
+        G.close()
+
+
+def test_stage_matches_oracle_stage():
+    s = ri.blackoil_system(12, 10, 6, seed=22)
+    G = GpuSystem(s)
+    A = oracle.Matrix.from_system(s)
+    v = np.random.default_rng(7).standard_normal(G.n)
+    prm = (_params(15) * 0.05).astype(np.float32)
+    S = _stage_solver(G, s, K.KRY_PC_BILU0_LEARNED, prm)
+    try:
+        z = _pc_apply(G, S, v)
+        applies, falls = K.SolverGetLearnedStats(S)
+    finally:
+        K.SolverDestroy(S)
+        G.close()
+    pc = oracle.PC.learned(oracle.PC(A, "bilu0"), s["grid"], prm.astype(np.float64),
+                           np.asarray(s["lnk"], dtype=np.float32).astype(np.float64), bf16=True)
+    zr = pc.apply(v)
+    assert (applies, falls) == (1, pc.learned_stats()[1])
+    assert relerr(z, zr) <= 1e-3
+
+
+def test_zero_network_solve_equals_plain_fgmres():
+    s = ri.blackoil_system(16, 12, 8, seed=23)
+    G = GpuSystem(s)
+    b = np.asarray(s["b"])
+    res = {}
+    for name, pc, prm in [("plain", K.KRY_PC_BILU0, None), ("zero", K.KRY_PC_BILU0_LEARNED, np.zeros(NP))]:
+        S = _stage_solver(G, s, pc, prm)
+        K.SolverSetRtol(S, 1e-8)
+        K.SolverSetMaxit(S, 1000)
+        bt, bh = G.vec(b)
+        xt, xh = G.vec()
+        rc = K.SolverSolve(S, bh, xh)
+        torch.cuda.synchronize()
+        res[name] = (rc, K.SolverGetIters(S), xt.cpu().numpy())
+        if pc == K.KRY_PC_BILU0_LEARNED:
+            a, f = K.SolverGetLearnedStats(S)
+            assert a == f and a >= K.SolverGetIters(S)
+        K.SolverDestroy(S)
+    G.close()
+    assert res["plain"][0] == res["zero"][0] == 0
+    assert res["plain"][1] == res["zero"][1]
+    assert np.array_equal(res["plain"][2], res["zero"][2])
+
+
+def test_learned_stage_requires_fgmres_and_params():
+    s = ri.blackoil_system(6, 5, 4, seed=24)
+    G = GpuSystem(s)
+    try:
+        S = K.SolverCreate(K.KRY_GMRES, K.KRY_PC_BILU0_LEARNED, G.map)
+        K.SolverSetMat(S, G.A)
+        K.SolverSetLearnedParams(S, np.zeros(NP, dtype=np.float32), np.zeros(G.nb, dtype=np.float32))
+        with pytest.raises(K.KrylovError):
+            K.SolverAssemble(S)
+        K.SolverDestroy(S)
+        S = K.SolverCreate(K.KRY_FGMRES, K.KRY_PC_BILU0_LEARNED, G.map)
+        K.SolverSetMat(S, G.A)
+        with pytest.raises(K.KrylovError):
+            K.SolverAssemble(S)                  # no parameters yet
+        K.SolverDestroy(S)
+        S = K.SolverCreate(K.KRY_FGMRES, K.KRY_PC_BILU0, G.map)
+        with pytest.raises(K.KrylovError):
+            K.SolverSetLearnedParams(S, np.zeros(NP, dtype=np.float32), np.zeros(G.nb, dtype=np.float32))
+        K.SolverDestroy(S)
+    finally:
+        G.close()
