@@ -236,6 +236,13 @@ int SolverGetLearnedStats(SOLVER *s, int64_t *applies, int64_t *fallbacks);
  *   LearnedSave / LearnedLoad: checkpoint (parameters, Adam moments and
  *     step count) in a little-endian binary file.
  * All calls synchronize the object's stream (LearnedSetStream). */
+/* Training pair of the stage (extension (4) harvest): from the residual
+ * r1 = v - A M_base^-1 v and its exact correction d = A^-1 r1 (FP64,
+ * interleaved, 3 values per cell, device), writes in = [r1 / s, ln k] and
+ * target = d / s, channel-major FP32 on the device, s = ||r1|| / sqrt(n)
+ * (returned in *s_host).  Runs on the VEC / MAT stream and synchronizes. */
+int LearnedMakePair(int64_t cells, const double *r1, const double *d, const float *logk,
+                    float *in, float *target, double *s_host);
 LEARNED *LearnedCreate(int nx, int ny, int nz, int training);
 int LearnedDestroy(LEARNED **L);
 int LearnedNumParams(void);

@@ -9,6 +9,10 @@ when the library reports an error.
 
 Build with `python -m paper_1701_05913_amd.build` (or
 `__graft_entry__.build()`).
+
+torch ships its own HIP runtime; the binding imports torch before it
+loads the library, so that the library binds to the runtime already in
+the process and both share one GPU context.
 """
 from __future__ import annotations
 
@@ -42,6 +46,10 @@ class KrylovError(RuntimeError):
 
 if not os.path.exists(LIBRARY):
     raise ImportError(f"{LIBRARY} is not built; run `python -m paper_1701_05913_amd.build`")
+
+# one HIP runtime per process: torch's, loaded before the library (the
+# library's own dependency then resolves to it)
+import torch  # noqa: E402,F401
 
 _lib = C.CDLL(LIBRARY)
 
@@ -92,6 +100,7 @@ _SIGS = {
     "LearnedLossGrad": (C.c_int, [P, P, P, C.POINTER(C.c_float), P]),
     "LearnedAdamStep": (C.c_int, [P, C.c_float, C.c_float, C.c_float, C.c_float]),
     "LearnedSave": (C.c_int, [P, C.c_char_p]), "LearnedLoad": (C.c_int, [P, C.c_char_p]),
+    "LearnedMakePair": (C.c_int, [I64, P, P, P, P, P, C.POINTER(D)]),
 }
 for _name, (_res, _args) in _SIGS.items():
     _f = getattr(_lib, _name)
@@ -368,6 +377,14 @@ def SolverGetLearnedStats(s):
     a, f = C.c_int64(0), C.c_int64(0)
     _check(_lib.SolverGetLearnedStats(s, C.byref(a), C.byref(f)))
     return a.value, f.value
+
+
+def LearnedMakePair(cells, r1, d, logk, inp, target):
+    """Returns s; r1, d: CUDA float64 tensors; logk, inp, target: CUDA float32."""
+    sv = C.c_double(0)
+    _check(_lib.LearnedMakePair(cells, _dptr(r1), _dptr(d), _fdptr(logk), _fdptr(inp),
+                                _fdptr(target), C.byref(sv)))
+    return sv.value
 
 
 def LearnedCreate(nx, ny, nz, training=False):

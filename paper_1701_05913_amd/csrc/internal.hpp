@@ -179,6 +179,9 @@ int sell_build_perm_free(hipStream_t s, int nrows, int bs, const int *d_rowptr,
 int spmv_f64(hipStream_t s, const MAT_ *A, double alpha, const double *x,
              double beta, const double *z, double *y, int ndot,
              const double *u0, const double *u1, double *partial);
+// number of partial-sum pairs a fused-dot SpMV of A writes (one per block;
+// its partial buffer needs twice this many doubles)
+int spmv_partial_blocks(const MAT_ *A);
 int spmv_sell_f32(hipStream_t s, const Sell &S, int nrows, float alpha,
                   const float *x, float beta, const float *z, float *y);
 int spmv_sell_f64(hipStream_t s, const Sell &S, int nrows, double alpha,

@@ -336,7 +336,7 @@ __global__ void k_zero_int(int *p) {
 // ---------------------------------------------------------------------------
 // host helpers
 // ---------------------------------------------------------------------------
-static int spmv_blocks(const MAT_ *A) { return (A->sell.nslices * 64 + 255) / 256; }
+static int spmv_blocks(const MAT_ *A) { return spmv_partial_blocks(A); }
 
 static int ensure_workspace(SOLVER_ *S) {
     const int64_t n = (int64_t)S->A->nb * S->A->bs;

@@ -800,6 +800,42 @@ extern "C" int LearnedLoad(LEARNED *L, const char *path) {
     return KRY_OK;
 }
 
+// training pair: in = [r1 / s, ln k], target = d / s (channel-major FP32)
+__global__ void k_make_pair(int64_t cells, const double *__restrict__ r1, const double *__restrict__ d,
+                            const float *__restrict__ lnk, const double *__restrict__ nrm,
+                            float *__restrict__ in, float *__restrict__ target) {
+    const int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (c >= cells) return;
+    const double s = nrm[0] / sqrt(3.0 * (double)cells);
+    const double inv = s > 0.0 ? 1.0 / s : 0.0;
+#pragma unroll
+    for (int k = 0; k < 3; k++) {
+        in[k * cells + c] = static_cast<float>(r1[c * 3 + k] * inv);
+        target[k * cells + c] = static_cast<float>(d[c * 3 + k] * inv);
+    }
+    in[3 * cells + c] = lnk[c];
+}
+
+extern "C" int LearnedMakePair(int64_t cells, const double *r1, const double *d, const float *logk,
+                               float *in, float *target, double *s_host) {
+    if (cells <= 0 || !r1 || !d || !logk || !in || !target)
+        return set_error(KRY_ERR_ARG, "LearnedMakePair: bad argument");
+    hipStream_t s = global_stream();
+    DBuf<double> part, nrm;
+    KRY_TRY(part.alloc(RED_BLOCKS * 2));
+    KRY_TRY(nrm.alloc(1));
+    KRY_TRY(vec_dot_partial(s, 3 * cells, r1, r1, nullptr, nullptr, part.p));
+    KRY_TRY(sum_partials(s, part.p, RED_BLOCKS, 2, 1, nrm.p, SUM_SQRT));
+    hipLaunchKernelGGL(k_make_pair, dim3((cells + 255) / 256), dim3(256), 0, s, cells, r1, d, logk, nrm.p,
+                       in, target);
+    KRY_HIP(hipGetLastError());
+    double h = 0.0;
+    KRY_HIP(hipMemcpyAsync(&h, nrm.p, sizeof(double), hipMemcpyDeviceToHost, s));
+    KRY_HIP(hipStreamSynchronize(s));
+    if (s_host) *s_host = h / std::sqrt(3.0 * (double)cells);
+    return KRY_OK;
+}
+
 // ---------------------------------------------------------------------------
 // the stage inside a solver
 // ---------------------------------------------------------------------------
@@ -828,7 +864,8 @@ int learned_stage_create(hipStream_t s, const MAT_ *A, const float *params_host,
     KRY_TRY(L->r.alloc(n));
     KRY_TRY(L->z2.alloc(n));
     KRY_TRY(L->nrm.alloc(2));
-    KRY_TRY(L->partial.alloc(RED_BLOCKS * 2));
+    // one partial pair per SpMV block (the fused-dot SpMV's layout)
+    KRY_TRY(L->partial.alloc((size_t)spmv_partial_blocks(A) * 2));
     KRY_TRY(L->counters.alloc(2));
     KRY_HIP(hipMemsetAsync(L->counters.p, 0, 2 * sizeof(unsigned long long), s));
     KRY_HIP(hipStreamSynchronize(s));
@@ -842,15 +879,16 @@ int learned_stage_apply(hipStream_t s, const MAT_ *A, LearnedStage &L, const dou
     const int64_t cells = N.cells, n = 3 * cells;
     TimedScope t("learned_stage", s);
     // r1 = v - A z1 and ||r1||
+    const int nsb = spmv_partial_blocks(A);
     KRY_TRY(spmv_f64(s, A, -1.0, z, 1.0, v, L.r.p, 1, nullptr, nullptr, L.partial.p));
-    KRY_TRY(sum_partials(s, L.partial.p, RED_BLOCKS, 2, 1, L.nrm.p, SUM_SQRT));
+    KRY_TRY(sum_partials(s, L.partial.p, nsb, 2, 1, L.nrm.p, SUM_SQRT));
     const dim3 g((cells + 255) / 256), g3((n + 255) / 256), b(256);
     hipLaunchKernelGGL(k_stage_input, g, b, 0, s, cells, L.r.p, L.nrm.p, L.lnk.p, N.h0.p);
     KRY_TRY(net_forward(s, N));
     hipLaunchKernelGGL(k_stage_update, g3, b, 0, s, cells, z, N.out.p, L.nrm.p, L.z2.p);
     // ||v - A z2||
     KRY_TRY(spmv_f64(s, A, -1.0, L.z2.p, 1.0, v, L.r.p, 1, nullptr, nullptr, L.partial.p));
-    KRY_TRY(sum_partials(s, L.partial.p, RED_BLOCKS, 2, 1, L.nrm.p + 1, SUM_SQRT));
+    KRY_TRY(sum_partials(s, L.partial.p, nsb, 2, 1, L.nrm.p + 1, SUM_SQRT));
     hipLaunchKernelGGL(k_stage_select, g3, b, 0, s, n, L.z2.p, L.nrm.p, z, L.counters.p);
     KRY_HIP(hipGetLastError());
     return KRY_OK;

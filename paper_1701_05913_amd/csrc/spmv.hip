@@ -221,6 +221,8 @@ static int launch_spmv(hipStream_t s, const Sell &S, const TA *val, int nrows, T
     return KRY_OK;
 }
 
+int spmv_partial_blocks(const MAT_ *A) { return static_cast<int>(sell_grid(A->sell).x); }
+
 int spmv_f64(hipStream_t s, const MAT_ *A, double alpha, const double *x, double beta,
              const double *z, double *y, int ndot, const double *u0, const double *u1,
              double *partial) {

@@ -1,0 +1,228 @@
+"""Train the learned preconditioner stage on the GPU and evaluate it.
+
+Harvest: for each training system (seeded black-oil generator, known
+x_true with b = A x_true), FGMRES(m)+BILU(0) runs from x = 0 one restart
+cycle at a time; after every cycle the current residual v = b - A x gives
+the stage's input r1 = v - A z1 (z1 = BILU(0)^-1 v) and its exact target
+A^-1 r1 = (x_true - x) - z1.  Each pair is normalised by s = ||r1|| /
+sqrt(n) (LearnedMakePair) and kept in device memory.
+
+Train: Adam on the mean squared error of the network output against the
+normalised target, one pair per step, cosine learning-rate decay, seeded
+shuffling; the checkpoint (parameters, Adam moments, step count) is written
+with LearnedSave.
+
+Evaluate: FGMRES(30) with BILU(0) alone and with the learned stage on
+held-out seeds, to the same relative tolerance; iterations, wall time and
+the fraction of stage applications that fell back.
+
+Every arithmetic step runs in libkrylov.so; torch only provides device
+memory.
+
+  python -m paper_1701_05913_amd.learned_train --out weights.bin
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import time
+
+import numpy as np
+import torch
+
+import paper_1701_05913_amd as K
+import reservoir_inputs as ri
+
+DEV = "cuda:0"
+
+
+class System:
+    """One generated system uploaded through the C ABI."""
+
+    def __init__(self, grid, seed, perm="layered"):
+        s = ri.blackoil_system(*grid, seed=seed, perm=perm)
+        self.grid, self.seed = grid, seed
+        self.nb, self.n = s["nb"], s["n"]
+        self.map = K.MapCreateLocal(self.n)
+        self.A = K.MatCreateBSR(self.map, self.nb, 3, np.asarray(s["rowptr"], np.int32),
+                                np.asarray(s["col"], np.int32),
+                                np.ascontiguousarray(np.asarray(s["val"], np.float64).reshape(-1)))
+        self.b = torch.from_numpy(np.asarray(s["b"], np.float64)).to(DEV)
+        self.x_true = torch.from_numpy(np.asarray(s["x_true"], np.float64)).to(DEV)
+        self.lnk = torch.from_numpy(np.asarray(s["lnk"], np.float32)).to(DEV)
+        self._vecs = []
+
+    def vec(self, t):
+        h = K.VecWrap(self.map, t)
+        self._vecs.append(h)
+        return h
+
+    def solver(self, pc, restart=30, rtol=1e-8, maxit=2000, params=None):
+        S = K.SolverCreate(K.KRY_FGMRES, pc, self.map)
+        K.SolverSetMat(S, self.A)
+        K.SolverSetStream(S, torch.cuda.current_stream())
+        K.SolverSetRestart(S, restart)
+        K.SolverSetRtol(S, rtol)
+        K.SolverSetMaxit(S, maxit)
+        if params is not None:
+            K.SolverSetLearnedParams(S, np.ascontiguousarray(params, np.float32), self.lnk)
+        K.SolverAssemble(S)
+        return S
+
+    def close(self):
+        torch.cuda.synchronize()
+        for h in self._vecs:
+            K.VecDestroy(h)
+        K.MatDestroy(self.A)
+        K.MapDestroy(self.map)
+
+
+def harvest(sys_, restart, cycles, stop_relres=1e-10):
+    """Pairs (input, target) on the device from restart cycles of one solve."""
+    K.KrylovSetStream(torch.cuda.current_stream())
+    S = sys_.solver(K.KRY_PC_BILU0, restart=restart, rtol=0.0, maxit=restart)
+    n, cells = sys_.n, sys_.nb
+    x = torch.zeros(n, dtype=torch.float64, device=DEV)
+    v = torch.empty_like(x)
+    z1 = torch.empty_like(x)
+    r1 = torch.empty_like(x)
+    d = torch.empty_like(x)
+    hb, hx, hv, hz, hr, hd = (sys_.vec(t) for t in (sys_.b, x, v, z1, r1, d))
+    hxt = sys_.vec(sys_.x_true)
+    bnorm = K.VecNorm2(hb)
+    pairs = []
+    for _ in range(cycles):
+        K.SolverSolve(S, hb, hx)                     # one FGMRES(m) cycle from x
+        v.copy_(sys_.b)
+        K.MatVecAMXPBY(-1.0, sys_.A, hx, 1.0, hv)    # v = b - A x
+        if K.VecNorm2(hv) <= stop_relres * bnorm:
+            break
+        K.SolverPCApply(S, hv, hz)                   # z1 = BILU(0)^-1 v
+        r1.copy_(v)
+        K.MatVecAMXPBY(-1.0, sys_.A, hz, 1.0, hr)    # r1 = v - A z1
+        K.VecAXPBYZ(1.0, hxt, -1.0, hx, hd)          # d = x_true - x
+        K.VecAXPBY(-1.0, hz, 1.0, hd)                # d -= z1  (= A^-1 r1)
+        inp = torch.empty(4 * cells, dtype=torch.float32, device=DEV)
+        tgt = torch.empty(3 * cells, dtype=torch.float32, device=DEV)
+        K.LearnedMakePair(cells, r1, d, sys_.lnk, inp, tgt)
+        pairs.append((inp, tgt))
+    K.SolverDestroy(S)
+    return pairs
+
+
+def init_params(seed, last_scale=0.1):
+    """Uniform(-1/sqrt(fan_in), +1/sqrt(fan_in)); the output layer scaled
+    down so the first corrections are small."""
+    rng = np.random.default_rng(seed)
+    ch = (4, 32, 32, 32, 3)
+    out = []
+    for l in range(4):
+        fan = ch[l] * 27
+        bound = 1.0 / math.sqrt(fan)
+        sc = last_scale if l == 3 else 1.0
+        out.append(sc * rng.uniform(-bound, bound, ch[l + 1] * fan))
+        out.append(sc * rng.uniform(-bound, bound, ch[l + 1]))
+    return np.concatenate(out).astype(np.float32)
+
+
+def train(pairs, grid, epochs, lr, seed, log_every=200):
+    L = K.LearnedCreate(*grid, True)
+    K.LearnedSetStream(L, torch.cuda.current_stream())
+    K.LearnedSetParams(L, init_params(seed))
+    rng = np.random.default_rng(seed)
+    total = epochs * len(pairs)
+    step, curve, t0 = 0, [], time.perf_counter()
+    for ep in range(epochs):
+        order = rng.permutation(len(pairs))
+        acc = 0.0
+        for i in order:
+            inp, tgt = pairs[i]
+            loss = K.LearnedLossGrad(L, inp, tgt)
+            lr_t = 0.5 * lr * (1.0 + math.cos(math.pi * step / max(total, 1)))
+            K.LearnedAdamStep(L, lr_t, 0.9, 0.999, 1e-8)
+            acc += loss
+            step += 1
+            if step % log_every == 0:
+                print(f"  step {step}/{total} loss {loss:.4e}", flush=True)
+        curve.append(acc / len(pairs))
+        print(f"epoch {ep}: mean loss {curve[-1]:.4e} ({time.perf_counter() - t0:.1f} s)", flush=True)
+    return L, curve, time.perf_counter() - t0
+
+
+def evaluate(grid, seeds, params, rtol=1e-8, restart=30):
+    rows = []
+    for seed in seeds:
+        sys_ = System(grid, seed)
+        row = {"seed": seed, "grid": list(grid)}
+        for name, pc, prm in [("bilu0", K.KRY_PC_BILU0, None),
+                              ("bilu0_learned", K.KRY_PC_BILU0_LEARNED, params)]:
+            S = sys_.solver(pc, restart=restart, rtol=rtol, params=prm)
+            x = torch.zeros(sys_.n, dtype=torch.float64, device=DEV)
+            hb, hx = sys_.vec(sys_.b), sys_.vec(x)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            rc = K.SolverSolve(S, hb, hx)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            ent = {"status": rc, "iters": K.SolverGetIters(S), "relres": K.SolverGetResidual(S),
+                   "solve_s": round(dt, 4)}
+            if prm is not None:
+                a, f = K.SolverGetLearnedStats(S)
+                ent["stage_applies"], ent["stage_fallbacks"] = a, f
+            row[name] = ent
+            K.SolverDestroy(S)
+        print(json.dumps(row), flush=True)
+        rows.append(row)
+        sys_.close()
+    return rows
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
+    ap.add_argument("--out", required=True, help="checkpoint file to write")
+    ap.add_argument("--grid", default="64,64,64")
+    ap.add_argument("--train-seeds", default="0:32", help="first:last (exclusive)")
+    ap.add_argument("--eval-seeds", default="10000:10004")
+    ap.add_argument("--restart", type=int, default=10, help="FGMRES restart during harvest")
+    ap.add_argument("--cycles", type=int, default=40, help="restart cycles harvested per system")
+    ap.add_argument("--epochs", type=int, default=4)
+    ap.add_argument("--lr", type=float, default=1e-3)
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--report", default=None, help="JSON summary file")
+    a = ap.parse_args(argv)
+    # torch's CUDA context first, then the library (see the binding's notes)
+    torch.zeros(1, device=DEV)
+    grid = tuple(int(v) for v in a.grid.split(","))
+    t0, t1 = (int(v) for v in a.train_seeds.split(":"))
+    e0, e1 = (int(v) for v in a.eval_seeds.split(":"))
+
+    pairs, th = [], time.perf_counter()
+    for seed in range(t0, t1):
+        sys_ = System(grid, seed)
+        p = harvest(sys_, a.restart, a.cycles)
+        pairs += p
+        sys_.close()
+        print(f"harvest seed {seed}: {len(p)} pairs (total {len(pairs)})", flush=True)
+    t_harvest = time.perf_counter() - th
+
+    L, curve, t_train = train(pairs, grid, a.epochs, a.lr, a.seed)
+    K.LearnedSave(L, a.out)
+    params = K.LearnedGetParams(L)
+    K.LearnedDestroy(L)
+    del pairs
+    torch.cuda.empty_cache()
+
+    rows = evaluate(grid, range(e0, e1), params)
+    summary = {"grid": list(grid), "train_seeds": [t0, t1], "eval_seeds": [e0, e1],
+               "restart_harvest": a.restart, "cycles": a.cycles, "epochs": a.epochs, "lr": a.lr,
+               "harvest_s": round(t_harvest, 1), "train_s": round(t_train, 1),
+               "loss_per_epoch": curve, "eval": rows}
+    if a.report:
+        with open(a.report, "w") as f:
+            json.dump(summary, f, indent=1)
+    print(json.dumps({k: v for k, v in summary.items() if k != "eval"}))
+
+
+if __name__ == "__main__":
+    main()

@@ -292,3 +292,34 @@ def test_learned_stage_requires_fgmres_and_params():
         K.SolverDestroy(S)
     finally:
         G.close()
+
+
+def test_stage_decision_on_a_grid_with_many_spmv_blocks():
+    # 64 x 48 x 48 cells: the fused-dot SpMV runs 576 blocks (more than the
+    # fixed 512-way reductions), so the stage's residual norms must take
+    # one partial per SpMV block
+    import scipy.sparse as sp
+    s = ri.blackoil_system(64, 48, 48, seed=25)
+    G = GpuSystem(s)
+    A = sp.bsr_matrix((np.asarray(s["val"]).reshape(-1, 3, 3), np.asarray(s["col"]),
+                       np.asarray(s["rowptr"])), shape=(G.n, G.n))
+    v = np.random.default_rng(8).standard_normal(G.n)
+    Sb = _stage_solver(G, s, K.KRY_PC_BILU0, None)
+    Sz = _stage_solver(G, s, K.KRY_PC_BILU0_LEARNED, np.zeros(NP))
+    Sr = _stage_solver(G, s, K.KRY_PC_BILU0_LEARNED, (_params(16) * 0.05).astype(np.float32))
+    try:
+        z1 = _pc_apply(G, Sb, v)
+        assert np.array_equal(_pc_apply(G, Sz, v), z1)
+        assert K.SolverGetLearnedStats(Sz) == (1, 1)
+        z = _pc_apply(G, Sr, v)
+        applies, falls = K.SolverGetLearnedStats(Sr)
+        n1 = np.linalg.norm(v - A @ z1)
+        if falls == 1:
+            assert np.array_equal(z, z1)
+        else:
+            assert np.linalg.norm(v - A @ z) < n1
+        assert applies == 1
+    finally:
+        for S in (Sb, Sz, Sr):
+            K.SolverDestroy(S)
+        G.close()
