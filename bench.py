@@ -5,7 +5,8 @@ timed on the host.
 
 One step = one full pass of the solve path for every configuration in
 CONFIGS (preconditioner setup + solve from x0 = 0 each time, inputs
-resident in HBM).  `value` is the mean time-to-solution of the plain
+resident in HBM).  The learned-stage configuration loads the trained
+network shipped in paper_1701_05913_amd/weights/.  `value` is the mean time-to-solution of the plain
 FP64 GMRES(30) + BILU(0) solve; every configuration's time, iterations and
 true residual are reported under "variants".
 
@@ -48,7 +49,14 @@ CONFIGS = [
     ("fgmres30_bilu0_bf16", "FGMRES", "BILU0", "BF16_FACTORS", None),
     ("fgmres30_cpr_f64", "FGMRES", "CPR", "F64", ("PF", 4)),
     ("fgmres30_cpr_f32", "FGMRES", "CPR", "F32", ("PF", 4)),
+    ("fgmres30_bilu0_learned", "FGMRES", "BILU0_LEARNED", "F64", None),
 ]
+WEIGHTS = os.path.join(ROOT, "paper_1701_05913_amd", "weights", "bilu0_blackoil64.bin")
+
+# matrix-core FLOPs per cell of each conv layer (3x3x3 taps, 2 per MAC)
+CONV_FLOPS_PER_CELL = {"conv_l1_fwd": 2 * 27 * 4 * 32, "conv_l2_fwd": 2 * 27 * 32 * 32,
+                       "conv_l3_fwd": 2 * 27 * 32 * 32, "conv_l4_fwd": 2 * 27 * 32 * 3}
+MFMA_BF16_PEAK_TFLOPS = 2500.0
 HEADLINE = "gmres30_bilu0_f64"
 
 
@@ -94,30 +102,35 @@ def traffic_from_profiles(kernel):
         return None
 
 
-def cpu_baseline(s, rtol, budget_s=40.0):
+def cpu_baseline(s, rtol, gpu_iters, budget_s=40.0):
     """The FP64 oracle (single-threaded C, as written) on the same system:
-    BILU(0) setup + GMRES(30) to rtol.  If the solve would take longer than
-    the budget, a prefix of iterations is timed and scaled to the oracle's
-    per-iteration cost times the GPU-measured iteration count."""
+    BILU(0) setup + GMRES(30) to rtol.  A 10-iteration prefix sizes the run:
+    if the whole solve (about gpu_iters + one restart cycle of iterations)
+    fits the budget it runs to the tolerance; otherwise a fixed-iteration
+    prefix that fits is timed and scaled to the GPU's iteration count."""
     import oracle
     A = oracle.Matrix.from_system(s)
     t0 = time.perf_counter()
     pc = oracle.PC(A, "bilu0")
     t_setup = time.perf_counter() - t0
-    # prefix timing to size the run
     t0 = time.perf_counter()
     oracle.gmres(A, pc, s["b"], restart=30, maxit=10, rtol=0.0, fixed_iters=True)
     per_it = (time.perf_counter() - t0) / 10
-    if per_it * 1000 < budget_s:
+    if t_setup + per_it * (gpu_iters + 30) < budget_s:
         t0 = time.perf_counter()
-        r = oracle.gmres(A, pc, s["b"], restart=30, maxit=1000, rtol=rtol)
+        r = oracle.gmres(A, pc, s["b"], restart=30, maxit=5000, rtol=rtol)
         t_solve = time.perf_counter() - t0
-        return dict(value=t_setup + t_solve, unit="s", cores=1, kind="oracle",
+        return dict(value=round(t_setup + t_solve, 4), unit="s", cores=1, kind="oracle",
                     iters=r["iters"], true_relres=r["relres"],
-                    sample="full BILU(0) setup + GMRES(30) solve to the same rtol, "
-                           "single-threaded oracle")
-    return dict(value=None, unit="s", cores=1, kind="oracle",
-                sample=f"not run: estimated {per_it:.3f} s per iteration exceeds the budget")
+                    sample="the whole workload: BILU(0) setup + GMRES(30) solve to the same "
+                           "rtol, single-threaded oracle")
+    k = max(10, int((budget_s - t_setup) / per_it))
+    t0 = time.perf_counter()
+    oracle.gmres(A, pc, s["b"], restart=30, maxit=k, rtol=0.0, fixed_iters=True)
+    per_it = (time.perf_counter() - t0) / k
+    return dict(value=round(t_setup + per_it * gpu_iters, 4), unit="s", cores=1, kind="oracle",
+                sample=f"BILU(0) setup + {k} GMRES(30) iterations timed, scaled to the GPU's "
+                       f"{gpu_iters} iterations, single-threaded oracle")
 
 
 def main():
@@ -131,7 +144,19 @@ def main():
     ap.add_argument("--configs", default="all")
     ap.add_argument("--layout", default="auto", choices=["auto", "levels", "grid"],
                     help="ILU sweep layout (see SolverSetSweepLayout)")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
+                    help="only run one device-to-device copy of MIB MiB (the reference "
+                         "kernel for scaling rocprofv3 FETCH_SIZE / WRITE_SIZE) and exit")
     args = ap.parse_args()
+    if args.copy_probe:
+        import torch
+        src = torch.ones(args.copy_probe * 131072, dtype=torch.float64, device="cuda:0")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes": src.numel() * 8}))
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this build measures one GPU holding one rank's share; "
               "multi-GPU runs are not supported (use --gpus 1)", file=sys.stderr)
@@ -163,6 +188,7 @@ def main():
     torch.cuda.synchronize()
     t_upload = time.perf_counter() - t0
     bh, xh = K.VecWrap(m, b), K.VecWrap(m, x)
+    lnk = torch.from_numpy(np.asarray(s["lnk"], dtype=np.float32)).to(dev)
 
     configs = CONFIGS if args.configs == "all" else [c for c in CONFIGS if c[0] in args.configs.split(",")]
     solvers = {}
@@ -177,6 +203,8 @@ def main():
             K.SolverSetCPR(S, getattr(K, f"KRY_CPR_{cpr[0]}"), cpr[1])
         K.SolverSetStream(S, stream)
         K.SolverSetSweepLayout(S, getattr(K, f"KRY_SWEEP_{args.layout.upper()}"))
+        if pc.endswith("_LEARNED"):
+            K.SolverSetLearned(S, WEIGHTS, lnk)
         solvers[name] = S
 
     def run_one(name):
@@ -189,8 +217,11 @@ def main():
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
         st, ss = K.SolverGetTimes(S)
-        return dict(time_s=dt, setup_s=st, solve_s=ss, iters=K.SolverGetIters(S),
-                    true_relres=K.SolverGetResidual(S), status=rc)
+        out = dict(time_s=dt, setup_s=st, solve_s=ss, iters=K.SolverGetIters(S),
+                   true_relres=K.SolverGetResidual(S), status=rc)
+        if name.endswith("_learned"):
+            out["stage_applies"], out["stage_fallbacks"] = K.SolverGetLearnedStats(S)
+        return out
 
     for _ in range(args.warmup):
         for name, *_ in configs:
@@ -222,6 +253,17 @@ def main():
             ent.update(bytes_per_launch=abytes[kname], gbs=round(gbs, 1),
                        frac_hbm=round(gbs / HBM_PEAK_GBS, 4))
         kernels[kname] = ent
+    for kname in ["ilu_grid_untile", "learned_stage"]:
+        cnt, ms = K.KernelTimingQuery(kname)
+        if cnt:
+            kernels[kname] = dict(launches=cnt, total_ms=round(ms, 4), avg_us=round(1000 * ms / cnt, 3))
+    for kname, fpc in CONV_FLOPS_PER_CELL.items():
+        cnt, ms = K.KernelTimingQuery(kname)
+        if cnt:
+            tfl = fpc * nb / (ms / cnt * 1e-3) / 1e12
+            kernels[kname] = dict(launches=cnt, total_ms=round(ms, 4), avg_us=round(1000 * ms / cnt, 3),
+                                  flops_per_launch=fpc * nb, tflops=round(tfl, 2),
+                                  frac_mfma_bf16=round(tfl / MFMA_BF16_PEAK_TFLOPS, 4))
     # dominant kernel of the headline configuration's families
     cand = {k: v for k, v in kernels.items() if k in abytes}
     dom = max(cand, key=lambda k: cand[k]["total_ms"]) if cand else None
@@ -241,6 +283,9 @@ def main():
             solve_s=round(float(np.mean([r["solve_s"] for r in rs])), 5),
             iters=rs[-1]["iters"], true_relres=rs[-1]["true_relres"],
             converged=all(r["status"] == 0 for r in rs))
+        if "stage_applies" in rs[-1]:
+            variants[name].update(stage_applies=rs[-1]["stage_applies"],
+                                  stage_fallbacks=rs[-1]["stage_fallbacks"])
     head = variants.get(HEADLINE) or next(iter(variants.values()))
 
     for S in solvers.values():
@@ -252,7 +297,7 @@ def main():
 
     cpu = None
     if not args.no_cpu:
-        cpu = cpu_baseline(s, args.rtol)
+        cpu = cpu_baseline(s, args.rtol, head["iters"])
 
     out = {
         "metric": METRIC, "value": head["time_s"], "unit": "s", "n_gpus": 1,

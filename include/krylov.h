@@ -252,6 +252,17 @@ int LearnedGetParams(LEARNED *L, float *params_host);
 int LearnedForward(LEARNED *L, const float *in, float *out);
 int LearnedLossGrad(LEARNED *L, const float *in, const float *target, float *loss_host,
                     float *grad);
+/* LearnedBackward: parameter gradient of any loss from dout = dL/d(out)
+ *   ([3][cells] FP32, device) and the activations of the last
+ *   LearnedForward of this (training) object; grad as in LearnedLossGrad.
+ * LearnedResidualGrad: the residual loss of the stage,
+ *   loss = ||A e - r1/s||^2 / n with e = out (the last output) and r1/s the
+ *   first three channels of `in`, and dout = (2/n) A^T (A e - r1/s); At is
+ *   the transpose of A as its own MAT (both 3x3-block, one block row per
+ *   cell of this object's grid).  The loss is returned on the host. */
+int LearnedBackward(LEARNED *L, const float *dout, float *grad);
+int LearnedResidualGrad(LEARNED *L, const MAT *A, const MAT *At, const float *in,
+                        const float *out, float *dout, double *loss_host);
 int LearnedAdamStep(LEARNED *L, float lr, float beta1, float beta2, float eps);
 int LearnedSave(LEARNED *L, const char *path);
 int LearnedLoad(LEARNED *L, const char *path);

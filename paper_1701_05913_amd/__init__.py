@@ -101,6 +101,8 @@ _SIGS = {
     "LearnedAdamStep": (C.c_int, [P, C.c_float, C.c_float, C.c_float, C.c_float]),
     "LearnedSave": (C.c_int, [P, C.c_char_p]), "LearnedLoad": (C.c_int, [P, C.c_char_p]),
     "LearnedMakePair": (C.c_int, [I64, P, P, P, P, P, C.POINTER(D)]),
+    "LearnedBackward": (C.c_int, [P, P, P]),
+    "LearnedResidualGrad": (C.c_int, [P, P, P, P, P, P, C.POINTER(D)]),
 }
 for _name, (_res, _args) in _SIGS.items():
     _f = getattr(_lib, _name)
@@ -425,6 +427,17 @@ def LearnedLossGrad(L, inp, target, grad=None):
     _check(_lib.LearnedLossGrad(L, _fdptr(inp), _fdptr(target), C.byref(loss),
                                 _fdptr(grad) if grad is not None else None))
     return loss.value
+
+
+def LearnedBackward(L, dout, grad=None):
+    return _check(_lib.LearnedBackward(L, _fdptr(dout), _fdptr(grad) if grad is not None else None))
+
+
+def LearnedResidualGrad(L, A, At, inp, out, dout):
+    """Returns the residual loss; A, At: MAT handles."""
+    lv = C.c_double(0)
+    _check(_lib.LearnedResidualGrad(L, A, At, _fdptr(inp), _fdptr(out), _fdptr(dout), C.byref(lv)))
+    return lv.value
 
 
 def LearnedAdamStep(L, lr, beta1=0.9, beta2=0.999, eps=1e-8):

@@ -399,6 +399,49 @@ __global__ __launch_bounds__(256) void k_loss(int64_t cells, const float *__rest
     }
 }
 
+// output gradient given by the caller (channel-major FP32): dz4 and the
+// per-block sums of the last layer's bias gradient (slot 0 unused)
+__global__ __launch_bounds__(256) void k_outgrad(int64_t cells, const float *__restrict__ dout,
+                                                 uint16_t *__restrict__ dz4, float *__restrict__ part) {
+    __shared__ float sh[4][4];
+    const int64_t c = blockIdx.x * (int64_t)256 + threadIdx.x;
+    float gs[3] = {0.0f, 0.0f, 0.0f};
+    if (c < cells) {
+#pragma unroll
+        for (int k = 0; k < 3; k++) {
+            gs[k] = dout[k * cells + c];
+            dz4[c * 4 + k] = f2bf(gs[k]);
+        }
+        dz4[c * 4 + 3] = 0;
+    }
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    float v[4] = {0.0f, gs[0], gs[1], gs[2]};
+#pragma unroll
+    for (int k = 0; k < 4; k++) {
+        float s = wave_sum(v[k]);
+        if (lane == 0) sh[w][k] = s;
+    }
+    __syncthreads();
+    if (threadIdx.x < 4) {
+        const int k = threadIdx.x;
+        part[(size_t)blockIdx.x * 4 + k] = sh[0][k] + sh[1][k] + sh[2][k] + sh[3][k];
+    }
+}
+
+// channel-major FP32 [>= 3][cells] <-> interleaved FP64 [cells][3]
+__global__ void k_cm_to_il(int64_t cells, const float *__restrict__ x, double *__restrict__ y) {
+    const int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (c >= cells) return;
+#pragma unroll
+    for (int k = 0; k < 3; k++) y[c * 3 + k] = static_cast<double>(x[k * cells + c]);
+}
+__global__ void k_il_to_cm(int64_t cells, const double *__restrict__ x, float *__restrict__ y) {
+    const int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (c >= cells) return;
+#pragma unroll
+    for (int k = 0; k < 3; k++) y[k * cells + c] = static_cast<float>(x[c * 3 + k]);
+}
+
 __global__ void k_loss_final(const float *__restrict__ part, int nblk, int64_t cells,
                              float *__restrict__ loss, float *__restrict__ gb4) {
     const int k = threadIdx.x;
@@ -588,11 +631,28 @@ static int net_forward(hipStream_t s, ConvNet &N) {
 }
 
 // loss and full parameter gradient for target (channel-major [3][cells])
+static int net_backward_from_dz4(hipStream_t s, ConvNet &N);
+
 static int net_backward(hipStream_t s, ConvNet &N, const float *target) {
     const int nlb = static_cast<int>((N.cells + 255) / 256);
     hipLaunchKernelGGL(k_loss, dim3(nlb), dim3(256), 0, s, N.cells, N.out.p, target, N.dz4.p, N.part.p);
     hipLaunchKernelGGL(k_loss_final, dim3(1), dim3(64), 0, s, N.part.p, nlb, N.cells, N.loss.p,
                        N.grad.p + NET_OFF[3] + 3 * 32 * 27);
+    return net_backward_from_dz4(s, N);
+}
+
+// gradient of an arbitrary loss given dL/d(out) (channel-major FP32)
+static int net_backward_dout(hipStream_t s, ConvNet &N, const float *dout) {
+    const int nlb = static_cast<int>((N.cells + 255) / 256);
+    hipLaunchKernelGGL(k_outgrad, dim3(nlb), dim3(256), 0, s, N.cells, dout, N.dz4.p, N.part.p);
+    hipLaunchKernelGGL(k_loss_final, dim3(1), dim3(64), 0, s, N.part.p, nlb, N.cells, N.loss.p,
+                       N.grad.p + NET_OFF[3] + 3 * 32 * 27);
+    return net_backward_from_dz4(s, N);
+}
+
+// parameter gradients from dz4 (the output gradient) and the activations
+// of the last forward pass
+static int net_backward_from_dz4(hipStream_t s, ConvNet &N) {
     const dim3 g(conv_blocks(N)), b(256);
     const int nwg = wgrad_blocks(N);
     constexpr int NN32 = (27 * 32 + 15) / 16 * 16, NN4 = (27 * 4 + 15) / 16 * 16;
@@ -650,6 +710,7 @@ using namespace kry;
 struct LEARNED_ {
     ConvNet net;
     hipStream_t stream = nullptr;
+    DBuf<double> e, r, res, g, partial, nrm;   // residual-loss scratch
 };
 
 static int copy_in(hipStream_t s, void *dst, const void *src, size_t bytes, int where) {
@@ -723,6 +784,51 @@ extern "C" int LearnedLossGrad(LEARNED *L, const float *in, const float *target,
     KRY_HIP(hipMemcpyAsync(&lh, N.loss.p, sizeof(float), hipMemcpyDeviceToHost, L->stream));
     KRY_HIP(hipStreamSynchronize(L->stream));
     if (loss_host) *loss_host = lh;
+    return KRY_OK;
+}
+
+extern "C" int LearnedBackward(LEARNED *L, const float *dout, float *grad) {
+    if (!L || !dout) return set_error(KRY_ERR_ARG, "LearnedBackward: NULL argument");
+    ConvNet &N = L->net;
+    if (!N.training) return set_error(KRY_ERR_ARG, "LearnedBackward: created without training buffers");
+    KRY_TRY(net_backward_dout(L->stream, N, dout));
+    if (grad)
+        KRY_HIP(hipMemcpyAsync(grad, N.grad.p, sizeof(float) * NET_OFF[4], hipMemcpyDeviceToDevice, L->stream));
+    KRY_HIP(hipStreamSynchronize(L->stream));
+    return KRY_OK;
+}
+
+extern "C" int LearnedResidualGrad(LEARNED *L, const MAT *A, const MAT *At, const float *in,
+                                   const float *out, float *dout, double *loss_host) {
+    if (!L || !A || !At || !in || !out || !dout)
+        return set_error(KRY_ERR_ARG, "LearnedResidualGrad: NULL argument");
+    const int64_t cells = L->net.cells, n = 3 * cells;
+    if (A->bs != 3 || At->bs != 3 || A->nb != cells || At->nb != cells)
+        return set_error(KRY_ERR_DIM, "LearnedResidualGrad: matrices must be 3x3-block with one block row per cell");
+    hipStream_t s = L->stream;
+    const int nsb = std::max(spmv_partial_blocks(A), spmv_partial_blocks(At));
+    if (L->e.n < (size_t)n) {
+        KRY_TRY(L->e.alloc(n));
+        KRY_TRY(L->r.alloc(n));
+        KRY_TRY(L->res.alloc(n));
+        KRY_TRY(L->g.alloc(n));
+        KRY_TRY(L->nrm.alloc(1));
+    }
+    if (L->partial.n < (size_t)nsb * 2) KRY_TRY(L->partial.alloc((size_t)nsb * 2));
+    const dim3 gc((cells + 255) / 256), b(256);
+    hipLaunchKernelGGL(k_cm_to_il, gc, b, 0, s, cells, out, L->e.p);
+    hipLaunchKernelGGL(k_cm_to_il, gc, b, 0, s, cells, in, L->r.p);
+    // res = A e - r1/s, with its squared norm
+    KRY_TRY(spmv_f64(s, A, 1.0, L->e.p, -1.0, L->r.p, L->res.p, 1, nullptr, nullptr, L->partial.p));
+    KRY_TRY(sum_partials(s, L->partial.p, spmv_partial_blocks(A), 2, 1, L->nrm.p, SUM_PLAIN));
+    // dL/de = (2/n) A^T res
+    KRY_TRY(spmv_f64(s, At, 2.0 / (double)n, L->res.p, 0.0, nullptr, L->g.p, 0, nullptr, nullptr, nullptr));
+    hipLaunchKernelGGL(k_il_to_cm, gc, b, 0, s, cells, L->g.p, dout);
+    KRY_HIP(hipGetLastError());
+    double h = 0.0;
+    KRY_HIP(hipMemcpyAsync(&h, L->nrm.p, sizeof(double), hipMemcpyDeviceToHost, s));
+    KRY_HIP(hipStreamSynchronize(s));
+    if (loss_host) *loss_host = h / (double)n;
     return KRY_OK;
 }
 

@@ -7,10 +7,15 @@ the stage's input r1 = v - A z1 (z1 = BILU(0)^-1 v) and its exact target
 A^-1 r1 = (x_true - x) - z1.  Each pair is normalised by s = ||r1|| /
 sqrt(n) (LearnedMakePair) and kept in device memory.
 
-Train: Adam on the mean squared error of the network output against the
-normalised target, one pair per step, cosine learning-rate decay, seeded
-shuffling; the checkpoint (parameters, Adam moments, step count) is written
-with LearnedSave.
+Train: Adam, one pair per step, cosine learning-rate decay, seeded
+shuffling, on one of two losses:
+  mse       mean squared error of the output against the normalised
+            target A^-1 r1 / s;
+  residual  ||A e - r1 / s||^2 / n for the output e (what the stage's
+            acceptance test measures; its gradient (2/n) A^T (A e - r1/s)
+            needs A and its transpose, kept on the device per system).
+The checkpoint (parameters, Adam moments, step count) is written with
+LearnedSave; --init starts from the parameters of a checkpoint.
 
 Evaluate: FGMRES(30) with BILU(0) alone and with the learned stage on
 held-out seeds, to the same relative tolerance; iterations, wall time and
@@ -40,7 +45,7 @@ DEV = "cuda:0"
 class System:
     """One generated system uploaded through the C ABI."""
 
-    def __init__(self, grid, seed, perm="layered"):
+    def __init__(self, grid, seed, perm="layered", transpose=False):
         s = ri.blackoil_system(*grid, seed=seed, perm=perm)
         self.grid, self.seed = grid, seed
         self.nb, self.n = s["nb"], s["n"]
@@ -51,6 +56,15 @@ class System:
         self.b = torch.from_numpy(np.asarray(s["b"], np.float64)).to(DEV)
         self.x_true = torch.from_numpy(np.asarray(s["x_true"], np.float64)).to(DEV)
         self.lnk = torch.from_numpy(np.asarray(s["lnk"], np.float32)).to(DEV)
+        self.At = None
+        if transpose:
+            import scipy.sparse as sp
+            T = sp.bsr_matrix((np.asarray(s["val"]).reshape(-1, 3, 3), np.asarray(s["col"]),
+                               np.asarray(s["rowptr"])), shape=(self.n, self.n)).T.tobsr(blocksize=(3, 3))
+            T.sort_indices()
+            self.At = K.MatCreateBSR(self.map, self.nb, 3, T.indptr.astype(np.int32),
+                                     T.indices.astype(np.int32),
+                                     np.ascontiguousarray(T.data.reshape(-1), dtype=np.float64))
         self._vecs = []
 
     def vec(self, t):
@@ -74,6 +88,8 @@ class System:
         torch.cuda.synchronize()
         for h in self._vecs:
             K.VecDestroy(h)
+        if self.At is not None:
+            K.MatDestroy(self.At)
         K.MatDestroy(self.A)
         K.MapDestroy(self.map)
 
@@ -126,10 +142,28 @@ def init_params(seed, last_scale=0.1):
     return np.concatenate(out).astype(np.float32)
 
 
-def train(pairs, grid, epochs, lr, seed, log_every=200):
+def zero_loss(pairs, grid, loss):
+    """Mean loss of the zero network: the mean square of the targets (mse)
+    or 1 (residual, by the normalisation)."""
+    if loss == "residual":
+        return 1.0
     L = K.LearnedCreate(*grid, True)
     K.LearnedSetStream(L, torch.cuda.current_stream())
-    K.LearnedSetParams(L, init_params(seed))
+    K.LearnedSetParams(L, np.zeros(K.LearnedNumParams(), np.float32))
+    tot = sum(K.LearnedLossGrad(L, inp, tgt) for inp, tgt, _ in pairs)
+    K.LearnedDestroy(L)
+    return tot / max(len(pairs), 1)
+
+
+def train(pairs, grid, epochs, lr, seed, loss="mse", systems=None, init=None, log_every=500):
+    """pairs: (input, target, system index); systems: needed for the
+    residual loss."""
+    L = K.LearnedCreate(*grid, True)
+    K.LearnedSetStream(L, torch.cuda.current_stream())
+    K.LearnedSetParams(L, init_params(seed) if init is None else init)
+    cells = grid[0] * grid[1] * grid[2]
+    out = torch.empty(3 * cells, dtype=torch.float32, device=DEV)
+    dout = torch.empty_like(out)
     rng = np.random.default_rng(seed)
     total = epochs * len(pairs)
     step, curve, t0 = 0, [], time.perf_counter()
@@ -137,14 +171,19 @@ def train(pairs, grid, epochs, lr, seed, log_every=200):
         order = rng.permutation(len(pairs))
         acc = 0.0
         for i in order:
-            inp, tgt = pairs[i]
-            loss = K.LearnedLossGrad(L, inp, tgt)
+            inp, tgt, k = pairs[i]
+            if loss == "mse":
+                lv = K.LearnedLossGrad(L, inp, tgt)
+            else:
+                K.LearnedForward(L, inp, out)
+                lv = K.LearnedResidualGrad(L, systems[k].A, systems[k].At, inp, out, dout)
+                K.LearnedBackward(L, dout)
             lr_t = 0.5 * lr * (1.0 + math.cos(math.pi * step / max(total, 1)))
             K.LearnedAdamStep(L, lr_t, 0.9, 0.999, 1e-8)
-            acc += loss
+            acc += lv
             step += 1
             if step % log_every == 0:
-                print(f"  step {step}/{total} loss {loss:.4e}", flush=True)
+                print(f"  step {step}/{total} loss {lv:.4e}", flush=True)
         curve.append(acc / len(pairs))
         print(f"epoch {ep}: mean loss {curve[-1]:.4e} ({time.perf_counter() - t0:.1f} s)", flush=True)
     return L, curve, time.perf_counter() - t0
@@ -184,11 +223,15 @@ def main(argv=None):
     ap.add_argument("--grid", default="64,64,64")
     ap.add_argument("--train-seeds", default="0:32", help="first:last (exclusive)")
     ap.add_argument("--eval-seeds", default="10000:10004")
+    ap.add_argument("--eval-grids", default="64,64,64;128,128,64",
+                    help="grids of the held-out systems, ';'-separated")
     ap.add_argument("--restart", type=int, default=10, help="FGMRES restart during harvest")
     ap.add_argument("--cycles", type=int, default=40, help="restart cycles harvested per system")
     ap.add_argument("--epochs", type=int, default=4)
     ap.add_argument("--lr", type=float, default=1e-3)
     ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--loss", choices=("mse", "residual"), default="residual")
+    ap.add_argument("--init", default=None, help="checkpoint to start from")
     ap.add_argument("--report", default=None, help="JSON summary file")
     a = ap.parse_args(argv)
     # torch's CUDA context first, then the library (see the binding's notes)
@@ -197,26 +240,46 @@ def main(argv=None):
     t0, t1 = (int(v) for v in a.train_seeds.split(":"))
     e0, e1 = (int(v) for v in a.eval_seeds.split(":"))
 
-    pairs, th = [], time.perf_counter()
+    keep = a.loss == "residual"
+    pairs, systems, th = [], [], time.perf_counter()
     for seed in range(t0, t1):
-        sys_ = System(grid, seed)
+        sys_ = System(grid, seed, transpose=keep)
         p = harvest(sys_, a.restart, a.cycles)
-        pairs += p
-        sys_.close()
+        pairs += [(inp, tgt, len(systems)) for inp, tgt in p]
+        if keep:
+            systems.append(sys_)
+        else:
+            sys_.close()
         print(f"harvest seed {seed}: {len(p)} pairs (total {len(pairs)})", flush=True)
     t_harvest = time.perf_counter() - th
 
-    L, curve, t_train = train(pairs, grid, a.epochs, a.lr, a.seed)
+    init = None
+    if a.init:
+        Li = K.LearnedCreate(*grid, False)
+        K.LearnedLoad(Li, a.init)
+        init = K.LearnedGetParams(Li)
+        K.LearnedDestroy(Li)
+    loss0 = zero_loss(pairs, grid, a.loss)
+    print(f"zero-network {a.loss} loss {loss0:.4e} over {len(pairs)} pairs", flush=True)
+    L, curve, t_train = train(pairs, grid, a.epochs, a.lr, a.seed, loss=a.loss, systems=systems,
+                              init=init)
     K.LearnedSave(L, a.out)
     params = K.LearnedGetParams(L)
     K.LearnedDestroy(L)
+    npairs = len(pairs)
     del pairs
+    for sys_ in systems:
+        sys_.close()
     torch.cuda.empty_cache()
 
-    rows = evaluate(grid, range(e0, e1), params)
+    rows = []
+    for eg in a.eval_grids.split(";"):
+        rows += evaluate(tuple(int(v) for v in eg.split(",")), range(e0, e1), params)
     summary = {"grid": list(grid), "train_seeds": [t0, t1], "eval_seeds": [e0, e1],
                "restart_harvest": a.restart, "cycles": a.cycles, "epochs": a.epochs, "lr": a.lr,
-               "harvest_s": round(t_harvest, 1), "train_s": round(t_train, 1),
+               "loss": a.loss, "init": a.init,
+               "pairs": npairs, "harvest_s": round(t_harvest, 1),
+               "train_s": round(t_train, 1), "zero_network_loss": loss0,
                "loss_per_epoch": curve, "eval": rows}
     if a.report:
         with open(a.report, "w") as f:
