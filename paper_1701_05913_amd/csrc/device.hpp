@@ -225,4 +225,51 @@ __device__ __forceinline__ void lds_wait_pair(int *p, int v, int *q, int w, int 
     lds_acquire();
 }
 
+// Inverse of a BS x BS block by Gaussian elimination with partial
+// pivoting (first maximal pivot on ties); false (R undefined) for a
+// non-finite or tiny pivot: |pivot| < 1e-300 for BS = 1, < 1e-14 ||A||_inf
+// otherwise.
+template <int BS>
+__device__ bool dev_block_inverse(const double *A, double *R) {
+    double M[BS * BS];
+    double anorm = 0.0;
+#pragma unroll
+    for (int r = 0; r < BS; r++) {
+        double s = 0.0;
+#pragma unroll
+        for (int c = 0; c < BS; c++) {
+            M[r * BS + c] = A[r * BS + c];
+            R[r * BS + c] = (r == c) ? 1.0 : 0.0;
+            s += fabs(A[r * BS + c]);
+        }
+        anorm = fmax(anorm, s);
+    }
+    for (int k = 0; k < BS; k++) {
+        int piv = k;
+        double best = fabs(M[k * BS + k]);
+        for (int r = k + 1; r < BS; r++)
+            if (fabs(M[r * BS + k]) > best) { best = fabs(M[r * BS + k]); piv = r; }
+        if (!isfinite(best)) return false;
+        if (BS == 1 ? best < 1e-300 : best < 1e-14 * anorm) return false;
+        if (piv != k) {
+            for (int c = 0; c < BS; c++) {
+                double t = M[k * BS + c]; M[k * BS + c] = M[piv * BS + c]; M[piv * BS + c] = t;
+                t = R[k * BS + c]; R[k * BS + c] = R[piv * BS + c]; R[piv * BS + c] = t;
+            }
+        }
+        for (int r = k + 1; r < BS; r++) {
+            const double f = M[r * BS + k] / M[k * BS + k];
+            for (int c = k; c < BS; c++) M[r * BS + c] -= f * M[k * BS + c];
+            for (int c = 0; c < BS; c++) R[r * BS + c] -= f * R[k * BS + c];
+        }
+    }
+    for (int k = BS - 1; k >= 0; k--)
+        for (int c = 0; c < BS; c++) {
+            double s = R[k * BS + c];
+            for (int j = k + 1; j < BS; j++) s -= M[k * BS + j] * R[j * BS + c];
+            R[k * BS + c] = s / M[k * BS + k];
+        }
+    return true;
+}
+
 }  // namespace kry

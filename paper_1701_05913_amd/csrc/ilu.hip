@@ -102,56 +102,8 @@ static bool schedule_is_acyclic(int nb, const LevelSlices &L, F for_deps) {
 }
 
 // ---------------------------------------------------------------------------
-// device: small dense block algebra
-// ---------------------------------------------------------------------------
-// Inverse by Gaussian elimination with partial pivoting (first maximal
-// pivot on ties).  Singular when a pivot is non-finite or below
-// 1e-14 ||A||_inf (bs > 1) / 1e-300 (bs = 1).
-template <int BS>
-__device__ bool dev_block_inverse(const double *A, double *R) {
-    double M[BS * BS];
-    double anorm = 0.0;
-#pragma unroll
-    for (int r = 0; r < BS; r++) {
-        double s = 0.0;
-#pragma unroll
-        for (int c = 0; c < BS; c++) {
-            M[r * BS + c] = A[r * BS + c];
-            R[r * BS + c] = (r == c) ? 1.0 : 0.0;
-            s += fabs(A[r * BS + c]);
-        }
-        anorm = fmax(anorm, s);
-    }
-    for (int k = 0; k < BS; k++) {
-        int piv = k;
-        double best = fabs(M[k * BS + k]);
-        for (int r = k + 1; r < BS; r++)
-            if (fabs(M[r * BS + k]) > best) { best = fabs(M[r * BS + k]); piv = r; }
-        if (!isfinite(best)) return false;
-        if (BS == 1 ? best < 1e-300 : best < 1e-14 * anorm) return false;
-        if (piv != k) {
-            for (int c = 0; c < BS; c++) {
-                double t = M[k * BS + c]; M[k * BS + c] = M[piv * BS + c]; M[piv * BS + c] = t;
-                t = R[k * BS + c]; R[k * BS + c] = R[piv * BS + c]; R[piv * BS + c] = t;
-            }
-        }
-        for (int r = k + 1; r < BS; r++) {
-            const double f = M[r * BS + k] / M[k * BS + k];
-            for (int c = k; c < BS; c++) M[r * BS + c] -= f * M[k * BS + c];
-            for (int c = 0; c < BS; c++) R[r * BS + c] -= f * R[k * BS + c];
-        }
-    }
-    for (int k = BS - 1; k >= 0; k--)
-        for (int c = 0; c < BS; c++) {
-            double s = R[k * BS + c];
-            for (int j = k + 1; j < BS; j++) s -= M[k * BS + j] * R[j * BS + c];
-            R[k * BS + c] = s / M[k * BS + k];
-        }
-    return true;
-}
-
-// ---------------------------------------------------------------------------
-// numeric factorization of the rows of one level
+// numeric factorization of the rows of one level (block inverse:
+// dev_block_inverse, device.hpp)
 // ---------------------------------------------------------------------------
 template <int BS>
 __global__ __launch_bounds__(256) void k_ilu_factor_level(
@@ -449,6 +401,19 @@ int ilu_setup(hipStream_t s, const MAT_ *A, const double *d_val, IluFactor &F, i
     F.bs = bs;
     F.nb = nb;
     F.prec = prec;
+    if (layout == KRY_SWEEP_GRID && A->gnx == 0)
+        return set_error(KRY_ERR_ARG, "grid sweep layout requested for a matrix that is not a 7-point grid stencil");
+    const bool use_grid = layout == KRY_SWEEP_GRID || (layout == KRY_SWEEP_AUTO && A->gnx > 0);
+    if (use_grid && ilu_grid_can_factor(A)) {
+        // no level analysis: the grid-tiled factorization writes the sweep
+        // layout directly
+        F.nlev_f = F.nlev_b = A->gnx + A->gny + A->gnz - 2;
+        KRY_TRY(ilu_grid_factor_setup(s, A, d_val, F, d_err));
+        KRY_TRY(F.ctr.alloc(2));
+        KRY_HIP(hipMemsetAsync(F.ctr.p, 0, 2 * sizeof(int), s));
+        KRY_HIP(hipStreamSynchronize(s));
+        return KRY_OK;
+    }
     // level sets
     std::vector<int> levf(nb, 0), levb(nb, 0);
     int nlf = 0, nlb = 0;
@@ -476,9 +441,6 @@ int ilu_setup(hipStream_t s, const MAT_ *A, const double *d_val, IluFactor &F, i
         for (int p = dg[i] + 1; p < rp[i + 1]; p++) f(ci[p]);
     });
     if (!okf || !okb) return set_error(KRY_ERR_ARG, "ILU: inconsistent level schedule");
-    if (layout == KRY_SWEEP_GRID && A->gnx == 0)
-        return set_error(KRY_ERR_ARG, "grid sweep layout requested for a matrix that is not a 7-point grid stencil");
-    const bool use_grid = layout == KRY_SWEEP_GRID || (layout == KRY_SWEEP_AUTO && A->gnx > 0);
 
     KRY_TRY(upload_layout(s, LF, F.L, bs, !use_grid));
     if (!use_grid) KRY_TRY(upload_layout(s, LB, F.U, bs, true));

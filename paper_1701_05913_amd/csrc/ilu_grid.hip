@@ -120,8 +120,162 @@ __global__ void k_grid_fill_sentinel(int64_t n, T *__restrict__ y) {
         y[i] = sentinel_value<T>();
 }
 
-int ilu_grid_setup(hipStream_t s, const MAT_ *A, const double *lu, const double *uinv,
-                   IluFactor &F) {
+// ---------------------------------------------------------------------------
+// grid-tiled numeric factorization (nx >= 3 and ny >= 3)
+// ---------------------------------------------------------------------------
+// For a 7-point stencil in natural order with nx, ny >= 3, ILU(0) changes
+// only the diagonal blocks: no product L_ik U_kj of the elimination lands on
+// an off-diagonal entry of row i, so
+//   D_c = A_cc - sum over the lower neighbours n of (A_cn D_n^-1) A_nc,
+// with the neighbours taken in column order (k-1, j-1, i-1) as the
+// row-wise elimination takes them.  The kernel walks the forward
+// hyperplanes like the forward sweep (one wavefront per tile, one lane per
+// x-line), takes D_n^-1 of i-1 from the lane's previous step, of j-1 and
+// k-1 from neighbouring lanes or from the face entries published by the
+// upstream tiles, and writes the packed sweep layout directly:
+// Lt = A_cn D_n^-1, Ut = the upper blocks of A, Dt = D_c^-1.  Positions in
+// the block rows follow from the cell's neighbours (one rowptr load per row).
+template <int BS>
+__global__ __launch_bounds__(64) void k_grid_factor(GridTiles G, const int *__restrict__ rowptr,
+                                                    const double *__restrict__ val,
+                                                    double *__restrict__ Lt, double *__restrict__ Ut,
+                                                    double *__restrict__ Dt, double *faces, int *ctr,
+                                                    int *err) {
+    constexpr int B2 = BS * BS;
+    const int lane = threadIdx.x;
+    const int TJ = G.TJ, TK = G.TK, NF = G.NF, nx = G.nx, ny = G.ny, nz = G.nz, S = G.S;
+    const int64_t sJ = nx, sK = (int64_t)nx * ny;
+    const int jj = lane % TJ, kk = lane / TJ;
+    const int fj = jj == TJ - 1 && kk < TK ? kk : -1;       // published face entries
+    const int fk = kk == TK - 1 ? TK + jj : -1;
+    for (;;) {
+        int t0 = 0;
+        if (lane == 0) t0 = atomicAdd(ctr, 1);
+        const int T = __shfl(t0, 0, 64);
+        if (T >= G.ntiles) break;
+        const int JK = G.order[T];
+        const int J = JK & 0xffff, K = JK >> 16;
+        const int j = J * TJ + jj, k = K * TK + kk;
+        const bool lane_ok = lane < TJ * TK && j < ny && k < nz;
+        const int64_t cl = lane_ok ? sJ * j + sK * k : 0;
+        const double *srcj = (jj == 0 && J > 0 && lane_ok)
+                                 ? faces + (((int64_t)G.tidx[(J - 1) * G.NK + K] * S + (TJ - 1)) * NF + kk) * B2
+                                 : nullptr;
+        const double *srck = (kk == 0 && K > 0 && lane_ok)
+                                 ? faces + (((int64_t)G.tidx[J * G.NK + K - 1] * S + (TK - 1)) * NF + TK + jj) * B2
+                                 : nullptr;
+        double *frow = faces + (int64_t)T * S * NF * B2;
+        double dp[B2];
+#pragma unroll
+        for (int e = 0; e < B2; e++) dp[e] = 0.0;
+        for (int t = 0; t < S; t++) {
+            const int i = t - jj - kk;
+            const bool valid = lane_ok && i >= 0 && i < nx;
+            // D^-1 of the lower neighbours: (k-1, j-1, i-1)
+            double dn[3][B2];
+#pragma unroll
+            for (int e = 0; e < B2; e++) {
+                dn[0][e] = __shfl_up(dp[e], TJ, 64);
+                dn[1][e] = __shfl_up(dp[e], 1, 64);
+                dn[2][e] = dp[e];
+            }
+            if (valid && k > 0 && kk == 0 && srck) wait_values<double, B2>(srck + (int64_t)t * NF * B2, dn[0], err);
+            if (valid && j > 0 && jj == 0 && srcj) wait_values<double, B2>(srcj + (int64_t)t * NF * B2, dn[1], err);
+            double D[B2], L[3][B2], R[B2];
+#pragma unroll
+            for (int e = 0; e < B2; e++) {
+                D[e] = 0.0;
+                R[e] = 0.0;
+#pragma unroll
+                for (int b = 0; b < 3; b++) L[b][e] = 0.0;
+            }
+            const int64_t c = cl + i;
+            if (valid) {
+                // neighbours present, in column order: k-1, j-1, i-1, i+1, j+1, k+1
+                const bool has[6] = {k > 0, j > 0, i > 0, i < nx - 1, j < ny - 1, k < nz - 1};
+                const int64_t nbr[3] = {c - sK, c - sJ, c - 1};
+                // A_nc sits in row n after n's lower blocks, its diagonal and
+                // the upper neighbours of n that precede column c
+                int qn[3] = {0, 0, 0};
+                if (has[0]) qn[0] = rowptr[nbr[0]] + ((k - 1 > 0) + (j > 0) + (i > 0)) + 1 + has[3] + has[4];
+                if (has[1]) qn[1] = rowptr[nbr[1]] + ((k > 0) + (j - 1 > 0) + (i > 0)) + 1 + has[3];
+                if (has[2]) qn[2] = rowptr[nbr[2]] + ((k > 0) + (j > 0) + (i - 1 > 0)) + 1;
+                int p = rowptr[c];
+                // L = A_cn D_n^-1 for row c's lower blocks
+#pragma unroll
+                for (int b = 0; b < 3; b++) {
+                    if (!has[b]) continue;
+                    const double *a = val + (int64_t)p * B2;
+#pragma unroll
+                    for (int r = 0; r < BS; r++)
+#pragma unroll
+                        for (int cc = 0; cc < BS; cc++) {
+                            double sacc = 0.0;
+#pragma unroll
+                            for (int m = 0; m < BS; m++) sacc += a[r * BS + m] * dn[b][m * BS + cc];
+                            L[b][r * BS + cc] = sacc;
+                        }
+                    p++;
+                }
+                // diagonal block, minus L A_nc in column order
+                const double *ad = val + (int64_t)p * B2;
+#pragma unroll
+                for (int e = 0; e < B2; e++) D[e] = ad[e];
+#pragma unroll
+                for (int b = 0; b < 3; b++) {
+                    if (!has[b]) continue;
+                    const double *u = val + (int64_t)qn[b] * B2;
+#pragma unroll
+                    for (int r = 0; r < BS; r++)
+#pragma unroll
+                        for (int cc = 0; cc < BS; cc++) {
+                            double sacc = 0.0;
+#pragma unroll
+                            for (int m = 0; m < BS; m++) sacc += L[b][r * BS + m] * u[m * BS + cc];
+                            D[r * BS + cc] -= sacc;
+                        }
+                }
+                if (!dev_block_inverse<BS>(D, R)) {
+                    __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+#pragma unroll
+                    for (int e = 0; e < B2; e++) R[e] = 0.0;
+                }
+                // upper blocks (unchanged) and the inverse, at the backward step
+                const int tb = (nx - 1 - i) + (TJ - 1 - jj) + (TK - 1 - kk);
+                double *ub = Ut + (int64_t)T * S * 3 * B2 * 64 + lane;
+                double *db = Dt + (int64_t)T * S * B2 * 64 + lane;
+                int pu = p + 1;
+#pragma unroll
+                for (int b = 0; b < 3; b++) {
+                    if (!has[3 + b]) continue;
+#pragma unroll
+                    for (int e = 0; e < B2; e++)
+                        ub[(((int64_t)tb * 3 + b) * B2 + e) * 64] = val[(int64_t)pu * B2 + e];
+                    pu++;
+                }
+#pragma unroll
+                for (int e = 0; e < B2; e++) db[((int64_t)tb * B2 + e) * 64] = R[e];
+            }
+            // forward blocks of this step (zeros for idle lanes and steps)
+            double *lf = Lt + (int64_t)T * S * 3 * B2 * 64 + lane;
+#pragma unroll
+            for (int b = 0; b < 3; b++)
+#pragma unroll
+                for (int e = 0; e < B2; e++) lf[(((int64_t)t * 3 + b) * B2 + e) * 64] = L[b][e];
+            if (fj >= 0)
+#pragma unroll
+                for (int e = 0; e < B2; e++) publish<double>(frow + ((int64_t)t * NF + fj) * B2 + e, R[e]);
+            if (fk >= 0)
+#pragma unroll
+                for (int e = 0; e < B2; e++) publish<double>(frow + ((int64_t)t * NF + fk) * B2 + e, R[e]);
+#pragma unroll
+            for (int e = 0; e < B2; e++) dp[e] = R[e];
+        }
+    }
+}
+
+// tiling of the (j, k) plane and the tile order (J + K diagonals)
+static int grid_tiling(const MAT_ *A, IluFactor &F) {
     GridTiles &G = F.G;
     G.nx = A->gnx;
     G.ny = A->gny;
@@ -150,21 +304,22 @@ int ilu_grid_setup(hipStream_t s, const MAT_ *A, const double *lu, const double 
     KRY_HIP(hipMemcpy(F.tidx.p, tid.data(), sizeof(int) * G.ntiles, hipMemcpyHostToDevice));
     G.order = F.order.p;
     G.tidx = F.tidx.p;
+    const int b2 = A->bs * A->bs;
+    const int64_t steps = (int64_t)G.ntiles * G.S;
+    KRY_TRY(F.lt64.alloc(steps * 3 * b2 * 64));
+    KRY_TRY(F.ut64.alloc(steps * 3 * b2 * 64));
+    KRY_TRY(F.dt64.alloc(steps * b2 * 64));
+    return KRY_OK;
+}
+
+// reduced-precision copies of the FP64 planes, result and face buffers
+static int grid_finish(hipStream_t s, const MAT_ *A, IluFactor &F) {
+    const GridTiles &G = F.G;
     const int bs = A->bs, b2 = bs * bs;
     const int64_t steps = (int64_t)G.ntiles * G.S;
     const int64_t nlu = steps * 3 * b2 * 64, nd = steps * b2 * 64;
     const int64_t nyt = steps * bs * 64, nf = steps * G.NF * bs;
-    KRY_TRY(F.lt64.alloc(nlu));
-    KRY_TRY(F.ut64.alloc(nlu));
-    KRY_TRY(F.dt64.alloc(nd));
-    const dim3 g((steps * 64 + 255) / 256), blk(256);
-    if (bs == 1)
-        hipLaunchKernelGGL(k_grid_pack<1>, g, blk, 0, s, G, A->rowptr.p, A->col.p, A->diag.p, lu,
-                           uinv, F.lt64.p, F.ut64.p, F.dt64.p);
-    else
-        hipLaunchKernelGGL(k_grid_pack<3>, g, blk, 0, s, G, A->rowptr.p, A->col.p, A->diag.p, lu,
-                           uinv, F.lt64.p, F.ut64.p, F.dt64.p);
-    KRY_HIP(hipGetLastError());
+    const dim3 blk(256);
     if (F.prec != KRY_PREC_F64) {
         KRY_TRY(F.dt32.alloc(nd));
         hipLaunchKernelGGL(k_grid_round_f32, dim3(2048), blk, 0, s, nd, F.dt64.p, F.dt32.p);
@@ -200,6 +355,59 @@ int ilu_grid_setup(hipStream_t s, const MAT_ *A, const double *lu, const double 
     KRY_HIP(hipGetLastError());
     F.grid = true;
     return KRY_OK;
+}
+
+int ilu_grid_setup(hipStream_t s, const MAT_ *A, const double *lu, const double *uinv,
+                   IluFactor &F) {
+    KRY_TRY(grid_tiling(A, F));
+    const GridTiles &G = F.G;
+    const int64_t steps = (int64_t)G.ntiles * G.S;
+    const dim3 g((steps * 64 + 255) / 256), blk(256);
+    if (A->bs == 1)
+        hipLaunchKernelGGL(k_grid_pack<1>, g, blk, 0, s, G, A->rowptr.p, A->col.p, A->diag.p, lu,
+                           uinv, F.lt64.p, F.ut64.p, F.dt64.p);
+    else
+        hipLaunchKernelGGL(k_grid_pack<3>, g, blk, 0, s, G, A->rowptr.p, A->col.p, A->diag.p, lu,
+                           uinv, F.lt64.p, F.ut64.p, F.dt64.p);
+    KRY_HIP(hipGetLastError());
+    return grid_finish(s, A, F);
+}
+
+bool ilu_grid_can_factor(const MAT_ *A) {
+    return A->gnx >= 3 && A->gny >= 3 && A->gnz >= 1 && (A->bs == 1 || A->bs == 3);
+}
+
+int ilu_grid_factor_setup(hipStream_t s, const MAT_ *A, const double *d_val, IluFactor &F,
+                          int *d_err) {
+    if (!ilu_grid_can_factor(A)) return set_error(KRY_ERR_ARG, "grid factorization needs nx, ny >= 3");
+    KRY_TRY(grid_tiling(A, F));
+    const GridTiles &G = F.G;
+    const int b2 = A->bs * A->bs;
+    const int64_t steps = (int64_t)G.ntiles * G.S;
+    // backward planes are written only where a cell exists
+    KRY_HIP(hipMemsetAsync(F.ut64.p, 0, F.ut64.bytes(), s));
+    KRY_HIP(hipMemsetAsync(F.dt64.p, 0, F.dt64.bytes(), s));
+    DBuf<double> faces;
+    DBuf<int> ctr;
+    const int64_t nf = steps * G.NF * b2;
+    KRY_TRY(faces.alloc(nf));
+    KRY_TRY(ctr.alloc(1));
+    hipLaunchKernelGGL(k_grid_fill_sentinel<double>, dim3(1024), dim3(256), 0, s, nf, faces.p);
+    KRY_HIP(hipMemsetAsync(ctr.p, 0, sizeof(int), s));
+    const int wgs = std::min(G.ntiles, 1024);
+    {
+        TimedScope t("ilu_grid_factor", s);
+        if (A->bs == 1)
+            hipLaunchKernelGGL(k_grid_factor<1>, dim3(wgs), dim3(64), 0, s, G, A->rowptr.p, d_val,
+                               F.lt64.p, F.ut64.p, F.dt64.p, faces.p, ctr.p, d_err);
+        else
+            hipLaunchKernelGGL(k_grid_factor<3>, dim3(wgs), dim3(64), 0, s, G, A->rowptr.p, d_val,
+                               F.lt64.p, F.ut64.p, F.dt64.p, faces.p, ctr.p, d_err);
+    }
+    KRY_HIP(hipGetLastError());
+    // the face buffer and counter are freed on return
+    KRY_HIP(hipStreamSynchronize(s));
+    return grid_finish(s, A, F);
 }
 
 // ---------------------------------------------------------------------------

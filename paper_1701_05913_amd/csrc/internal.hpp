@@ -242,6 +242,11 @@ const char *sweep_timer_name(bool fwd, int bs, int factor_bytes, int add_mode);
 // grid-tiled layout and sweeps (ilu_grid.hip)
 int ilu_grid_setup(hipStream_t s, const MAT_ *A, const double *lu, const double *uinv,
                    IluFactor &F);
+// numeric factorization straight into the grid layout (7-point stencils in
+// natural order with nx, ny >= 3, where ILU(0) only changes diagonal blocks)
+bool ilu_grid_can_factor(const MAT_ *A);
+int ilu_grid_factor_setup(hipStream_t s, const MAT_ *A, const double *d_val, IluFactor &F,
+                          int *d_err);
 int ilu_grid_apply(hipStream_t s, IluFactor &F, const void *b, int in_type, void *xscr,
                    int out_type, int add_mode, const void *add_in, void *add_out, int *d_err);
 

@@ -117,6 +117,11 @@ def test_grid_detection():
 @pytest.mark.parametrize("kind,grid", [("scalar", SMALL_SCALAR), ("scalar", (32, 32, 32)),
                                        ("block", SMALL_BLOCK), ("block", (64, 64, 64)),
                                        ("block", (20, 5, 3)), ("block", (9, 17, 2)),
+                                       # nx or ny = 2: the grid layout takes the factor
+                                       # from the row-wise elimination (fill lands on
+                                       # off-diagonal blocks), not the grid factorization
+                                       ("block", (2, 6, 5)), ("block", (7, 2, 6)),
+                                       ("scalar", (2, 9, 7)),
                                        ("block", (40, 1, 1)), ("block", (1, 1, 1))])
 def test_ilu_apply_parity_fp64(kind, grid, layout):
     s = _sys(kind, grid, seed=2)
