@@ -22,7 +22,8 @@ _SRC = os.path.join(_HERE, "oracle.c")
 
 OK, NOT_CONVERGED, ERR_ARG, ERR_ZERO_PIVOT, ERR_BREAKDOWN = 0, 1, -1, -4, -5
 PREC = {"f64": 0, "f32": 1, "bf16": 2}
-PC_KIND = {"none": 0, "bilu0": 1, "ilu0": 1, "cpr_pf": 2, "cpr_fp": 3}
+PC_KIND = {"none": 0, "bilu0": 1, "ilu0": 1, "cpr_pf": 2, "cpr_fp": 3,
+           "cpr_fpf": 5, "cpr_ffpf": 6}
 
 
 def build(force: bool = True) -> str:
@@ -192,7 +193,8 @@ def cpr_pressure_matrix(A: Matrix, w):
 
 
 class PC:
-    """Oracle preconditioner: kind in none/bilu0/cpr_pf/cpr_fp, precision
+    """Oracle preconditioner: kind in none/bilu0/cpr_pf/cpr_fp/cpr_fpf/
+    cpr_ffpf, precision
     f64/f32/bf16, p_sweeps = ILU(0) sweeps of the CPR pressure stage."""
 
     def __init__(self, A: Matrix, kind="bilu0", prec="f64", p_sweeps=4):

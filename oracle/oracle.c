@@ -345,7 +345,7 @@ static void lowp_apply(lowp_lu *L, const float *b, float *x)
 }
 
 /* ======================================================================
- * C8. CPR with quasi-IMPES decoupling (eqs. (5)-(9), Algorithms 5-6).
+ * C8. CPR with quasi-IMPES decoupling (eqs. (5)-(9), Algorithms 5-8).
  * Block unknown 0 is the pressure; Pi_r picks it, Pi_p injects it.
  * Quasi-IMPES weight of cell i from its diagonal block
  *   D_i = [[d_pp, d_ps^T], [d_sp, D_ss]]:  w_i^T = [1, -d_ps^T D_ss^{-1}],
@@ -408,12 +408,14 @@ or_pc *or_pc_create(int kind, int nb, int bs, const int *rp, const int *ci,
     int b2 = bs * bs, e = OR_OK;
     pc->kind = kind; pc->nb = nb; pc->bs = bs; pc->prec = prec;
     pc->p_sweeps = p_sweeps; pc->rp = rp; pc->ci = ci; pc->a = a;
-    if (kind == OR_PC_BILU0 || kind == OR_PC_CPR_PF || kind == OR_PC_CPR_FP) {
+    const int is_cpr = kind == OR_PC_CPR_PF || kind == OR_PC_CPR_FP ||
+                       kind == OR_PC_CPR_FPF || kind == OR_PC_CPR_FFPF;
+    if (kind == OR_PC_BILU0 || is_cpr) {
         pc->lu = (double *)malloc(sizeof(double) * nnzb * b2);
         e = or_bilu0(nb, bs, rp, ci, a, pc->lu);
         if (!e && prec != OR_PREC_F64) e = lowp_init(&pc->lp, nb, bs, rp, ci, pc->lu, prec);
     }
-    if (!e && (kind == OR_PC_CPR_PF || kind == OR_PC_CPR_FP)) {
+    if (!e && is_cpr) {
         if (bs != 3) e = OR_ERR_ARG;
         if (!e) {
             pc->w = (double *)malloc(sizeof(double) * 3 * (size_t)nb);
@@ -512,6 +514,109 @@ static void pstage_f32(or_pc *pc, const float *rpv, float *p)
     free(res); free(d);
 }
 
+/* Stages of the multi-stage CPR variants (Algorithms 7 and 8), each acting
+ * on the running iterate x: the residual r = f - A x, the full-system stage
+ * x <- x + BILU^-1 r, and the pressure stage x <- x + Pi_p P(Pi_r W r). */
+static void cpr_resid_f64(or_pc *pc, const double *f, const double *x, double *r)
+{
+    memcpy(r, f, sizeof(double) * 3 * (size_t)pc->nb);
+    or_bsr_amxpby(pc->nb, 3, pc->rp, pc->ci, pc->a, -1.0, x, 1.0, r);
+}
+
+static void cpr_full_f64(or_pc *pc, const double *r, double *x)
+{
+    const size_t n = 3 * (size_t)pc->nb;
+    double *t = (double *)malloc(sizeof(double) * n);
+    or_bilu0_solve(pc->nb, 3, pc->rp, pc->ci, pc->lu, r, t);
+    for (size_t i = 0; i < n; i++) x[i] += t[i];
+    free(t);
+}
+
+static void cpr_pressure_f64(or_pc *pc, const double *r, double *x)
+{
+    const int nb = pc->nb;
+    double *rpv = (double *)calloc((size_t)nb + 1, sizeof(double));
+    double *p = (double *)calloc((size_t)nb + 1, sizeof(double));
+    for (int i = 0; i < nb; i++)
+        rpv[i] = pc->w[3 * i] * r[3 * i] + pc->w[3 * i + 1] * r[3 * i + 1]
+               + pc->w[3 * i + 2] * r[3 * i + 2];
+    pstage_f64(pc, rpv, p);
+    for (int i = 0; i < nb; i++) x[3 * i] += p[i];
+    free(rpv); free(p);
+}
+
+static void cpr_resid_f32(or_pc *pc, const float *f, const float *x, float *r)
+{
+    for (int i = 0; i < pc->nb; i++)
+        for (int rr = 0; rr < 3; rr++) {
+            float s = 0.0f;
+            for (int q = pc->rp[i]; q < pc->rp[i + 1]; q++) {
+                const float *B = pc->af + (size_t)q * 9;
+                const float *xj = x + (size_t)pc->ci[q] * 3;
+                s += B[rr * 3] * xj[0] + B[rr * 3 + 1] * xj[1] + B[rr * 3 + 2] * xj[2];
+            }
+            r[3 * i + rr] = f[3 * i + rr] - s;
+        }
+}
+
+static void cpr_full_f32(or_pc *pc, const float *r, float *x)
+{
+    const size_t n = 3 * (size_t)pc->nb;
+    float *t = (float *)malloc(sizeof(float) * n);
+    lowp_apply(&pc->lp, r, t);
+    for (size_t i = 0; i < n; i++) x[i] += t[i];
+    free(t);
+}
+
+static void cpr_pressure_f32(or_pc *pc, const float *r, float *x)
+{
+    const int nb = pc->nb;
+    float *rpv = (float *)calloc((size_t)nb + 1, sizeof(float));
+    float *p = (float *)calloc((size_t)nb + 1, sizeof(float));
+    for (int i = 0; i < nb; i++)
+        rpv[i] = (float)pc->w[3 * i] * r[3 * i] + (float)pc->w[3 * i + 1] * r[3 * i + 1]
+               + (float)pc->w[3 * i + 2] * r[3 * i + 2];
+    pstage_f32(pc, rpv, p);
+    for (int i = 0; i < nb; i++) x[3 * i] += p[i];
+    free(rpv); free(p);
+}
+
+/* Algorithm 7 (FPF) and Algorithm 8 (FFPF) from x = 0; the first
+ * full-system stage sees r = f. */
+static void cpr_multistage_f64(or_pc *pc, const double *f, double *x)
+{
+    const size_t n = 3 * (size_t)pc->nb;
+    double *r = (double *)malloc(sizeof(double) * n);
+    memset(x, 0, sizeof(double) * n);
+    cpr_full_f64(pc, f, x);                       /* x = R^-1 f        */
+    if (pc->kind == OR_PC_CPR_FFPF) {
+        cpr_resid_f64(pc, f, x, r);               /* r = f - A x       */
+        cpr_full_f64(pc, r, x);                   /* x = x + R^-1 r    */
+    }
+    cpr_resid_f64(pc, f, x, r);                   /* r = f - A x       */
+    cpr_pressure_f64(pc, r, x);                   /* x = x + Pi_p(..)  */
+    cpr_resid_f64(pc, f, x, r);                   /* r = f - A x       */
+    cpr_full_f64(pc, r, x);                       /* x = x + R^-1 r    */
+    free(r);
+}
+
+static void cpr_multistage_f32(or_pc *pc, const float *f, float *x)
+{
+    const size_t n = 3 * (size_t)pc->nb;
+    float *r = (float *)malloc(sizeof(float) * n);
+    memset(x, 0, sizeof(float) * n);
+    cpr_full_f32(pc, f, x);
+    if (pc->kind == OR_PC_CPR_FFPF) {
+        cpr_resid_f32(pc, f, x, r);
+        cpr_full_f32(pc, r, x);
+    }
+    cpr_resid_f32(pc, f, x, r);
+    cpr_pressure_f32(pc, r, x);
+    cpr_resid_f32(pc, f, x, r);
+    cpr_full_f32(pc, r, x);
+    free(r);
+}
+
 static void conv_apply_learned(or_pc *pc, const double *v, double *z);
 
 void or_pc_apply(or_pc *pc, const double *v, double *z)
@@ -529,6 +634,10 @@ void or_pc_apply(or_pc *pc, const double *v, double *z)
     if (pc->prec == OR_PREC_F64) {
         if (pc->kind == OR_PC_BILU0) {
             or_bilu0_solve(nb, bs, pc->rp, pc->ci, pc->lu, v, z);
+            return;
+        }
+        if (pc->kind == OR_PC_CPR_FPF || pc->kind == OR_PC_CPR_FFPF) {
+            cpr_multistage_f64(pc, v, z);
             return;
         }
         double *rpv = (double *)calloc((size_t)nb + 1, sizeof(double));
@@ -569,6 +678,8 @@ void or_pc_apply(or_pc *pc, const double *v, double *z)
     for (size_t i = 0; i < n; i++) vf[i] = (float)v[i];
     if (pc->kind == OR_PC_BILU0) {
         lowp_apply(&pc->lp, vf, zf);
+    } else if (pc->kind == OR_PC_CPR_FPF || pc->kind == OR_PC_CPR_FFPF) {
+        cpr_multistage_f32(pc, vf, zf);
     } else {
         float *rpv = (float *)calloc((size_t)nb + 1, sizeof(float));
         float *p = (float *)malloc(sizeof(float) * nb);

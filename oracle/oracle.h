@@ -58,7 +58,7 @@ void or_bilu0_solve_upper(int nb, int bs, const int *rp, const int *ci,
 /* ---- preconditioner objects (Figure 29: setup / solve / destroy) ------- */
 typedef struct or_pc or_pc;
 enum { OR_PC_NONE = 0, OR_PC_BILU0 = 1, OR_PC_CPR_PF = 2, OR_PC_CPR_FP = 3,
-       OR_PC_LEARNED = 4 };
+       OR_PC_LEARNED = 4, OR_PC_CPR_FPF = 5, OR_PC_CPR_FFPF = 6 };
 
 or_pc *or_pc_create(int kind, int nb, int bs, const int *rp, const int *ci,
                     const double *a, int prec, int p_sweeps, int *err);

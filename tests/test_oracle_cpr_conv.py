@@ -1,5 +1,5 @@
-"""Pins of the oracle's CPR two-stage preconditioner with quasi-IMPES
-decoupling (eqs. (5)-(9), Algorithms 5-6), its reduced-precision
+"""Pins of the oracle's CPR multi-stage preconditioners with quasi-IMPES
+decoupling (eqs. (5)-(9), Algorithms 5-8), their reduced-precision
 emulation, and the learned stage (conv net, Adam, apply with fallback)."""
 import os
 
@@ -8,7 +8,7 @@ import pytest
 
 import oracle
 import reservoir_inputs as ri
-from tests._helpers import bsr_from_dense, dense, relerr
+from tests._helpers import bsr_from_dense, dense, dense_from_bsr, lu_dense_from_factor, relerr
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
 
@@ -63,7 +63,10 @@ def _decoupled_1d(nb=15, seed=0):
     return D
 
 
-@pytest.mark.parametrize("kind", ["cpr_pf", "cpr_fp"])
+CPR_KINDS = ["cpr_pf", "cpr_fp", "cpr_fpf", "cpr_ffpf"]
+
+
+@pytest.mark.parametrize("kind", CPR_KINDS)
 def test_cpr_exact_when_stages_are_exact(kind):
     D = _decoupled_1d()
     s = bsr_from_dense(D, 3)
@@ -101,7 +104,63 @@ def test_converged_pressure_stage_solves_pressure_only_systems():
     assert relerr(z1, x) > 1e-6
 
 
-@pytest.mark.parametrize("kind", ["bilu0", "cpr_pf", "cpr_fp"])
+# stage order of each variant, first applied first (Algorithms 5-8; the
+# PF variant in the two-stage reading)
+STAGES = {"cpr_pf": "PF", "cpr_fp": "FP", "cpr_fpf": "FPF", "cpr_ffpf": "FFPF"}
+
+
+@pytest.mark.parametrize("p_sweeps", [1, 3])
+@pytest.mark.parametrize("kind", CPR_KINDS)
+def test_cpr_error_propagator_is_product_of_stage_propagators(kind, p_sweeps):
+    """Each stage x <- x + B (f - A x) multiplies the error by (I - B A), so
+    the preconditioner is M^-1 = (I - prod_k (I - B_k A)) A^-1, with the
+    last stage leftmost.  B_F = (L U)^-1 from the dense block factor;
+    B_P = Pi_p S Pi_r W with S the closed form of s stationary sweeps from
+    zero, S = (I - (I - M_p^-1 A_pp)^s) A_pp^-1."""
+    s = ri.blackoil_system(3, 3, 2, seed=11)
+    A = oracle.Matrix.from_system(s)
+    D = dense(s)
+    n, nb = A.n, A.nb
+    rc, lu = oracle.bilu0(A)
+    assert rc == 0
+    L, U = lu_dense_from_factor(A.rowptr, A.col, lu, 3)
+    BF = np.linalg.inv(L @ U)
+    rc, w = oracle.cpr_weights(A)
+    app = oracle.cpr_pressure_matrix(A, w)
+    P = oracle.Matrix(A.rowptr, A.col, app, 1)
+    rc, plu = oracle.bilu0(P)
+    assert rc == 0
+    Lp, Up = lu_dense_from_factor(A.rowptr, A.col, plu, 1)
+    App = dense_from_bsr(A.rowptr, A.col, app, 1)
+    G = np.eye(nb) - np.linalg.solve(Lp @ Up, App)
+    S = (np.eye(nb) - np.linalg.matrix_power(G, p_sweeps)) @ np.linalg.inv(App)
+    R = np.zeros((nb, n))
+    Pi = np.zeros((n, nb))
+    for i in range(nb):
+        R[i, 3 * i:3 * i + 3] = w[3 * i:3 * i + 3]
+        Pi[3 * i, i] = 1.0
+    BP = Pi @ S @ R
+    E = np.eye(n)
+    for st in STAGES[kind]:
+        E = (np.eye(n) - (BF if st == "F" else BP) @ D) @ E
+    Minv = (np.eye(n) - E) @ np.linalg.inv(D)
+    v = np.random.default_rng(12).standard_normal(n)
+    z = oracle.PC(A, kind, p_sweeps=p_sweeps).apply(v)
+    assert relerr(z, Minv @ v) < 1e-11
+
+
+def test_cpr_variants_differ():
+    # the four step sequences are different operators on a generic system
+    s = ri.blackoil_system(5, 4, 3, seed=13)
+    A = oracle.Matrix.from_system(s)
+    v = np.random.default_rng(14).standard_normal(A.n)
+    zs = [oracle.PC(A, k).apply(v) for k in CPR_KINDS]
+    for a in range(4):
+        for b in range(a + 1, 4):
+            assert relerr(zs[a], zs[b]) > 1e-6
+
+
+@pytest.mark.parametrize("kind", ["bilu0"] + CPR_KINDS)
 def test_reduced_precision_apply_close_to_fp64(kind):
     s = ri.blackoil_system(8, 8, 8, seed=6)
     A = oracle.Matrix.from_system(s)

@@ -66,6 +66,19 @@ MUTANTS = [
      "or_bsr_amxpby(nb, 3, pc->rp, pc->ci, pc->a, -1.0, z, 1.0, r);\n            or_bilu0_solve(nb, 3, pc->rp, pc->ci, pc->lu, r, t);",
      "or_bilu0_solve(nb, 3, pc->rp, pc->ci, pc->lu, r, t);",
      [lambda: tc.test_cpr_exact_when_stages_are_exact("cpr_pf")]),
+    ("cpr_ffpf_skips_second_full_stage",
+     "if (pc->kind == OR_PC_CPR_FFPF) {\n        cpr_resid_f64(pc, f, x, r);",
+     "if (0) {\n        cpr_resid_f64(pc, f, x, r);",
+     [lambda: tc.test_cpr_error_propagator_is_product_of_stage_propagators("cpr_ffpf", 1)]),
+    ("cpr_fpf_last_stage_on_f",
+     "    cpr_resid_f64(pc, f, x, r);                   /* r = f - A x       */\n    cpr_full_f64(pc, r, x);                       /* x = x + R^-1 r    */\n    free(r);",
+     "    cpr_full_f64(pc, f, x);\n    free(r);",
+     [lambda: tc.test_cpr_exact_when_stages_are_exact("cpr_fpf"),
+      lambda: tc.test_cpr_error_propagator_is_product_of_stage_propagators("cpr_fpf", 1)]),
+    ("cpr_multistage_pressure_ignores_weights",
+     "        rpv[i] = pc->w[3 * i] * r[3 * i] + pc->w[3 * i + 1] * r[3 * i + 1]\n               + pc->w[3 * i + 2] * r[3 * i + 2];\n    pstage_f64(pc, rpv, p);\n    for (int i = 0; i < nb; i++) x[3 * i] += p[i];",
+     "        rpv[i] = r[3 * i];\n    pstage_f64(pc, rpv, p);\n    for (int i = 0; i < nb; i++) x[3 * i] += p[i];",
+     [lambda: tc.test_cpr_error_propagator_is_product_of_stage_propagators("cpr_fpf", 3)]),
     ("gelu_grad_missing_density_term",
      "return 0.5 * (1.0 + erf(x / sqrt(2.0))) + x * exp(-0.5 * x * x) / sqrt(2.0 * pi);",
      "return 0.5 * (1.0 + erf(x / sqrt(2.0)));",
