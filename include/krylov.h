@@ -64,9 +64,12 @@ enum { KRY_PC_NONE = 0, KRY_PC_ILU0 = 1, KRY_PC_BILU0 = 1, KRY_PC_CPR = 2,
        KRY_PC_BILU0_LEARNED = 4, KRY_PC_CPR_LEARNED = 5 };
 /* precision of the preconditioner apply (mixed-precision extension) */
 enum { KRY_PREC_F64 = 0, KRY_PREC_F32 = 1, KRY_PREC_BF16_FACTORS = 2 };
-/* CPR stage order: PF = pressure then full (Algorithm 6, corrected);
- * FP = full then pressure (Algorithm 5) */
-enum { KRY_CPR_PF = 0, KRY_CPR_FP = 1 };
+/* CPR stage order (Section 4.2.1): PF = pressure then full (Algorithm 6,
+ * read as the two-stage method); FP = full then pressure (Algorithm 5);
+ * FPF = full, pressure, full (Algorithm 7); FFPF = full, full, pressure,
+ * full (Algorithm 8).  Every stage after the first acts on the residual
+ * of the running iterate. */
+enum { KRY_CPR_PF = 0, KRY_CPR_FP = 1, KRY_CPR_FPF = 2, KRY_CPR_FFPF = 3 };
 /* layout of the ILU triangular sweeps: AUTO picks GRID when the matrix is a
  * 7-point stencil on an nx x ny x nz grid (nx, ny, nz >= 2) in natural
  * order, LEVELS otherwise */
@@ -168,8 +171,9 @@ int  SolverSetAugk(SOLVER *s, int64_t k);       /* LGMRES: only k = 0 */
  *   FP32 diagonal inverses and FP32 arithmetic); requires FGMRES for
  *   anything but FP64.  Outer iteration, orthogonalization, Givens and
  *   true residuals stay FP64.
- * SolverSetCPR: stage order and number of ILU(0) sweeps of the pressure
- *   stage (default PF, 4).
+ * SolverSetCPR: stage order (KRY_CPR_*) and number of ILU(0) sweeps of the
+ *   pressure stage (default PF, 4); KRY_ERR_ARG for another variant or
+ *   p_sweeps < 1.
  * SolverSetStream: HIP stream (hipStream_t) for all work of the solver. */
 int SolverSetPrecision(SOLVER *s, int prec);
 int SolverSetCPR(SOLVER *s, int variant, int p_sweeps);

@@ -34,7 +34,7 @@ KRY_GMRES, KRY_FGMRES, KRY_BICGSTAB = 0, 1, 2
 KRY_PC_NONE, KRY_PC_ILU0, KRY_PC_BILU0, KRY_PC_CPR, KRY_PC_CUSTOM = 0, 1, 1, 2, 3
 KRY_PC_BILU0_LEARNED, KRY_PC_CPR_LEARNED = 4, 5
 KRY_PREC_F64, KRY_PREC_F32, KRY_PREC_BF16_FACTORS = 0, 1, 2
-KRY_CPR_PF, KRY_CPR_FP = 0, 1
+KRY_CPR_PF, KRY_CPR_FP, KRY_CPR_FPF, KRY_CPR_FFPF = 0, 1, 2, 3
 KRY_SWEEP_AUTO, KRY_SWEEP_LEVELS, KRY_SWEEP_GRID = 0, 1, 2
 
 

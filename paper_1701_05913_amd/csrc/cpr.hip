@@ -1,5 +1,5 @@
-// CPR two-stage preconditioner with quasi-IMPES decoupling (Section 4.2.1:
-// eqs. (5)-(9), Algorithms 5 and 6).
+// CPR multi-stage preconditioners with quasi-IMPES decoupling (Section
+// 4.2.1: eqs. (5)-(9), Algorithms 5-8).
 //
 // Block unknown 0 is the pressure; Pi_r takes component 0 of each block
 // (eq. (7)), Pi_p injects a pressure vector into a zero vector (eq. (8)).
@@ -12,6 +12,10 @@
 //   PF (Algorithm 6 with its garbled steps 2 and 4 read as the classical
 //   two-stage CPR):  z1 = Pi_p(P(Pi_r W v)); r = v - A z1; z = z1 + BILU^-1 r
 //   FP (Algorithm 5):  z1 = BILU^-1 v; r = v - A z1; z = z1 + Pi_p(P(Pi_r W r))
+//   FPF (Algorithm 7) and FFPF (Algorithm 8): a running iterate x, from
+//   x = BILU^-1 v, then each further stage on r = v - A x:
+//   F: x += BILU^-1 r;  P: x += Pi_p(P(Pi_r W r)).  FPF = F,P,F;
+//   FFPF = F,F,P,F.
 // Reduced precision: every vector inside the apply is FP32; the pressure
 // factor is FP32 in both reduced variants, the block factor FP32 or BF16.
 #include <type_traits>
@@ -79,6 +83,20 @@ __global__ void k_restrict(int nb, const double *__restrict__ w, const TIN *__re
             static_cast<T>(w[3 * i + 2]) * v2;
 }
 
+// x_i0 += p_i (pressure injection into the running iterate)
+template <typename T>
+__global__ void k_inject_inplace(int nb, const T *__restrict__ p, T *__restrict__ x) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nb) return;
+    x[3 * (int64_t)i] += p[i];
+}
+
+__global__ void k_widen(int64_t n, const float *__restrict__ x, double *__restrict__ y) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        y[i] = static_cast<double>(x[i]);
+}
+
 // z = z1 + Pi_p p  (double output)
 template <typename T>
 __global__ void k_inject_add(int nb, const T *__restrict__ z1, const T *__restrict__ p,
@@ -141,10 +159,10 @@ int cpr_setup(hipStream_t s, MAT_ *A, CprPC &C, int variant, int sweeps, int pre
         if (variant == KRY_CPR_PF) KRY_TRY(ensure_col0_f32(s, A));
         else KRY_TRY(ensure_sell_f32(s, A->sell));
     }
-    // scratch: rp, p, p2, d (nb each) and vf, r2, xs, z1 (n each)
+    // scratch: rp, p, p2, d (nb each) and vf, r2, xs, z1, z2 (n each)
     const size_t el = prec == KRY_PREC_F64 ? sizeof(double) : sizeof(float);
     const size_t nbp = ((size_t)nb + 63) / 64 * 64, np = 3 * nbp;
-    KRY_TRY(C.work.alloc(el * (4 * nbp + 4 * np)));
+    KRY_TRY(C.work.alloc(el * (4 * nbp + 5 * np)));
     KRY_HIP(hipStreamSynchronize(s));
     return KRY_OK;
 }
@@ -156,7 +174,7 @@ static int cpr_apply_t(hipStream_t s, MAT_ *A, CprPC &C, const double *v, double
     const size_t nbp = ((size_t)nb + 63) / 64 * 64, np = 3 * nbp;
     T *base = reinterpret_cast<T *>(C.work.p);
     T *rp = base, *p = base + nbp, *p2 = base + 2 * nbp, *d = base + 3 * nbp;
-    T *vf = base + 4 * nbp, *r2 = vf + np, *xs = r2 + np, *z1 = xs + np;
+    T *vf = base + 4 * nbp, *r2 = vf + np, *xs = r2 + np, *z1 = xs + np, *z2 = z1 + np;
     const int tin = std::is_same<T, double>::value ? 0 : 1;
     const dim3 g((nb + 255) / 256), blk(256);
     const T *vin = reinterpret_cast<const T *>(v);
@@ -180,7 +198,32 @@ static int cpr_apply_t(hipStream_t s, MAT_ *A, CprPC &C, const double *v, double
         }
         return KRY_OK;
     };
-    if (C.variant == KRY_CPR_PF) {
+    // r2 = v - A x over the full blocks
+    auto residual = [&](const T *x) -> int {
+        if (tin == 0)
+            return spmv_f64(s, A, -1.0, (const double *)x, 1.0, v, (double *)r2, 0, nullptr,
+                            nullptr, nullptr);
+        return spmv_sell_f32(s, A->sell, nb, -1.0f, (const float *)x, 1.0f, (const float *)vin,
+                             (float *)r2);
+    };
+    if (C.variant == KRY_CPR_FPF || C.variant == KRY_CPR_FFPF) {
+        KRY_TRY(ilu_apply(s, C.ilu_a, vin, tin, z1, tin, 0, nullptr, nullptr, err));
+        if (C.variant == KRY_CPR_FFPF) {
+            KRY_TRY(residual(z1));
+            KRY_TRY(ilu_apply(s, C.ilu_a, r2, tin, xs, tin, 1, z1, z2, err));
+            std::swap(z1, z2);
+        }
+        KRY_TRY(residual(z1));
+        KRY_TRY(pressure_stage(r2));
+        hipLaunchKernelGGL(k_inject_inplace<T>, g, blk, 0, s, nb, p, z1);
+        KRY_TRY(residual(z1));
+        if (tin == 0) {
+            KRY_TRY(ilu_apply(s, C.ilu_a, r2, tin, xs, tin, 1, z1, z, err));
+        } else {
+            KRY_TRY(ilu_apply(s, C.ilu_a, r2, tin, xs, tin, 1, z1, z2, err));
+            hipLaunchKernelGGL(k_widen, dim3(2048), blk, 0, s, n, (const float *)z2, z);
+        }
+    } else if (C.variant == KRY_CPR_PF) {
         KRY_TRY(pressure_stage(vin));
         if (tin == 0)
             KRY_TRY(spmv_col0_residual_f64(s, A, (const double *)vin, (const double *)p, (double *)r2));

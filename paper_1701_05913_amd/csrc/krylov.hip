@@ -708,7 +708,7 @@ extern "C" int SolverSetPrecision(SOLVER *s, int prec) {
     return KRY_OK;
 }
 extern "C" int SolverSetCPR(SOLVER *s, int variant, int p_sweeps) {
-    if (!s || (variant != KRY_CPR_PF && variant != KRY_CPR_FP) || p_sweeps < 1)
+    if (!s || variant < KRY_CPR_PF || variant > KRY_CPR_FFPF || p_sweeps < 1)
         return set_error(KRY_ERR_ARG, "SolverSetCPR: bad argument");
     s->cpr_variant = variant;
     s->cpr_sweeps = p_sweeps;

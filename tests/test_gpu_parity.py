@@ -172,9 +172,13 @@ def test_ilu_apply_parity_reduced(kind, grid, prec, tol, layout):
     assert relerr(z, ref64) > 1e-9
 
 
-# ---- CPR two-stage -----------------------------------------------------------------
+# ---- CPR multi-stage ---------------------------------------------------------------
+CPR_VARIANTS = {K.KRY_CPR_PF: "cpr_pf", K.KRY_CPR_FP: "cpr_fp", K.KRY_CPR_FPF: "cpr_fpf",
+                K.KRY_CPR_FFPF: "cpr_ffpf"}
+
+
 @pytest.mark.parametrize("layout", LAYOUTS)
-@pytest.mark.parametrize("variant", [K.KRY_CPR_PF, K.KRY_CPR_FP])
+@pytest.mark.parametrize("variant", list(CPR_VARIANTS))
 @pytest.mark.parametrize("prec,tol", [(K.KRY_PREC_F64, 1e-10), (K.KRY_PREC_F32, 1e-5),
                                       (K.KRY_PREC_BF16_FACTORS, 1e-4)])
 @pytest.mark.parametrize("grid", [SMALL_BLOCK, (32, 32, 16)])
@@ -183,14 +187,30 @@ def test_cpr_apply_parity(grid, variant, prec, tol, layout):
     A = oracle.Matrix.from_system(s)
     v = np.random.default_rng(8).standard_normal(A.n)
     name = {K.KRY_PREC_F64: "f64", K.KRY_PREC_F32: "f32", K.KRY_PREC_BF16_FACTORS: "bf16"}[prec]
-    kind = "cpr_pf" if variant == K.KRY_CPR_PF else "cpr_fp"
-    ref = oracle.PC(A, kind, name, p_sweeps=4).apply(v)
+    ref = oracle.PC(A, CPR_VARIANTS[variant], name, p_sweeps=4).apply(v)
     g = GpuSystem(s)
     try:
         z = pc_apply(g, K.KRY_PC_CPR, v, prec=prec, cpr=(variant, 4), layout=layout)
     finally:
         g.close()
     assert relerr(z, ref) <= tol
+
+
+@pytest.mark.parametrize("variant", list(CPR_VARIANTS))
+@pytest.mark.parametrize("prec", [K.KRY_PREC_F64, K.KRY_PREC_F32])
+def test_cpr_fgmres_solve(variant, prec):
+    # FGMRES(30) with each CPR stage order, rtol 1e-8, against the oracle
+    s = ri.blackoil_system(*SMALL_BLOCK, seed=9)
+    A = oracle.Matrix.from_system(s)
+    g = GpuSystem(s)
+    try:
+        gpu = solve(g, K.KRY_FGMRES, K.KRY_PC_CPR, rtol=1e-8, maxit=2000, prec=prec,
+                    cpr=(variant, 4))
+    finally:
+        g.close()
+    name = "f64" if prec == K.KRY_PREC_F64 else "f32"
+    _check_solve(s, gpu, A, oracle.PC(A, CPR_VARIANTS[variant], name, p_sweeps=4), 1e-8,
+                 oracle.gmres, restart=30, maxit=2000, flexible=True)
 
 
 # ---- solves ------------------------------------------------------------------
