@@ -49,108 +49,258 @@ struct SmallLayout {
 };
 
 // ---------------------------------------------------------------------------
-// CGS2 kernels: V column-major with leading dimension ldv
+// CGS2 kernels.  V is column-major with leading dimension ldv, a multiple of
+// 64, so every column (and w, itself a column of V) is 512-byte aligned.
+// Each pass writes one partial per workgroup; a one-block kernel sums them
+// in block order.  (A last-arriving-block reduction inside the pass would
+// need an agent-scope release per block, which writes back and invalidates
+// the non-coherent L2 of every XCD, evicting V: slower than a launch.)
 // ---------------------------------------------------------------------------
+constexpr int CGS_ROWS = 4;      // rows per thread in passes 1 and 3: two 16-byte loads per column
+constexpr int CGS_CH = 256;      // rows per LDS tile in pass 2
+constexpr int CGS_MAXBLK = 1024; // largest grid of a pass (partials per column)
+
+// Lane l ends with the wavefront total of column l >> (6 - log2 MAXC): each
+// butterfly step hands half of the remaining columns to the partner lane,
+// so MAXC columns cost MAXC - 1 + (6 - log2 MAXC) shuffles.
 template <int MAXC>
-__device__ __forceinline__ void block_reduce_cols(double *acc, int nc, double *lds /*4*MAXC*/,
-                                                  double *out /*MAXC*/) {
-    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+__device__ __forceinline__ double wave_transpose_sum(double (&acc)[MAXC]) {
+    const int lane = threadIdx.x & 63;
+    int off = 32;
 #pragma unroll
-    for (int k = 0; k < MAXC; k++) {
-        if (k < nc) {
-            double v = wave_sum(acc[k]);
-            if (l == 0) lds[w * MAXC + k] = v;
+    for (int half = MAXC / 2; half >= 1; half >>= 1, off >>= 1) {
+        const bool upper = (lane & off) != 0;
+#pragma unroll
+        for (int c = 0; c < half; c++) {
+            const double send = upper ? acc[c] : acc[c + half];
+            const double keep = upper ? acc[c + half] : acc[c];
+            acc[c] = keep + __shfl_xor(send, off, 64);
         }
     }
+    double s = acc[0];
+    for (; off >= 1; off >>= 1) s += __shfl_xor(s, off, 64);
+    return s;
+}
+
+template <int MAXC>
+constexpr int cgs_shift() {
+    return MAXC == 64 ? 0 : MAXC == 32 ? 1 : MAXC == 16 ? 2 : 3;
+}
+
+// out[k] = block total of acc[k], k < nc (256 threads; lds >= 4 * MAXC)
+template <int MAXC>
+__device__ __forceinline__ void block_reduce_cols(double (&acc)[MAXC], int nc, double *lds,
+                                                  double *out) {
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+    const double s = wave_transpose_sum<MAXC>(acc);
+    constexpr int SH = cgs_shift<MAXC>();
+    if ((l & ((1 << SH) - 1)) == 0) lds[w * MAXC + (l >> SH)] = s;
     __syncthreads();
-    if (threadIdx.x < nc) {
-        const int k = threadIdx.x;
-        out[k] = lds[k] + lds[MAXC + k] + lds[2 * MAXC + k] + lds[3 * MAXC + k];
+    if (threadIdx.x < nc)
+        out[threadIdx.x] = lds[threadIdx.x] + lds[MAXC + threadIdx.x] + lds[2 * MAXC + threadIdx.x] +
+                           lds[3 * MAXC + threadIdx.x];
+}
+
+// out[k] = sum over blocks b of partial[b * MAXCOL + k], k < nc, in one
+// block of NT threads: thread t takes column t % MAXC and the blocks
+// b = t / MAXC (mod NT / MAXC), four independent loads in flight, then the
+// groups are added in order (deterministic)
+template <int MAXC, int NT>
+__global__ __launch_bounds__(NT) void k_sum_cols(const double *__restrict__ partial, int nblocks,
+                                                 int nc, double *__restrict__ out) {
+    constexpr int G = NT / MAXC;
+    __shared__ double lds[NT];
+    const int k = threadIdx.x % MAXC, g = threadIdx.x / MAXC;
+    double s = 0.0;
+    if (k < nc) {
+        int b = g;
+        for (; b + 3 * G < nblocks; b += 4 * G) {
+            const double a0 = partial[(size_t)b * MAXCOL + k];
+            const double a1 = partial[(size_t)(b + G) * MAXCOL + k];
+            const double a2 = partial[(size_t)(b + 2 * G) * MAXCOL + k];
+            const double a3 = partial[(size_t)(b + 3 * G) * MAXCOL + k];
+            s += a0;
+            s += a1;
+            s += a2;
+            s += a3;
+        }
+        for (; b < nblocks; b += G) s += partial[(size_t)b * MAXCOL + k];
+    }
+    lds[threadIdx.x] = s;
+    __syncthreads();
+    if ((int)threadIdx.x < nc) {
+        double r = 0.0;
+#pragma unroll 8
+        for (int q = 0; q < G; q++) r += lds[q * MAXC + threadIdx.x];
+        out[threadIdx.x] = r;
     }
 }
 
-// pass 1: partial[b * MAXCOL + k] = sum_i V[k][i] w[i]
+// pass 1: partials of V^T w
 template <int MAXC>
-__global__ __launch_bounds__(256) void k_gemvt(int64_t n, const double *__restrict__ V,
-                                               int64_t ldv, int nc, const double *__restrict__ w,
-                                               double *__restrict__ partial) {
-    __shared__ double lds[4 * MAXC];
+__global__ __launch_bounds__(256) void k_cgs_dots(int n, const double *__restrict__ V, int64_t ldv,
+                                                  int nc, const double *__restrict__ w,
+                                                  double *__restrict__ partial) {
+    __shared__ double lds[256];
     double acc[MAXC];
 #pragma unroll
     for (int k = 0; k < MAXC; k++) acc[k] = 0.0;
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
-         i += (int64_t)gridDim.x * blockDim.x) {
-        const double wi = w[i];
+    const int nq = n / CGS_ROWS;
+    for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < nq; q += gridDim.x * blockDim.x) {
+        const unsigned off = (unsigned)q * CGS_ROWS;
+        const double2 w0 = *reinterpret_cast<const double2 *>(w + off);
+        const double2 w1 = *reinterpret_cast<const double2 *>(w + off + 2);
 #pragma unroll
         for (int k = 0; k < MAXC; k++)
-            if (k < nc) acc[k] += V[k * ldv + i] * wi;
+            if (k < nc) {
+                const double2 *col = reinterpret_cast<const double2 *>(V + k * ldv + off);
+                const double2 a = col[0], b = col[1];
+                acc[k] += a.x * w0.x + a.y * w0.y + b.x * w1.x + b.y * w1.y;
+            }
+    }
+    // ragged tail (n not a multiple of CGS_ROWS)
+    if (blockIdx.x == 0 && (int)threadIdx.x < n - nq * CGS_ROWS) {
+        const int r = nq * CGS_ROWS + threadIdx.x;
+        const double wr = w[r];
+#pragma unroll
+        for (int k = 0; k < MAXC; k++)
+            if (k < nc) acc[k] += V[k * ldv + r] * wr;
     }
     block_reduce_cols<MAXC>(acc, nc, lds, partial + (size_t)blockIdx.x * MAXCOL);
 }
 
-// w -= V h, then (NORM = 0) partial dots V^T w or (NORM = 1) partial ||w||^2
-template <int MAXC, int NORM>
-__global__ __launch_bounds__(256) void k_gemvn_update(int64_t n, const double *__restrict__ V,
-                                                      int64_t ldv, int nc,
-                                                      const double *__restrict__ h, double *w,
-                                                      double *__restrict__ partial) {
-    __shared__ double lds[4 * MAXC];
+// pass 2: w -= V h, then partials of V^T w.  A row's t is final only after all
+// nc columns, so each block stages a tile of CGS_CH rows of V in LDS: the
+// threads form t row by row, then every wavefront takes MAXC / 4 columns
+// of the tile for the dot products.  The next tile's V is loaded into
+// registers while the current tile's products run.
+template <int MAXC>
+__global__ __launch_bounds__(256) void k_cgs_update_dots(int n, const double *__restrict__ V,
+                                                         int64_t ldv, int nc, const double *h,
+                                                         double *__restrict__ w,
+                                                         double *__restrict__ partial) {
+    constexpr int CPW = MAXC / 4;
+    __shared__ double tile[MAXC][CGS_CH];
+    __shared__ double tl[CGS_CH];
+    __shared__ double lds[256];
     __shared__ double hs[MAXC];
-    if (threadIdx.x < nc) hs[threadIdx.x] = h[threadIdx.x];
+    if (threadIdx.x < MAXC) hs[threadIdx.x] = (int)threadIdx.x < nc ? h[threadIdx.x] : 0.0;
     __syncthreads();
-    double acc[NORM ? 1 : MAXC];
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    double acc[CPW];
 #pragma unroll
-    for (int k = 0; k < (NORM ? 1 : MAXC); k++) acc[k] = 0.0;
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
-         i += (int64_t)gridDim.x * blockDim.x) {
-        double v[MAXC];
-        double t = w[i];
+    for (int c = 0; c < CPW; c++) acc[c] = 0.0;
+    double pre[MAXC], wpre = 0.0;
+    const int stride = gridDim.x * CGS_CH;
+    auto load = [&](int b) {
+        const int r = b + threadIdx.x;
+        const bool ok = r < n;
+        wpre = ok ? w[r] : 0.0;
+#pragma unroll
+        for (int k = 0; k < MAXC; k++)
+            if (k < nc) pre[k] = ok ? V[k * ldv + r] : 0.0;
+    };
+    int base = blockIdx.x * CGS_CH;
+    if (base < n) load(base);
+    for (; base < n; base += stride) {
+        double t = wpre;
 #pragma unroll
         for (int k = 0; k < MAXC; k++)
             if (k < nc) {
-                v[k] = V[k * ldv + i];
-                t -= v[k] * hs[k];
+                tile[k][threadIdx.x] = pre[k];
+                t -= pre[k] * hs[k];
             }
-        w[i] = t;
-        if (NORM) {
-            acc[0] += t * t;
-        } else {
+        if (base + (int)threadIdx.x < n) w[base + threadIdx.x] = t;
+        tl[threadIdx.x] = t;
+        __syncthreads();
+        if (base + stride < n) load(base + stride);
 #pragma unroll
-            for (int k = 0; k < MAXC; k++)
-                if (k < nc) acc[k] += v[k] * t;
+        for (int c = 0; c < CPW; c++) {
+            const int k = wv * CPW + c;
+            if (k < nc) {
+#pragma unroll
+                for (int q = 0; q < CGS_CH / 64; q++)
+                    acc[c] += tile[k][lane + 64 * q] * tl[lane + 64 * q];
+            }
         }
+        __syncthreads();
     }
-    block_reduce_cols<NORM ? 1 : MAXC>(acc, NORM ? 1 : nc, lds, partial + (size_t)blockIdx.x * MAXCOL);
+#pragma unroll
+    for (int c = 0; c < CPW; c++) {
+        const double s = wave_sum(acc[c]);
+        if (lane == 0) lds[wv * CPW + c] = s;
+    }
+    __syncthreads();
+    if ((int)threadIdx.x < nc) partial[(size_t)blockIdx.x * MAXCOL + threadIdx.x] = lds[threadIdx.x];
 }
 
-// out[k] = sum over blocks of partial[b * MAXCOL + k]
-__global__ __launch_bounds__(256) void k_sum_cols(const double *__restrict__ partial, int nblocks,
-                                                  int nc, double *__restrict__ out) {
-    __shared__ double lds[4];
-    for (int k = 0; k < nc; k++) {
-        double s = 0.0;
-        for (int b = threadIdx.x; b < nblocks; b += blockDim.x) s += partial[(size_t)b * MAXCOL + k];
-        s = block_sum<256>(s, lds);
-        if (threadIdx.x == 0) out[k] = s;
+// pass 3: w -= V h and partials of ||w||^2
+template <int MAXC>
+__global__ __launch_bounds__(256) void k_cgs_update_norm(int n, const double *__restrict__ V,
+                                                         int64_t ldv, int nc, const double *h,
+                                                         double *__restrict__ w,
+                                                         double *__restrict__ partial) {
+    __shared__ double lds[256];
+    __shared__ double hs[MAXC];
+    if (threadIdx.x < MAXC) hs[threadIdx.x] = (int)threadIdx.x < nc ? h[threadIdx.x] : 0.0;
+    __syncthreads();
+    double acc = 0.0;
+    const int nq = n / CGS_ROWS;
+    for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < nq; q += gridDim.x * blockDim.x) {
+        const unsigned off = (unsigned)q * CGS_ROWS;
+        double2 t0 = *reinterpret_cast<const double2 *>(w + off);
+        double2 t1 = *reinterpret_cast<const double2 *>(w + off + 2);
+#pragma unroll
+        for (int k = 0; k < MAXC; k++)
+            if (k < nc) {
+                const double2 *col = reinterpret_cast<const double2 *>(V + k * ldv + off);
+                const double2 a = col[0], b = col[1];
+                t0.x -= a.x * hs[k];
+                t0.y -= a.y * hs[k];
+                t1.x -= b.x * hs[k];
+                t1.y -= b.y * hs[k];
+            }
+        *reinterpret_cast<double2 *>(w + off) = t0;
+        *reinterpret_cast<double2 *>(w + off + 2) = t1;
+        acc += t0.x * t0.x + t0.y * t0.y + t1.x * t1.x + t1.y * t1.y;
     }
+    if (blockIdx.x == 0 && (int)threadIdx.x < n - nq * CGS_ROWS) {
+        const int r = nq * CGS_ROWS + threadIdx.x;
+        double t = w[r];
+#pragma unroll
+        for (int k = 0; k < MAXC; k++)
+            if (k < nc) t -= V[k * ldv + r] * hs[k];
+        w[r] = t;
+        acc += t * t;
+    }
+    acc = wave_sum(acc);
+    if ((threadIdx.x & 63) == 0) lds[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) partial[(size_t)blockIdx.x * MAXCOL] = lds[0] + lds[1] + lds[2] + lds[3];
 }
 
-// Finish Arnoldi step j: column j of H = h1 + h2, h_{j+1,j} = ||w||, apply
-// the previous Givens rotations, form rotation j, update g and the
-// residual estimate |g_{j+1}|.
+// Finish Arnoldi step j: ||w||^2 from the pass-3 partials (block sum in a
+// fixed order); column j of H = h1 + h2 and h_{j+1,j} = ||w||; apply the
+// previous Givens rotations, form rotation j, update g and the residual
+// estimate |g_{j+1}|.  The operands are loaded into LDS by all threads; the
+// rotation sweep itself is serial on thread 0.
 __global__ __launch_bounds__(256) void k_arnoldi_finish(const double *__restrict__ partial,
                                                         int nblocks, int j, int m, double *small,
                                                         SmallLayout L) {
     __shared__ double lds[4];
+    __shared__ double col[MAXCOL + 1], cs[MAXCOL], sn[MAXCOL];
     double s = 0.0;
     for (int b = threadIdx.x; b < nblocks; b += blockDim.x) s += partial[(size_t)b * MAXCOL];
+    const double *h1 = small + L.h1, *h2 = small + L.h2;
+    if ((int)threadIdx.x <= j) col[threadIdx.x] = h1[threadIdx.x] + h2[threadIdx.x];
+    if ((int)threadIdx.x < j) {
+        cs[threadIdx.x] = small[L.cs + threadIdx.x];
+        sn[threadIdx.x] = small[L.sn + threadIdx.x];
+    }
     s = block_sum<256>(s, lds);
     if (threadIdx.x != 0) return;
-    double *col = small + L.H + (size_t)j * (m + 1);
-    double *cs = small + L.cs, *sn = small + L.sn, *g = small + L.g, *sc = small + L.sc;
-    const double *h1 = small + L.h1, *h2 = small + L.h2;
+    double *H = small + L.H + (size_t)j * (m + 1), *g = small + L.g, *sc = small + L.sc;
     const double hn = sqrt(s);
-    for (int k = 0; k <= j; k++) col[k] = h1[k] + h2[k];
     col[j + 1] = hn;
     sc[SC_HN] = hn;
     sc[SC_INVHN] = hn != 0.0 ? 1.0 / hn : 0.0;
@@ -166,13 +316,15 @@ __global__ __launch_bounds__(256) void k_arnoldi_finish(const double *__restrict
         c = col[j] / r;
         sv = col[j + 1] / r;
     }
-    cs[j] = c;
-    sn[j] = sv;
+    small[L.cs + j] = c;
+    small[L.sn + j] = sv;
     col[j] = r;
     col[j + 1] = 0.0;
-    g[j + 1] = -sv * g[j];
-    g[j] = c * g[j];
-    sc[SC_EST] = fabs(g[j + 1]);
+    for (int k = 0; k <= j + 1; k++) H[k] = col[k];
+    const double gj = g[j];
+    g[j + 1] = -sv * gj;
+    g[j] = c * gj;
+    sc[SC_EST] = fabs(sv * gj);
 }
 
 // g = beta e_1 and the first basis vector scale factor
@@ -351,7 +503,8 @@ static int ensure_workspace(SOLVER_ *S) {
     KRY_TRY(S->wrk.alloc((size_t)8 * ldv));
     SmallLayout L(m);
     KRY_TRY(S->small.alloc(L.total));
-    const size_t np = std::max<size_t>((size_t)RED_BLOCKS * MAXCOL, (size_t)spmv_blocks(S->A) * 2);
+    const size_t np = std::max<size_t>({(size_t)RED_BLOCKS * MAXCOL, (size_t)CGS_MAXBLK * MAXCOL,
+                                        (size_t)spmv_blocks(S->A) * 2});
     KRY_TRY(S->partial.alloc(np));
     if (!S->h_pinned) KRY_HIP(hipHostMalloc(reinterpret_cast<void **>(&S->h_pinned), 64 * sizeof(double)));
     KRY_HIP(hipMemsetAsync(S->small.p, 0, S->small.bytes(), S->stream));
@@ -366,27 +519,38 @@ static int readback(SOLVER_ *S, const double *d, int n, double *h) {
     return KRY_OK;
 }
 
+// grids of the three passes (measured at 64^3 x 3 unknowns, 8 to 30
+// columns); pass 2 holds MAXC x 256 doubles of LDS per block
 template <int MAXC>
-static void launch_cgs(hipStream_t st, int64_t n, const double *V, int64_t ldv, int nc,
-                       double *w, double *small, SmallLayout L, double *partial, int j, int m) {
-    const dim3 g(RED_BLOCKS), b(256);
-    hipLaunchKernelGGL(k_gemvt<MAXC>, g, b, 0, st, n, V, ldv, nc, w, partial);
-    hipLaunchKernelGGL(k_sum_cols, dim3(1), b, 0, st, partial, RED_BLOCKS, nc, small + L.h1);
-    hipLaunchKernelGGL((k_gemvn_update<MAXC, 0>), g, b, 0, st, n, V, ldv, nc, small + L.h1, w, partial);
-    hipLaunchKernelGGL(k_sum_cols, dim3(1), b, 0, st, partial, RED_BLOCKS, nc, small + L.h2);
-    hipLaunchKernelGGL((k_gemvn_update<MAXC, 1>), g, b, 0, st, n, V, ldv, nc, small + L.h2, w, partial);
-    hipLaunchKernelGGL(k_arnoldi_finish, dim3(1), b, 0, st, partial, RED_BLOCKS, j, m, small, L);
+static void launch_cgs(hipStream_t st, int n, const double *V, int64_t ldv, int nc, double *w,
+                       double *small, SmallLayout L, double *partial, int j, int m) {
+    const dim3 b(256);
+    const int g1 = MAXC >= 32 ? 256 : 512;
+    const int g2 = MAXC == 64 ? 256 : MAXC == 16 ? 1024 : 512;
+    const int g3 = 512;
+    static_assert(CGS_MAXBLK >= 1024, "partials sized for the largest grid");
+    hipLaunchKernelGGL(k_cgs_dots<MAXC>, dim3(g1), b, 0, st, n, V, ldv, nc, w, partial);
+    hipLaunchKernelGGL((k_sum_cols<MAXC, 1024>), dim3(1), dim3(1024), 0, st, partial, g1, nc,
+                       small + L.h1);
+    hipLaunchKernelGGL(k_cgs_update_dots<MAXC>, dim3(g2), b, 0, st, n, V, ldv, nc, small + L.h1, w,
+                       partial);
+    hipLaunchKernelGGL((k_sum_cols<MAXC, 1024>), dim3(1), dim3(1024), 0, st, partial, g2, nc,
+                       small + L.h2);
+    hipLaunchKernelGGL(k_cgs_update_norm<MAXC>, dim3(g3), b, 0, st, n, V, ldv, nc, small + L.h2, w,
+                       partial);
+    hipLaunchKernelGGL(k_arnoldi_finish, dim3(1), b, 0, st, partial, g3, j, m, small, L);
 }
 
 static int cgs2_step(SOLVER_ *S, int j, double *w) {
-    const int64_t n = (int64_t)S->A->nb * S->A->bs;
+    const int n = S->A->nb * S->A->bs;
     const int nc = j + 1;
     SmallLayout L(S->restart);
     TimedScope ts("cgs2", S->stream);
-    if (nc <= 8) launch_cgs<8>(S->stream, n, S->V.p, S->ldv, nc, w, S->small.p, L, S->partial.p, j, S->restart);
-    else if (nc <= 16) launch_cgs<16>(S->stream, n, S->V.p, S->ldv, nc, w, S->small.p, L, S->partial.p, j, S->restart);
-    else if (nc <= 32) launch_cgs<32>(S->stream, n, S->V.p, S->ldv, nc, w, S->small.p, L, S->partial.p, j, S->restart);
-    else launch_cgs<64>(S->stream, n, S->V.p, S->ldv, nc, w, S->small.p, L, S->partial.p, j, S->restart);
+    double *sm = S->small.p, *pt = S->partial.p;
+    if (nc <= 8) launch_cgs<8>(S->stream, n, S->V.p, S->ldv, nc, w, sm, L, pt, j, S->restart);
+    else if (nc <= 16) launch_cgs<16>(S->stream, n, S->V.p, S->ldv, nc, w, sm, L, pt, j, S->restart);
+    else if (nc <= 32) launch_cgs<32>(S->stream, n, S->V.p, S->ldv, nc, w, sm, L, pt, j, S->restart);
+    else launch_cgs<64>(S->stream, n, S->V.p, S->ldv, nc, w, sm, L, pt, j, S->restart);
     KRY_HIP(hipGetLastError());
     return KRY_OK;
 }
