@@ -98,6 +98,44 @@ __device__ __forceinline__ void publish(T *p, T v) {
     __hip_atomic_store(reinterpret_cast<U *>(p), u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// true when the high 32 bits of v equal the sentinel's: only NaNs of the
+// sentinel's payload family qualify (one 32-bit compare per value)
+template <typename T>
+__device__ __forceinline__ bool sentinel_like(T v) {
+    using U = typename Bits<T>::U;
+    constexpr int SH = static_cast<int>(sizeof(U)) * 8 - 32;
+    return static_cast<uint32_t>(Bits<T>::to(v) >> SH) ==
+           static_cast<uint32_t>(Bits<T>::sentinel >> SH);
+}
+
+// Publish BS values that the caller has already made not sentinel_like
+// (canonical NaN instead): relaxed agent-scope stores, no per-value check.
+template <typename T, int BS>
+__device__ __forceinline__ void publish_checked(T *p, const T (&v)[BS]) {
+    using U = typename Bits<T>::U;
+#pragma unroll
+    for (int r = 0; r < BS; r++)
+        __hip_atomic_store(reinterpret_cast<U *>(p + r), Bits<T>::to(v[r]), __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// out = v with every sentinel_like value replaced by the canonical NaN; the
+// replacement runs only in lanes that need it (a rare, exec-skipped branch)
+template <typename T, int BS>
+__device__ __forceinline__ void unsentinel(const T (&v)[BS], T (&out)[BS]) {
+    bool odd = false;
+#pragma unroll
+    for (int r = 0; r < BS; r++) {
+        out[r] = v[r];
+        odd |= sentinel_like(v[r]);
+    }
+    if (__builtin_expect(odd, 0)) {
+#pragma unroll
+        for (int r = 0; r < BS; r++)
+            if (sentinel_like(out[r])) out[r] = Bits<T>::from(Bits<T>::qnan);
+    }
+}
+
 constexpr uint32_t SPIN_LIMIT = 1u << 22;
 constexpr int ERR_STALL_FLAG = 2;
 

@@ -409,8 +409,8 @@ int ilu_setup(hipStream_t s, const MAT_ *A, const double *d_val, IluFactor &F, i
         // layout directly
         F.nlev_f = F.nlev_b = A->gnx + A->gny + A->gnz - 2;
         KRY_TRY(ilu_grid_factor_setup(s, A, d_val, F, d_err));
-        KRY_TRY(F.ctr.alloc(2));
-        KRY_HIP(hipMemsetAsync(F.ctr.p, 0, 2 * sizeof(int), s));
+        KRY_TRY(F.ctr.alloc(2 * GRID_QUEUES));
+        KRY_HIP(hipMemsetAsync(F.ctr.p, 0, 2 * GRID_QUEUES * sizeof(int), s));
         KRY_HIP(hipStreamSynchronize(s));
         return KRY_OK;
     }
@@ -523,8 +523,8 @@ int ilu_setup(hipStream_t s, const MAT_ *A, const double *d_val, IluFactor &F, i
         hipLaunchKernelGGL(k_fill_sentinel<float>, dim3(1024), dim3(256), 0, s, n, F.y32.p);
     }
     KRY_HIP(hipGetLastError());
-    KRY_TRY(F.ctr.alloc(2));
-    KRY_HIP(hipMemsetAsync(F.ctr.p, 0, 2 * sizeof(int), s));
+    KRY_TRY(F.ctr.alloc(2 * GRID_QUEUES));
+    KRY_HIP(hipMemsetAsync(F.ctr.p, 0, 2 * GRID_QUEUES * sizeof(int), s));
     F.grid_waves = std::min(std::max(F.L.nslices, F.U.nslices), sweep_waves_cap());
     // the working copy is freed on return: wait for the kernels using it
     KRY_HIP(hipStreamSynchronize(s));

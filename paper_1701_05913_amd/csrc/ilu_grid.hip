@@ -298,12 +298,31 @@ static int grid_tiling(const MAT_ *A, IluFactor &F) {
                 ord.push_back(J | (K << 16));
             }
         }
+    // queues of tile columns: tiles sharing J (the k-face neighbours) stay
+    // on one XCD and exchange faces through its L2
+    G.NQ = GRID_QUEUES;
+    std::vector<int> qt, qo(G.NQ + 1, 0);
+    qt.reserve(G.ntiles);
+    for (int q = 0; q < G.NQ; q++) {
+        qo[q] = static_cast<int>(qt.size());
+        for (int T = 0; T < G.ntiles; T++)
+            if ((ord[T] & 0xffff) % G.NQ == q) qt.push_back(T);
+    }
+    qo[G.NQ] = static_cast<int>(qt.size());
+    G.qmax = 0;
+    for (int q = 0; q < G.NQ; q++) G.qmax = std::max(G.qmax, qo[q + 1] - qo[q]);
     KRY_TRY(F.order.alloc(G.ntiles));
     KRY_TRY(F.tidx.alloc(G.ntiles));
+    KRY_TRY(F.qtiles.alloc(G.ntiles));
+    KRY_TRY(F.qoff.alloc(G.NQ + 1));
     KRY_HIP(hipMemcpy(F.order.p, ord.data(), sizeof(int) * G.ntiles, hipMemcpyHostToDevice));
     KRY_HIP(hipMemcpy(F.tidx.p, tid.data(), sizeof(int) * G.ntiles, hipMemcpyHostToDevice));
+    KRY_HIP(hipMemcpy(F.qtiles.p, qt.data(), sizeof(int) * G.ntiles, hipMemcpyHostToDevice));
+    KRY_HIP(hipMemcpy(F.qoff.p, qo.data(), sizeof(int) * (G.NQ + 1), hipMemcpyHostToDevice));
     G.order = F.order.p;
     G.tidx = F.tidx.p;
+    G.qtiles = F.qtiles.p;
+    G.qoff = F.qoff.p;
     const int b2 = A->bs * A->bs;
     const int64_t steps = (int64_t)G.ntiles * G.S;
     KRY_TRY(F.lt64.alloc(steps * 3 * b2 * 64));
@@ -451,7 +470,7 @@ __device__ __forceinline__ void block_sub(TC (&acc)[BS], const TC (&v)[NV], int 
 // the lane at the end of the wave receives 0
 template <bool UP>
 __device__ __forceinline__ int lane_shift1(int v) {
-    return __builtin_amdgcn_update_dpp(0, v, UP ? 0x130 : 0x138, 0xF, 0xF, false);
+    return __builtin_amdgcn_update_dpp(0, v, UP ? 0x130 : 0x138, 0xF, 0xF, true);
 }
 template <bool UP>
 __device__ __forceinline__ float lane_shift1(float v) {
@@ -540,9 +559,18 @@ __device__ void boundary_role(int S, int nx, int base, int lane, int NF, const T
 // The next tile of this workgroup (same value in every wavefront).  Each
 // role runs its own tile loop, so every wavefront passes the two barriers
 // once per tile and once more at the end.
-__device__ __forceinline__ int next_tile(int *ctr, int *tile) {
+// next tile of this workgroup's queue (b % NQ), first to last or, for the
+// backward sweep, last to first; -1 when the queue is empty.  Within a
+// queue the tiles come in dependency order and every queue is served by at
+// least one workgroup, so every taken tile's producers are running.
+__device__ __forceinline__ int next_tile(const GridTiles &G, int *ctr, int *tile, bool rev) {
     __syncthreads();
-    if (threadIdx.x == 0) *tile = atomicAdd(ctr, 1);
+    if (threadIdx.x == 0) {
+        const int q = blockIdx.x % G.NQ;
+        const int i = atomicAdd(ctr + q, 1);
+        const int len = G.qoff[q + 1] - G.qoff[q];
+        *tile = i < len ? G.qtiles[G.qoff[q] + (rev ? len - 1 - i : i)] : -1;
+    }
     __syncthreads();
     return *tile;
 }
@@ -559,7 +587,7 @@ __global__ __launch_bounds__(GWG) void k_grid_fwd(GridTiles G, const TF *__restr
     // wave-uniform role index (an SGPR), so the roles are real branches
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
-    if (blockIdx.x == 0 && threadIdx.x == 0) *other_ctr = 0;
+    if (blockIdx.x == 0 && (int)threadIdx.x < G.NQ) other_ctr[threadIdx.x] = 0;
     if (threadIdx.x < D) full[threadIdx.x] = -1;
     if (threadIdx.x < DB) bfull[threadIdx.x] = -1;
     if (threadIdx.x == 0) {
@@ -574,9 +602,10 @@ __global__ __launch_bounds__(GWG) void k_grid_fwd(GridTiles G, const TF *__restr
         // face entries this lane publishes (high faces feed tiles J+1, K+1)
         const int fj = jj == TJ - 1 && kk < TK ? kk : -1;
         const int fk = kk == TK - 1 ? TK + jj : -1;
+        const int oj = fj * BS, ok = fk * BS;
         for (int base = 0;; base += S) {
-            const int T = next_tile(ctr, &tile);
-            if (T >= G.ntiles) break;
+            const int T = next_tile(G, ctr, &tile, false);
+            if (T < 0) break;
             TC *yrow = yt + (int64_t)T * S * BS * 64 + lane;
             TC *frow = ff + (int64_t)T * S * NF * BS;
             TC yp[BS];
@@ -614,12 +643,13 @@ __global__ __launch_bounds__(GWG) void k_grid_fwd(GridTiles G, const TF *__restr
                     yp[r] = acc[r];
                     yrow[(t * BS + r) * 64] = acc[r];
                 }
-                if (fj >= 0)
-#pragma unroll
-                    for (int r = 0; r < BS; r++) publish<TC>(frow + ((int64_t)t * NF + fj) * BS + r, acc[r]);
-                if (fk >= 0)
-#pragma unroll
-                    for (int r = 0; r < BS; r++) publish<TC>(frow + ((int64_t)t * NF + fk) * BS + r, acc[r]);
+                {
+                    TC pub[BS];
+                    unsentinel<TC, BS>(acc, pub);
+                    TC *ft = frow + (int64_t)t * NF * BS;
+                    if (fj >= 0) publish_checked<TC, BS>(ft + oj, pub);
+                    if (fk >= 0) publish_checked<TC, BS>(ft + ok, pub);
+                }
                 // every LDS read of this step has returned: hand both slots back
                 lds_release();
                 if (lane == 0) {
@@ -642,8 +672,8 @@ __global__ __launch_bounds__(GWG) void k_grid_fwd(GridTiles G, const TF *__restr
         // ---- boundary: faces of tiles (J-1, K) and (J, K-1) ----
         const int f = lane % NF;
         for (int base = 0;; base += S) {
-            const int T = next_tile(ctr, &tile);
-            if (T >= G.ntiles) break;
+            const int T = next_tile(G, ctr, &tile, false);
+            if (T < 0) break;
             const int JK = G.order[T];
             const int J = JK & 0xffff, K = JK >> 16;
             const TC *src = nullptr;
@@ -664,8 +694,8 @@ __global__ __launch_bounds__(GWG) void k_grid_fwd(GridTiles G, const TF *__restr
         // ---- loaders: planes of steps w, w + NLOAD, ... ----
         const int w = wave - 2;
         for (int base = 0;; base += S) {
-            const int T = next_tile(ctr, &tile);
-            if (T >= G.ntiles) break;
+            const int T = next_tile(G, ctr, &tile, false);
+            if (T < 0) break;
             const int JK = G.order[T];
             const int j = (JK & 0xffff) * TJ + jj, k = (JK >> 16) * TK + kk;
             const bool lane_ok = lane < TJ * TK && j < G.ny && k < G.nz;
@@ -716,7 +746,7 @@ __global__ __launch_bounds__(GWG) void k_grid_bwd(GridTiles G, const TF *__restr
     __shared__ int full[D], bfull[DB], cons, bcons, tile;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
-    if (blockIdx.x == 0 && threadIdx.x == 0) *other_ctr = 0;
+    if (blockIdx.x == 0 && (int)threadIdx.x < G.NQ) other_ctr[threadIdx.x] = 0;
     if (threadIdx.x < D) full[threadIdx.x] = -1;
     if (threadIdx.x < DB) bfull[threadIdx.x] = -1;
     if (threadIdx.x == 0) {
@@ -730,8 +760,9 @@ __global__ __launch_bounds__(GWG) void k_grid_bwd(GridTiles G, const TF *__restr
         // face entries this lane publishes (low faces feed tiles J-1, K-1)
         const int fj = jj == 0 && kk < TK ? kk : -1;
         const int fk = kk == 0 ? TK + jj : -1;
+        const int oj = fj * BS, ok = fk * BS;
         for (int base = 0;; base += S) {
-            const int T = G.ntiles - 1 - next_tile(ctr, &tile);   // reverse tile order
+            const int T = next_tile(G, ctr, &tile, true);   // reverse tile order
             if (T < 0) break;
             TC *yrow = yt + (int64_t)T * S * BS * 64 + lane;
             TC *frow = fb + (int64_t)T * S * NF * BS;
@@ -776,12 +807,13 @@ __global__ __launch_bounds__(GWG) void k_grid_bwd(GridTiles G, const TF *__restr
                     xp[r] = static_cast<TC>(static_cast<TO>(res[r]));
                     yrow[((S - 1 - t) * BS + r) * 64] = res[r];
                 }
-                if (fj >= 0)
-#pragma unroll
-                    for (int r = 0; r < BS; r++) publish<TC>(frow + ((int64_t)t * NF + fj) * BS + r, xp[r]);
-                if (fk >= 0)
-#pragma unroll
-                    for (int r = 0; r < BS; r++) publish<TC>(frow + ((int64_t)t * NF + fk) * BS + r, xp[r]);
+                {
+                    TC pub[BS];
+                    unsentinel<TC, BS>(xp, pub);
+                    TC *ft = frow + (int64_t)t * NF * BS;
+                    if (fj >= 0) publish_checked<TC, BS>(ft + oj, pub);
+                    if (fk >= 0) publish_checked<TC, BS>(ft + ok, pub);
+                }
                 lds_release();
                 if (lane == 0) {
                     lds_put(&bcons, st + 1);
@@ -803,7 +835,7 @@ __global__ __launch_bounds__(GWG) void k_grid_bwd(GridTiles G, const TF *__restr
         // ---- boundary: faces of tiles (J+1, K) and (J, K+1) ----
         const int f = lane % NF;
         for (int base = 0;; base += S) {
-            const int T = G.ntiles - 1 - next_tile(ctr, &tile);
+            const int T = next_tile(G, ctr, &tile, true);
             if (T < 0) break;
             const int JK = G.order[T];
             const int J = JK & 0xffff, K = JK >> 16;
@@ -825,7 +857,7 @@ __global__ __launch_bounds__(GWG) void k_grid_bwd(GridTiles G, const TF *__restr
         // ---- loaders: U blocks, diagonal inverse, forward result ----
         const int w = wave - 2;
         for (int base = 0;; base += S) {
-            const int T = G.ntiles - 1 - next_tile(ctr, &tile);
+            const int T = next_tile(G, ctr, &tile, true);
             if (T < 0) break;
             const TF *ub = Ut + (int64_t)T * S * NM * 64 + lane;
             const TD *db = Dt + (int64_t)T * S * B2 * 64 + lane;
@@ -905,17 +937,19 @@ template <int BS, typename TF, typename TD, typename TC, typename TIN, typename 
 static int grid_pair(hipStream_t s, IluFactor &F, const TF *lt, const TF *ut, const TD *dt,
                      TC *yt, TC *ff, TC *fb, const TIN *b, TO *xo, const TAI *add_in,
                      TAO *add_out, int *err) {
-    // one workgroup per tile in flight (LDS-bound); 256 CUs
-    const int wgs = std::min(F.G.ntiles, 512);
+    // one workgroup per tile in flight (LDS-bound, 256 CUs): NQ workgroups
+    // per queue position, so every queue has a workgroup per tile up to
+    // the cap, and always at least one
+    const int wgs = F.G.NQ * std::max(1, std::min(F.G.qmax, 512 / F.G.NQ));
     {
         TimedScope t(sweep_timer_name(true, BS, sizeof(TF), ADD), s);
         hipLaunchKernelGGL((k_grid_fwd<BS, TF, TC, TIN>), dim3(wgs), dim3(GWG), 0, s, F.G, lt, b,
-                           yt, ff, fb, F.ctr.p, F.ctr.p + 1, err);
+                           yt, ff, fb, F.ctr.p, F.ctr.p + F.G.NQ, err);
     }
     {
         TimedScope t(sweep_timer_name(false, BS, sizeof(TF), 0), s);
         hipLaunchKernelGGL((k_grid_bwd<BS, TF, TD, TC, TO>), dim3(wgs), dim3(GWG), 0, s, F.G, ut,
-                           dt, yt, fb, ff, F.ctr.p + 1, F.ctr.p, err);
+                           dt, yt, fb, ff, F.ctr.p + F.G.NQ, F.ctr.p, err);
     }
     {
         TimedScope t("ilu_grid_untile", s);

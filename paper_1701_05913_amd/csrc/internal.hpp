@@ -200,12 +200,20 @@ int ensure_col0_f32(hipStream_t s, MAT_ *A);
 // 7-point grid tiling: a tile is TJ x TK x-lines (one lane each) of a
 // wavefront; S = nx + TJ + TK - 2 hyperplane steps per tile; order[t] =
 // J | (K << 16) lists tiles by increasing J + K.
+constexpr int GRID_QUEUES = 8;   // tile queues of the grid sweeps: one per XCD
+
 struct GridTiles {
     int nx = 0, ny = 0, nz = 0;
     int TJ = 0, TK = 0, NJ = 0, NK = 0, ntiles = 0, S = 0;
     int NF = 0;                      // face cells per step: TK (j-face) + TJ (k-face)
     const int *order = nullptr;      // tile T -> J | K << 16, in J + K order
     const int *tidx = nullptr;       // J * NK + K -> tile T
+    // tile queues: queue q holds the tiles with J % NQ == q in tile order
+    // (qtiles[qoff[q] .. qoff[q + 1])); workgroup b serves queue b % NQ,
+    // which the dispatcher places on XCD b % 8
+    int NQ = 0, qmax = 0;            // queue count, longest queue
+    const int *qtiles = nullptr;
+    const int *qoff = nullptr;
 };
 
 struct IluFactor {
@@ -218,12 +226,13 @@ struct IluFactor {
     DBuf<float> dinvf;
     DBuf<double> y64;       // forward result (sentinel between sweeps)
     DBuf<float> y32;
-    DBuf<int> ctr;          // [0] forward, [1] backward slice counters
+    DBuf<int> ctr;          // level sweeps: [0] forward, [1] backward slice counters;
+                            // grid sweeps: GRID_QUEUES forward, then backward tile counters
     int grid_waves = 0;     // waves launched per sweep
     // grid-tiled sweeps (7-point stencils in natural order)
     bool grid = false;
     GridTiles G;
-    DBuf<int> order, tidx;
+    DBuf<int> order, tidx, qtiles, qoff;
     DBuf<double> lt64, ut64, dt64;
     DBuf<float> lt32, ut32, dt32;
     DBuf<uint16_t> lt16, ut16;
