@@ -262,6 +262,15 @@ __device__ __forceinline__ void lds_wait_pair(int *p, int v, int *q, int w, int 
     }
     lds_acquire();
 }
+// lds_wait_pair, skipped when stamps read ahead of time (pa from p, pb
+// from q, during the previous step) already show the step ready; the
+// acquire still orders the data reads that follow after the stamps
+__device__ __forceinline__ void lds_wait_pair_pre(int pa, int pb, int *p, int v, int *q, int w,
+                                                  int *err) {
+    const int a = __builtin_amdgcn_readfirstlane(pa), b = __builtin_amdgcn_readfirstlane(pb);
+    if (a == v && (w < 0 || b == w)) lds_acquire();
+    else lds_wait_pair(p, v, q, w, err);
+}
 
 // Inverse of a BS x BS block by Gaussian elimination with partial
 // pivoting (first maximal pivot on ties); false (R undefined) for a

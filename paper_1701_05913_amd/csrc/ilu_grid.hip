@@ -611,13 +611,16 @@ __global__ __launch_bounds__(GWG) void k_grid_fwd(GridTiles G, const TF *__restr
             TC yp[BS];
 #pragma unroll
             for (int r = 0; r < BS; r++) yp[r] = TC(0);
+            int pa = -2, pb = -2;   // stamps of the next step, read one step early
             // step t computes with the planes in vc and reads the planes of
             // step t + 1 into vn; the two arrays swap roles every step
             auto step = [&](int t, const TC (&vc)[NV], TC (&vn)[NV]) {
                 const int st = base + t, bslot = t % DB;
                 const bool more = t + 1 < S;
-                // one poll for this step's boundary and the next step's planes
-                lds_wait_pair(&bfull[bslot], st, &full[(t + 1) % D], more ? st + 1 : -1, err);
+                // this step's boundary and the next step's planes: one poll,
+                // skipped when the stamps read during the previous step show both
+                lds_wait_pair_pre(pa, pb, &bfull[bslot], st, &full[(t + 1) % D], more ? st + 1 : -1,
+                                  err);
                 TC yj[BS], yk[BS];
 #pragma unroll
                 for (int r = 0; r < BS; r++) {
@@ -632,6 +635,8 @@ __global__ __launch_bounds__(GWG) void k_grid_fwd(GridTiles G, const TF *__restr
 #pragma unroll
                     for (int e = 0; e < NV; e++) vn[e] = ring[(t + 1) % D][e][lane];
                 }
+                pa = lds_get(&bfull[(t + 1) % DB]);
+                pb = t + 2 < S ? lds_get(&full[(t + 2) % D]) : -1;
                 TC acc[BS];
 #pragma unroll
                 for (int r = 0; r < BS; r++) acc[r] = vc[NM + r];
@@ -769,10 +774,12 @@ __global__ __launch_bounds__(GWG) void k_grid_bwd(GridTiles G, const TF *__restr
             TC xp[BS];
 #pragma unroll
             for (int r = 0; r < BS; r++) xp[r] = TC(0);
+            int pa = -2, pb = -2;   // stamps of the next step, read one step early
             auto step = [&](int t, const TC (&vc)[NV], TC (&vn)[NV]) {
                 const int st = base + t, bslot = t % DB;
                 const bool more = t + 1 < S;
-                lds_wait_pair(&bfull[bslot], st, &full[(t + 1) % D], more ? st + 1 : -1, err);
+                lds_wait_pair_pre(pa, pb, &bfull[bslot], st, &full[(t + 1) % D], more ? st + 1 : -1,
+                                  err);
                 TC xj[BS], xk[BS];
 #pragma unroll
                 for (int r = 0; r < BS; r++) {
@@ -787,6 +794,8 @@ __global__ __launch_bounds__(GWG) void k_grid_bwd(GridTiles G, const TF *__restr
 #pragma unroll
                     for (int e = 0; e < NV; e++) vn[e] = ring[(t + 1) % D][e][lane];
                 }
+                pa = lds_get(&bfull[(t + 1) % DB]);
+                pb = t + 2 < S ? lds_get(&full[(t + 2) % D]) : -1;
                 TC acc[BS];
 #pragma unroll
                 for (int r = 0; r < BS; r++) acc[r] = vc[NM + B2 + r];
