@@ -261,6 +261,20 @@ def gmres(A, pc, b, x0=None, restart=30, maxit=500, rtol=1e-6, atol=0.0,
                   flexible, left, check_at_cycle_end, fixed_iters, hist)
 
 
+def lgmres(A, pc, b, x0=None, restart=30, aug_k=2, maxit=500, rtol=1e-6, atol=0.0,
+           fixed_iters=False, hist=False):
+    """LGMRES(restart, aug_k), right preconditioned, flexible storage."""
+    fn = lambda *args: lib().or_lgmres(*args[:-2], int(aug_k), *args[-2:])
+    return _solve(fn, A, pc, b, x0, restart, maxit, rtol, atol, True, False, False,
+                  fixed_iters, hist)
+
+
+def pcg(A, pc, b, x0=None, maxit=500, rtol=1e-6, atol=0.0, fixed_iters=False, hist=False):
+    """Preconditioned CG (Algorithm 2) for SPD A and M."""
+    return _solve(lib().or_pcg, A, pc, b, x0, 0, maxit, rtol, atol, False, False, False,
+                  fixed_iters, hist)
+
+
 def bicgstab(A, pc, b, x0=None, maxit=500, rtol=1e-6, atol=0.0,
              fixed_iters=False, hist=False):
     return _solve(lib().or_bicgstab, A, pc, b, x0, 0, maxit, rtol, atol,

@@ -853,6 +853,173 @@ int or_gmres(int nb, int bs, const int *rp, const int *ci, const double *a,
 }
 
 /* ======================================================================
+ * C6b. LGMRES(m, k) (named with its aug_k parameter in Section 3; the
+ * algorithm is not printed).  Baker, Jessup & Manteuffel (2005), right
+ * preconditioned: every cycle runs m Arnoldi steps on preconditioned
+ * directions u_j = M^-1 v_j, then one more step for each stored
+ * correction of the previous cycles (newest first, at most k of them,
+ * each normalized), with u_j the correction itself.  The new iterate is
+ * x + U y, y minimizing ||beta e_1 - H y||; the correction U y of the
+ * cycle becomes the newest stored one.  maxit counts Arnoldi steps of
+ * both kinds; the tolerance tests follow or_gmres.
+ * ====================================================================== */
+int or_lgmres(int nb, int bs, const int *rp, const int *ci, const double *a,
+              or_pc *pc, const double *b, double *x, const or_krylov_opts *o,
+              int aug_k, or_krylov_result *res, double *hist)
+{
+    const size_t n = (size_t)nb * bs;
+    const int m = o->restart, k = aug_k, mt = o->restart + aug_k;
+    if (m < 1 || k < 0 || o->maxit < 0) return OR_ERR_ARG;
+    double *V = (double *)malloc(sizeof(double) * n * (mt + 1));
+    double *U = (double *)malloc(sizeof(double) * n * mt);
+    double *Zs = (double *)malloc(sizeof(double) * n * (k > 0 ? k : 1));  /* newest first */
+    double *H = (double *)calloc((size_t)(mt + 1) * mt, sizeof(double));
+    double *cs = (double *)malloc(sizeof(double) * mt);
+    double *sn = (double *)malloc(sizeof(double) * mt);
+    double *g = (double *)malloc(sizeof(double) * (mt + 1));
+    double *y = (double *)malloc(sizeof(double) * mt);
+    double *r = (double *)malloc(sizeof(double) * n);
+    double *w = (double *)malloc(sizeof(double) * n);
+    double *dx = (double *)malloc(sizeof(double) * n);
+    const double bnorm = nrm2((int)n, b);
+    const double tol = fmax(o->rtol * bnorm, o->atol);
+    int nits = 0, cycles = 0, nstored = 0, status = OR_NOT_CONVERGED;
+    double relres = 0.0;
+#define HH(i, j) H[(size_t)(i) * mt + (j)]
+    for (;;) {
+        memcpy(r, b, sizeof(double) * n);
+        or_bsr_amxpby(nb, bs, rp, ci, a, -1.0, x, 1.0, r);
+        double tnorm = nrm2((int)n, r);
+        relres = bnorm > 0 ? tnorm / bnorm : tnorm;
+        if (hist && nits == 0) hist[0] = tnorm;
+        if (!o->fixed_iters && tnorm <= tol) { status = OR_OK; break; }
+        if (nits >= o->maxit) break;
+        double beta = tnorm;
+        if (beta == 0.0 || !isfinite(beta)) { status = isfinite(beta) ? OR_OK : OR_ERR_BREAKDOWN; break; }
+        for (size_t i = 0; i < n; i++) V[i] = r[i] / beta;
+        for (int i = 0; i <= mt; i++) g[i] = 0.0;
+        g[0] = beta;
+        const int steps = m + nstored;
+        int jend = 0;
+        cycles++;
+        for (int j = 0; j < steps; j++) {
+            double *uj = U + n * j;
+            if (j < m) or_pc_apply(pc, V + n * j, uj);
+            else memcpy(uj, Zs + n * (j - m), sizeof(double) * n);
+            or_bsr_spmv(nb, bs, rp, ci, a, uj, w);
+            for (int q = 0; q <= j; q++) {           /* MGS */
+                double h = dot((int)n, w, V + n * q);
+                HH(q, j) = h;
+                for (size_t i = 0; i < n; i++) w[i] -= h * V[n * q + i];
+            }
+            double hn = nrm2((int)n, w);
+            HH(j + 1, j) = hn;
+            if (hn != 0.0)
+                for (size_t i = 0; i < n; i++) V[n * (j + 1) + i] = w[i] / hn;
+            for (int q = 0; q < j; q++) {            /* old rotations */
+                double t = cs[q] * HH(q, j) + sn[q] * HH(q + 1, j);
+                HH(q + 1, j) = -sn[q] * HH(q, j) + cs[q] * HH(q + 1, j);
+                HH(q, j) = t;
+            }
+            double rr = hypot(HH(j, j), HH(j + 1, j));
+            if (rr == 0.0) { cs[j] = 1.0; sn[j] = 0.0; }
+            else { cs[j] = HH(j, j) / rr; sn[j] = HH(j + 1, j) / rr; }
+            HH(j, j) = rr;
+            HH(j + 1, j) = 0.0;
+            g[j + 1] = -sn[j] * g[j];
+            g[j] = cs[j] * g[j];
+            nits++;
+            jend = j + 1;
+            if (hist) hist[nits] = fabs(g[j + 1]);
+            if (nits >= o->maxit) break;
+            if (hn == 0.0) break;                     /* lucky breakdown */
+            if (!o->fixed_iters && fabs(g[j + 1]) <= tol) break;
+        }
+        for (int i = jend - 1; i >= 0; i--) {
+            double s = g[i];
+            for (int q = i + 1; q < jend; q++) s -= HH(i, q) * y[q];
+            y[i] = HH(i, i) != 0.0 ? s / HH(i, i) : 0.0;
+        }
+        for (size_t i = 0; i < n; i++) dx[i] = 0.0;
+        for (int q = 0; q < jend; q++)
+            for (size_t i = 0; i < n; i++) dx[i] += y[q] * U[n * q + i];
+        for (size_t i = 0; i < n; i++) x[i] += dx[i];
+        if (k > 0) {                                  /* store the correction, newest first */
+            const double dn = nrm2((int)n, dx);
+            if (dn > 0.0 && isfinite(dn)) {
+                const int keep = nstored < k ? nstored : k - 1;
+                memmove(Zs + n, Zs, sizeof(double) * n * keep);
+                for (size_t i = 0; i < n; i++) Zs[i] = dx[i] / dn;
+                nstored = keep + 1;
+            }
+        }
+        for (size_t i = 0; i < (size_t)(mt + 1) * mt; i++) H[i] = 0.0;
+    }
+#undef HH
+    if (o->fixed_iters && nits >= o->maxit) status = relres <= o->rtol ? OR_OK : OR_NOT_CONVERGED;
+    if (res) { res->iters = nits; res->true_relres = relres; res->restarts = cycles; }
+    free(V); free(U); free(Zs); free(H); free(cs); free(sn); free(g); free(y);
+    free(r); free(w); free(dx);
+    return status;
+}
+
+/* ======================================================================
+ * C6c. Preconditioned conjugate gradients, Algorithm 2, for symmetric
+ * positive definite A and M.  The stopping test is on the recursively
+ * updated residual, ||r|| <= max(rtol ||b||, atol), as printed; the
+ * reported relative residual is the true one at exit.  A curvature
+ * (p, A p) <= 0 or a non-finite scalar ends with OR_ERR_BREAKDOWN.
+ * ====================================================================== */
+int or_pcg(int nb, int bs, const int *rp, const int *ci, const double *a,
+           or_pc *pc, const double *b, double *x, const or_krylov_opts *o,
+           or_krylov_result *res, double *hist)
+{
+    const size_t n = (size_t)nb * bs;
+    if (o->maxit < 0) return OR_ERR_ARG;
+    double *r = (double *)malloc(sizeof(double) * n);
+    double *z = (double *)malloc(sizeof(double) * n);
+    double *p = (double *)malloc(sizeof(double) * n);
+    double *q = (double *)malloc(sizeof(double) * n);
+    const double bnorm = nrm2((int)n, b);
+    const double tol = fmax(o->rtol * bnorm, o->atol);
+    int nits = 0, status = OR_NOT_CONVERGED;
+    memcpy(r, b, sizeof(double) * n);                 /* r = b - A x0 */
+    or_bsr_amxpby(nb, bs, rp, ci, a, -1.0, x, 1.0, r);
+    double rn = nrm2((int)n, r);
+    if (hist) hist[0] = rn;
+    double rho_prev = 0.0;
+    if (!o->fixed_iters && rn <= tol) status = OR_OK;
+    while (status != OR_OK && nits < o->maxit) {
+        or_pc_apply(pc, r, z);                        /* M z = r */
+        const double rho = dot((int)n, r, z);
+        if (nits == 0) memcpy(p, z, sizeof(double) * n);
+        else {
+            const double beta = rho / rho_prev;
+            for (size_t i = 0; i < n; i++) p[i] = z[i] + beta * p[i];
+        }
+        or_bsr_spmv(nb, bs, rp, ci, a, p, q);         /* q = A p */
+        const double pq = dot((int)n, p, q);
+        if (!(pq > 0.0) || !isfinite(rho)) { status = OR_ERR_BREAKDOWN; break; }
+        const double alpha = rho / pq;
+        for (size_t i = 0; i < n; i++) x[i] += alpha * p[i];
+        for (size_t i = 0; i < n; i++) r[i] -= alpha * q[i];
+        rho_prev = rho;
+        nits++;
+        rn = nrm2((int)n, r);
+        if (hist) hist[nits] = rn;
+        if (!o->fixed_iters && rn <= tol) status = OR_OK;
+    }
+    memcpy(q, b, sizeof(double) * n);                 /* true residual at exit */
+    or_bsr_amxpby(nb, bs, rp, ci, a, -1.0, x, 1.0, q);
+    const double relres = bnorm > 0 ? nrm2((int)n, q) / bnorm : nrm2((int)n, q);
+    if (o->fixed_iters && status != OR_ERR_BREAKDOWN)
+        status = relres <= o->rtol ? OR_OK : OR_NOT_CONVERGED;
+    if (res) { res->iters = nits; res->true_relres = relres; res->restarts = 0; }
+    free(r); free(z); free(p); free(q);
+    return status;
+}
+
+/* ======================================================================
  * C7. BiCGSTAB (van der Vorst 1992), right-preconditioned.  The paper
  * names the method (Section 3) without printing it.  Breakdown
  * (|rho| < 1e-300 ||rhat|| ||r||, <rhat, v> = 0, or omega = 0) restarts

@@ -80,7 +80,7 @@ void or_cpr_extract_pressure(int nb, const int *rp, const int *ci,
                              const double *a, const double *w,
                              double *app /* nnzb values, pattern of A */);
 
-/* ---- Krylov solvers (Algorithm 1; BiCGSTAB named in Section 3) -------- */
+/* ---- Krylov solvers (Algorithms 1-2; BiCGSTAB and LGMRES named in Section 3) */
 typedef struct {
     int    restart;      /* m of GMRES(m) */
     int    maxit;        /* total iterations (Arnoldi steps / BiCGSTAB its) */
@@ -100,6 +100,15 @@ typedef struct {
 int or_gmres(int nb, int bs, const int *rp, const int *ci, const double *a,
              or_pc *pc, const double *b, double *x, const or_krylov_opts *o,
              or_krylov_result *res, double *hist /* maxit+1 or NULL */);
+/* LGMRES(m = o->restart, k = aug_k): GMRES augmented with up to k stored
+ * corrections of earlier cycles (flexible storage; Section 3 names it) */
+int or_lgmres(int nb, int bs, const int *rp, const int *ci, const double *a,
+              or_pc *pc, const double *b, double *x, const or_krylov_opts *o,
+              int aug_k, or_krylov_result *res, double *hist /* maxit+1 or NULL */);
+/* preconditioned conjugate gradients (Algorithm 2), SPD A and M */
+int or_pcg(int nb, int bs, const int *rp, const int *ci, const double *a,
+           or_pc *pc, const double *b, double *x, const or_krylov_opts *o,
+           or_krylov_result *res, double *hist /* maxit+1 or NULL */);
 int or_bicgstab(int nb, int bs, const int *rp, const int *ci,
                 const double *a, or_pc *pc, const double *b, double *x,
                 const or_krylov_opts *o, or_krylov_result *res,

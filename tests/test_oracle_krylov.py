@@ -151,3 +151,124 @@ def test_zero_rhs_returns_zero():
     A = oracle.Matrix.from_system(s)
     r = oracle.gmres(A, oracle.PC(A, "bilu0"), np.zeros(A.n), rtol=1e-8)
     assert r["status"] == 0 and r["iters"] == 0 and np.all(r["x"] == 0)
+
+
+# ---- LGMRES (Section 3 names it with aug_k) and PCG (Algorithm 2) --------------
+def _dense_minv(A, kind="bilu0"):
+    from tests._helpers import lu_dense_from_factor
+    rc, lu = oracle.bilu0(A)
+    assert rc == 0
+    L, U = lu_dense_from_factor(A.rowptr, A.col, lu, A.bs)
+    return np.linalg.inv(L @ U), L @ U
+
+
+def _orth(cols):
+    q, _ = np.linalg.qr(np.column_stack(cols))
+    return q
+
+
+def test_lgmres_without_augmentation_is_fgmres():
+    s = ri.blackoil_system(6, 5, 4, seed=3)
+    A = oracle.Matrix.from_system(s)
+    pc = oracle.PC(A, "bilu0")
+    a = oracle.lgmres(A, pc, s["b"], restart=5, aug_k=0, maxit=15, fixed_iters=True)
+    b = oracle.gmres(A, pc, s["b"], restart=5, maxit=15, flexible=True, fixed_iters=True)
+    assert relerr(a["x"], b["x"]) < 1e-12
+
+
+@pytest.mark.parametrize("k", [1, 2])
+def test_lgmres_cycles_minimize_over_augmented_space(k):
+    """Each cycle's iterate is x + argmin ||r - A d|| over d in
+    M^-1 K_m(A M^-1, r) + span(stored corrections), built here from an
+    explicit (orthonormalized) power basis and a dense least-squares solve;
+    the stored corrections are this test's own previous cycle updates."""
+    s = ri.blackoil_system(3, 3, 2, seed=4)
+    A = oracle.Matrix.from_system(s)
+    D = dense(s)
+    Minv, _ = _dense_minv(A)
+    b = s["b"]
+    m = 4
+    x = np.zeros(A.n)
+    Z = []
+    steps = 0
+    pc = oracle.PC(A, "bilu0")
+    for c in range(4):
+        r = b - D @ x
+        cols = [r]
+        for _ in range(m - 1):
+            cols.append(D @ (Minv @ _orth(cols)[:, -1]))
+        Kb = _orth(cols)
+        Ub = np.column_stack([Minv @ Kb] + Z)
+        d = np.linalg.lstsq(D @ Ub, r, rcond=None)[0]
+        dx = Ub @ d
+        x = x + dx
+        Z = ([dx / np.linalg.norm(dx)] + Z)[:k]
+        steps += m + min(c, k)
+        got = oracle.lgmres(A, pc, b, restart=m, aug_k=k, maxit=steps, fixed_iters=True)
+        assert got["restarts"] == c + 1
+        assert relerr(got["x"], x) < 1e-8, (c, relerr(got["x"], x))
+
+
+def test_lgmres_converges_where_restarted_gmres_stalls():
+    s = ri.blackoil_system(6, 5, 4, seed=3)
+    A = oracle.Matrix.from_system(s)
+    pc = oracle.PC(A, "bilu0")
+    a = oracle.lgmres(A, pc, s["b"], restart=5, aug_k=2, maxit=1000, rtol=1e-10)
+    g = oracle.gmres(A, pc, s["b"], restart=5, maxit=1000, rtol=1e-10, flexible=True)
+    assert a["status"] == 0 and a["relres"] <= 1e-10
+    assert a["iters"] < 0.5 * g["iters"]
+
+
+def test_ilu0_of_symmetric_matrix_is_symmetric():
+    # U = D L^T when A is symmetric, so M = L U is symmetric: a valid CG
+    # preconditioner (IC(0) in LU form)
+    s = ri.scalar_system(4, 4, 3, seed=2)
+    A = oracle.Matrix.from_system(s)
+    _, M = _dense_minv(A)
+    assert np.abs(M - M.T).max() <= 1e-13 * np.abs(M).max()
+    assert np.linalg.eigvalsh(M).min() > 0
+
+
+def test_pcg_iterates_minimize_energy_error_over_krylov_space():
+    """x_k = x_0 + B c with B a basis of K_k(M^-1 A, M^-1 r_0) and
+    (B^T A B) c = B^T r_0 (the Galerkin condition, solved densely)."""
+    s = ri.scalar_system(4, 4, 3, seed=2)
+    A = oracle.Matrix.from_system(s)
+    D = dense(s)
+    Minv, _ = _dense_minv(A)
+    b = s["b"]
+    pc = oracle.PC(A, "ilu0")
+    z0 = Minv @ b
+    cols = [z0]
+    for k in range(1, 7):
+        B = _orth(cols)
+        c = np.linalg.solve(B.T @ D @ B, B.T @ b)
+        ref = B @ c
+        got = oracle.pcg(A, pc, b, maxit=k, fixed_iters=True)
+        assert relerr(got["x"], ref) < 1e-9, (k, relerr(got["x"], ref))
+        cols.append(Minv @ (D @ B[:, -1]))
+
+
+def test_cg_exact_after_as_many_steps_as_distinct_eigenvalues():
+    # SPD with eigenvalues {1, 4, 9}: the error lies in a 3-dimensional
+    # Krylov space, so CG is exact after 3 steps and not after 2
+    rng = np.random.default_rng(6)
+    Q, _ = np.linalg.qr(rng.standard_normal((12, 12)))
+    D = Q @ np.diag([1.0] * 4 + [4.0] * 4 + [9.0] * 4) @ Q.T
+    D = (D + D.T) / 2
+    st = bsr_from_dense(D, 1)
+    A = oracle.Matrix.from_system(st)
+    b = rng.standard_normal(12)
+    pc = oracle.PC(A, "none")
+    assert oracle.pcg(A, pc, b, maxit=3, fixed_iters=True)["relres"] < 1e-12
+    assert oracle.pcg(A, pc, b, maxit=2, fixed_iters=True)["relres"] > 1e-3
+
+
+def test_pcg_reports_breakdown_on_indefinite_matrix():
+    D = np.diag([2.0, -1.0, 3.0, 1.0])
+    D[0, 1] = D[1, 0] = 0.5
+    st = bsr_from_dense(D, 1)
+    A = oracle.Matrix.from_system(st)
+    # b along the negative-curvature direction: (p, A p) < 0 at the first step
+    got = oracle.pcg(A, oracle.PC(A, "none"), np.array([0.0, 1.0, 0.0, 0.0]), maxit=10, rtol=1e-12)
+    assert got["status"] == oracle.ERR_BREAKDOWN

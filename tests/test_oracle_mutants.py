@@ -79,6 +79,22 @@ MUTANTS = [
      "        rpv[i] = pc->w[3 * i] * r[3 * i] + pc->w[3 * i + 1] * r[3 * i + 1]\n               + pc->w[3 * i + 2] * r[3 * i + 2];\n    pstage_f64(pc, rpv, p);\n    for (int i = 0; i < nb; i++) x[3 * i] += p[i];",
      "        rpv[i] = r[3 * i];\n    pstage_f64(pc, rpv, p);\n    for (int i = 0; i < nb; i++) x[3 * i] += p[i];",
      [lambda: tc.test_cpr_error_propagator_is_product_of_stage_propagators("cpr_fpf", 3)]),
+    ("pcg_beta_inverted",
+     "const double beta = rho / rho_prev;",
+     "const double beta = rho_prev / rho;",
+     [lambda: tk.test_pcg_iterates_minimize_energy_error_over_krylov_space()]),
+    ("pcg_alpha_on_rr",
+     "const double alpha = rho / pq;",
+     "const double alpha = dot((int)n, r, r) / pq;",
+     [lambda: tk.test_pcg_iterates_minimize_energy_error_over_krylov_space()]),
+    ("lgmres_skips_stored_corrections",
+     "const int steps = m + nstored;",
+     "const int steps = m + 0 * nstored;",
+     [lambda: tk.test_lgmres_cycles_minimize_over_augmented_space(1)]),
+    ("lgmres_stores_iterate_not_correction",
+     "for (size_t i = 0; i < n; i++) Zs[i] = dx[i] / dn;",
+     "for (size_t i = 0; i < n; i++) Zs[i] = x[i] / dn;",
+     [lambda: tk.test_lgmres_cycles_minimize_over_augmented_space(2)]),
     ("gelu_grad_missing_density_term",
      "return 0.5 * (1.0 + erf(x / sqrt(2.0))) + x * exp(-0.5 * x * x) / sqrt(2.0 * pi);",
      "return 0.5 * (1.0 + erf(x / sqrt(2.0)));",
