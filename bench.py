@@ -52,7 +52,12 @@ CONFIGS = [
     ("fgmres30_cpr_fpf_f64", "FGMRES", "CPR", "F64", ("FPF", 4)),
     ("fgmres30_cpr_ffpf_f64", "FGMRES", "CPR", "F64", ("FFPF", 4)),
     ("fgmres30_bilu0_learned", "FGMRES", "BILU0_LEARNED", "F64", None),
+    ("lgmres30_2_bilu0_f64", "GMRES", "BILU0", "F64", None),
+    ("pcg_ilu0_scalar_f64", "CG", "ILU0", "F64", None),
 ]
+# per-configuration extras: LGMRES augmentation, and the symmetric scalar
+# system of the same grid (CG needs a symmetric positive definite matrix)
+EXTRAS = {"lgmres30_2_bilu0_f64": dict(aug_k=2), "pcg_ilu0_scalar_f64": dict(system="scalar")}
 WEIGHTS = os.path.join(ROOT, "paper_1701_05913_amd", "weights", "bilu0_blackoil64.bin")
 
 # matrix-core FLOPs per cell of each conv layer (3x3x3 taps, 2 per MAC)
@@ -193,13 +198,28 @@ def main():
     lnk = torch.from_numpy(np.asarray(s["lnk"], dtype=np.float32)).to(dev)
 
     configs = CONFIGS if args.configs == "all" else [c for c in CONFIGS if c[0] in args.configs.split(",")]
+    # the scalar system, built only when a configuration needs it
+    sys_vecs = {"blackoil": (m, A, bh, xh, x)}
+    if any(EXTRAS.get(c[0], {}).get("system") == "scalar" for c in configs):
+        ss = ri.scalar_system(*wl["grid"], seed=0)
+        ns = len(ss["rowptr"]) - 1
+        m1 = K.MapCreateLocal(ns)
+        A1 = K.MatCreateCSR(m1, ns, torch.from_numpy(np.ascontiguousarray(ss["rowptr"], dtype=np.int32)).to(dev),
+                            torch.from_numpy(np.ascontiguousarray(ss["col"], dtype=np.int32)).to(dev),
+                            torch.from_numpy(np.ascontiguousarray(ss["val"].reshape(-1))).to(dev))
+        b1 = torch.from_numpy(ss["b"]).to(dev)
+        x1 = torch.zeros(ns, dtype=torch.float64, device=dev)
+        sys_vecs["scalar"] = (m1, A1, K.VecWrap(m1, b1), K.VecWrap(m1, x1), x1)
     solvers = {}
     for name, st, pc, prec, cpr in configs:
-        S = K.SolverCreate(getattr(K, f"KRY_{st}"), getattr(K, f"KRY_PC_{pc}"), m)
-        K.SolverSetMat(S, A)
+        ex = EXTRAS.get(name, {})
+        mm, AA = sys_vecs[ex.get("system", "blackoil")][:2]
+        S = K.SolverCreate(getattr(K, f"KRY_{st}"), getattr(K, f"KRY_PC_{pc}"), mm)
+        K.SolverSetMat(S, AA)
         K.SolverSetRtol(S, args.rtol)
         K.SolverSetMaxit(S, 5000)
         K.SolverSetRestart(S, 30)
+        K.SolverSetAugk(S, ex.get("aug_k", 0))
         K.SolverSetPrecision(S, getattr(K, f"KRY_PREC_{prec}"))
         if cpr:
             K.SolverSetCPR(S, getattr(K, f"KRY_CPR_{cpr[0]}"), cpr[1])
@@ -211,11 +231,12 @@ def main():
 
     def run_one(name):
         S = solvers[name]
-        x.zero_()
+        _, _, bv, xv, xt = sys_vecs[EXTRAS.get(name, {}).get("system", "blackoil")]
+        xt.zero_()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         K.SolverAssemble(S)
-        rc = K.SolverSolve(S, bh, xh)
+        rc = K.SolverSolve(S, bv, xv)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
         st, ss = K.SolverGetTimes(S)
@@ -296,6 +317,12 @@ def main():
     K.VecDestroy(xh)
     K.MatDestroy(A)
     K.MapDestroy(m)
+    if "scalar" in sys_vecs:
+        m1, A1, b1h, x1h, _ = sys_vecs["scalar"]
+        K.VecDestroy(b1h)
+        K.VecDestroy(x1h)
+        K.MatDestroy(A1)
+        K.MapDestroy(m1)
 
     cpu = None
     if not args.no_cpu:

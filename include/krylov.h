@@ -56,7 +56,10 @@ extern "C" {
 /* ---- enumerations -------------------------------------------------------- */
 enum { KRY_HOST = 0, KRY_DEVICE = 1 };
 enum { KRY_F64 = 0 };                         /* VEC data type             */
-enum { KRY_GMRES = 0, KRY_FGMRES = 1, KRY_BICGSTAB = 2 };
+/* GMRES(m) (Algorithm 1, right preconditioned), FGMRES(m), BiCGSTAB, and
+ * preconditioned CG (Algorithm 2; A and M symmetric positive definite).
+ * GMRES and FGMRES become LGMRES(m, k) with SolverSetAugk(k > 0). */
+enum { KRY_GMRES = 0, KRY_FGMRES = 1, KRY_BICGSTAB = 2, KRY_CG = 3 };
 enum { KRY_PC_NONE = 0, KRY_PC_ILU0 = 1, KRY_PC_BILU0 = 1, KRY_PC_CPR = 2,
        KRY_PC_CUSTOM = 3,
        /* learned-stage extension: base preconditioner followed by the
@@ -162,8 +165,14 @@ int  SolverSetMaxit(SOLVER *s, int64_t it);
 int  SolverSetRtol(SOLVER *s, double tol);
 int  SolverSetAtol(SOLVER *s, double tol);
 int  SolverSetBtol(SOLVER *s, double tol);
-int  SolverSetRestart(SOLVER *s, int64_t m);    /* 1 <= m <= 64 */
-int  SolverSetAugk(SOLVER *s, int64_t k);       /* LGMRES: only k = 0 */
+int  SolverSetRestart(SOLVER *s, int64_t m);    /* 1 <= m, m + aug_k <= 63 */
+/* aug_k (Section 3, the SOLVER structure): k > 0 turns GMRES/FGMRES into
+ * LGMRES(m, k): every cycle adds one Arnoldi step per stored correction
+ * x_i - x_{i-1} of the last k cycles (normalized, newest first; Baker,
+ * Jessup & Manteuffel), with flexible storage of the directions.  0 <= k,
+ * restart + k <= 63, else KRY_ERR_ARG; SolverAssemble rejects k > 0 for
+ * BiCGSTAB and CG. */
+int  SolverSetAugk(SOLVER *s, int64_t k);
 
 /* Extensions beyond the paper:
  * SolverSetPrecision: precision of the preconditioner apply (FP64, FP32

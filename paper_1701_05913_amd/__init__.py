@@ -30,7 +30,7 @@ KRY_ERR_ARG, KRY_ERR_DIM, KRY_ERR_ALLOC, KRY_ERR_ZERO_PIVOT = -1, -2, -3, -4
 KRY_ERR_BREAKDOWN, KRY_ERR_HIP, KRY_ERR_UNSUPPORTED, KRY_ERR_STALL = -5, -6, -7, -8
 KRY_HOST, KRY_DEVICE = 0, 1
 KRY_F64 = 0
-KRY_GMRES, KRY_FGMRES, KRY_BICGSTAB = 0, 1, 2
+KRY_GMRES, KRY_FGMRES, KRY_BICGSTAB, KRY_CG = 0, 1, 2, 3
 KRY_PC_NONE, KRY_PC_ILU0, KRY_PC_BILU0, KRY_PC_CPR, KRY_PC_CUSTOM = 0, 1, 1, 2, 3
 KRY_PC_BILU0_LEARNED, KRY_PC_CPR_LEARNED = 4, 5
 KRY_PREC_F64, KRY_PREC_F32, KRY_PREC_BF16_FACTORS = 0, 1, 2

@@ -339,6 +339,7 @@ struct SOLVER_ {
     // Krylov workspace
     int64_t ldv = 0;
     kry::DBuf<double> V, Z, wrk, H, small, partial;
+    kry::DBuf<double> AUG;       // LGMRES: stored corrections (aug_k columns)
     double *h_pinned = nullptr;  // host-visible readback slots
 };
 

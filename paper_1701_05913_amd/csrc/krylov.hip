@@ -481,6 +481,71 @@ __global__ void k_bicg_next(double *sc) {
     sc[SC_RHO0] = sc[SC_RHO];
 }
 
+// ---------------------------------------------------------------------------
+// preconditioned CG (Algorithm 2): scalars in device memory
+// ---------------------------------------------------------------------------
+// rho = (r, z); beta = rho / rho_prev (unused on the first step)
+__global__ void k_cg_rho(const double *__restrict__ partial, int nblocks, double *sc) {
+    __shared__ double lds[4];
+    double s = 0.0;
+    for (int b = threadIdx.x; b < nblocks; b += blockDim.x) s += partial[(size_t)b * 2];
+    s = block_sum<256>(s, lds);
+    if (threadIdx.x != 0) return;
+    sc[SC_RHO] = s;
+    sc[SC_BETAB] = s / sc[SC_RHO0];
+    if (!isfinite(s)) sc[SC_FLAGS] = 1.0;
+}
+
+// p = z + beta p
+__global__ void k_cg_p(int64_t n, const double *__restrict__ z, double *__restrict__ p,
+                       const double *__restrict__ sc) {
+    const double beta = sc[SC_BETAB];
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = z[i] + beta * p[i];
+}
+
+// alpha = rho / (p, A p) from the SpMV's fused partials; a curvature that is
+// not positive (or not finite) flags a breakdown and zeroes alpha
+__global__ void k_cg_alpha(const double *__restrict__ partial, int nblocks, double *sc) {
+    __shared__ double lds[4];
+    double s = 0.0;
+    for (int b = threadIdx.x; b < nblocks; b += blockDim.x) s += partial[(size_t)b * 2];
+    s = block_sum<256>(s, lds);
+    if (threadIdx.x != 0) return;
+    sc[SC_RV] = s;
+    const bool brk = !(s > 0.0) || !isfinite(s) || sc[SC_FLAGS] != 0.0;
+    if (brk) sc[SC_FLAGS] = 1.0;
+    sc[SC_ALPHA] = brk ? 0.0 : sc[SC_RHO] / s;
+}
+
+// x += alpha p; r -= alpha q; partial ||r||^2
+__global__ __launch_bounds__(256) void k_cg_update(int64_t n, double *__restrict__ x,
+                                                   double *__restrict__ r,
+                                                   const double *__restrict__ p,
+                                                   const double *__restrict__ q,
+                                                   const double *__restrict__ sc,
+                                                   double *__restrict__ partial) {
+    __shared__ double lds[4];
+    const double alpha = sc[SC_ALPHA];
+    double acc = 0.0;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        x[i] += alpha * p[i];
+        const double ri = r[i] - alpha * q[i];
+        r[i] = ri;
+        acc += ri * ri;
+    }
+    acc = block_sum<256>(acc, lds);
+    if (threadIdx.x == 0) partial[blockIdx.x * 2] = acc;
+}
+
+__global__ void k_cg_start(double *sc) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    sc[SC_RHO0] = 1.0;
+    sc[SC_FLAGS] = 0.0;
+}
+
 __global__ void k_zero_int(int *p) {
     if (threadIdx.x == 0 && blockIdx.x == 0) *p = 0;
 }
@@ -490,18 +555,27 @@ __global__ void k_zero_int(int *p) {
 // ---------------------------------------------------------------------------
 static int spmv_blocks(const MAT_ *A) { return spmv_partial_blocks(A); }
 
+// Arnoldi columns per cycle: restart, plus aug_k correction steps (LGMRES)
+static int total_cols(const SOLVER_ *S) { return S->restart + static_cast<int>(S->augk); }
+static SmallLayout layout_of(const SOLVER_ *S) { return SmallLayout(total_cols(S)); }
+// U = [M^-1 v_j ..., corrections] is stored whenever the directions are not
+// M^-1 V (flexible preconditioning, or augmentation)
+static bool stores_z(const SOLVER_ *S) { return S->type == KRY_FGMRES || S->augk > 0; }
+
 static int ensure_workspace(SOLVER_ *S) {
     const int64_t n = (int64_t)S->A->nb * S->A->bs;
     const int64_t ldv = (n + 63) / 64 * 64;
-    const int m = S->restart;
+    const int m = total_cols(S);
+    SmallLayout L(m);
     if (S->ldv == ldv && S->V.p && (int64_t)S->V.n >= (m + 1) * ldv &&
-        (S->type != KRY_FGMRES || (int64_t)S->Z.n >= m * ldv))
+        (!stores_z(S) || (int64_t)S->Z.n >= m * ldv) &&
+        (S->augk == 0 || (int64_t)S->AUG.n >= S->augk * ldv) && S->small.n >= L.total)
         return KRY_OK;
     S->ldv = ldv;
     KRY_TRY(S->V.alloc((size_t)(m + 1) * ldv));
-    if (S->type == KRY_FGMRES) KRY_TRY(S->Z.alloc((size_t)m * ldv));
+    if (stores_z(S)) KRY_TRY(S->Z.alloc((size_t)m * ldv));
+    if (S->augk > 0) KRY_TRY(S->AUG.alloc((size_t)S->augk * ldv));
     KRY_TRY(S->wrk.alloc((size_t)8 * ldv));
-    SmallLayout L(m);
     KRY_TRY(S->small.alloc(L.total));
     const size_t np = std::max<size_t>({(size_t)RED_BLOCKS * MAXCOL, (size_t)CGS_MAXBLK * MAXCOL,
                                         (size_t)spmv_blocks(S->A) * 2});
@@ -544,13 +618,13 @@ static void launch_cgs(hipStream_t st, int n, const double *V, int64_t ldv, int 
 static int cgs2_step(SOLVER_ *S, int j, double *w) {
     const int n = S->A->nb * S->A->bs;
     const int nc = j + 1;
-    SmallLayout L(S->restart);
+    const SmallLayout L = layout_of(S);
     TimedScope ts("cgs2", S->stream);
     double *sm = S->small.p, *pt = S->partial.p;
-    if (nc <= 8) launch_cgs<8>(S->stream, n, S->V.p, S->ldv, nc, w, sm, L, pt, j, S->restart);
-    else if (nc <= 16) launch_cgs<16>(S->stream, n, S->V.p, S->ldv, nc, w, sm, L, pt, j, S->restart);
-    else if (nc <= 32) launch_cgs<32>(S->stream, n, S->V.p, S->ldv, nc, w, sm, L, pt, j, S->restart);
-    else launch_cgs<64>(S->stream, n, S->V.p, S->ldv, nc, w, sm, L, pt, j, S->restart);
+    if (nc <= 8) launch_cgs<8>(S->stream, n, S->V.p, S->ldv, nc, w, sm, L, pt, j, L.m);
+    else if (nc <= 16) launch_cgs<16>(S->stream, n, S->V.p, S->ldv, nc, w, sm, L, pt, j, L.m);
+    else if (nc <= 32) launch_cgs<32>(S->stream, n, S->V.p, S->ldv, nc, w, sm, L, pt, j, L.m);
+    else launch_cgs<64>(S->stream, n, S->V.p, S->ldv, nc, w, sm, L, pt, j, L.m);
     KRY_HIP(hipGetLastError());
     return KRY_OK;
 }
@@ -568,7 +642,7 @@ static int gemvn_acc(SOLVER_ *S, const double *Z, int nc, const double *y, doubl
 
 // r = b - A x with ||r|| into sc[SC_BETA]; returns it on the host
 static int true_residual(SOLVER_ *S, const double *b, const double *x, double *r, double *beta) {
-    SmallLayout L(S->restart);
+    const SmallLayout L = layout_of(S);
     double *sc = S->small.p + L.sc;
     KRY_TRY(spmv_f64(S->stream, S->A, -1.0, x, 1.0, b, r, 1, nullptr, nullptr, S->partial.p));
     KRY_TRY(sum_partials(S->stream, S->partial.p, spmv_blocks(S->A), 2, 1, sc + SC_BETA, SUM_SQRT));
@@ -577,7 +651,7 @@ static int true_residual(SOLVER_ *S, const double *b, const double *x, double *r
 
 static double host_norm(SOLVER_ *S, const double *b) {
     const int64_t n = (int64_t)S->A->nb * S->A->bs;
-    SmallLayout L(S->restart);
+    const SmallLayout L = layout_of(S);
     double *sc = S->small.p + L.sc;
     double v = NAN;
     if (vec_dot_partial(S->stream, n, b, b, nullptr, nullptr, S->partial.p) ||
@@ -638,12 +712,17 @@ int check_device_error(SOLVER_ *S) {
 // ---------------------------------------------------------------------------
 // GMRES(m) / FGMRES(m)
 // ---------------------------------------------------------------------------
+// GMRES(m) / FGMRES(m) (Algorithm 1, right preconditioned), and LGMRES(m, k)
+// when aug_k = k > 0 (Baker, Jessup & Manteuffel): every cycle adds one
+// Arnoldi step per stored correction of the previous cycles (newest first,
+// at most k, each normalized), with the correction itself as the direction;
+// the cycle's correction U y becomes the newest stored one.
 static int gmres_solve(SOLVER_ *S, const double *b, double *x) {
     const int64_t n = (int64_t)S->A->nb * S->A->bs;
-    const int m = S->restart;
-    const bool flexible = S->type == KRY_FGMRES;
+    const int m = S->restart, k = static_cast<int>(S->augk);
+    const bool flexible = stores_z(S);
     KRY_TRY(ensure_workspace(S));
-    SmallLayout L(m);
+    const SmallLayout L = layout_of(S);
     double *small = S->small.p, *sc = small + L.sc;
     double *ztmp = S->wrk.p, *utmp = S->wrk.p + S->ldv;
     const double bnorm = host_norm(S, b);
@@ -653,6 +732,7 @@ static int gmres_solve(SOLVER_ *S, const double *b, double *x) {
     S->hist.clear();
     int status = KRY_NOT_CONVERGED;
     double relres = 0.0;
+    int nstored = 0, head = 0;   // corrections: the i-th newest in AUG slot (head + i) % k
     for (;;) {
         double beta = 0.0;
         KRY_TRY(true_residual(S, b, x, S->V.p, &beta));
@@ -664,11 +744,16 @@ static int gmres_solve(SOLVER_ *S, const double *b, double *x) {
         hipLaunchKernelGGL(k_cycle_start, dim3(1), dim3(64), 0, S->stream, small, L);
         KRY_TRY(vec_scale_copy(S->stream, n, dc(sc + SC_INVBETA), S->V.p, S->V.p));
         int jend = 0;
-        for (int j = 0; j < m; j++) {
+        const int steps = m + nstored;
+        for (int j = 0; j < steps; j++) {
             double *vj = S->V.p + (size_t)j * S->ldv;
             double *zj = flexible ? S->Z.p + (size_t)j * S->ldv : ztmp;
             double *w = S->V.p + (size_t)(j + 1) * S->ldv;
-            KRY_TRY(pc_apply(S, vj, zj));
+            if (j < m)
+                KRY_TRY(pc_apply(S, vj, zj));
+            else
+                KRY_HIP(hipMemcpyAsync(zj, S->AUG.p + (size_t)((head + j - m) % k) * S->ldv,
+                                       sizeof(double) * n, hipMemcpyDeviceToDevice, S->stream));
             KRY_TRY(spmv_f64(S->stream, S->A, 1.0, zj, 0.0, nullptr, w, 0, nullptr, nullptr, nullptr));
             KRY_TRY(cgs2_step(S, j, w));
             double hv[3];                                  // SC_HN, SC_INVHN, SC_EST
@@ -683,7 +768,18 @@ static int gmres_solve(SOLVER_ *S, const double *b, double *x) {
             KRY_TRY(vec_scale_copy(S->stream, n, dc(sc + SC_INVHN), w, w));
         }
         hipLaunchKernelGGL(k_ls_solve, dim3(1), dim3(64), 0, S->stream, small, L, jend);
-        if (flexible) {
+        if (k > 0) {
+            // dx = U y; x += dx; dx / ||dx|| becomes the newest correction
+            KRY_TRY(gemvn_acc(S, S->Z.p, jend, small + L.y, 0.0, utmp));
+            KRY_TRY(vec_axpbyz(S->stream, n, hc(1.0), utmp, hc(1.0), x, x));
+            const double dn = host_norm(S, utmp);
+            if (dn > 0.0 && std::isfinite(dn)) {
+                head = (head + k - 1) % k;
+                KRY_TRY(vec_scale_copy(S->stream, n, hc(1.0 / dn), utmp,
+                                       S->AUG.p + (size_t)head * S->ldv));
+                nstored = std::min(nstored + 1, k);
+            }
+        } else if (flexible) {
             KRY_TRY(gemvn_acc(S, S->Z.p, jend, small + L.y, 1.0, x));
         } else {
             KRY_TRY(gemvn_acc(S, S->V.p, jend, small + L.y, 0.0, utmp));
@@ -702,7 +798,7 @@ static int gmres_solve(SOLVER_ *S, const double *b, double *x) {
 static int bicgstab_solve(SOLVER_ *S, const double *b, double *x) {
     const int64_t n = (int64_t)S->A->nb * S->A->bs;
     KRY_TRY(ensure_workspace(S));
-    SmallLayout L(S->restart);
+    const SmallLayout L = layout_of(S);
     double *sc = S->small.p + L.sc;
     const int64_t ld = S->ldv;
     double *r = S->wrk.p, *rh = r + ld, *p = rh + ld, *v = p + ld, *ph = v + ld;
@@ -773,6 +869,63 @@ static int bicgstab_solve(SOLVER_ *S, const double *b, double *x) {
     return status;
 }
 
+// ---------------------------------------------------------------------------
+// preconditioned CG, Algorithm 2: stops on the recursively updated ||r||,
+// reports the true residual; negative curvature ends with KRY_ERR_BREAKDOWN
+// ---------------------------------------------------------------------------
+static int cg_solve(SOLVER_ *S, const double *b, double *x) {
+    const int64_t n = (int64_t)S->A->nb * S->A->bs;
+    KRY_TRY(ensure_workspace(S));
+    const SmallLayout L = layout_of(S);
+    double *sc = S->small.p + L.sc;
+    const int64_t ld = S->ldv;
+    double *r = S->wrk.p, *z = r + ld, *p = z + ld, *q = p + ld;
+    double *part = S->partial.p;
+    const int nsb = spmv_blocks(S->A);
+    const dim3 gv(2048), bv(256);
+    const double bnorm = host_norm(S, b);
+    if (!std::isfinite(bnorm)) return set_error(KRY_ERR_BREAKDOWN, "non-finite right-hand side");
+    const double tol = std::max(S->rtol * bnorm, S->atol);
+    S->hist.clear();
+    double rn = 0.0;
+    KRY_TRY(true_residual(S, b, x, r, &rn));
+    S->hist.push_back(rn);
+    if (!std::isfinite(rn)) return set_error(KRY_ERR_BREAKDOWN, "non-finite residual");
+    int nits = 0, status = rn <= tol ? KRY_OK : KRY_NOT_CONVERGED;
+    hipLaunchKernelGGL(k_cg_start, dim3(1), dim3(64), 0, S->stream, sc);
+    while (status != KRY_OK && nits < S->maxit) {
+        KRY_TRY(pc_apply(S, r, z));
+        KRY_TRY(vec_dot_partial(S->stream, n, r, z, nullptr, nullptr, part));
+        hipLaunchKernelGGL(k_cg_rho, dim3(1), dim3(256), 0, S->stream, part, RED_BLOCKS, sc);
+        if (nits == 0)
+            KRY_HIP(hipMemcpyAsync(p, z, sizeof(double) * n, hipMemcpyDeviceToDevice, S->stream));
+        else
+            hipLaunchKernelGGL(k_cg_p, gv, bv, 0, S->stream, n, z, p, sc);
+        KRY_TRY(spmv_f64(S->stream, S->A, 1.0, p, 0.0, nullptr, q, 1, p, nullptr, part));
+        hipLaunchKernelGGL(k_cg_alpha, dim3(1), dim3(256), 0, S->stream, part, nsb, sc);
+        hipLaunchKernelGGL(k_cg_update, dim3(RED_BLOCKS), bv, 0, S->stream, n, x, r, p, q, sc, part);
+        KRY_TRY(sum_partials(S->stream, part, RED_BLOCKS, 2, 1, sc + SC_RNORM, SUM_SQRT));
+        hipLaunchKernelGGL(k_bicg_next, dim3(1), dim3(64), 0, S->stream, sc);
+        static_assert(SC_FLAGS > SC_RNORM, "one readback covers both slots");
+        double v[SC_FLAGS + 1];
+        KRY_TRY(readback(S, sc, SC_FLAGS + 1, v));
+        if (v[SC_FLAGS] != 0.0) {
+            status = set_error(KRY_ERR_BREAKDOWN, "CG: curvature (p, A p) not positive");
+            break;
+        }
+        nits++;
+        rn = v[SC_RNORM];
+        S->hist.push_back(rn);
+        if (rn <= tol) status = KRY_OK;
+        else if (!std::isfinite(rn)) { status = set_error(KRY_ERR_BREAKDOWN, "CG: non-finite residual"); break; }
+    }
+    double tn = 0.0;
+    KRY_TRY(true_residual(S, b, x, q, &tn));
+    S->nits = nits;
+    S->residual = bnorm > 0 ? tn / bnorm : tn;
+    return status;
+}
+
 }  // namespace kry
 
 using namespace kry;
@@ -793,7 +946,7 @@ extern "C" void SolverSetDefaultAugk(int64_t k) { g_def_augk = k; }
 
 extern "C" SOLVER *SolverCreate(int solver_type, int pc_type, MAP *map) {
     if (!map) { set_error(KRY_ERR_ARG, "SolverCreate: map is NULL"); return nullptr; }
-    if (solver_type != KRY_GMRES && solver_type != KRY_FGMRES && solver_type != KRY_BICGSTAB) {
+    if (solver_type < KRY_GMRES || solver_type > KRY_CG) {
         set_error(KRY_ERR_UNSUPPORTED, "SolverCreate: solver type %d", solver_type);
         return nullptr;
     }
@@ -810,7 +963,7 @@ extern "C" SOLVER *SolverCreate(int solver_type, int pc_type, MAP *map) {
     s->atol = g_def_atol;
     s->btol = g_def_btol;
     s->restart = static_cast<int>(std::min<int64_t>(std::max<int64_t>(g_def_restart, 1), MAXCOL - 1));
-    s->augk = g_def_augk;
+    s->augk = std::max<int64_t>(0, std::min<int64_t>(g_def_augk, MAXCOL - 1 - s->restart));
     return s;
 }
 
@@ -853,15 +1006,18 @@ extern "C" int SolverSetBtol(SOLVER *s, double t) {
     return KRY_OK;
 }
 extern "C" int SolverSetRestart(SOLVER *s, int64_t m) {
-    if (!s || m < 1 || m > MAXCOL - 1) return set_error(KRY_ERR_ARG, "SolverSetRestart: need 1 <= m <= %d", MAXCOL - 1);
+    if (!s || m < 1 || m + s->augk > MAXCOL - 1)
+        return set_error(KRY_ERR_ARG, "SolverSetRestart: need 1 <= m and m + aug_k <= %d", MAXCOL - 1);
     s->restart = static_cast<int>(m);
     s->ldv = 0;
     return KRY_OK;
 }
 extern "C" int SolverSetAugk(SOLVER *s, int64_t k) {
     if (!s) return set_error(KRY_ERR_ARG, "SolverSetAugk: NULL solver");
-    if (k != 0) return set_error(KRY_ERR_UNSUPPORTED, "SolverSetAugk: LGMRES augmentation is not implemented");
-    s->augk = 0;
+    if (k < 0 || s->restart + k > MAXCOL - 1)
+        return set_error(KRY_ERR_ARG, "SolverSetAugk: need 0 <= k and restart + k <= %d", MAXCOL - 1);
+    s->augk = k;
+    s->ldv = 0;
     return KRY_OK;
 }
 extern "C" int SolverSetPrecision(SOLVER *s, int prec) {
@@ -907,6 +1063,8 @@ extern "C" int SolverAssemble(SOLVER *s) {
     if (!s || !s->A) return set_error(KRY_ERR_ARG, "SolverAssemble: no matrix");
     if (s->prec != KRY_PREC_F64 && s->type != KRY_FGMRES)
         return set_error(KRY_ERR_ARG, "reduced-precision preconditioning needs FGMRES");
+    if (s->augk > 0 && s->type != KRY_GMRES && s->type != KRY_FGMRES)
+        return set_error(KRY_ERR_ARG, "aug_k > 0 (LGMRES) applies to GMRES and FGMRES");
     if (s->prec != KRY_PREC_F64 && (s->pc_type == KRY_PC_NONE || s->pc_type == KRY_PC_CUSTOM))
         return set_error(KRY_ERR_ARG, "reduced precision applies to ILU and CPR preconditioners");
     const bool learned = s->pc_type == KRY_PC_BILU0_LEARNED || s->pc_type == KRY_PC_CPR_LEARNED;
@@ -964,7 +1122,9 @@ extern "C" int SolverSolve(SOLVER *s, VEC *b, VEC *x) {
     if (b->n != n || x->n != n) return set_error(KRY_ERR_DIM, "SolverSolve: vector sizes differ from the matrix");
     if (b->data == x->data) return set_error(KRY_ERR_ARG, "SolverSolve: b and x alias");
     const auto t0 = std::chrono::steady_clock::now();
-    int rc = (s->type == KRY_BICGSTAB) ? bicgstab_solve(s, b->data, x->data) : gmres_solve(s, b->data, x->data);
+    int rc = s->type == KRY_BICGSTAB ? bicgstab_solve(s, b->data, x->data)
+             : s->type == KRY_CG     ? cg_solve(s, b->data, x->data)
+                                     : gmres_solve(s, b->data, x->data);
     const int erc = check_device_error(s);
     if (hipStreamSynchronize(s->stream) != hipSuccess && rc >= 0) rc = set_error(KRY_ERR_HIP, "SolverSolve: stream error");
     s->t_solve = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();

@@ -43,13 +43,14 @@ class GpuSystem:
 
 
 def make_solver(g, solver, pc, rtol=1e-8, maxit=5000, restart=30,
-                prec=K.KRY_PREC_F64, cpr=(K.KRY_CPR_PF, 4), layout=K.KRY_SWEEP_AUTO):
+                prec=K.KRY_PREC_F64, cpr=(K.KRY_CPR_PF, 4), layout=K.KRY_SWEEP_AUTO, aug_k=0):
     S = K.SolverCreate(solver, pc, g.map)
     K.SolverSetSweepLayout(S, layout)
     K.SolverSetMat(S, g.A)
     K.SolverSetRtol(S, rtol)
     K.SolverSetMaxit(S, maxit)
     K.SolverSetRestart(S, restart)
+    K.SolverSetAugk(S, aug_k)
     K.SolverSetPrecision(S, prec)
     if pc == K.KRY_PC_CPR:
         K.SolverSetCPR(S, cpr[0], cpr[1])

@@ -54,7 +54,10 @@ def test_host_side_argument_errors_without_gpu():
     with pytest.raises(K.KrylovError):
         K.SolverSetRestart(s, 0)
     with pytest.raises(K.KrylovError):
-        K.SolverSetAugk(s, 2)                    # LGMRES not implemented
+        K.SolverSetAugk(s, -1)                   # aug_k < 0
+    with pytest.raises(K.KrylovError):
+        K.SolverSetAugk(s, 40)                   # restart 30 + aug_k > 63
+    K.SolverSetAugk(s, 2)                        # LGMRES(30, 2)
     with pytest.raises(K.KrylovError):
         K.SolverAssemble(s)                      # no matrix
     K.SolverDestroy(s)

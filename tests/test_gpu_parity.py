@@ -21,6 +21,7 @@ if not torch.cuda.is_available():
     pytest.skip("no GPU", allow_module_level=True)
 
 import paper_1701_05913_amd as K  # noqa: E402
+from tests._helpers import bsr_from_dense  # noqa: E402
 from tests.gpu_helpers import GpuSystem, pc_apply, relerr, solve  # noqa: E402
 
 SMALL_SCALAR = (37, 29, 23)     # 24 679 rows: many slices, ragged tail
@@ -308,3 +309,95 @@ def test_blackoil64_bilu0(solver):
         _check_solve(s, gpu, A, pc, 1e-8, oracle.gmres, restart=30, maxit=5000)
     else:
         _check_bicgstab(s, gpu, A, pc, 1e-8, 5000)
+
+
+# ---- LGMRES (aug_k > 0) and preconditioned CG (Algorithm 2) ------------------------
+@pytest.mark.parametrize("grid", [SMALL_BLOCK, (32, 32, 16)])
+def test_lgmres_solve(grid):
+    # LGMRES(10, 2) + BILU(0), rtol 1e-8, against the oracle's LGMRES
+    s = ri.blackoil_system(*grid, seed=6)
+    A = oracle.Matrix.from_system(s)
+    g = GpuSystem(s)
+    try:
+        gpu = solve(g, K.KRY_GMRES, K.KRY_PC_BILU0, rtol=1e-8, maxit=3000, restart=10, aug_k=2)
+    finally:
+        g.close()
+    ref = _check_solve(s, gpu, A, oracle.PC(A, "bilu0"), 1e-8, oracle.lgmres, restart=10,
+                       aug_k=2, maxit=3000)
+    plain = oracle.gmres(A, oracle.PC(A, "bilu0"), s["b"], restart=10, maxit=3000, rtol=1e-8)
+    assert ref["iters"] < plain["iters"]
+
+
+def test_lgmres_matches_oracle_cycle_by_cycle():
+    # fixed step counts covering three cycles with corrections in use
+    s = ri.blackoil_system(*SMALL_BLOCK, seed=7)
+    A = oracle.Matrix.from_system(s)
+    g = GpuSystem(s)
+    try:
+        for steps in (8, 8 + 9, 8 + 9 + 10):
+            gpu = solve(g, K.KRY_FGMRES, K.KRY_PC_BILU0, rtol=1e-30, maxit=steps, restart=8,
+                        aug_k=2)
+            ref = oracle.lgmres(A, oracle.PC(A, "bilu0"), s["b"], restart=8, aug_k=2,
+                                maxit=steps, fixed_iters=True)
+            assert gpu["iters"] == steps
+            assert relerr(gpu["x"], ref["x"]) <= 1e-9, (steps, relerr(gpu["x"], ref["x"]))
+    finally:
+        g.close()
+
+
+@pytest.mark.parametrize("pc,kind", [(K.KRY_PC_ILU0, "ilu0"), (K.KRY_PC_NONE, "none")])
+def test_pcg_scalar32(pc, kind):
+    # the 32^3 scalar (symmetric) system: PCG with ILU(0) and plain CG, rtol 1e-8
+    s = ri.scalar_system(32, 32, 32, seed=0)
+    A = oracle.Matrix.from_system(s)
+    g = GpuSystem(s)
+    try:
+        gpu = solve(g, K.KRY_CG, pc, rtol=1e-8, maxit=5000)
+    finally:
+        g.close()
+    ref = oracle.pcg(A, oracle.PC(A, kind), s["b"], rtol=1e-8, maxit=5000)
+    assert ref["status"] == 0 and gpu["status"] == K.KRY_OK, gpu
+    r = s["b"] - oracle.spmv(A, gpu["x"])
+    assert np.linalg.norm(r) <= 1.05e-8 * np.linalg.norm(s["b"])
+    assert abs(gpu["iters"] - ref["iters"]) <= max(1, 0.05 * ref["iters"]), (gpu["iters"], ref["iters"])
+    # the same number of steps from the oracle agrees closely
+    fixed = oracle.pcg(A, oracle.PC(A, kind), s["b"], maxit=gpu["iters"], fixed_iters=True)
+    assert relerr(gpu["x"], fixed["x"]) <= 1e-6
+
+
+def test_pcg_breakdown_on_indefinite_matrix():
+    D = np.diag([2.0, -1.0, 3.0, 1.0])
+    D[0, 1] = D[1, 0] = 0.5
+    st = bsr_from_dense(D, 1)
+    g = GpuSystem(st)
+    try:
+        # b along the negative-curvature direction: (p, A p) < 0 at the first step
+        with pytest.raises(K.KrylovError) as e:
+            solve(g, K.KRY_CG, K.KRY_PC_NONE, b=np.array([0.0, 1.0, 0.0, 0.0]), rtol=1e-12,
+                  maxit=10)
+        assert e.value.code == K.KRY_ERR_BREAKDOWN
+    finally:
+        g.close()
+
+
+def test_augk_argument_checks():
+    s = ri.blackoil_system(4, 4, 4, seed=1)
+    g = GpuSystem(s)
+    try:
+        S = K.SolverCreate(K.KRY_GMRES, K.KRY_PC_BILU0, g.map)
+        K.SolverSetRestart(S, 30)
+        for bad in (-1, 34):
+            with pytest.raises(K.KrylovError):
+                K.SolverSetAugk(S, bad)
+        K.SolverSetAugk(S, 33)
+        with pytest.raises(K.KrylovError):
+            K.SolverSetRestart(S, 31)
+        K.SolverDestroy(S)
+        S = K.SolverCreate(K.KRY_BICGSTAB, K.KRY_PC_BILU0, g.map)
+        K.SolverSetMat(S, g.A)
+        K.SolverSetAugk(S, 2)
+        with pytest.raises(K.KrylovError):
+            K.SolverAssemble(S)
+        K.SolverDestroy(S)
+    finally:
+        g.close()
