@@ -55,6 +55,8 @@ def load(path: str):
     L.or_pc_create.argtypes = [I, I, I, P, P, P, I, I, C.POINTER(I)]
     L.or_pc_create.restype = P
     L.or_pc_create_learned.argtypes = [P, I, I, I, P, P, I]
+    L.or_pc_create_ras.argtypes = [I, I, P, P, P, I, P, I, C.POINTER(I)]
+    L.or_pc_create_ras.restype = P
     L.or_pc_create_learned.restype = P
     L.or_pc_apply.argtypes = [P, P, P]
     L.or_pc_destroy.argtypes = [P]
@@ -217,6 +219,22 @@ class PC:
         obj.h = lib().or_pc_create_learned(base.h, nx, ny, nz, _p(params),
                                            _p(lnk), int(bf16))
         base.h = None      # ownership moved
+        return obj
+
+    @classmethod
+    def ras(cls, A: "Matrix", starts, overlap=1):
+        """Restricted additive Schwarz with block ILU(0) subdomain solves;
+        `starts` = block-row offsets of the owned ranges (0 .. nb)."""
+        obj = cls.__new__(cls)
+        obj.A = A
+        st = _i32(starts)
+        obj._starts = st
+        err = C.c_int(0)
+        obj.h = lib().or_pc_create_ras(*A.args(), int(st.size - 1), _p(st), int(overlap),
+                                       C.byref(err))
+        obj.err = err.value
+        if not obj.h:
+            raise RuntimeError(f"oracle RAS setup failed: {obj.err}")
         return obj
 
     def apply(self, v):

@@ -383,8 +383,19 @@ void or_cpr_extract_pressure(int nb, const int *rp, const int *ci,
 /* ======================================================================
  * Preconditioner objects (Figure 29)
  * ====================================================================== */
+/* one subdomain of RAS: owned block rows [o0, o1), the overlapped set
+ * idx[0..nidx) (ascending global block rows), the principal submatrix of A
+ * on it in local numbering and its block ILU(0) factor */
+typedef struct {
+    int o0, o1, nidx;
+    int *idx, *rp, *ci;
+    double *a, *lu;
+} ras_sub;
+
 struct or_pc {
     int kind, nb, bs, prec, p_sweeps;
+    int nsub;
+    ras_sub *subs;              /* RAS */
     const int *rp, *ci;
     const double *a;
     double *lu;                 /* FP64 (block) ILU(0) factor of A        */
@@ -461,6 +472,101 @@ or_pc *or_pc_create_learned(or_pc *base, int nx, int ny, int nz,
     return pc;
 }
 
+/* ======================================================================
+ * C9b. Restricted additive Schwarz (Section 4.1, Cai & Sarkis): the block
+ * rows are cut into nsub contiguous owned ranges [starts[s], starts[s+1]);
+ * subdomain s grows by `overlap` rounds of graph neighbours (the column
+ * indices of its rows), its principal submatrix A_s is factored by block
+ * ILU(0), and
+ *     M^-1 v = sum_s R0_s^T (L_s U_s)^-1 R_s v,
+ * R_s restricting to the overlapped set, R0_s^T writing back only the
+ * owned rows (restricted prolongation).
+ * ====================================================================== */
+or_pc *or_pc_create_ras(int nb, int bs, const int *rp, const int *ci,
+                        const double *a, int nsub, const int *starts,
+                        int overlap, int *err)
+{
+    int e = OR_OK;
+    if (nsub < 1 || overlap < 0 || starts[0] != 0 || starts[nsub] != nb) e = OR_ERR_ARG;
+    for (int s = 0; !e && s < nsub; s++)
+        if (starts[s + 1] <= starts[s]) e = OR_ERR_ARG;
+    if (e) { if (err) *err = e; return NULL; }
+    or_pc *pc = (or_pc *)calloc(1, sizeof(or_pc));
+    const int b2 = bs * bs;
+    pc->kind = OR_PC_RAS; pc->nb = nb; pc->bs = bs; pc->prec = OR_PREC_F64;
+    pc->rp = rp; pc->ci = ci; pc->a = a;
+    pc->nsub = nsub;
+    pc->subs = (ras_sub *)calloc((size_t)nsub, sizeof(ras_sub));
+    char *in = (char *)malloc((size_t)nb);
+    char *add = (char *)malloc((size_t)nb);
+    int *loc = (int *)malloc(sizeof(int) * (size_t)nb);
+    for (int s = 0; !e && s < nsub; s++) {
+        ras_sub *S = &pc->subs[s];
+        S->o0 = starts[s]; S->o1 = starts[s + 1];
+        for (int r = 0; r < nb; r++) in[r] = (char)(r >= S->o0 && r < S->o1);
+        for (int d = 0; d < overlap; d++) {            /* one round of neighbours */
+            for (int r = 0; r < nb; r++) add[r] = 0;
+            for (int r = 0; r < nb; r++)
+                if (in[r])
+                    for (int q = rp[r]; q < rp[r + 1]; q++) add[ci[q]] = 1;
+            for (int r = 0; r < nb; r++) in[r] = (char)(in[r] | add[r]);
+        }
+        S->nidx = 0;
+        for (int r = 0; r < nb; r++) S->nidx += in[r];
+        S->idx = (int *)malloc(sizeof(int) * (size_t)S->nidx);
+        for (int r = 0, l = 0; r < nb; r++) {
+            loc[r] = in[r] ? l : -1;
+            if (in[r]) S->idx[l++] = r;
+        }
+        /* principal submatrix in local numbering (columns stay ascending) */
+        S->rp = (int *)malloc(sizeof(int) * (size_t)(S->nidx + 1));
+        S->rp[0] = 0;
+        for (int l = 0; l < S->nidx; l++) {
+            int g = S->idx[l], c = 0;
+            for (int q = rp[g]; q < rp[g + 1]; q++) c += loc[ci[q]] >= 0;
+            S->rp[l + 1] = S->rp[l] + c;
+        }
+        const int nnz = S->rp[S->nidx];
+        S->ci = (int *)malloc(sizeof(int) * (size_t)(nnz > 0 ? nnz : 1));
+        S->a = (double *)malloc(sizeof(double) * (size_t)(nnz > 0 ? nnz : 1) * b2);
+        S->lu = (double *)malloc(sizeof(double) * (size_t)(nnz > 0 ? nnz : 1) * b2);
+        for (int l = 0, p = 0; l < S->nidx; l++) {
+            int g = S->idx[l];
+            for (int q = rp[g]; q < rp[g + 1]; q++)
+                if (loc[ci[q]] >= 0) {
+                    S->ci[p] = loc[ci[q]];
+                    memcpy(S->a + (size_t)p * b2, a + (size_t)q * b2, sizeof(double) * b2);
+                    p++;
+                }
+        }
+        e = or_bilu0(S->nidx, bs, S->rp, S->ci, S->a, S->lu);
+    }
+    free(in); free(add); free(loc);
+    if (err) *err = e;
+    if (e) { or_pc_destroy(pc); return NULL; }
+    return pc;
+}
+
+static void ras_apply(or_pc *pc, const double *v, double *z)
+{
+    const int bs = pc->bs;
+    for (int s = 0; s < pc->nsub; s++) {
+        const ras_sub *S = &pc->subs[s];
+        const size_t nl = (size_t)S->nidx * bs;
+        double *vl = (double *)malloc(sizeof(double) * nl);
+        double *xl = (double *)malloc(sizeof(double) * nl);
+        for (int l = 0; l < S->nidx; l++)                 /* R_s v */
+            memcpy(vl + (size_t)l * bs, v + (size_t)S->idx[l] * bs, sizeof(double) * bs);
+        or_bilu0_solve(S->nidx, bs, S->rp, S->ci, S->lu, vl, xl);
+        for (int l = 0; l < S->nidx; l++) {               /* owned rows only */
+            const int g = S->idx[l];
+            if (g >= S->o0 && g < S->o1)
+                memcpy(z + (size_t)g * bs, xl + (size_t)l * bs, sizeof(double) * bs);
+        }
+        free(vl); free(xl);
+    }
+}
+
 void or_pc_destroy(or_pc *pc)
 {
     if (!pc) return;
@@ -470,6 +576,11 @@ void or_pc_destroy(or_pc *pc)
     if (pc->lpp.f) lowp_free(&pc->lpp);
     if (pc->base) or_pc_destroy(pc->base);
     free(pc->params); free(pc->lnk);
+    for (int s = 0; s < pc->nsub; s++) {
+        free(pc->subs[s].idx); free(pc->subs[s].rp); free(pc->subs[s].ci);
+        free(pc->subs[s].a); free(pc->subs[s].lu);
+    }
+    free(pc->subs);
     free(pc);
 }
 
@@ -629,6 +740,10 @@ void or_pc_apply(or_pc *pc, const double *v, double *z)
     }
     if (pc->kind == OR_PC_LEARNED) {
         conv_apply_learned(pc, v, z);
+        return;
+    }
+    if (pc->kind == OR_PC_RAS) {
+        ras_apply(pc, v, z);
         return;
     }
     if (pc->prec == OR_PREC_F64) {

@@ -58,7 +58,7 @@ void or_bilu0_solve_upper(int nb, int bs, const int *rp, const int *ci,
 /* ---- preconditioner objects (Figure 29: setup / solve / destroy) ------- */
 typedef struct or_pc or_pc;
 enum { OR_PC_NONE = 0, OR_PC_BILU0 = 1, OR_PC_CPR_PF = 2, OR_PC_CPR_FP = 3,
-       OR_PC_LEARNED = 4, OR_PC_CPR_FPF = 5, OR_PC_CPR_FFPF = 6 };
+       OR_PC_LEARNED = 4, OR_PC_CPR_FPF = 5, OR_PC_CPR_FFPF = 6, OR_PC_RAS = 7 };
 
 or_pc *or_pc_create(int kind, int nb, int bs, const int *rp, const int *ci,
                     const double *a, int prec, int p_sweeps, int *err);
@@ -69,6 +69,12 @@ or_pc *or_pc_create(int kind, int nb, int bs, const int *rp, const int *ci,
 or_pc *or_pc_create_learned(or_pc *base, int nx, int ny, int nz,
                             const double *params, const double *lnk,
                             int bf16_emul);
+/* RAS with block ILU(0) local solves: owned block rows
+ * [starts[s], starts[s+1]) for s < nsub, `overlap` rounds of graph
+ * neighbours (restricted prolongation) */
+or_pc *or_pc_create_ras(int nb, int bs, const int *rp, const int *ci,
+                        const double *a, int nsub, const int *starts,
+                        int overlap, int *err);
 void or_pc_apply(or_pc *pc, const double *v, double *z);
 void or_pc_destroy(or_pc *pc);
 /* counters of the learned stage: applications and fallbacks */

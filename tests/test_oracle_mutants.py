@@ -10,6 +10,7 @@ import oracle
 from tests import test_oracle_cpr_conv as tc
 from tests import test_oracle_krylov as tk
 from tests import test_oracle_linalg as tl
+from tests import test_oracle_ras as tr
 
 # (name, exact text in oracle.c, replacement, pins expected to fail)
 MUTANTS = [
@@ -95,6 +96,14 @@ MUTANTS = [
      "for (size_t i = 0; i < n; i++) Zs[i] = dx[i] / dn;",
      "for (size_t i = 0; i < n; i++) Zs[i] = x[i] / dn;",
      [lambda: tk.test_lgmres_cycles_minimize_over_augmented_space(2)]),
+    ("ras_prolongs_overlap_rows",
+     "if (g >= S->o0 && g < S->o1)",
+     "if (g >= 0)",
+     [lambda: tr.test_ras_matches_dense_restricted_schwarz([0, 12, 24, 36], 1)]),
+    ("ras_overlap_not_grown",
+     "for (int d = 0; d < overlap; d++) {",
+     "for (int d = 0; d < 0 * overlap; d++) {",
+     [lambda: tr.test_ras_matches_dense_restricted_schwarz([0, 5, 23, 36], 2)]),
     ("gelu_grad_missing_density_term",
      "return 0.5 * (1.0 + erf(x / sqrt(2.0))) + x * exp(-0.5 * x * x) / sqrt(2.0 * pi);",
      "return 0.5 * (1.0 + erf(x / sqrt(2.0)));",
