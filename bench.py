@@ -54,10 +54,13 @@ CONFIGS = [
     ("fgmres30_bilu0_learned", "FGMRES", "BILU0_LEARNED", "F64", None),
     ("lgmres30_2_bilu0_f64", "GMRES", "BILU0", "F64", None),
     ("pcg_ilu0_scalar_f64", "CG", "ILU0", "F64", None),
+    ("gmres30_ras4_f64", "GMRES", "RAS", "F64", None),
+    ("gmres30_ras8_f64", "GMRES", "RAS", "F64", None),
 ]
 # per-configuration extras: LGMRES augmentation, and the symmetric scalar
 # system of the same grid (CG needs a symmetric positive definite matrix)
-EXTRAS = {"lgmres30_2_bilu0_f64": dict(aug_k=2), "pcg_ilu0_scalar_f64": dict(system="scalar")}
+EXTRAS = {"lgmres30_2_bilu0_f64": dict(aug_k=2), "pcg_ilu0_scalar_f64": dict(system="scalar"),
+          "gmres30_ras4_f64": dict(ras=(4, 1)), "gmres30_ras8_f64": dict(ras=(8, 1))}
 WEIGHTS = os.path.join(ROOT, "paper_1701_05913_amd", "weights", "bilu0_blackoil64.bin")
 
 # matrix-core FLOPs per cell of each conv layer (3x3x3 taps, 2 per MAC)
@@ -220,6 +223,8 @@ def main():
         K.SolverSetMaxit(S, 5000)
         K.SolverSetRestart(S, 30)
         K.SolverSetAugk(S, ex.get("aug_k", 0))
+        if "ras" in ex:
+            K.SolverSetRAS(S, *ex["ras"])
         K.SolverSetPrecision(S, getattr(K, f"KRY_PREC_{prec}"))
         if cpr:
             K.SolverSetCPR(S, getattr(K, f"KRY_CPR_{cpr[0]}"), cpr[1])
@@ -276,7 +281,7 @@ def main():
             ent.update(bytes_per_launch=abytes[kname], gbs=round(gbs, 1),
                        frac_hbm=round(gbs / HBM_PEAK_GBS, 4))
         kernels[kname] = ent
-    for kname in ["ilu_grid_untile", "learned_stage"]:
+    for kname in ["ilu_grid_untile", "learned_stage", "ras_apply", "ras_ilu_fwd", "ras_ilu_bwd"]:
         cnt, ms = K.KernelTimingQuery(kname)
         if cnt:
             kernels[kname] = dict(launches=cnt, total_ms=round(ms, 4), avg_us=round(1000 * ms / cnt, 3))

@@ -64,7 +64,10 @@ enum { KRY_PC_NONE = 0, KRY_PC_ILU0 = 1, KRY_PC_BILU0 = 1, KRY_PC_CPR = 2,
        KRY_PC_CUSTOM = 3,
        /* learned-stage extension: base preconditioner followed by the
         * convolutional correction with its residual-test fallback */
-       KRY_PC_BILU0_LEARNED = 4, KRY_PC_CPR_LEARNED = 5 };
+       KRY_PC_BILU0_LEARNED = 4, KRY_PC_CPR_LEARNED = 5,
+       /* restricted additive Schwarz with block ILU(0) subdomain solves
+        * (Section 4.1): see SolverSetRAS */
+       KRY_PC_RAS = 6 };
 /* precision of the preconditioner apply (mixed-precision extension) */
 enum { KRY_PREC_F64 = 0, KRY_PREC_F32 = 1, KRY_PREC_BF16_FACTORS = 2 };
 /* CPR stage order (Section 4.2.1): PF = pressure then full (Algorithm 6,
@@ -126,6 +129,12 @@ MAT *MatCreateCSR(MAP *map, int32_t n, const int32_t *rowptr,
 MAT *MatCreateBSR(MAP *map, int32_t nb, int32_t bs, const int32_t *browptr,
                   const int32_t *bcol, const double *bval, int where);
 void MatDestroy(MAT **mat);
+/* New values for the same pattern (nnzb * bs * bs doubles in the block
+ * order of MatCreate*, host or device, copied): a Newton loop's next
+ * Jacobian.  A solver holding the matrix refactors at its next
+ * SolverAssemble, reusing what depends on the pattern only (the RAS
+ * subdomain patterns and tilings). */
+int  MatUpdateValues(MAT *A, const double *val, int where);
 /* The 7-point grid the pattern was recognised as (MatCreate checks every
  * row against the stencil in natural order cell = i + nx (j + ny k));
  * returns KRY_OK and the sizes, or KRY_ERR_ARG with zeros when the pattern
@@ -186,6 +195,16 @@ int  SolverSetAugk(SOLVER *s, int64_t k);
  * SolverSetStream: HIP stream (hipStream_t) for all work of the solver. */
 int SolverSetPrecision(SOLVER *s, int prec);
 int SolverSetCPR(SOLVER *s, int variant, int p_sweeps);
+/* Restricted additive Schwarz (Section 4.1, the RAS preconditioner, with
+ * ILU(0) as the local solver and the paper's default overlap of 1): the
+ * matrix must be a 7-point grid stencil in natural order (MatGetGrid); it
+ * is cut into nsub z-slabs of nz/nsub layers (owned rows), each grown by
+ * `overlap` layers on both sides, factored by block ILU(0) and swept on a
+ * stream of its own; the solution is written back on the owned rows only.
+ * FP64 only.  Defaults nsub = 4, overlap = 1; KRY_ERR_ARG for nsub < 1 or
+ * overlap < 0, and at SolverAssemble for nsub > nz; KRY_ERR_UNSUPPORTED
+ * for a matrix that is not a grid stencil or a reduced precision. */
+int SolverSetRAS(SOLVER *s, int nsub, int overlap);
 /* SolverSetSweepLayout: KRY_SWEEP_AUTO (default), KRY_SWEEP_LEVELS (generic
  * level-scheduled sweeps), or KRY_SWEEP_GRID (grid-tiled sweeps; assembly
  * fails with KRY_ERR_ARG if the matrix is not a 7-point grid stencil).

@@ -7,7 +7,7 @@ library's HIP kernels.  There is no fallback: importing this package fails
 when the library has not been built, and every call raises KrylovError
 when the library reports an error.
 
-Build with `python -m paper_1701_05913_amd.build` (or
+Build with `python paper_1701_05913_amd/build.py` (or
 `__graft_entry__.build()`).
 
 torch ships its own HIP runtime; the binding imports torch before it
@@ -32,7 +32,7 @@ KRY_HOST, KRY_DEVICE = 0, 1
 KRY_F64 = 0
 KRY_GMRES, KRY_FGMRES, KRY_BICGSTAB, KRY_CG = 0, 1, 2, 3
 KRY_PC_NONE, KRY_PC_ILU0, KRY_PC_BILU0, KRY_PC_CPR, KRY_PC_CUSTOM = 0, 1, 1, 2, 3
-KRY_PC_BILU0_LEARNED, KRY_PC_CPR_LEARNED = 4, 5
+KRY_PC_BILU0_LEARNED, KRY_PC_CPR_LEARNED, KRY_PC_RAS = 4, 5, 6
 KRY_PREC_F64, KRY_PREC_F32, KRY_PREC_BF16_FACTORS = 0, 1, 2
 KRY_CPR_PF, KRY_CPR_FP, KRY_CPR_FPF, KRY_CPR_FFPF = 0, 1, 2, 3
 KRY_SWEEP_AUTO, KRY_SWEEP_LEVELS, KRY_SWEEP_GRID = 0, 1, 2
@@ -45,7 +45,7 @@ class KrylovError(RuntimeError):
 
 
 if not os.path.exists(LIBRARY):
-    raise ImportError(f"{LIBRARY} is not built; run `python -m paper_1701_05913_amd.build`")
+    raise ImportError(f"{LIBRARY} is not built; run `python paper_1701_05913_amd/build.py`")
 
 # one HIP runtime per process: torch's, loaded before the library (the
 # library's own dependency then resolves to it)
@@ -66,6 +66,7 @@ _SIGS = {
     "MatCreateCSR": (P, [P, I32, P, P, P, C.c_int]),
     "MatCreateBSR": (P, [P, I32, I32, P, P, P, C.c_int]),
     "MatDestroy": (None, [C.POINTER(P)]), "MatVecMXY": (C.c_int, [P, P, P]),
+    "MatUpdateValues": (C.c_int, [P, P, C.c_int]),
     "MatVecAMXPBY": (C.c_int, [D, P, P, D, P]), "MatGetNnzBlocks": (I64, [P]),
     "MatGetGrid": (C.c_int, [P, C.POINTER(I32), C.POINTER(I32), C.POINTER(I32)]),
     "SolverCreate": (P, [C.c_int, C.c_int, P]),
@@ -80,6 +81,7 @@ _SIGS = {
     "SolverSetRestart": (C.c_int, [P, I64]), "SolverSetAugk": (C.c_int, [P, I64]),
     "SolverSetPrecision": (C.c_int, [P, C.c_int]),
     "SolverSetCPR": (C.c_int, [P, C.c_int, C.c_int]),
+    "SolverSetRAS": (C.c_int, [P, C.c_int, C.c_int]),
     "SolverSetSweepLayout": (C.c_int, [P, C.c_int]),
     "SolverSetStream": (C.c_int, [P, P]),
     "SolverGetResidual": (D, [P]), "SolverGetIters": (C.c_int, [P]),
@@ -243,6 +245,11 @@ def MatDestroy(a):
     _lib.MatDestroy(C.byref(h))
 
 
+def MatUpdateValues(a, val):
+    vp, w = _ptr(val, np.float64)
+    return _check(_lib.MatUpdateValues(a, vp, w))
+
+
 def MatVecMXY(a, x, y):
     return _check(_lib.MatVecMXY(a, x, y))
 
@@ -302,6 +309,7 @@ def SolverSetRestart(s, m): return _check(_lib.SolverSetRestart(s, m))
 def SolverSetAugk(s, k): return _check(_lib.SolverSetAugk(s, k))
 def SolverSetPrecision(s, p): return _check(_lib.SolverSetPrecision(s, p))
 def SolverSetCPR(s, variant, p_sweeps): return _check(_lib.SolverSetCPR(s, variant, p_sweeps))
+def SolverSetRAS(s, nsub, overlap): return _check(_lib.SolverSetRAS(s, nsub, overlap))
 def SolverSetSweepLayout(s, layout): return _check(_lib.SolverSetSweepLayout(s, layout))
 
 

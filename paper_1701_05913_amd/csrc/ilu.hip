@@ -554,13 +554,13 @@ static int sweep_pair(hipStream_t s, IluFactor &F, const TF *lval, const TF *uva
                       TC *y, const TIN *b, TO *xo, const TAI *add_in, TAO *add_out, int *err) {
     const dim3 grid((F.grid_waves + 3) / 4), block(256);
     {
-        TimedScope t(sweep_timer_name(true, BS, sizeof(TF), ADD), s);
+        TimedScope t(F.timer_fwd ? F.timer_fwd : sweep_timer_name(true, BS, sizeof(TF), ADD), s);
         hipLaunchKernelGGL((k_ilu_fwd<BS, TF, TC, TIN, TO>), grid, block, 0, s, F.L.nslices,
                            F.L.perm.p, F.L.off.p, F.L.col.p, lval, b, y, xo, F.ctr.p,
                            F.ctr.p + 1, err);
     }
     {
-        TimedScope t(sweep_timer_name(false, BS, sizeof(TF), ADD), s);
+        TimedScope t(F.timer_bwd ? F.timer_bwd : sweep_timer_name(false, BS, sizeof(TF), ADD), s);
         hipLaunchKernelGGL((k_ilu_bwd<BS, TF, TD, TC, TO, ADD, TAI, TAO>), grid, block, 0, s,
                            F.U.nslices, F.U.perm.p, F.U.off.p, F.U.col.p, uval, dinv, y, xo,
                            add_in, add_out, F.ctr.p + 1, F.ctr.p, err);

@@ -136,11 +136,11 @@ __global__ void k_grid_fill_sentinel(int64_t n, T *__restrict__ y) {
 // Lt = A_cn D_n^-1, Ut = the upper blocks of A, Dt = D_c^-1.  Positions in
 // the block rows follow from the cell's neighbours (one rowptr load per row).
 template <int BS>
-__global__ __launch_bounds__(64) void k_grid_factor(GridTiles G, const int *__restrict__ rowptr,
-                                                    const double *__restrict__ val,
-                                                    double *__restrict__ Lt, double *__restrict__ Ut,
-                                                    double *__restrict__ Dt, double *faces, int *ctr,
-                                                    int *err) {
+__device__ __forceinline__ void grid_factor_body(const GridTiles &G, const int *__restrict__ rowptr,
+                                                 const double *__restrict__ val,
+                                                 double *__restrict__ Lt, double *__restrict__ Ut,
+                                                 double *__restrict__ Dt, double *faces, int *ctr,
+                                                 int *err) {
     constexpr int B2 = BS * BS;
     const int lane = threadIdx.x;
     const int TJ = G.TJ, TK = G.TK, NF = G.NF, nx = G.nx, ny = G.ny, nz = G.nz, S = G.S;
@@ -274,6 +274,26 @@ __global__ __launch_bounds__(64) void k_grid_factor(GridTiles G, const int *__re
     }
 }
 
+template <int BS>
+__global__ __launch_bounds__(64) void k_grid_factor(GridTiles G, const int *__restrict__ rowptr,
+                                                    const double *__restrict__ val,
+                                                    double *__restrict__ Lt, double *__restrict__ Ut,
+                                                    double *__restrict__ Dt, double *faces, int *ctr,
+                                                    int *err) {
+    grid_factor_body<BS>(G, rowptr, val, Lt, Ut, Dt, faces, ctr, err);
+}
+
+// the factorizations of several independent grids in one launch: grid g
+// owns the workgroups [wg0, next wg0)
+template <int BS>
+__global__ __launch_bounds__(64) void k_grid_factor_multi(const FactorMulti *__restrict__ d,
+                                                          int ngrid, int *err) {
+    int g = 0;
+    while (g + 1 < ngrid && (int)blockIdx.x >= d[g + 1].wg0) g++;
+    const FactorMulti D = d[g];
+    grid_factor_body<BS>(D.G, D.rowptr, D.val, D.lt, D.ut, D.dt, D.faces, D.ctr, err);
+}
+
 // tiling of the (j, k) plane and the tile order (J + K diagonals)
 static int grid_tiling(const MAT_ *A, IluFactor &F) {
     GridTiles &G = F.G;
@@ -390,6 +410,63 @@ int ilu_grid_setup(hipStream_t s, const MAT_ *A, const double *lu, const double 
                            uinv, F.lt64.p, F.ut64.p, F.dt64.p);
     KRY_HIP(hipGetLastError());
     return grid_finish(s, A, F);
+}
+
+// Allocate a grid factor's tiling, planes, work buffers and tile counters
+// for a later factor launch (FP64 only): F is complete once a factor launch
+// on `faces` (sentinel-filled, steps * NF * bs^2) and `fctr` (zero) ran.
+int grid_factor_prepare(hipStream_t s, const MAT_ *A, IluFactor &F, DBuf<double> &faces,
+                        DBuf<int> &fctr) {
+    if (!ilu_grid_can_factor(A)) return set_error(KRY_ERR_ARG, "grid factorization needs nx, ny >= 3");
+    F.bs = A->bs;
+    F.nb = A->nb;
+    F.prec = KRY_PREC_F64;
+    F.nlev_f = F.nlev_b = A->gnx + A->gny + A->gnz - 2;
+    KRY_TRY(grid_tiling(A, F));
+    const GridTiles &G = F.G;
+    const int64_t steps = (int64_t)G.ntiles * G.S;
+    KRY_TRY(faces.alloc(steps * G.NF * A->bs * A->bs));
+    KRY_TRY(fctr.alloc(1));
+    KRY_TRY(F.ctr.alloc(2 * GRID_QUEUES));
+    KRY_HIP(hipMemsetAsync(F.ctr.p, 0, 2 * GRID_QUEUES * sizeof(int), s));
+    return grid_finish(s, A, F);
+}
+
+// re-arm the work buffers of a prepared factor before a factor launch
+int grid_factor_rearm(hipStream_t s, IluFactor &F, DBuf<double> &faces, DBuf<int> &fctr) {
+    KRY_HIP(hipMemsetAsync(F.ut64.p, 0, F.ut64.bytes(), s));
+    KRY_HIP(hipMemsetAsync(F.dt64.p, 0, F.dt64.bytes(), s));
+    hipLaunchKernelGGL(k_grid_fill_sentinel<double>, dim3(1024), dim3(256), 0, s,
+                       (int64_t)faces.n, faces.p);
+    KRY_HIP(hipMemsetAsync(fctr.p, 0, sizeof(int), s));
+    KRY_HIP(hipGetLastError());
+    return KRY_OK;
+}
+
+int grid_factor_desc(const MAT_ *A, const IluFactor &F, DBuf<double> &faces, DBuf<int> &fctr,
+                     int wg0, FactorMulti &d, int *wgs) {
+    d.G = F.G;
+    d.rowptr = A->rowptr.p;
+    d.val = A->val.p;
+    d.lt = F.lt64.p;
+    d.ut = F.ut64.p;
+    d.dt = F.dt64.p;
+    d.faces = faces.p;
+    d.ctr = fctr.p;
+    d.wg0 = wg0;
+    *wgs = std::min(F.G.ntiles, 1024);
+    return KRY_OK;
+}
+
+int grid_factor_multi(hipStream_t s, int bs, const FactorMulti *d_desc, int ngrid, int total_wgs,
+                      int *err) {
+    TimedScope t("ras_grid_factor", s);
+    if (bs == 1)
+        hipLaunchKernelGGL(k_grid_factor_multi<1>, dim3(total_wgs), dim3(64), 0, s, d_desc, ngrid, err);
+    else
+        hipLaunchKernelGGL(k_grid_factor_multi<3>, dim3(total_wgs), dim3(64), 0, s, d_desc, ngrid, err);
+    KRY_HIP(hipGetLastError());
+    return KRY_OK;
 }
 
 bool ilu_grid_can_factor(const MAT_ *A) {
@@ -563,10 +640,11 @@ __device__ void boundary_role(int S, int nx, int base, int lane, int NF, const T
 // backward sweep, last to first; -1 when the queue is empty.  Within a
 // queue the tiles come in dependency order and every queue is served by at
 // least one workgroup, so every taken tile's producers are running.
-__device__ __forceinline__ int next_tile(const GridTiles &G, int *ctr, int *tile, bool rev) {
+__device__ __forceinline__ int next_tile(const GridTiles &G, int *ctr, int *tile, bool rev,
+                                         int blk) {
     __syncthreads();
     if (threadIdx.x == 0) {
-        const int q = blockIdx.x % G.NQ;
+        const int q = blk % G.NQ;
         const int i = atomicAdd(ctr + q, 1);
         const int len = G.qoff[q + 1] - G.qoff[q];
         *tile = i < len ? G.qtiles[G.qoff[q] + (rev ? len - 1 - i : i)] : -1;
@@ -575,10 +653,12 @@ __device__ __forceinline__ int next_tile(const GridTiles &G, int *ctr, int *tile
     return *tile;
 }
 
+// forward sweep of one grid; blk = this workgroup's index within the grid's
+// workgroups (a multiple of GRID_QUEUES of them)
 template <int BS, typename TF, typename TC, typename TIN>
-__global__ __launch_bounds__(GWG) void k_grid_fwd(GridTiles G, const TF *__restrict__ Lt,
-                                                  const TIN *__restrict__ b, TC *yt, TC *ff,
-                                                  TC *fb, int *ctr, int *other_ctr, int *err) {
+__device__ __forceinline__ void grid_fwd_body(const GridTiles &G, const TF *__restrict__ Lt,
+                                              const TIN *__restrict__ b, TC *yt, TC *ff, TC *fb,
+                                              int *ctr, int *other_ctr, int *err, int blk) {
     constexpr int B2 = BS * BS, NM = 3 * B2, NV = NM + BS;
     constexpr int D = ring_depth<NV, TC>();
     __shared__ TC ring[D][NV][64];
@@ -587,7 +667,7 @@ __global__ __launch_bounds__(GWG) void k_grid_fwd(GridTiles G, const TF *__restr
     // wave-uniform role index (an SGPR), so the roles are real branches
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
-    if (blockIdx.x == 0 && (int)threadIdx.x < G.NQ) other_ctr[threadIdx.x] = 0;
+    if (blk == 0 && (int)threadIdx.x < G.NQ) other_ctr[threadIdx.x] = 0;
     if (threadIdx.x < D) full[threadIdx.x] = -1;
     if (threadIdx.x < DB) bfull[threadIdx.x] = -1;
     if (threadIdx.x == 0) {
@@ -604,7 +684,7 @@ __global__ __launch_bounds__(GWG) void k_grid_fwd(GridTiles G, const TF *__restr
         const int fk = kk == TK - 1 ? TK + jj : -1;
         const int oj = fj * BS, ok = fk * BS;
         for (int base = 0;; base += S) {
-            const int T = next_tile(G, ctr, &tile, false);
+            const int T = next_tile(G, ctr, &tile, false, blk);
             if (T < 0) break;
             TC *yrow = yt + (int64_t)T * S * BS * 64 + lane;
             TC *frow = ff + (int64_t)T * S * NF * BS;
@@ -677,7 +757,7 @@ __global__ __launch_bounds__(GWG) void k_grid_fwd(GridTiles G, const TF *__restr
         // ---- boundary: faces of tiles (J-1, K) and (J, K-1) ----
         const int f = lane % NF;
         for (int base = 0;; base += S) {
-            const int T = next_tile(G, ctr, &tile, false);
+            const int T = next_tile(G, ctr, &tile, false, blk);
             if (T < 0) break;
             const int JK = G.order[T];
             const int J = JK & 0xffff, K = JK >> 16;
@@ -699,7 +779,7 @@ __global__ __launch_bounds__(GWG) void k_grid_fwd(GridTiles G, const TF *__restr
         // ---- loaders: planes of steps w, w + NLOAD, ... ----
         const int w = wave - 2;
         for (int base = 0;; base += S) {
-            const int T = next_tile(G, ctr, &tile, false);
+            const int T = next_tile(G, ctr, &tile, false, blk);
             if (T < 0) break;
             const int JK = G.order[T];
             const int j = (JK & 0xffff) * TJ + jj, k = (JK >> 16) * TK + kk;
@@ -741,9 +821,9 @@ __global__ __launch_bounds__(GWG) void k_grid_fwd(GridTiles G, const TF *__restr
 }
 
 template <int BS, typename TF, typename TD, typename TC, typename TO>
-__global__ __launch_bounds__(GWG) void k_grid_bwd(GridTiles G, const TF *__restrict__ Ut,
-                                                  const TD *__restrict__ Dt, TC *yt, TC *fb,
-                                                  TC *ff, int *ctr, int *other_ctr, int *err) {
+__device__ __forceinline__ void grid_bwd_body(const GridTiles &G, const TF *__restrict__ Ut,
+                                              const TD *__restrict__ Dt, TC *yt, TC *fb, TC *ff,
+                                              int *ctr, int *other_ctr, int *err, int blk) {
     constexpr int B2 = BS * BS, NM = 3 * B2, NV = NM + B2 + BS;
     constexpr int D = ring_depth<NV, TC>();
     __shared__ TC ring[D][NV][64];
@@ -751,7 +831,7 @@ __global__ __launch_bounds__(GWG) void k_grid_bwd(GridTiles G, const TF *__restr
     __shared__ int full[D], bfull[DB], cons, bcons, tile;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
-    if (blockIdx.x == 0 && (int)threadIdx.x < G.NQ) other_ctr[threadIdx.x] = 0;
+    if (blk == 0 && (int)threadIdx.x < G.NQ) other_ctr[threadIdx.x] = 0;
     if (threadIdx.x < D) full[threadIdx.x] = -1;
     if (threadIdx.x < DB) bfull[threadIdx.x] = -1;
     if (threadIdx.x == 0) {
@@ -767,7 +847,7 @@ __global__ __launch_bounds__(GWG) void k_grid_bwd(GridTiles G, const TF *__restr
         const int fk = kk == 0 ? TK + jj : -1;
         const int oj = fj * BS, ok = fk * BS;
         for (int base = 0;; base += S) {
-            const int T = next_tile(G, ctr, &tile, true);   // reverse tile order
+            const int T = next_tile(G, ctr, &tile, true, blk);   // reverse tile order
             if (T < 0) break;
             TC *yrow = yt + (int64_t)T * S * BS * 64 + lane;
             TC *frow = fb + (int64_t)T * S * NF * BS;
@@ -844,7 +924,7 @@ __global__ __launch_bounds__(GWG) void k_grid_bwd(GridTiles G, const TF *__restr
         // ---- boundary: faces of tiles (J+1, K) and (J, K+1) ----
         const int f = lane % NF;
         for (int base = 0;; base += S) {
-            const int T = next_tile(G, ctr, &tile, true);
+            const int T = next_tile(G, ctr, &tile, true, blk);
             if (T < 0) break;
             const int JK = G.order[T];
             const int J = JK & 0xffff, K = JK >> 16;
@@ -866,7 +946,7 @@ __global__ __launch_bounds__(GWG) void k_grid_bwd(GridTiles G, const TF *__restr
         // ---- loaders: U blocks, diagonal inverse, forward result ----
         const int w = wave - 2;
         for (int base = 0;; base += S) {
-            const int T = next_tile(G, ctr, &tile, true);
+            const int T = next_tile(G, ctr, &tile, true, blk);
             if (T < 0) break;
             const TF *ub = Ut + (int64_t)T * S * NM * 64 + lane;
             const TD *db = Dt + (int64_t)T * S * B2 * 64 + lane;
@@ -907,13 +987,17 @@ __global__ __launch_bounds__(GWG) void k_grid_bwd(GridTiles G, const TF *__restr
 // Copy the tile-step-major result to natural order, with the caller's
 // epilogue (the add modes of ilu_apply): one block per (tile, 8 steps),
 // reads in contiguous 64-lane rows.
+// natural-order copy of the tile-step result of one grid with the fused
+// epilogue; only cells c in [c0, c1) are written (all of them for a whole
+// grid; a subdomain's owned rows under RAS)
 template <int BS, typename TC, typename TO, int ADD, typename TAI, typename TAO>
-__global__ __launch_bounds__(256) void k_grid_untile(GridTiles G, const TC *__restrict__ yt,
-                                                     TO *__restrict__ xo,
-                                                     const TAI *__restrict__ add_in,
-                                                     TAO *__restrict__ add_out) {
+__device__ __forceinline__ void grid_untile_body(const GridTiles &G, const TC *__restrict__ yt,
+                                                 TO *__restrict__ xo,
+                                                 const TAI *__restrict__ add_in,
+                                                 TAO *__restrict__ add_out, int64_t c0,
+                                                 int64_t c1, int blk) {
     const int nchunk = (G.S + 7) / 8;
-    const int T = blockIdx.x / nchunk, t0 = (blockIdx.x % nchunk) * 8;
+    const int T = blk / nchunk, t0 = (blk % nchunk) * 8;
     const int lane = threadIdx.x & 63;
     const int JK = G.order[T];
     const int jj = lane % G.TJ, kk = lane / G.TJ;
@@ -924,6 +1008,7 @@ __global__ __launch_bounds__(256) void k_grid_untile(GridTiles G, const TC *__re
         const int i = t - jj - kk;
         if (i < 0 || i >= G.nx) continue;
         const int64_t c = cl + i;
+        if (c < c0 || c >= c1) continue;
         const TC *src = yt + ((int64_t)T * G.S + t) * BS * 64 + lane;
 #pragma unroll
         for (int r = 0; r < BS; r++) {
@@ -936,6 +1021,120 @@ __global__ __launch_bounds__(256) void k_grid_untile(GridTiles G, const TC *__re
             }
         }
     }
+}
+
+template <int BS, typename TF, typename TC, typename TIN>
+__global__ __launch_bounds__(GWG) void k_grid_fwd(GridTiles G, const TF *__restrict__ Lt,
+                                                  const TIN *__restrict__ b, TC *yt, TC *ff,
+                                                  TC *fb, int *ctr, int *other_ctr, int *err) {
+    grid_fwd_body<BS, TF, TC, TIN>(G, Lt, b, yt, ff, fb, ctr, other_ctr, err, blockIdx.x);
+}
+
+template <int BS, typename TF, typename TD, typename TC, typename TO>
+__global__ __launch_bounds__(GWG) void k_grid_bwd(GridTiles G, const TF *__restrict__ Ut,
+                                                  const TD *__restrict__ Dt, TC *yt, TC *fb,
+                                                  TC *ff, int *ctr, int *other_ctr, int *err) {
+    grid_bwd_body<BS, TF, TD, TC, TO>(G, Ut, Dt, yt, fb, ff, ctr, other_ctr, err, blockIdx.x);
+}
+
+template <int BS, typename TC, typename TO, int ADD, typename TAI, typename TAO>
+__global__ __launch_bounds__(256) void k_grid_untile(GridTiles G, const TC *__restrict__ yt,
+                                                     TO *__restrict__ xo,
+                                                     const TAI *__restrict__ add_in,
+                                                     TAO *__restrict__ add_out) {
+    grid_untile_body<BS, TC, TO, ADD, TAI, TAO>(G, yt, xo, add_in, add_out, 0, INT64_MAX,
+                                                blockIdx.x);
+}
+
+// ---------------------------------------------------------------------------
+// several independent grids in one launch (the subdomains of RAS): grid g
+// owns the workgroups [wg0, wg0 + wgs) of each kernel (multiples of
+// GRID_QUEUES, so a workgroup's queue, and XCD, keep their mapping)
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int find_grid(const GridMulti *__restrict__ d, int ngrid, int blk,
+                                         int GridMulti::*wg0) {
+    int g = 0;
+    while (g + 1 < ngrid && blk >= d[g + 1].*wg0) g++;
+    return g;
+}
+
+template <int BS>
+__global__ __launch_bounds__(GWG) void k_grid_fwd_multi(const GridMulti *__restrict__ d, int ngrid,
+                                                        const double *__restrict__ v, int *err) {
+    const int g = find_grid(d, ngrid, blockIdx.x, &GridMulti::wg0);
+    const GridMulti D = d[g];
+    grid_fwd_body<BS, double, double, double>(D.G, D.lt, v + D.boff, D.yt, D.ff, D.fb, D.ctr,
+                                              D.ctr + D.G.NQ, err, blockIdx.x - D.wg0);
+}
+
+template <int BS>
+__global__ __launch_bounds__(GWG) void k_grid_bwd_multi(const GridMulti *__restrict__ d, int ngrid,
+                                                        int *err) {
+    const int g = find_grid(d, ngrid, blockIdx.x, &GridMulti::wg0);
+    const GridMulti D = d[g];
+    grid_bwd_body<BS, double, double, double, double>(D.G, D.ut, D.dt, D.yt, D.fb, D.ff,
+                                                      D.ctr + D.G.NQ, D.ctr, err,
+                                                      blockIdx.x - D.wg0);
+}
+
+template <int BS>
+__global__ __launch_bounds__(256) void k_grid_untile_multi(const GridMulti *__restrict__ d,
+                                                           int ngrid, double *__restrict__ z) {
+    const int g = find_grid(d, ngrid, blockIdx.x, &GridMulti::ub0);
+    const GridMulti D = d[g];
+    grid_untile_body<BS, double, double, 0, double, double>(
+        D.G, D.yt, z + D.boff, nullptr, nullptr, D.own0, D.own1, blockIdx.x - D.ub0);
+}
+
+int grid_multi_launch_size(const IluFactor &F, int *wgs, int *untile_blocks) {
+    if (!F.grid) return set_error(KRY_ERR_ARG, "grid_multi: not a grid-tiled factor");
+    *wgs = F.G.NQ * std::max(1, std::min(F.G.qmax, 512 / F.G.NQ));
+    *untile_blocks = F.G.ntiles * ((F.G.S + 7) / 8);
+    return KRY_OK;
+}
+
+int grid_multi_desc(const IluFactor &F, int64_t boff, int64_t own0, int64_t own1, int wg0,
+                    int ub0, GridMulti &d) {
+    if (!F.grid || F.prec != KRY_PREC_F64)
+        return set_error(KRY_ERR_ARG, "grid_multi: needs an FP64 grid-tiled factor");
+    d.G = F.G;
+    d.lt = F.lt64.p;
+    d.ut = F.ut64.p;
+    d.dt = F.dt64.p;
+    d.yt = F.yt64.p;
+    d.ff = F.ff64.p;
+    d.fb = F.fb64.p;
+    d.ctr = F.ctr.p;
+    d.boff = boff;
+    d.own0 = own0;
+    d.own1 = own1;
+    d.wg0 = wg0;
+    d.ub0 = ub0;
+    return KRY_OK;
+}
+
+int grid_multi_apply(hipStream_t s, int bs, const GridMulti *d_desc, int ngrid, int total_wgs,
+                     int total_untile, const double *v, double *z, int *err) {
+    {
+        TimedScope t("ras_ilu_fwd", s);
+        if (bs == 1)
+            hipLaunchKernelGGL(k_grid_fwd_multi<1>, dim3(total_wgs), dim3(GWG), 0, s, d_desc, ngrid, v, err);
+        else
+            hipLaunchKernelGGL(k_grid_fwd_multi<3>, dim3(total_wgs), dim3(GWG), 0, s, d_desc, ngrid, v, err);
+    }
+    {
+        TimedScope t("ras_ilu_bwd", s);
+        if (bs == 1)
+            hipLaunchKernelGGL(k_grid_bwd_multi<1>, dim3(total_wgs), dim3(GWG), 0, s, d_desc, ngrid, err);
+        else
+            hipLaunchKernelGGL(k_grid_bwd_multi<3>, dim3(total_wgs), dim3(GWG), 0, s, d_desc, ngrid, err);
+    }
+    if (bs == 1)
+        hipLaunchKernelGGL(k_grid_untile_multi<1>, dim3(total_untile), dim3(256), 0, s, d_desc, ngrid, z);
+    else
+        hipLaunchKernelGGL(k_grid_untile_multi<3>, dim3(total_untile), dim3(256), 0, s, d_desc, ngrid, z);
+    KRY_HIP(hipGetLastError());
+    return KRY_OK;
 }
 
 // ---------------------------------------------------------------------------
@@ -951,12 +1150,12 @@ static int grid_pair(hipStream_t s, IluFactor &F, const TF *lt, const TF *ut, co
     // the cap, and always at least one
     const int wgs = F.G.NQ * std::max(1, std::min(F.G.qmax, 512 / F.G.NQ));
     {
-        TimedScope t(sweep_timer_name(true, BS, sizeof(TF), ADD), s);
+        TimedScope t(F.timer_fwd ? F.timer_fwd : sweep_timer_name(true, BS, sizeof(TF), ADD), s);
         hipLaunchKernelGGL((k_grid_fwd<BS, TF, TC, TIN>), dim3(wgs), dim3(GWG), 0, s, F.G, lt, b,
                            yt, ff, fb, F.ctr.p, F.ctr.p + F.G.NQ, err);
     }
     {
-        TimedScope t(sweep_timer_name(false, BS, sizeof(TF), 0), s);
+        TimedScope t(F.timer_bwd ? F.timer_bwd : sweep_timer_name(false, BS, sizeof(TF), 0), s);
         hipLaunchKernelGGL((k_grid_bwd<BS, TF, TD, TC, TO>), dim3(wgs), dim3(GWG), 0, s, F.G, ut,
                            dt, yt, fb, ff, F.ctr.p + F.G.NQ, F.ctr.p, err);
     }

@@ -218,6 +218,9 @@ struct GridTiles {
 
 struct IluFactor {
     int bs = 1, nb = 0;
+    // timer names of this factor's sweeps: nullptr = the per-kind names of
+    // sweep_timer_name; a subdomain factor reports under its own names
+    const char *timer_fwd = nullptr, *timer_bwd = nullptr;
     int prec = KRY_PREC_F64;
     int nlev_f = 0, nlev_b = 0;
     Sell L;                 // forward order, strictly lower blocks
@@ -284,6 +287,80 @@ struct CprPC {
     IluFactor ilu_a;        // block ILU(0) of A
     DBuf<char> work;        // scratch vectors
 };
+// One grid of a multi-grid sweep launch (the subdomains of RAS): its tiling,
+// FP64 factor planes and work buffers, its tile counters (GRID_QUEUES
+// forward, then backward), the offset of its rows in the caller's vectors,
+// its output rows [own0, own1) (local numbering) and its first workgroup in
+// the sweep and untile launches.
+struct GridMulti {
+    GridTiles G;
+    const double *lt, *ut, *dt;
+    double *yt, *ff, *fb;
+    int *ctr;
+    int64_t boff, own0, own1;
+    int wg0, ub0;
+};
+int grid_multi_launch_size(const IluFactor &F, int *wgs, int *untile_blocks);
+int grid_multi_desc(const IluFactor &F, int64_t boff, int64_t own0, int64_t own1, int wg0,
+                    int ub0, GridMulti &d);
+// every grid's forward sweep of v + boff, backward sweep, and untile of
+// rows [own0, own1) into z + boff, in three launches on s
+int grid_multi_apply(hipStream_t s, int bs, const GridMulti *d_desc, int ngrid, int total_wgs,
+                     int total_untile, const double *v, double *z, int *err);
+
+// One grid of a multi-grid factor launch: its tiling, matrix, FP64 planes,
+// face buffer and tile counter, and its first workgroup.
+struct FactorMulti {
+    GridTiles G;
+    const int *rowptr;
+    const double *val;
+    double *lt, *ut, *dt, *faces;
+    int *ctr;
+    int wg0;
+};
+int grid_factor_prepare(hipStream_t s, const MAT_ *A, IluFactor &F, DBuf<double> &faces,
+                        DBuf<int> &fctr);
+int grid_factor_rearm(hipStream_t s, IluFactor &F, DBuf<double> &faces, DBuf<int> &fctr);
+int grid_factor_desc(const MAT_ *A, const IluFactor &F, DBuf<double> &faces, DBuf<int> &fctr,
+                     int wg0, FactorMulti &d, int *wgs);
+int grid_factor_multi(hipStream_t s, int bs, const FactorMulti *d_desc, int ngrid, int total_wgs,
+                      int *err);
+
+// matrix from device-resident block CSR arrays (pattern validated and grid
+// detected as for MatCreate*)
+MAT *mat_create_device(MAP *map, int nb, int bs, const int *rowptr, const int *col,
+                       const double *val);
+
+// restricted additive Schwarz: z-slab subdomains of a 7-point grid matrix,
+// block ILU(0) on each overlapped slab
+struct RasSub {
+    int lo = 0, hi = 0, o0 = 0, o1 = 0;   // overlapped / owned block rows
+    MAP *map = nullptr;
+    MAT *A = nullptr;
+    IluFactor F;
+    DBuf<int> pos;                        // A's value blocks of the subdomain matrix
+    DBuf<double> faces;                   // grid factorization work buffers
+    DBuf<int> fctr;
+    DBuf<double> x;                       // local solution (non-grid subdomains)
+};
+struct RasPC {
+    int nsub = 0, overlap = 1, bs = 1, layout = 0;
+    const MAT_ *A = nullptr;              // the matrix whose pattern the subdomains hold
+    std::vector<std::unique_ptr<RasSub>> subs;
+    bool multi = false;                   // all subdomains grid-tiled: one launch per sweep
+    DBuf<GridMulti> desc;
+    DBuf<FactorMulti> fdesc;
+    int wgs = 0, untile_blocks = 0, factor_wgs = 0;
+    ~RasPC();
+};
+// symbolic setup (subdomain patterns, tilings, buffers) and the numeric
+// factorization; ras_refactor repeats only the latter for new values of the
+// same matrix
+int ras_setup(hipStream_t s, MAT_ *A, RasPC &R, int nsub, int overlap, int prec, int *d_err,
+              int layout);
+int ras_refactor(hipStream_t s, const MAT_ *A, RasPC &R, int *d_err);
+int ras_apply(hipStream_t s, RasPC &R, const double *v, double *z, int *d_err);
+
 int cpr_setup(hipStream_t s, MAT_ *A, CprPC &C, int variant, int sweeps,
               int prec, int *d_err, int layout);
 int cpr_apply(hipStream_t s, MAT_ *A, CprPC &C, const double *v, double *z,
@@ -327,6 +404,8 @@ struct SOLVER_ {
     void *cdata = nullptr;
     std::unique_ptr<kry::IluFactor> ilu;
     std::unique_ptr<kry::CprPC> cpr;
+    std::unique_ptr<kry::RasPC> ras;
+    int ras_nsub = 4, ras_overlap = 1;
     std::unique_ptr<kry::LearnedStage, kry::LearnedStageDeleter> learned;
     std::vector<float> learned_params;     // host copy until assembly
     kry::DBuf<float> learned_lnk;          // ln k per cell

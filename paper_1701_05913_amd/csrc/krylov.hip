@@ -684,6 +684,8 @@ int pc_apply(SOLVER_ *S, const double *v, double *z) {
     case KRY_PC_CPR_LEARNED:
         KRY_TRY(cpr_apply(S->stream, S->A, *S->cpr, v, z, S->err.p));
         return learned_stage_apply(S->stream, S->A, *S->learned, v, z);
+    case KRY_PC_RAS:
+        return ras_apply(S->stream, *S->ras, v, z, S->err.p);
     case KRY_PC_CUSTOM: {
         VEC_ vv, zz;
         vv.map = zz.map = S->map;
@@ -950,7 +952,7 @@ extern "C" SOLVER *SolverCreate(int solver_type, int pc_type, MAP *map) {
         set_error(KRY_ERR_UNSUPPORTED, "SolverCreate: solver type %d", solver_type);
         return nullptr;
     }
-    if (pc_type < KRY_PC_NONE || pc_type > KRY_PC_CPR_LEARNED) {
+    if (pc_type < KRY_PC_NONE || pc_type > KRY_PC_RAS) {
         set_error(KRY_ERR_UNSUPPORTED, "SolverCreate: preconditioner type %d", pc_type);
         return nullptr;
     }
@@ -981,6 +983,7 @@ extern "C" int SolverSetMat(SOLVER *s, MAT *A) {
     if (!s || !A) return set_error(KRY_ERR_ARG, "SolverSetMat: NULL argument");
     if ((int64_t)A->nb * A->bs != s->map->nlocal) return set_error(KRY_ERR_DIM, "SolverSetMat: size mismatch");
     s->A = A;
+    s->ras.reset();   // subdomain patterns belong to the previous matrix
     s->assembled = false;
     return KRY_OK;
 }
@@ -1035,6 +1038,13 @@ extern "C" int SolverSetCPR(SOLVER *s, int variant, int p_sweeps) {
     s->assembled = false;
     return KRY_OK;
 }
+extern "C" int SolverSetRAS(SOLVER *s, int nsub, int overlap) {
+    if (!s || nsub < 1 || overlap < 0) return set_error(KRY_ERR_ARG, "SolverSetRAS: bad argument");
+    s->ras_nsub = nsub;
+    s->ras_overlap = overlap;
+    s->assembled = false;
+    return KRY_OK;
+}
 extern "C" int SolverSetSweepLayout(SOLVER *s, int layout) {
     if (!s || layout < KRY_SWEEP_AUTO || layout > KRY_SWEEP_GRID)
         return set_error(KRY_ERR_ARG, "SolverSetSweepLayout: bad argument");
@@ -1077,6 +1087,11 @@ extern "C" int SolverAssemble(SOLVER *s) {
     hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(64), 0, s->stream, s->err.p);
     s->ilu.reset();
     s->cpr.reset();
+    // RAS keeps its subdomain patterns when the matrix and options are unchanged
+    const bool ras_reuse = s->pc_type == KRY_PC_RAS && s->ras && s->ras->A == s->A &&
+                           s->ras->nsub == s->ras_nsub && s->ras->overlap == s->ras_overlap &&
+                           s->ras->layout == s->sweep_layout && s->prec == KRY_PREC_F64;
+    if (!ras_reuse) s->ras.reset();
     s->learned.reset();
     switch (s->pc_type) {
     case KRY_PC_NONE:
@@ -1091,6 +1106,19 @@ extern "C" int SolverAssemble(SOLVER *s) {
         s->cpr.reset(new CprPC());
         KRY_TRY(cpr_setup(s->stream, s->A, *s->cpr, s->cpr_variant, s->cpr_sweeps, s->prec, s->err.p,
                           s->sweep_layout));
+        break;
+    case KRY_PC_RAS:
+        if (ras_reuse) {
+            KRY_TRY(ras_refactor(s->stream, s->A, *s->ras, s->err.p));
+        } else {
+            s->ras.reset(new RasPC());
+            const int rc = ras_setup(s->stream, s->A, *s->ras, s->ras_nsub, s->ras_overlap, s->prec,
+                                     s->err.p, s->sweep_layout);
+            if (rc < 0) {
+                s->ras.reset();
+                return rc;
+            }
+        }
         break;
     case KRY_PC_CUSTOM:
         if (!s->csolve) return set_error(KRY_ERR_ARG, "custom preconditioner not set");

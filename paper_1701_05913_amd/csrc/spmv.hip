@@ -380,6 +380,11 @@ static MAT *mat_create(MAP *map, int32_t nb, int32_t bs, const int32_t *rowptr,
     return A.release();
 }
 
+MAT *mat_create_device(MAP *map, int nb, int bs, const int *rowptr, const int *col,
+                       const double *val) {
+    return mat_create(map, nb, bs, rowptr, col, val, KRY_DEVICE);
+}
+
 }  // namespace kry
 
 using namespace kry;
@@ -392,6 +397,24 @@ extern "C" MAT *MatCreateCSR(MAP *map, int32_t n, const int32_t *rowptr, const i
 extern "C" MAT *MatCreateBSR(MAP *map, int32_t nb, int32_t bs, const int32_t *browptr,
                              const int32_t *bcol, const double *bval, int where) {
     return mat_create(map, nb, bs, browptr, bcol, bval, where);
+}
+
+extern "C" int MatUpdateValues(MAT *A, const double *val, int where) {
+    if (!A || !val) return set_error(KRY_ERR_ARG, "MatUpdateValues: NULL argument");
+    if (where != KRY_HOST && where != KRY_DEVICE)
+        return set_error(KRY_ERR_ARG, "MatUpdateValues: where must be KRY_HOST or KRY_DEVICE");
+    hipStream_t s = global_stream();
+    const size_t bytes = sizeof(double) * (size_t)A->nnzb * A->bs * A->bs;
+    KRY_HIP(hipMemcpyAsync(A->val.p, val, bytes,
+                           where == KRY_HOST ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice, s));
+    // the SpMV layout holds its own copy of the values; reduced-precision
+    // copies are rebuilt on demand
+    KRY_TRY(sell_build(s, A));
+    A->sell.valf.release();
+    A->sell.valh.release();
+    A->col0f.release();
+    KRY_HIP(hipStreamSynchronize(s));
+    return KRY_OK;
 }
 
 extern "C" void MatDestroy(MAT **mat) {

@@ -43,7 +43,8 @@ class GpuSystem:
 
 
 def make_solver(g, solver, pc, rtol=1e-8, maxit=5000, restart=30,
-                prec=K.KRY_PREC_F64, cpr=(K.KRY_CPR_PF, 4), layout=K.KRY_SWEEP_AUTO, aug_k=0):
+                prec=K.KRY_PREC_F64, cpr=(K.KRY_CPR_PF, 4), layout=K.KRY_SWEEP_AUTO, aug_k=0,
+                ras=(4, 1)):
     S = K.SolverCreate(solver, pc, g.map)
     K.SolverSetSweepLayout(S, layout)
     K.SolverSetMat(S, g.A)
@@ -54,6 +55,8 @@ def make_solver(g, solver, pc, rtol=1e-8, maxit=5000, restart=30,
     K.SolverSetPrecision(S, prec)
     if pc == K.KRY_PC_CPR:
         K.SolverSetCPR(S, cpr[0], cpr[1])
+    if pc == K.KRY_PC_RAS:
+        K.SolverSetRAS(S, ras[0], ras[1])
     K.SolverSetStream(S, torch.cuda.current_stream())
     return S
 
@@ -74,8 +77,8 @@ def solve(g, solver, pc, b=None, x0=None, **kw):
 
 
 def pc_apply(g, pc, v, prec=K.KRY_PREC_F64, cpr=(K.KRY_CPR_PF, 4), solver=K.KRY_FGMRES,
-             layout=K.KRY_SWEEP_AUTO, repeat=1):
-    S = make_solver(g, solver, pc, prec=prec, cpr=cpr, layout=layout)
+             layout=K.KRY_SWEEP_AUTO, repeat=1, ras=(4, 1)):
+    S = make_solver(g, solver, pc, prec=prec, cpr=cpr, layout=layout, ras=ras)
     try:
         K.SolverAssemble(S)
         vt, vh = g.vec(v)

@@ -22,7 +22,7 @@ if not torch.cuda.is_available():
 
 import paper_1701_05913_amd as K  # noqa: E402
 from tests._helpers import bsr_from_dense  # noqa: E402
-from tests.gpu_helpers import GpuSystem, pc_apply, relerr, solve  # noqa: E402
+from tests.gpu_helpers import GpuSystem, make_solver, pc_apply, relerr, solve  # noqa: E402
 
 SMALL_SCALAR = (37, 29, 23)     # 24 679 rows: many slices, ragged tail
 SMALL_BLOCK = (13, 11, 9)       # 1 287 block rows, ragged tail
@@ -398,6 +398,139 @@ def test_augk_argument_checks():
         K.SolverSetAugk(S, 2)
         with pytest.raises(K.KrylovError):
             K.SolverAssemble(S)
+        K.SolverDestroy(S)
+    finally:
+        g.close()
+
+
+# ---- restricted additive Schwarz (z-slab subdomains, block ILU(0)) -----------------
+def _slab_starts(grid, nsub):
+    nx, ny, nz = grid
+    return [q * nz // nsub * nx * ny for q in range(nsub + 1)]
+
+
+@pytest.mark.parametrize("grid,nsub,overlap", [((13, 11, 9), 2, 1), ((13, 11, 9), 3, 0),
+                                               ((13, 11, 9), 3, 2), ((13, 11, 9), 9, 0),
+                                               ((32, 32, 16), 4, 1), ((32, 32, 16), 4, 2)])
+def test_ras_apply_parity(grid, nsub, overlap):
+    s = ri.blackoil_system(*grid, seed=8)
+    A = oracle.Matrix.from_system(s)
+    v = np.random.default_rng(9).standard_normal(A.n)
+    ref = oracle.PC.ras(A, _slab_starts(grid, nsub), overlap).apply(v)
+    g = GpuSystem(s)
+    try:
+        zs = pc_apply(g, K.KRY_PC_RAS, v, ras=(nsub, overlap), repeat=2)
+    finally:
+        g.close()
+    # a second apply on the same subdomain streams and buffers repeats the first
+    assert np.array_equal(zs[0], zs[1])
+    z = zs[1]
+    assert relerr(z, ref) <= 1e-10
+    # RAS really differs from global BILU(0) when there is more than one slab
+    assert relerr(z, oracle.PC(A, "bilu0").apply(v)) > 1e-8
+
+
+def test_ras_scalar_grid_parity():
+    grid = (16, 12, 10)
+    s = ri.scalar_system(*grid, seed=3)
+    A = oracle.Matrix.from_system(s)
+    v = np.random.default_rng(10).standard_normal(A.n)
+    ref = oracle.PC.ras(A, _slab_starts(grid, 3), 1).apply(v)
+    g = GpuSystem(s)
+    try:
+        z = pc_apply(g, K.KRY_PC_RAS, v, ras=(3, 1))
+    finally:
+        g.close()
+    assert relerr(z, ref) <= 1e-10
+
+
+@pytest.mark.parametrize("solver", [K.KRY_GMRES, K.KRY_FGMRES])
+def test_ras_solve(solver):
+    grid = (32, 32, 16)
+    s = ri.blackoil_system(*grid, seed=11)
+    A = oracle.Matrix.from_system(s)
+    g = GpuSystem(s)
+    try:
+        gpu = solve(g, solver, K.KRY_PC_RAS, rtol=1e-8, maxit=3000, ras=(4, 1))
+    finally:
+        g.close()
+    _check_solve(s, gpu, A, oracle.PC.ras(A, _slab_starts(grid, 4), 1), 1e-8, oracle.gmres,
+                 restart=30, maxit=3000, flexible=solver == K.KRY_FGMRES)
+
+
+def test_ras_errors():
+    s = ri.blackoil_system(6, 5, 4, seed=1)
+    g = GpuSystem(s)
+    try:
+        for ras, prec in (((5, 1), K.KRY_PREC_F64), ((2, 1), K.KRY_PREC_F32)):
+            S = K.SolverCreate(K.KRY_FGMRES, K.KRY_PC_RAS, g.map)
+            K.SolverSetMat(S, g.A)
+            K.SolverSetRAS(S, *ras)
+            K.SolverSetPrecision(S, prec)
+            with pytest.raises(K.KrylovError):
+                K.SolverAssemble(S)
+            K.SolverDestroy(S)
+        S = K.SolverCreate(K.KRY_FGMRES, K.KRY_PC_RAS, g.map)
+        for bad in ((0, 1), (2, -1)):
+            with pytest.raises(K.KrylovError):
+                K.SolverSetRAS(S, *bad)
+        K.SolverDestroy(S)
+    finally:
+        g.close()
+    # a matrix that is not a grid stencil
+    D = np.diag([4.0, 5.0, 6.0, 7.0])
+    D[0, 3] = D[3, 0] = -1.0
+    g = GpuSystem(bsr_from_dense(D, 1))
+    try:
+        S = K.SolverCreate(K.KRY_FGMRES, K.KRY_PC_RAS, g.map)
+        K.SolverSetMat(S, g.A)
+        K.SolverSetRAS(S, 1, 1)
+        with pytest.raises(K.KrylovError) as e:
+            K.SolverAssemble(S)
+        assert e.value.code == K.KRY_ERR_UNSUPPORTED
+        K.SolverDestroy(S)
+    finally:
+        g.close()
+
+
+def test_ras_refactor_after_value_update():
+    # SolverAssemble after MatUpdateValues reuses the subdomain patterns and
+    # refactors with the new values
+    grid = (16, 12, 12)
+    s = ri.blackoil_system(*grid, seed=12)
+    A = oracle.Matrix.from_system(s)
+    v = np.random.default_rng(13).standard_normal(A.n)
+    starts = _slab_starts(grid, 3)
+    g = GpuSystem(s)
+    try:
+        S = make_solver(g, K.KRY_FGMRES, K.KRY_PC_RAS, ras=(3, 1))
+        vt, vh = g.vec(v)
+        zt, zh = g.vec()
+        K.SolverAssemble(S)
+        K.SolverPCApply(S, vh, zh)
+        torch.cuda.synchronize()
+        assert relerr(zt.cpu().numpy(), oracle.PC.ras(A, starts, 1).apply(v)) <= 1e-10
+        # new values, same pattern: scaled, with a heavier diagonal
+        val2 = s["val"].reshape(-1, 9).copy() * 1.5
+        diag = np.zeros(val2.shape[0], dtype=bool)
+        for i in range(A.nb):
+            for q in range(s["rowptr"][i], s["rowptr"][i + 1]):
+                if s["col"][q] == i:
+                    diag[q] = True
+        val2[np.ix_(np.flatnonzero(diag), [0, 4, 8])] += 2.0
+        K.MatUpdateValues(g.A, val2.reshape(-1))
+        K.SolverAssemble(S)
+        K.SolverPCApply(S, vh, zh)
+        torch.cuda.synchronize()
+        A2 = oracle.Matrix(s["rowptr"], s["col"], val2.reshape(-1), 3)
+        z2 = zt.cpu().numpy()
+        assert relerr(z2, oracle.PC.ras(A2, starts, 1).apply(v)) <= 1e-10
+        assert relerr(z2, oracle.PC.ras(A, starts, 1).apply(v)) > 1e-3
+        # and the matrix itself now multiplies with the new values
+        xt, xh = g.vec()
+        K.MatVecMXY(g.A, vh, xh)
+        torch.cuda.synchronize()
+        assert relerr(xt.cpu().numpy(), oracle.spmv(A2, v)) <= 1e-13
         K.SolverDestroy(S)
     finally:
         g.close()
