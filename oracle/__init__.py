@@ -57,6 +57,10 @@ def load(path: str):
     L.or_pc_create_learned.argtypes = [P, I, I, I, P, P, I]
     L.or_pc_create_ras.argtypes = [I, I, P, P, P, I, P, I, C.POINTER(I)]
     L.or_pc_create_ras.restype = P
+    L.or_pc_create_ras_part.argtypes = [I, I, P, P, P, I, P, I, C.POINTER(I)]
+    L.or_pc_create_ras_part.restype = P
+    L.or_pc_create_ras_sets.argtypes = [I, I, P, P, P, I, P, P, P, C.POINTER(I)]
+    L.or_pc_create_ras_sets.restype = P
     L.or_pc_create_learned.restype = P
     L.or_pc_apply.argtypes = [P, P, P]
     L.or_pc_destroy.argtypes = [P]
@@ -232,6 +236,39 @@ class PC:
         err = C.c_int(0)
         obj.h = lib().or_pc_create_ras(*A.args(), int(st.size - 1), _p(st), int(overlap),
                                        C.byref(err))
+        obj.err = err.value
+        if not obj.h:
+            raise RuntimeError(f"oracle RAS setup failed: {obj.err}")
+        return obj
+
+    @classmethod
+    def ras_part(cls, A: "Matrix", part, overlap=1):
+        """RAS with block row r owned by subdomain part[r]."""
+        obj = cls.__new__(cls)
+        obj.A = A
+        pa = _i32(part)
+        obj._part = pa
+        err = C.c_int(0)
+        obj.h = lib().or_pc_create_ras_part(*A.args(), int(pa.max()) + 1, _p(pa), int(overlap),
+                                            C.byref(err))
+        obj.err = err.value
+        if not obj.h:
+            raise RuntimeError(f"oracle RAS setup failed: {obj.err}")
+        return obj
+
+    @classmethod
+    def ras_sets(cls, A: "Matrix", part, sets):
+        """RAS with block row r owned by part[r] and subdomain s solving on
+        the block rows sets[s] (ascending, holding its owned rows)."""
+        obj = cls.__new__(cls)
+        obj.A = A
+        pa = _i32(part)
+        ptr = _i32(np.concatenate([[0], np.cumsum([len(x) for x in sets])]))
+        flat = _i32(np.concatenate([np.asarray(x) for x in sets]))
+        obj._keep = (pa, ptr, flat)
+        err = C.c_int(0)
+        obj.h = lib().or_pc_create_ras_sets(*A.args(), len(sets), _p(pa), _p(ptr), _p(flat),
+                                            C.byref(err))
         obj.err = err.value
         if not obj.h:
             raise RuntimeError(f"oracle RAS setup failed: {obj.err}")

@@ -383,11 +383,12 @@ void or_cpr_extract_pressure(int nb, const int *rp, const int *ci,
 /* ======================================================================
  * Preconditioner objects (Figure 29)
  * ====================================================================== */
-/* one subdomain of RAS: owned block rows [o0, o1), the overlapped set
- * idx[0..nidx) (ascending global block rows), the principal submatrix of A
- * on it in local numbering and its block ILU(0) factor */
+/* one subdomain of RAS: its number s (it owns the rows r with part[r] =
+ * s), the overlapped set idx[0..nidx) (ascending global block rows), the
+ * principal submatrix of A on it in local numbering and its block ILU(0)
+ * factor */
 typedef struct {
-    int o0, o1, nidx;
+    int s, nidx;
     int *idx, *rp, *ci;
     double *a, *lu;
 } ras_sub;
@@ -396,6 +397,7 @@ struct or_pc {
     int kind, nb, bs, prec, p_sweeps;
     int nsub;
     ras_sub *subs;              /* RAS */
+    int *part;                  /* RAS: owner subdomain of each block row */
     const int *rp, *ci;
     const double *a;
     double *lu;                 /* FP64 (block) ILU(0) factor of A        */
@@ -473,8 +475,8 @@ or_pc *or_pc_create_learned(or_pc *base, int nx, int ny, int nz,
 }
 
 /* ======================================================================
- * C9b. Restricted additive Schwarz (Section 4.1, Cai & Sarkis): the block
- * rows are cut into nsub contiguous owned ranges [starts[s], starts[s+1]);
+ * C9b. Restricted additive Schwarz (Section 4.1, Cai & Sarkis): block row
+ * r is owned by subdomain part[r] (contiguous ranges: or_pc_create_ras);
  * subdomain s grows by `overlap` rounds of graph neighbours (the column
  * indices of its rows), its principal submatrix A_s is factored by block
  * ILU(0), and
@@ -482,14 +484,17 @@ or_pc *or_pc_create_learned(or_pc *base, int nx, int ny, int nz,
  * R_s restricting to the overlapped set, R0_s^T writing back only the
  * owned rows (restricted prolongation).
  * ====================================================================== */
-or_pc *or_pc_create_ras(int nb, int bs, const int *rp, const int *ci,
-                        const double *a, int nsub, const int *starts,
-                        int overlap, int *err)
+/* Subdomain s of RAS: the rows with part[r] == s, grown by `overlap`
+ * rounds of graph neighbours, or (sets != NULL) the explicitly given
+ * overlapped set sets[s_ptr[s] .. s_ptr[s+1]) of ascending block rows. */
+static or_pc *ras_build(int nb, int bs, const int *rp, const int *ci, const double *a,
+                        int nsub, const int *part, int overlap, const int *s_ptr,
+                        const int *sets, int *err)
 {
     int e = OR_OK;
-    if (nsub < 1 || overlap < 0 || starts[0] != 0 || starts[nsub] != nb) e = OR_ERR_ARG;
-    for (int s = 0; !e && s < nsub; s++)
-        if (starts[s + 1] <= starts[s]) e = OR_ERR_ARG;
+    if (nsub < 1 || overlap < 0) e = OR_ERR_ARG;
+    for (int r = 0; !e && r < nb; r++)
+        if (part[r] < 0 || part[r] >= nsub) e = OR_ERR_ARG;
     if (e) { if (err) *err = e; return NULL; }
     or_pc *pc = (or_pc *)calloc(1, sizeof(or_pc));
     const int b2 = bs * bs;
@@ -497,22 +502,36 @@ or_pc *or_pc_create_ras(int nb, int bs, const int *rp, const int *ci,
     pc->rp = rp; pc->ci = ci; pc->a = a;
     pc->nsub = nsub;
     pc->subs = (ras_sub *)calloc((size_t)nsub, sizeof(ras_sub));
+    pc->part = (int *)malloc(sizeof(int) * (size_t)nb);
+    memcpy(pc->part, part, sizeof(int) * (size_t)nb);
     char *in = (char *)malloc((size_t)nb);
     char *add = (char *)malloc((size_t)nb);
     int *loc = (int *)malloc(sizeof(int) * (size_t)nb);
     for (int s = 0; !e && s < nsub; s++) {
         ras_sub *S = &pc->subs[s];
-        S->o0 = starts[s]; S->o1 = starts[s + 1];
-        for (int r = 0; r < nb; r++) in[r] = (char)(r >= S->o0 && r < S->o1);
-        for (int d = 0; d < overlap; d++) {            /* one round of neighbours */
-            for (int r = 0; r < nb; r++) add[r] = 0;
-            for (int r = 0; r < nb; r++)
-                if (in[r])
-                    for (int q = rp[r]; q < rp[r + 1]; q++) add[ci[q]] = 1;
-            for (int r = 0; r < nb; r++) in[r] = (char)(in[r] | add[r]);
+        S->s = s;
+        if (sets) {
+            for (int r = 0; r < nb; r++) in[r] = 0;
+            for (int q = s_ptr[s]; q < s_ptr[s + 1]; q++) {
+                if (sets[q] < 0 || sets[q] >= nb) { e = OR_ERR_ARG; break; }
+                in[sets[q]] = 1;
+            }
+            for (int r = 0; !e && r < nb; r++)      /* a set holds its owned rows */
+                if (part[r] == s && !in[r]) e = OR_ERR_ARG;
+            if (e) break;
+        } else {
+            for (int r = 0; r < nb; r++) in[r] = (char)(part[r] == s);
+            for (int d = 0; d < overlap; d++) {        /* one round of neighbours */
+                for (int r = 0; r < nb; r++) add[r] = 0;
+                for (int r = 0; r < nb; r++)
+                    if (in[r])
+                        for (int q = rp[r]; q < rp[r + 1]; q++) add[ci[q]] = 1;
+                for (int r = 0; r < nb; r++) in[r] = (char)(in[r] | add[r]);
+            }
         }
         S->nidx = 0;
         for (int r = 0; r < nb; r++) S->nidx += in[r];
+        if (S->nidx == 0) { e = OR_ERR_ARG; break; }   /* an empty subdomain */
         S->idx = (int *)malloc(sizeof(int) * (size_t)S->nidx);
         for (int r = 0, l = 0; r < nb; r++) {
             loc[r] = in[r] ? l : -1;
@@ -547,6 +566,38 @@ or_pc *or_pc_create_ras(int nb, int bs, const int *rp, const int *ci,
     return pc;
 }
 
+or_pc *or_pc_create_ras_part(int nb, int bs, const int *rp, const int *ci,
+                             const double *a, int nsub, const int *part,
+                             int overlap, int *err)
+{
+    return ras_build(nb, bs, rp, ci, a, nsub, part, overlap, NULL, NULL, err);
+}
+
+or_pc *or_pc_create_ras_sets(int nb, int bs, const int *rp, const int *ci,
+                             const double *a, int nsub, const int *part,
+                             const int *set_ptr, const int *sets, int *err)
+{
+    return ras_build(nb, bs, rp, ci, a, nsub, part, 0, set_ptr, sets, err);
+}
+
+/* contiguous owned ranges [starts[s], starts[s+1]) */
+or_pc *or_pc_create_ras(int nb, int bs, const int *rp, const int *ci,
+                        const double *a, int nsub, const int *starts,
+                        int overlap, int *err)
+{
+    int e = OR_OK;
+    if (nsub < 1 || overlap < 0 || starts[0] != 0 || starts[nsub] != nb) e = OR_ERR_ARG;
+    for (int s = 0; !e && s < nsub; s++)
+        if (starts[s + 1] <= starts[s]) e = OR_ERR_ARG;
+    if (e) { if (err) *err = e; return NULL; }
+    int *part = (int *)malloc(sizeof(int) * (size_t)(nb > 0 ? nb : 1));
+    for (int s = 0; s < nsub; s++)
+        for (int r = starts[s]; r < starts[s + 1]; r++) part[r] = s;
+    or_pc *pc = or_pc_create_ras_part(nb, bs, rp, ci, a, nsub, part, overlap, err);
+    free(part);
+    return pc;
+}
+
 static void ras_apply(or_pc *pc, const double *v, double *z)
 {
     const int bs = pc->bs;
@@ -560,7 +611,7 @@ static void ras_apply(or_pc *pc, const double *v, double *z)
         or_bilu0_solve(S->nidx, bs, S->rp, S->ci, S->lu, vl, xl);
         for (int l = 0; l < S->nidx; l++) {               /* owned rows only */
             const int g = S->idx[l];
-            if (g >= S->o0 && g < S->o1)
+            if (pc->part[g] == S->s)
                 memcpy(z + (size_t)g * bs, xl + (size_t)l * bs, sizeof(double) * bs);
         }
         free(vl); free(xl);
@@ -581,6 +632,7 @@ void or_pc_destroy(or_pc *pc)
         free(pc->subs[s].a); free(pc->subs[s].lu);
     }
     free(pc->subs);
+    free(pc->part);
     free(pc);
 }
 

@@ -69,6 +69,16 @@ or_pc *or_pc_create(int kind, int nb, int bs, const int *rp, const int *ci,
 or_pc *or_pc_create_learned(or_pc *base, int nx, int ny, int nz,
                             const double *params, const double *lnk,
                             int bf16_emul);
+/* RAS with a general partition: block row r owned by subdomain part[r] */
+or_pc *or_pc_create_ras_part(int nb, int bs, const int *rp, const int *ci,
+                             const double *a, int nsub, const int *part,
+                             int overlap, int *err);
+/* RAS with explicit overlapped sets: subdomain s solves on the ascending
+ * block rows sets[set_ptr[s] .. set_ptr[s+1]), which must hold its owned
+ * rows (part[r] == s) */
+or_pc *or_pc_create_ras_sets(int nb, int bs, const int *rp, const int *ci,
+                             const double *a, int nsub, const int *part,
+                             const int *set_ptr, const int *sets, int *err);
 /* RAS with block ILU(0) local solves: owned block rows
  * [starts[s], starts[s+1]) for s < nsub, `overlap` rounds of graph
  * neighbours (restricted prolongation) */

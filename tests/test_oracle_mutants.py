@@ -97,7 +97,7 @@ MUTANTS = [
      "for (size_t i = 0; i < n; i++) Zs[i] = x[i] / dn;",
      [lambda: tk.test_lgmres_cycles_minimize_over_augmented_space(2)]),
     ("ras_prolongs_overlap_rows",
-     "if (g >= S->o0 && g < S->o1)",
+     "if (pc->part[g] == S->s)",
      "if (g >= 0)",
      [lambda: tr.test_ras_matches_dense_restricted_schwarz([0, 12, 24, 36], 1)]),
     ("ras_overlap_not_grown",

@@ -6,26 +6,19 @@ import pytest
 import oracle
 import reservoir_inputs as ri
 from tests._helpers import bsr_from_dense, dense, lu_dense_from_factor, relerr
+from tests.ras_boxes import box_partition
 
 
-def _ras_dense(s, starts, overlap, v):
-    """RAS assembled densely: the overlapped set by breadth-first growth on
-    the block graph of the dense matrix, the principal submatrix sliced from
-    it, its block ILU(0) factor as dense L U, the restricted prolongation."""
+def _ras_dense_sets(s, part, sets, v):
+    """RAS assembled densely from explicit subdomain sets: the principal
+    submatrix sliced from the dense matrix, its block ILU(0) factor as dense
+    L U, the restricted prolongation onto the rows with part == s."""
     bs = s.get("bs", 1)
     D = dense(s)
-    nb = D.shape[0] // bs
-    adj = np.zeros((nb, nb), dtype=bool)
-    for i in range(nb):
-        for j in range(nb):
-            adj[i, j] = np.any(D[i * bs:(i + 1) * bs, j * bs:(j + 1) * bs] != 0)
+    part = np.asarray(part)
     z = np.zeros_like(v)
-    for o0, o1 in zip(starts[:-1], starts[1:]):
-        inset = np.zeros(nb, dtype=bool)
-        inset[o0:o1] = True
-        for _ in range(overlap):
-            inset = inset | adj[inset].any(axis=0)
-        idx = np.flatnonzero(inset)
+    for sid, idx in enumerate(sets):
+        idx = np.sort(np.asarray(idx))
         dofs = (idx[:, None] * bs + np.arange(bs)).reshape(-1)
         Ai = D[np.ix_(dofs, dofs)]
         sub = bsr_from_dense(Ai, bs)
@@ -34,9 +27,31 @@ def _ras_dense(s, starts, overlap, v):
         assert rc == 0
         L, U = lu_dense_from_factor(M.rowptr, M.col, lu, bs)
         xl = np.linalg.solve(L @ U, v[dofs])
-        own = (idx >= o0) & (idx < o1)
+        own = part[idx] == sid
         z[dofs.reshape(-1, bs)[own].reshape(-1)] = xl.reshape(-1, bs)[own].reshape(-1)
     return z
+
+
+def _ras_dense(s, starts, overlap, v):
+    """RAS with the overlapped sets grown breadth-first on the block graph of
+    the dense matrix from contiguous owned ranges."""
+    bs = s.get("bs", 1)
+    D = dense(s)
+    nb = D.shape[0] // bs
+    adj = np.zeros((nb, nb), dtype=bool)
+    for i in range(nb):
+        for j in range(nb):
+            adj[i, j] = np.any(D[i * bs:(i + 1) * bs, j * bs:(j + 1) * bs] != 0)
+    part = np.empty(nb, dtype=np.int32)
+    sets = []
+    for sid, (o0, o1) in enumerate(zip(starts[:-1], starts[1:])):
+        part[o0:o1] = sid
+        inset = np.zeros(nb, dtype=bool)
+        inset[o0:o1] = True
+        for _ in range(overlap):
+            inset = inset | adj[inset].any(axis=0)
+        sets.append(np.flatnonzero(inset))
+    return _ras_dense_sets(s, part, sets, v)
 
 
 def test_ras_one_subdomain_is_global_bilu0():
@@ -102,3 +117,77 @@ def test_fgmres_with_ras_converges():
         r = oracle.gmres(A, oracle.PC.ras(A, starts, 1), s["b"], restart=30, maxit=2000,
                          rtol=1e-8, flexible=True)
         assert r["status"] == 0 and r["relres"] <= 1e-8
+
+
+# ---- explicit subdomain sets: boxes of the grid grown in every direction ----
+@pytest.mark.parametrize("parts,overlap", [((2, 2, 1), 1), ((2, 2, 2), 0), ((2, 2, 2), 1),
+                                           ((3, 1, 2), 2)])
+def test_ras_sets_match_dense_on_boxes(parts, overlap):
+    grid = (5, 4, 3)
+    s = ri.blackoil_system(*grid, seed=14)
+    A = oracle.Matrix.from_system(s)
+    v = np.random.default_rng(15).standard_normal(A.n)
+    part, sets = box_partition(grid, parts, overlap)
+    got = oracle.PC.ras_sets(A, part, sets).apply(v)
+    assert relerr(got, _ras_dense_sets(s, part, sets, v)) < 1e-12
+
+
+@pytest.mark.parametrize("overlap", [0, 1, 2])
+def test_ras_boxes_on_slabs_are_graph_overlap(overlap):
+    # for z-slabs, growing the box by d cells is d rounds of graph neighbours
+    grid = (4, 3, 7)
+    s = ri.blackoil_system(*grid, seed=16)
+    A = oracle.Matrix.from_system(s)
+    v = np.random.default_rng(17).standard_normal(A.n)
+    part, sets = box_partition(grid, (1, 1, 3), overlap)
+    starts = [q * 7 // 3 * 12 for q in range(4)]
+    ref = oracle.PC.ras(A, starts, overlap).apply(v)
+    assert np.array_equal(oracle.PC.ras_sets(A, part, sets).apply(v), ref)
+    assert np.array_equal(oracle.PC.ras_part(A, part, overlap).apply(v), ref)
+
+
+def test_ras_sets_exact_for_lower_triangular_stencil():
+    # only the -x, -y, -z couplings: ILU(0) of every principal submatrix is
+    # its exact LU, so each subdomain solve is a dense solve
+    grid = (4, 4, 3)
+    nx, ny, nz = grid
+    n = nx * ny * nz
+    rng = np.random.default_rng(18)
+    D = np.zeros((n, n))
+    for k in range(nz):
+        for j in range(ny):
+            for i in range(nx):
+                r = (k * ny + j) * nx + i
+                D[r, r] = 2.0 + rng.random()
+                for d, ok in ((1, i > 0), (nx, j > 0), (nx * ny, k > 0)):
+                    if ok:
+                        D[r, r - d] = -0.5 - rng.random()
+    st = bsr_from_dense(D, 1)
+    A = oracle.Matrix.from_system(st)
+    v = rng.standard_normal(n)
+    part, sets = box_partition(grid, (2, 2, 1), 1)
+    z = np.zeros(n)
+    for sid, idx in enumerate(sets):
+        xl = np.linalg.solve(D[np.ix_(idx, idx)], v[idx])
+        own = part[idx] == sid
+        z[idx[own]] = xl[own]
+    assert relerr(oracle.PC.ras_sets(A, part, sets).apply(v), z) < 1e-13
+    # and the overlap matters: a grown box's local solve sees more of v
+    part0, sets0 = box_partition(grid, (2, 2, 1), 0)
+    assert relerr(oracle.PC.ras_sets(A, part0, sets0).apply(v), z) > 1e-6
+
+
+def test_ras_sets_rejects_bad_sets():
+    grid = (3, 3, 2)
+    s = ri.blackoil_system(*grid, seed=1)
+    A = oracle.Matrix.from_system(s)
+    part, sets = box_partition(grid, (1, 1, 2), 1)
+    missing = [sets[0], sets[1][:-1]]          # a set without one of its owned rows
+    outside = [sets[0], np.append(sets[1], 18)]
+    for bad in (missing, outside):
+        with pytest.raises(RuntimeError):
+            oracle.PC.ras_sets(A, part, bad)
+    bad_part = part.copy()
+    bad_part[0] = 2
+    with pytest.raises(RuntimeError):
+        oracle.PC.ras_sets(A, bad_part, sets)
