@@ -56,11 +56,17 @@ CONFIGS = [
     ("pcg_ilu0_scalar_f64", "CG", "ILU0", "F64", None),
     ("gmres30_ras4_f64", "GMRES", "RAS", "F64", None),
     ("gmres30_ras8_f64", "GMRES", "RAS", "F64", None),
+    ("gmres30_rasbox_1x4x4_f64", "GMRES", "RAS", "F64", None),
+    ("gmres30_rasbox_2x4x4_f64", "GMRES", "RAS", "F64", None),
+    ("gmres30_rasbox_2x2x2_f64", "GMRES", "RAS", "F64", None),
 ]
 # per-configuration extras: LGMRES augmentation, and the symmetric scalar
 # system of the same grid (CG needs a symmetric positive definite matrix)
 EXTRAS = {"lgmres30_2_bilu0_f64": dict(aug_k=2), "pcg_ilu0_scalar_f64": dict(system="scalar"),
-          "gmres30_ras4_f64": dict(ras=(4, 1)), "gmres30_ras8_f64": dict(ras=(8, 1))}
+          "gmres30_ras4_f64": dict(ras=(4, 1)), "gmres30_ras8_f64": dict(ras=(8, 1)),
+          "gmres30_rasbox_1x4x4_f64": dict(ras=(1, 4, 4, 1)),
+          "gmres30_rasbox_2x4x4_f64": dict(ras=(2, 4, 4, 1)),
+          "gmres30_rasbox_2x2x2_f64": dict(ras=(2, 2, 2, 1))}
 WEIGHTS = os.path.join(ROOT, "paper_1701_05913_amd", "weights", "bilu0_blackoil64.bin")
 
 # matrix-core FLOPs per cell of each conv layer (3x3x3 taps, 2 per MAC)
@@ -223,8 +229,11 @@ def main():
         K.SolverSetMaxit(S, 5000)
         K.SolverSetRestart(S, 30)
         K.SolverSetAugk(S, ex.get("aug_k", 0))
-        if "ras" in ex:
-            K.SolverSetRAS(S, *ex["ras"])
+        if "ras" in ex:   # (nsub, overlap) z-slabs or (px, py, pz, overlap) boxes
+            if len(ex["ras"]) == 4:
+                K.SolverSetRASBoxes(S, *ex["ras"])
+            else:
+                K.SolverSetRAS(S, *ex["ras"])
         K.SolverSetPrecision(S, getattr(K, f"KRY_PREC_{prec}"))
         if cpr:
             K.SolverSetCPR(S, getattr(K, f"KRY_CPR_{cpr[0]}"), cpr[1])

@@ -205,6 +205,14 @@ int SolverSetCPR(SOLVER *s, int variant, int p_sweeps);
  * overlap < 0, and at SolverAssemble for nsub > nz; KRY_ERR_UNSUPPORTED
  * for a matrix that is not a grid stencil or a reduced precision. */
 int SolverSetRAS(SOLVER *s, int nsub, int overlap);
+/* RAS on boxes: the grid is cut into px x py x pz boxes (sides n/p, the
+ * last ones taking the remainder); each box is grown by `overlap` cells in
+ * every direction, edges and corners included (for z-slabs, px = py = 1,
+ * exactly `overlap` rounds of graph neighbours), factored by block ILU(0)
+ * and swept with all other boxes in one launch.  Grown boxes must have
+ * sides >= 3 in x and y and >= 2 in z unless px = py = 1 (KRY_ERR_UNSUPPORTED
+ * at SolverAssemble).  SolverSetRAS(s, n, o) = SolverSetRASBoxes(s, 1, 1, n, o). */
+int SolverSetRASBoxes(SOLVER *s, int px, int py, int pz, int overlap);
 /* SolverSetSweepLayout: KRY_SWEEP_AUTO (default), KRY_SWEEP_LEVELS (generic
  * level-scheduled sweeps), or KRY_SWEEP_GRID (grid-tiled sweeps; assembly
  * fails with KRY_ERR_ARG if the matrix is not a 7-point grid stencil).

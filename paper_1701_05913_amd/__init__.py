@@ -82,6 +82,7 @@ _SIGS = {
     "SolverSetPrecision": (C.c_int, [P, C.c_int]),
     "SolverSetCPR": (C.c_int, [P, C.c_int, C.c_int]),
     "SolverSetRAS": (C.c_int, [P, C.c_int, C.c_int]),
+    "SolverSetRASBoxes": (C.c_int, [P, C.c_int, C.c_int, C.c_int, C.c_int]),
     "SolverSetSweepLayout": (C.c_int, [P, C.c_int]),
     "SolverSetStream": (C.c_int, [P, P]),
     "SolverGetResidual": (D, [P]), "SolverGetIters": (C.c_int, [P]),
@@ -310,6 +311,7 @@ def SolverSetAugk(s, k): return _check(_lib.SolverSetAugk(s, k))
 def SolverSetPrecision(s, p): return _check(_lib.SolverSetPrecision(s, p))
 def SolverSetCPR(s, variant, p_sweeps): return _check(_lib.SolverSetCPR(s, variant, p_sweeps))
 def SolverSetRAS(s, nsub, overlap): return _check(_lib.SolverSetRAS(s, nsub, overlap))
+def SolverSetRASBoxes(s, px, py, pz, overlap): return _check(_lib.SolverSetRASBoxes(s, px, py, pz, overlap))
 def SolverSetSweepLayout(s, layout): return _check(_lib.SolverSetSweepLayout(s, layout))
 
 

@@ -326,7 +326,7 @@ static int grid_tiling(const MAT_ *A, IluFactor &F) {
     for (int q = 0; q < G.NQ; q++) {
         qo[q] = static_cast<int>(qt.size());
         for (int T = 0; T < G.ntiles; T++)
-            if ((ord[T] & 0xffff) % G.NQ == q) qt.push_back(T);
+            if (((ord[T] & 0xffff) + F.qrot) % G.NQ == q) qt.push_back(T);
     }
     qo[G.NQ] = static_cast<int>(qt.size());
     G.qmax = 0;
@@ -655,10 +655,14 @@ __device__ __forceinline__ int next_tile(const GridTiles &G, int *ctr, int *tile
 
 // forward sweep of one grid; blk = this workgroup's index within the grid's
 // workgroups (a multiple of GRID_QUEUES of them)
+// b is read at cell (i, j, k) of the grid as b[(i + j vsJ + k vsK) BS + r]:
+// vsJ = nx, vsK = nx ny for a whole grid, the caller's strides for a box of
+// a larger grid
 template <int BS, typename TF, typename TC, typename TIN>
 __device__ __forceinline__ void grid_fwd_body(const GridTiles &G, const TF *__restrict__ Lt,
                                               const TIN *__restrict__ b, TC *yt, TC *ff, TC *fb,
-                                              int *ctr, int *other_ctr, int *err, int blk) {
+                                              int *ctr, int *other_ctr, int *err, int blk,
+                                              int64_t vsJ, int64_t vsK) {
     constexpr int B2 = BS * BS, NM = 3 * B2, NV = NM + BS;
     constexpr int D = ring_depth<NV, TC>();
     __shared__ TC ring[D][NV][64];
@@ -784,7 +788,7 @@ __device__ __forceinline__ void grid_fwd_body(const GridTiles &G, const TF *__re
             const int JK = G.order[T];
             const int j = (JK & 0xffff) * TJ + jj, k = (JK >> 16) * TK + kk;
             const bool lane_ok = lane < TJ * TK && j < G.ny && k < G.nz;
-            const int64_t cl = lane_ok ? sJ * j + sK * k : 0;
+            const int64_t cl = lane_ok ? vsJ * j + vsK * k : 0;
             const TF *lb = Lt + (int64_t)T * S * NM * 64 + lane;
             auto load_step = [&](int t, TC (&v)[NV]) {
 #pragma unroll
@@ -987,15 +991,22 @@ __device__ __forceinline__ void grid_bwd_body(const GridTiles &G, const TF *__re
 // Copy the tile-step-major result to natural order, with the caller's
 // epilogue (the add modes of ilu_apply): one block per (tile, 8 steps),
 // reads in contiguous 64-lane rows.
+// cells of a grid written by an untile: those with i in [i0, i1), j in
+// [j0, j1), k in [k0, k1), at (i + j vsJ + k vsK) BS of the output
+struct UntileBox {
+    int i0, i1, j0, j1, k0, k1;
+    int64_t vsJ, vsK;
+};
+
 // natural-order copy of the tile-step result of one grid with the fused
-// epilogue; only cells c in [c0, c1) are written (all of them for a whole
-// grid; a subdomain's owned rows under RAS)
+// epilogue, restricted to the cells of `box` (all of them for a whole grid;
+// a subdomain's owned cells under RAS)
 template <int BS, typename TC, typename TO, int ADD, typename TAI, typename TAO>
 __device__ __forceinline__ void grid_untile_body(const GridTiles &G, const TC *__restrict__ yt,
                                                  TO *__restrict__ xo,
                                                  const TAI *__restrict__ add_in,
-                                                 TAO *__restrict__ add_out, int64_t c0,
-                                                 int64_t c1, int blk) {
+                                                 TAO *__restrict__ add_out, const UntileBox &box,
+                                                 int blk) {
     const int nchunk = (G.S + 7) / 8;
     const int T = blk / nchunk, t0 = (blk % nchunk) * 8;
     const int lane = threadIdx.x & 63;
@@ -1003,12 +1014,12 @@ __device__ __forceinline__ void grid_untile_body(const GridTiles &G, const TC *_
     const int jj = lane % G.TJ, kk = lane / G.TJ;
     const int j = (JK & 0xffff) * G.TJ + jj, k = (JK >> 16) * G.TK + kk;
     if (lane >= G.TJ * G.TK || j >= G.ny || k >= G.nz) return;
-    const int64_t cl = (int64_t)G.nx * j + (int64_t)G.nx * G.ny * k;
+    if (j < box.j0 || j >= box.j1 || k < box.k0 || k >= box.k1) return;
+    const int64_t cl = box.vsJ * j + box.vsK * k;
     for (int t = t0 + (threadIdx.x >> 6); t < t0 + 8 && t < G.S; t += 4) {
         const int i = t - jj - kk;
-        if (i < 0 || i >= G.nx) continue;
+        if (i < box.i0 || i >= box.i1 || i >= G.nx) continue;
         const int64_t c = cl + i;
-        if (c < c0 || c >= c1) continue;
         const TC *src = yt + ((int64_t)T * G.S + t) * BS * 64 + lane;
 #pragma unroll
         for (int r = 0; r < BS; r++) {
@@ -1027,7 +1038,8 @@ template <int BS, typename TF, typename TC, typename TIN>
 __global__ __launch_bounds__(GWG) void k_grid_fwd(GridTiles G, const TF *__restrict__ Lt,
                                                   const TIN *__restrict__ b, TC *yt, TC *ff,
                                                   TC *fb, int *ctr, int *other_ctr, int *err) {
-    grid_fwd_body<BS, TF, TC, TIN>(G, Lt, b, yt, ff, fb, ctr, other_ctr, err, blockIdx.x);
+    grid_fwd_body<BS, TF, TC, TIN>(G, Lt, b, yt, ff, fb, ctr, other_ctr, err, blockIdx.x, G.nx,
+                                   (int64_t)G.nx * G.ny);
 }
 
 template <int BS, typename TF, typename TD, typename TC, typename TO>
@@ -1042,8 +1054,8 @@ __global__ __launch_bounds__(256) void k_grid_untile(GridTiles G, const TC *__re
                                                      TO *__restrict__ xo,
                                                      const TAI *__restrict__ add_in,
                                                      TAO *__restrict__ add_out) {
-    grid_untile_body<BS, TC, TO, ADD, TAI, TAO>(G, yt, xo, add_in, add_out, 0, INT64_MAX,
-                                                blockIdx.x);
+    const UntileBox all{0, G.nx, 0, G.ny, 0, G.nz, G.nx, (int64_t)G.nx * G.ny};
+    grid_untile_body<BS, TC, TO, ADD, TAI, TAO>(G, yt, xo, add_in, add_out, all, blockIdx.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -1064,7 +1076,8 @@ __global__ __launch_bounds__(GWG) void k_grid_fwd_multi(const GridMulti *__restr
     const int g = find_grid(d, ngrid, blockIdx.x, &GridMulti::wg0);
     const GridMulti D = d[g];
     grid_fwd_body<BS, double, double, double>(D.G, D.lt, v + D.boff, D.yt, D.ff, D.fb, D.ctr,
-                                              D.ctr + D.G.NQ, err, blockIdx.x - D.wg0);
+                                              D.ctr + D.G.NQ, err, blockIdx.x - D.wg0, D.vsJ,
+                                              D.vsK);
 }
 
 template <int BS>
@@ -1082,8 +1095,9 @@ __global__ __launch_bounds__(256) void k_grid_untile_multi(const GridMulti *__re
                                                            int ngrid, double *__restrict__ z) {
     const int g = find_grid(d, ngrid, blockIdx.x, &GridMulti::ub0);
     const GridMulti D = d[g];
-    grid_untile_body<BS, double, double, 0, double, double>(
-        D.G, D.yt, z + D.boff, nullptr, nullptr, D.own0, D.own1, blockIdx.x - D.ub0);
+    const UntileBox box{D.oi0, D.oi1, D.oj0, D.oj1, D.ok0, D.ok1, D.vsJ, D.vsK};
+    grid_untile_body<BS, double, double, 0, double, double>(D.G, D.yt, z + D.boff, nullptr,
+                                                            nullptr, box, blockIdx.x - D.ub0);
 }
 
 int grid_multi_launch_size(const IluFactor &F, int *wgs, int *untile_blocks) {
@@ -1093,8 +1107,8 @@ int grid_multi_launch_size(const IluFactor &F, int *wgs, int *untile_blocks) {
     return KRY_OK;
 }
 
-int grid_multi_desc(const IluFactor &F, int64_t boff, int64_t own0, int64_t own1, int wg0,
-                    int ub0, GridMulti &d) {
+int grid_multi_desc(const IluFactor &F, int64_t boff, int64_t vsJ, int64_t vsK, const int own[6],
+                    int wg0, int ub0, GridMulti &d) {
     if (!F.grid || F.prec != KRY_PREC_F64)
         return set_error(KRY_ERR_ARG, "grid_multi: needs an FP64 grid-tiled factor");
     d.G = F.G;
@@ -1106,8 +1120,14 @@ int grid_multi_desc(const IluFactor &F, int64_t boff, int64_t own0, int64_t own1
     d.fb = F.fb64.p;
     d.ctr = F.ctr.p;
     d.boff = boff;
-    d.own0 = own0;
-    d.own1 = own1;
+    d.vsJ = vsJ;
+    d.vsK = vsK;
+    d.oi0 = own[0];
+    d.oi1 = own[1];
+    d.oj0 = own[2];
+    d.oj1 = own[3];
+    d.ok0 = own[4];
+    d.ok1 = own[5];
     d.wg0 = wg0;
     d.ub0 = ub0;
     return KRY_OK;

@@ -221,6 +221,10 @@ struct IluFactor {
     // timer names of this factor's sweeps: nullptr = the per-kind names of
     // sweep_timer_name; a subdomain factor reports under its own names
     const char *timer_fwd = nullptr, *timer_bwd = nullptr;
+    // grid tiling: tile column J is served by queue (J + qrot) % GRID_QUEUES
+    // (workgroups b with b % GRID_QUEUES == queue, i.e. one XCD); several
+    // grids in one launch rotate their queues to spread over the XCDs
+    int qrot = 0;
     int prec = KRY_PREC_F64;
     int nlev_f = 0, nlev_b = 0;
     Sell L;                 // forward order, strictly lower blocks
@@ -287,24 +291,27 @@ struct CprPC {
     IluFactor ilu_a;        // block ILU(0) of A
     DBuf<char> work;        // scratch vectors
 };
-// One grid of a multi-grid sweep launch (the subdomains of RAS): its tiling,
-// FP64 factor planes and work buffers, its tile counters (GRID_QUEUES
-// forward, then backward), the offset of its rows in the caller's vectors,
-// its output rows [own0, own1) (local numbering) and its first workgroup in
-// the sweep and untile launches.
+// One grid of a multi-grid sweep launch (the subdomains of RAS, boxes of a
+// larger grid): its tiling, FP64 factor planes and work buffers, its tile
+// counters (GRID_QUEUES forward, then backward), where its cells sit in the
+// caller's vectors (offset of cell (0,0,0) in doubles, strides of j and k in
+// cells), the cells it writes back (local i, j, k ranges) and its first
+// workgroup in the sweep and untile launches.
 struct GridMulti {
     GridTiles G;
     const double *lt, *ut, *dt;
     double *yt, *ff, *fb;
     int *ctr;
-    int64_t boff, own0, own1;
+    int64_t boff, vsJ, vsK;
+    int oi0, oi1, oj0, oj1, ok0, ok1;
     int wg0, ub0;
 };
 int grid_multi_launch_size(const IluFactor &F, int *wgs, int *untile_blocks);
-int grid_multi_desc(const IluFactor &F, int64_t boff, int64_t own0, int64_t own1, int wg0,
-                    int ub0, GridMulti &d);
-// every grid's forward sweep of v + boff, backward sweep, and untile of
-// rows [own0, own1) into z + boff, in three launches on s
+// own = {i0, i1, j0, j1, k0, k1}: the cells written back, local coordinates
+int grid_multi_desc(const IluFactor &F, int64_t boff, int64_t vsJ, int64_t vsK, const int own[6],
+                    int wg0, int ub0, GridMulti &d);
+// every grid's forward sweep of its cells of v, backward sweep, and untile
+// of its owned cells into z, in three launches on s
 int grid_multi_apply(hipStream_t s, int bs, const GridMulti *d_desc, int ngrid, int total_wgs,
                      int total_untile, const double *v, double *z, int *err);
 
@@ -334,17 +341,19 @@ MAT *mat_create_device(MAP *map, int nb, int bs, const int *rowptr, const int *c
 // restricted additive Schwarz: z-slab subdomains of a 7-point grid matrix,
 // block ILU(0) on each overlapped slab
 struct RasSub {
-    int lo = 0, hi = 0, o0 = 0, o1 = 0;   // overlapped / owned block rows
+    int lo = 0, hi = 0, o0 = 0, o1 = 0;   // z-slabs: overlapped / owned block rows
+    int ob[6] = {0, 0, 0, 0, 0, 0};       // owned box: i0, i1, j0, j1, k0, k1
+    int gb[6] = {0, 0, 0, 0, 0, 0};       // overlapped box (grown by `overlap`)
     MAP *map = nullptr;
     MAT *A = nullptr;
     IluFactor F;
     DBuf<int> pos;                        // A's value blocks of the subdomain matrix
     DBuf<double> faces;                   // grid factorization work buffers
     DBuf<int> fctr;
-    DBuf<double> x;                       // local solution (non-grid subdomains)
+    DBuf<double> x;                       // local solution (level-scheduled slabs)
 };
 struct RasPC {
-    int nsub = 0, overlap = 1, bs = 1, layout = 0;
+    int px = 1, py = 1, pz = 1, overlap = 1, bs = 1, layout = 0;
     const MAT_ *A = nullptr;              // the matrix whose pattern the subdomains hold
     std::vector<std::unique_ptr<RasSub>> subs;
     bool multi = false;                   // all subdomains grid-tiled: one launch per sweep
@@ -353,11 +362,8 @@ struct RasPC {
     int wgs = 0, untile_blocks = 0, factor_wgs = 0;
     ~RasPC();
 };
-// symbolic setup (subdomain patterns, tilings, buffers) and the numeric
-// factorization; ras_refactor repeats only the latter for new values of the
-// same matrix
-int ras_setup(hipStream_t s, MAT_ *A, RasPC &R, int nsub, int overlap, int prec, int *d_err,
-              int layout);
+int ras_setup(hipStream_t s, MAT_ *A, RasPC &R, int px, int py, int pz, int overlap, int prec,
+              int *d_err, int layout);
 int ras_refactor(hipStream_t s, const MAT_ *A, RasPC &R, int *d_err);
 int ras_apply(hipStream_t s, RasPC &R, const double *v, double *z, int *d_err);
 
@@ -405,7 +411,7 @@ struct SOLVER_ {
     std::unique_ptr<kry::IluFactor> ilu;
     std::unique_ptr<kry::CprPC> cpr;
     std::unique_ptr<kry::RasPC> ras;
-    int ras_nsub = 4, ras_overlap = 1;
+    int ras_px = 1, ras_py = 1, ras_pz = 4, ras_overlap = 1;
     std::unique_ptr<kry::LearnedStage, kry::LearnedStageDeleter> learned;
     std::vector<float> learned_params;     // host copy until assembly
     kry::DBuf<float> learned_lnk;          // ln k per cell

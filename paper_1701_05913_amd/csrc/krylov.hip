@@ -1038,12 +1038,19 @@ extern "C" int SolverSetCPR(SOLVER *s, int variant, int p_sweeps) {
     s->assembled = false;
     return KRY_OK;
 }
-extern "C" int SolverSetRAS(SOLVER *s, int nsub, int overlap) {
-    if (!s || nsub < 1 || overlap < 0) return set_error(KRY_ERR_ARG, "SolverSetRAS: bad argument");
-    s->ras_nsub = nsub;
+extern "C" int SolverSetRASBoxes(SOLVER *s, int px, int py, int pz, int overlap) {
+    if (!s || px < 1 || py < 1 || pz < 1 || overlap < 0)
+        return set_error(KRY_ERR_ARG, "SolverSetRASBoxes: bad argument");
+    s->ras_px = px;
+    s->ras_py = py;
+    s->ras_pz = pz;
     s->ras_overlap = overlap;
     s->assembled = false;
     return KRY_OK;
+}
+extern "C" int SolverSetRAS(SOLVER *s, int nsub, int overlap) {
+    if (!s || nsub < 1 || overlap < 0) return set_error(KRY_ERR_ARG, "SolverSetRAS: bad argument");
+    return SolverSetRASBoxes(s, 1, 1, nsub, overlap);
 }
 extern "C" int SolverSetSweepLayout(SOLVER *s, int layout) {
     if (!s || layout < KRY_SWEEP_AUTO || layout > KRY_SWEEP_GRID)
@@ -1089,7 +1096,8 @@ extern "C" int SolverAssemble(SOLVER *s) {
     s->cpr.reset();
     // RAS keeps its subdomain patterns when the matrix and options are unchanged
     const bool ras_reuse = s->pc_type == KRY_PC_RAS && s->ras && s->ras->A == s->A &&
-                           s->ras->nsub == s->ras_nsub && s->ras->overlap == s->ras_overlap &&
+                           s->ras->px == s->ras_px && s->ras->py == s->ras_py &&
+                           s->ras->pz == s->ras_pz && s->ras->overlap == s->ras_overlap &&
                            s->ras->layout == s->sweep_layout && s->prec == KRY_PREC_F64;
     if (!ras_reuse) s->ras.reset();
     s->learned.reset();
@@ -1112,8 +1120,8 @@ extern "C" int SolverAssemble(SOLVER *s) {
             KRY_TRY(ras_refactor(s->stream, s->A, *s->ras, s->err.p));
         } else {
             s->ras.reset(new RasPC());
-            const int rc = ras_setup(s->stream, s->A, *s->ras, s->ras_nsub, s->ras_overlap, s->prec,
-                                     s->err.p, s->sweep_layout);
+            const int rc = ras_setup(s->stream, s->A, *s->ras, s->ras_px, s->ras_py, s->ras_pz,
+                                     s->ras_overlap, s->prec, s->err.p, s->sweep_layout);
             if (rc < 0) {
                 s->ras.reset();
                 return rc;

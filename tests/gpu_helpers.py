@@ -56,7 +56,11 @@ def make_solver(g, solver, pc, rtol=1e-8, maxit=5000, restart=30,
     if pc == K.KRY_PC_CPR:
         K.SolverSetCPR(S, cpr[0], cpr[1])
     if pc == K.KRY_PC_RAS:
-        K.SolverSetRAS(S, ras[0], ras[1])
+        # (nsub, overlap): z-slabs; (px, py, pz, overlap): boxes
+        if len(ras) == 4:
+            K.SolverSetRASBoxes(S, *ras)
+        else:
+            K.SolverSetRAS(S, *ras)
     K.SolverSetStream(S, torch.cuda.current_stream())
     return S
 

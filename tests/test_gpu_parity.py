@@ -22,6 +22,7 @@ if not torch.cuda.is_available():
 
 import paper_1701_05913_amd as K  # noqa: E402
 from tests._helpers import bsr_from_dense  # noqa: E402
+from tests.ras_boxes import box_partition  # noqa: E402
 from tests.gpu_helpers import GpuSystem, make_solver, pc_apply, relerr, solve  # noqa: E402
 
 SMALL_SCALAR = (37, 29, 23)     # 24 679 rows: many slices, ragged tail
@@ -409,6 +410,14 @@ def _slab_starts(grid, nsub):
     return [q * nz // nsub * nx * ny for q in range(nsub + 1)]
 
 
+def _ras_pc(A, grid, ras):
+    """The oracle's RAS for a GPU configuration: (nsub, overlap) z-slabs
+    (graph overlap) or (px, py, pz, overlap) boxes (grown boxes)."""
+    if len(ras) == 4:
+        return oracle.PC.ras_sets(A, *box_partition(grid, ras[:3], ras[3]))
+    return oracle.PC.ras(A, _slab_starts(grid, ras[0]), ras[1])
+
+
 @pytest.mark.parametrize("grid,nsub,overlap", [((13, 11, 9), 2, 1), ((13, 11, 9), 3, 0),
                                                ((13, 11, 9), 3, 2), ((13, 11, 9), 9, 0),
                                                ((32, 32, 16), 4, 1), ((32, 32, 16), 4, 2)])
@@ -493,23 +502,23 @@ def test_ras_errors():
         g.close()
 
 
-def test_ras_refactor_after_value_update():
+@pytest.mark.parametrize("ras", [(3, 1), (2, 2, 2, 1)])
+def test_ras_refactor_after_value_update(ras):
     # SolverAssemble after MatUpdateValues reuses the subdomain patterns and
     # refactors with the new values
     grid = (16, 12, 12)
     s = ri.blackoil_system(*grid, seed=12)
     A = oracle.Matrix.from_system(s)
     v = np.random.default_rng(13).standard_normal(A.n)
-    starts = _slab_starts(grid, 3)
     g = GpuSystem(s)
     try:
-        S = make_solver(g, K.KRY_FGMRES, K.KRY_PC_RAS, ras=(3, 1))
+        S = make_solver(g, K.KRY_FGMRES, K.KRY_PC_RAS, ras=ras)
         vt, vh = g.vec(v)
         zt, zh = g.vec()
         K.SolverAssemble(S)
         K.SolverPCApply(S, vh, zh)
         torch.cuda.synchronize()
-        assert relerr(zt.cpu().numpy(), oracle.PC.ras(A, starts, 1).apply(v)) <= 1e-10
+        assert relerr(zt.cpu().numpy(), _ras_pc(A, grid, ras).apply(v)) <= 1e-10
         # new values, same pattern: scaled, with a heavier diagonal
         val2 = s["val"].reshape(-1, 9).copy() * 1.5
         diag = np.zeros(val2.shape[0], dtype=bool)
@@ -524,13 +533,98 @@ def test_ras_refactor_after_value_update():
         torch.cuda.synchronize()
         A2 = oracle.Matrix(s["rowptr"], s["col"], val2.reshape(-1), 3)
         z2 = zt.cpu().numpy()
-        assert relerr(z2, oracle.PC.ras(A2, starts, 1).apply(v)) <= 1e-10
-        assert relerr(z2, oracle.PC.ras(A, starts, 1).apply(v)) > 1e-3
+        assert relerr(z2, _ras_pc(A2, grid, ras).apply(v)) <= 1e-10
+        assert relerr(z2, _ras_pc(A, grid, ras).apply(v)) > 1e-3
         # and the matrix itself now multiplies with the new values
         xt, xh = g.vec()
         K.MatVecMXY(g.A, vh, xh)
         torch.cuda.synchronize()
         assert relerr(xt.cpu().numpy(), oracle.spmv(A2, v)) <= 1e-13
+        K.SolverDestroy(S)
+    finally:
+        g.close()
+
+
+# ---- RAS on boxes of the grid (grown in every direction, one launch per sweep) ----
+@pytest.mark.parametrize("grid,parts,overlap", [((13, 11, 9), (2, 2, 1), 1),
+                                                ((13, 11, 9), (3, 2, 2), 2),
+                                                ((13, 11, 9), (2, 3, 2), 0),
+                                                ((24, 20, 12), (2, 2, 3), 1),
+                                                ((32, 32, 16), (1, 4, 4), 1),
+                                                ((32, 32, 16), (2, 2, 2), 1)])
+def test_ras_box_apply_parity(grid, parts, overlap):
+    s = ri.blackoil_system(*grid, seed=19)
+    A = oracle.Matrix.from_system(s)
+    v = np.random.default_rng(20).standard_normal(A.n)
+    ref = oracle.PC.ras_sets(A, *box_partition(grid, parts, overlap)).apply(v)
+    g = GpuSystem(s)
+    try:
+        zs = pc_apply(g, K.KRY_PC_RAS, v, ras=(*parts, overlap), repeat=2)
+    finally:
+        g.close()
+    assert np.array_equal(zs[0], zs[1])
+    assert relerr(zs[1], ref) <= 1e-10
+
+
+def test_ras_box_scalar_parity():
+    grid = (16, 12, 10)
+    s = ri.scalar_system(*grid, seed=21)
+    A = oracle.Matrix.from_system(s)
+    v = np.random.default_rng(22).standard_normal(A.n)
+    ref = oracle.PC.ras_sets(A, *box_partition(grid, (2, 2, 2), 1)).apply(v)
+    g = GpuSystem(s)
+    try:
+        z = pc_apply(g, K.KRY_PC_RAS, v, ras=(2, 2, 2, 1))
+    finally:
+        g.close()
+    assert relerr(z, ref) <= 1e-10
+
+
+def test_ras_boxes_on_slabs_equal_ras():
+    # px = py = 1 boxes are the z-slabs: the same subdomains, the same result
+    grid = (16, 12, 12)
+    s = ri.blackoil_system(*grid, seed=23)
+    v = np.random.default_rng(24).standard_normal(s["b"].size)
+    g = GpuSystem(s)
+    try:
+        zb = pc_apply(g, K.KRY_PC_RAS, v, ras=(1, 1, 3, 2))
+        zs = pc_apply(g, K.KRY_PC_RAS, v, ras=(3, 2))
+    finally:
+        g.close()
+    assert np.array_equal(zb, zs)
+
+
+def test_ras_box_solve():
+    grid = (32, 32, 16)
+    s = ri.blackoil_system(*grid, seed=11)
+    A = oracle.Matrix.from_system(s)
+    g = GpuSystem(s)
+    try:
+        gpu = solve(g, K.KRY_GMRES, K.KRY_PC_RAS, rtol=1e-8, maxit=3000, ras=(1, 4, 4, 1))
+    finally:
+        g.close()
+    _check_solve(s, gpu, A, _ras_pc(A, grid, (1, 4, 4, 1)), 1e-8, oracle.gmres, restart=30,
+                 maxit=3000, flexible=False)
+
+
+def test_ras_box_errors():
+    s = ri.blackoil_system(6, 5, 4, seed=1)
+    g = GpuSystem(s)
+    try:
+        # more boxes than cells along x; boxes one cell wide (too thin for
+        # the grid-tiled sweeps)
+        for ras, code in (((7, 1, 1, 1), K.KRY_ERR_ARG), ((6, 1, 1, 0), K.KRY_ERR_UNSUPPORTED)):
+            S = K.SolverCreate(K.KRY_FGMRES, K.KRY_PC_RAS, g.map)
+            K.SolverSetMat(S, g.A)
+            K.SolverSetRASBoxes(S, *ras)
+            with pytest.raises(K.KrylovError) as e:
+                K.SolverAssemble(S)
+            assert e.value.code == code
+            K.SolverDestroy(S)
+        S = K.SolverCreate(K.KRY_FGMRES, K.KRY_PC_RAS, g.map)
+        for bad in ((0, 1, 1, 1), (1, 0, 1, 1), (1, 1, 0, 1), (1, 1, 1, -1)):
+            with pytest.raises(K.KrylovError):
+                K.SolverSetRASBoxes(S, *bad)
         K.SolverDestroy(S)
     finally:
         g.close()
