@@ -23,7 +23,7 @@ _SRC = os.path.join(_HERE, "oracle.c")
 OK, NOT_CONVERGED, ERR_ARG, ERR_ZERO_PIVOT, ERR_BREAKDOWN = 0, 1, -1, -4, -5
 PREC = {"f64": 0, "f32": 1, "bf16": 2}
 PC_KIND = {"none": 0, "bilu0": 1, "ilu0": 1, "cpr_pf": 2, "cpr_fp": 3,
-           "cpr_fpf": 5, "cpr_ffpf": 6}
+           "cpr_fpf": 5, "cpr_ffpf": 6, "amg": 8}
 
 
 def build(force: bool = True) -> str:
@@ -77,6 +77,20 @@ def load(path: str):
     L.or_conv_loss_grad.argtypes = [I, I, I, P, P, P, P, P, I]
     L.or_conv_loss_grad.restype = D
     L.or_adam_step.argtypes = [I, P, P, P, P, I, D, D, D, D]
+    L.or_amg_defaults.argtypes = [P]
+    L.or_amg_create.argtypes = [I, P, P, P, P, C.POINTER(I)]
+    L.or_amg_create.restype = P
+    L.or_amg_vcycle.argtypes = [P, P, P]
+    L.or_amg_destroy.argtypes = [P]
+    L.or_amg_strength.argtypes = [I, P, P, P, D, D, P, P]
+    L.or_amg_strength.restype = I
+    L.or_amg_nlevels.argtypes = [P]
+    L.or_amg_nlevels.restype = I
+    L.or_amg_level_size.argtypes = [P, I, C.POINTER(I), C.POINTER(I), C.POINTER(I),
+                                    C.POINTER(I)]
+    L.or_amg_level_get.argtypes = [P, I, P, P, P, P, P, P, P]
+    L.or_pc_create_amg.argtypes = [I, I, I, P, P, P, P, C.POINTER(I)]
+    L.or_pc_create_amg.restype = P
     L.or_gelu.argtypes = [D]
     L.or_gelu.restype = D
     L.or_bf16_round.argtypes = [C.c_float]
@@ -198,6 +212,85 @@ def cpr_pressure_matrix(A: Matrix, w):
     return app
 
 
+class AmgOpts(C.Structure):
+    _fields_ = [("strength", C.c_double), ("max_row_sum", C.c_double), ("trunc", C.c_double),
+                ("max_levels", C.c_int), ("num_sweeps", C.c_int), ("gs_chunk", C.c_int),
+                ("coarse_size", C.c_int)]
+
+    @classmethod
+    def make(cls, **kw):
+        """Figure 34's defaults, with keyword overrides."""
+        o = cls()
+        lib().or_amg_defaults(C.byref(o))
+        for k, v in kw.items():
+            if k not in dict(cls._fields_):
+                raise KeyError(k)
+            setattr(o, k, v)
+        return o
+
+
+def amg_strength(A: Matrix, theta=0.5, max_row_sum=0.9):
+    """Strong dependencies of every row as a CSR pattern (srp, sci)."""
+    srp = np.empty(A.nb + 1, dtype=np.int32)
+    sci = np.empty(max(1, int(A.rowptr[-1])), dtype=np.int32)
+    m = lib().or_amg_strength(A.nb, _p(A.rowptr), _p(A.col), _p(A.val), float(theta),
+                              float(max_row_sum), _p(srp), _p(sci))
+    return srp, sci[:m].copy()
+
+
+class AMG:
+    """Oracle AMG hierarchy of a scalar matrix (Algorithm 3 on every level);
+    vcycle(b) is Algorithm 4 from x = 0."""
+
+    def __init__(self, A: Matrix, **opts):
+        if A.bs != 1:
+            raise ValueError("AMG takes a scalar matrix")
+        self.A = A
+        self.opts = AmgOpts.make(**opts)
+        err = C.c_int(0)
+        self.h = lib().or_amg_create(A.nb, _p(A.rowptr), _p(A.col), _p(A.val),
+                                     C.byref(self.opts), C.byref(err))
+        self.err = err.value
+        if not self.h:
+            raise RuntimeError(f"oracle AMG setup failed: {self.err}")
+
+    def vcycle(self, b):
+        b = _f64(b)
+        x = np.empty(self.A.n)
+        lib().or_amg_vcycle(self.h, _p(b), _p(x))
+        return x
+
+    @property
+    def nlevels(self):
+        return lib().or_amg_nlevels(self.h)
+
+    def level(self, l):
+        """dict(A=(rp, ci, a), cf, P=(rp, ci, v), n, nc); cf and P are None
+        on the coarsest level"""
+        n, nnz, nc, pnnz = (C.c_int() for _ in range(4))
+        lib().or_amg_level_size(self.h, l, C.byref(n), C.byref(nnz), C.byref(nc),
+                                C.byref(pnnz))
+        n, nnz, nc, pnnz = n.value, nnz.value, nc.value, pnnz.value
+        rp = np.empty(n + 1, dtype=np.int32)
+        ci = np.empty(max(nnz, 1), dtype=np.int32)
+        a = np.empty(max(nnz, 1))
+        cf = np.empty(max(n, 1), dtype=np.int32)
+        prp = np.empty(n + 1, dtype=np.int32)
+        pci = np.empty(max(pnnz, 1), dtype=np.int32)
+        pv = np.empty(max(pnnz, 1))
+        lib().or_amg_level_get(self.h, l, _p(rp), _p(ci), _p(a), _p(cf), _p(prp), _p(pci),
+                               _p(pv))
+        coarse = l == self.nlevels - 1
+        return dict(n=n, nc=nc, A=(rp, ci[:nnz], a[:nnz]),
+                    cf=None if coarse else cf[:n],
+                    P=None if coarse else (prp, pci[:pnnz], pv[:pnnz]))
+
+    def __del__(self):
+        if getattr(self, "h", None):
+            lib().or_amg_destroy(self.h)
+            self.h = None
+
+
 class PC:
     """Oracle preconditioner: kind in none/bilu0/cpr_pf/cpr_fp/cpr_fpf/
     cpr_ffpf, precision
@@ -223,6 +316,21 @@ class PC:
         obj.h = lib().or_pc_create_learned(base.h, nx, ny, nz, _p(params),
                                            _p(lnk), int(bf16))
         base.h = None      # ownership moved
+        return obj
+
+    @classmethod
+    def amg(cls, A: "Matrix", kind="amg", **opts):
+        """AMG preconditioners (FP64): kind "amg", one V-cycle on a scalar
+        matrix; or a CPR kind whose pressure stage is one V-cycle on A_pp."""
+        obj = cls.__new__(cls)
+        obj.A = A
+        obj._opts = AmgOpts.make(**opts)
+        err = C.c_int(0)
+        obj.h = lib().or_pc_create_amg(PC_KIND[kind], *A.args(), C.byref(obj._opts),
+                                       C.byref(err))
+        obj.err = err.value
+        if not obj.h:
+            raise RuntimeError(f"oracle AMG setup failed: {obj.err}")
         return obj
 
     @classmethod

@@ -381,6 +381,563 @@ void or_cpr_extract_pressure(int nb, const int *rp, const int *ci,
 }
 
 /* ======================================================================
+ * Algebraic multigrid (Section 4.2: Algorithms 3 and 4, eq. (4), the
+ * defaults of Figure 34).  Classical Ruge-Stueben AMG on a scalar CSR
+ * matrix, one level at a time (Algorithm 3):
+ *   strength       j is a strong dependency of i when
+ *                  -s a_ij >= theta max_{k != i} (-s a_ik), s = sign(a_ii);
+ *                  a row with |sum_j a_ij| > max_row_sum |a_ii| has none
+ *   coarse points  Ruge-Stueben first pass (the undecided point on which
+ *                  most undecided points strongly depend becomes C, ties to
+ *                  the smallest index; the points depending on it become F)
+ *                  and second pass (a strong F-F pair shares a C point)
+ *   interpolation  classical: an F point interpolates from its strong C
+ *                  points; its strong F neighbours are distributed over
+ *                  them through their entries of sign opposite to their
+ *                  diagonal (the "modified" restriction), weak neighbours
+ *                  are lumped into the diagonal; weights below trunc times
+ *                  the row's largest are dropped and the row rescaled to
+ *                  keep its sum
+ *   restriction    R = P^T; coarse matrix A_{l+1} = R A_l P (eq. (4))
+ *   smoother       hybrid Gauss-Seidel, forward: Gauss-Seidel inside
+ *                  contiguous chunks of gs_chunk rows (all rows when <= 0),
+ *                  Jacobi between chunks; num_sweeps sweeps before and
+ *                  after the coarse correction
+ *   cycle          V-cycle from x = 0 on every level (Algorithm 4), the
+ *                  coarsest level solved exactly (dense LU)
+ * Rounding order, where it decides a later integer choice: row sums and
+ * maxima in ascending column order; (A P)_iJ = sum over the entries of row
+ * i of A in ascending order of a_ik P_kJ; (R (A P))_IJ = sum over the
+ * entries of row I of R in ascending order of R_Ii (A P)_iJ.
+ * ====================================================================== */
+void or_amg_defaults(or_amg_opts *o)
+{
+    o->strength = 0.5;
+    o->max_row_sum = 0.9;
+    o->trunc = 1e-2;
+    o->max_levels = 8;
+    o->num_sweeps = 2;
+    o->gs_chunk = 0;
+    o->coarse_size = 9;
+}
+
+typedef struct {
+    int n, nc;
+    int *rp, *ci; double *a;            /* A_l                          */
+    int *cf;                            /* 1 = C point, 0 = F point     */
+    int *prp, *pci; double *pv;         /* P_l, n x nc                  */
+    int *trp, *tci; double *tv;         /* R_l = P_l^T, nc x n          */
+    double *lu; int *piv;               /* coarsest level: dense LU     */
+    double *x, *b, *r, *t;
+} amg_level;
+
+struct or_amg {
+    or_amg_opts o;
+    int nlev;
+    amg_level *lev;
+};
+
+/* strong dependencies S_i of every row, ascending; sci holds rp[n] ints */
+int or_amg_strength(int n, const int *rp, const int *ci, const double *a,
+                    double theta, double max_row_sum, int *srp, int *sci)
+{
+    int m = 0;
+    srp[0] = 0;
+    for (int i = 0; i < n; i++) {
+        double diag = 0.0, rsum = 0.0, mx = 0.0;
+        for (int q = rp[i]; q < rp[i + 1]; q++) {
+            if (ci[q] == i) diag = a[q];
+            rsum += a[q];
+        }
+        const double s = diag < 0.0 ? -1.0 : 1.0;
+        for (int q = rp[i]; q < rp[i + 1]; q++)
+            if (ci[q] != i && -s * a[q] > mx) mx = -s * a[q];
+        const int dependent = !(max_row_sum < 1.0 && fabs(rsum) > max_row_sum * fabs(diag));
+        if (dependent && mx > 0.0)
+            for (int q = rp[i]; q < rp[i + 1]; q++)
+                if (ci[q] != i && -s * a[q] >= theta * mx) sci[m++] = ci[q];
+        srp[i + 1] = m;
+    }
+    return m;
+}
+
+/* transpose of a pattern (rows of the result ascending) */
+static void pattern_transpose(int n, int m, const int *rp, const int *ci, int *trp, int *tci,
+                              const double *v, double *tv)
+{
+    for (int j = 0; j <= m; j++) trp[j] = 0;
+    for (int q = 0; q < rp[n]; q++) trp[ci[q] + 1]++;
+    for (int j = 0; j < m; j++) trp[j + 1] += trp[j];
+    int *fill = (int *)malloc(sizeof(int) * (size_t)(m + 1));
+    memcpy(fill, trp, sizeof(int) * (size_t)(m + 1));
+    for (int i = 0; i < n; i++)
+        for (int q = rp[i]; q < rp[i + 1]; q++) {
+            const int p = fill[ci[q]]++;
+            tci[p] = i;
+            if (v) tv[p] = v[q];
+        }
+    free(fill);
+}
+
+/* binary max-heap on (measure, -index) */
+typedef struct { int lam, i; } amg_hent;
+typedef struct { amg_hent *h; int n, cap; } amg_heap;
+
+static int hfirst(amg_hent a, amg_hent b) { return a.lam > b.lam || (a.lam == b.lam && a.i < b.i); }
+
+static void heap_push(amg_heap *H, int lam, int i)
+{
+    if (H->n == H->cap) {
+        H->cap = H->cap ? 2 * H->cap : 64;
+        H->h = (amg_hent *)realloc(H->h, sizeof(amg_hent) * (size_t)H->cap);
+    }
+    int c = H->n++;
+    H->h[c].lam = lam; H->h[c].i = i;
+    while (c > 0) {
+        int p = (c - 1) / 2;
+        if (!hfirst(H->h[c], H->h[p])) break;
+        amg_hent t = H->h[c]; H->h[c] = H->h[p]; H->h[p] = t;
+        c = p;
+    }
+}
+
+static amg_hent heap_pop(amg_heap *H)
+{
+    amg_hent top = H->h[0];
+    H->h[0] = H->h[--H->n];
+    int c = 0;
+    for (;;) {
+        int l = 2 * c + 1, r = l + 1, b = c;
+        if (l < H->n && hfirst(H->h[l], H->h[b])) b = l;
+        if (r < H->n && hfirst(H->h[r], H->h[b])) b = r;
+        if (b == c) break;
+        amg_hent t = H->h[c]; H->h[c] = H->h[b]; H->h[b] = t;
+        c = b;
+    }
+    return top;
+}
+
+/* C/F splitting: cf[i] = 1 (C) or 0 (F) */
+static void amg_coarsen(int n, const int *srp, const int *sci, const int *trp,
+                        const int *tci, int *cf)
+{
+    enum { UND = -1, FPT = 0, CPT = 1 };
+    int *lam = (int *)malloc(sizeof(int) * (size_t)(n + 1));
+    amg_heap H = { NULL, 0, 0 };
+    for (int i = 0; i < n; i++) {
+        lam[i] = trp[i + 1] - trp[i];               /* points depending on i */
+        cf[i] = (srp[i + 1] == srp[i] && lam[i] == 0) ? FPT : UND;
+        if (cf[i] == UND) heap_push(&H, lam[i], i);
+    }
+    /* first pass */
+    while (H.n > 0) {
+        const amg_hent e = heap_pop(&H);
+        const int i = e.i;
+        if (cf[i] != UND || e.lam != lam[i]) continue;   /* stale entry */
+        if (lam[i] == 0) { cf[i] = FPT; continue; }
+        cf[i] = CPT;
+        for (int q = trp[i]; q < trp[i + 1]; q++) {      /* j depends on i */
+            const int j = tci[q];
+            if (cf[j] != UND) continue;
+            cf[j] = FPT;
+            for (int p = srp[j]; p < srp[j + 1]; p++) {  /* j depends on k */
+                const int k = sci[p];
+                if (cf[k] == UND) { lam[k]++; heap_push(&H, lam[k], k); }
+            }
+        }
+        for (int q = srp[i]; q < srp[i + 1]; q++) {      /* i depends on j */
+            const int j = sci[q];
+            if (cf[j] == UND) { lam[j]--; heap_push(&H, lam[j], j); }
+        }
+    }
+    free(H.h);
+    /* second pass: every strong F neighbour j of an F point i must depend
+     * strongly on a C point of i; one offender becomes C, a second one
+     * makes i itself C instead */
+    int *mark = (int *)malloc(sizeof(int) * (size_t)(n + 1));
+    for (int i = 0; i < n; i++) mark[i] = -1;
+    for (int i = 0; i < n; i++) {
+        if (cf[i] != FPT) continue;
+        for (int q = srp[i]; q < srp[i + 1]; q++)
+            if (cf[sci[q]] == CPT) mark[sci[q]] = i;
+        int tent = -1;
+        for (int q = srp[i]; q < srp[i + 1] && cf[i] == FPT; q++) {
+            const int j = sci[q];
+            if (cf[j] != FPT || j == tent) continue;
+            int common = 0;
+            for (int p = srp[j]; p < srp[j + 1] && !common; p++)
+                common = mark[sci[p]] == i;
+            if (common) continue;
+            if (tent >= 0) cf[i] = CPT;
+            else { tent = j; mark[j] = i; }
+        }
+        if (cf[i] == FPT && tent >= 0) cf[tent] = CPT;
+    }
+    free(mark);
+    free(lam);
+}
+
+static int opposite(double akk, double akm)
+{
+    return (akk > 0.0 && akm < 0.0) || (akk < 0.0 && akm > 0.0);
+}
+
+/* classical interpolation with truncation; P rows: C point -> its coarse
+ * number with weight 1, F point -> its strong C points */
+static int amg_interp(int n, const int *rp, const int *ci, const double *a, const int *srp,
+                      const int *sci, const int *cf, double trunc, int *nc_out,
+                      int **prp_o, int **pci_o, double **pv_o)
+{
+    int *cmap = (int *)malloc(sizeof(int) * (size_t)(n + 1));
+    int nc = 0;
+    for (int i = 0; i < n; i++) cmap[i] = cf[i] ? nc++ : -1;
+    int *prp = (int *)malloc(sizeof(int) * (size_t)(n + 1));
+    int cap = srp[n] + n + 1;
+    int *pci = (int *)malloc(sizeof(int) * (size_t)cap);
+    double *pv = (double *)malloc(sizeof(double) * (size_t)cap);
+    int *sm = (int *)malloc(sizeof(int) * (size_t)(n + 1));   /* strong stamp */
+    int *pos = (int *)malloc(sizeof(int) * (size_t)(n + 1));  /* place in C_i */
+    int *cl = (int *)malloc(sizeof(int) * (size_t)(n + 1));
+    double *num = (double *)malloc(sizeof(double) * (size_t)(n + 1));
+    for (int i = 0; i < n; i++) { sm[i] = -1; pos[i] = -1; }
+    int m = 0, e = OR_OK;
+    prp[0] = 0;
+    for (int i = 0; i < n && !e; i++) {
+        if (cf[i]) {
+            pci[m] = cmap[i]; pv[m] = 1.0; m++;
+            prp[i + 1] = m;
+            continue;
+        }
+        int nci = 0;
+        for (int q = srp[i]; q < srp[i + 1]; q++) {
+            const int j = sci[q];
+            sm[j] = i;
+            if (cf[j]) { pos[j] = nci; cl[nci] = j; num[nci] = 0.0; nci++; }
+        }
+        if (nci == 0) { prp[i + 1] = m; continue; }
+        double diag = 0.0;
+        for (int q = rp[i]; q < rp[i + 1]; q++) if (ci[q] == i) diag = a[q];
+        for (int q = rp[i]; q < rp[i + 1]; q++) {
+            const int j = ci[q];
+            if (j == i) continue;
+            const int strong = sm[j] == i;
+            if (strong && cf[j]) {
+                num[pos[j]] += a[q];
+            } else if (strong) {                 /* strong F neighbour k = j */
+                double akk = 0.0, den = 0.0;
+                for (int p = rp[j]; p < rp[j + 1]; p++) if (ci[p] == j) akk = a[p];
+                for (int p = rp[j]; p < rp[j + 1]; p++) {
+                    const int mm = ci[p];
+                    if (sm[mm] == i && cf[mm] && pos[mm] >= 0 && opposite(akk, a[p])) den += a[p];
+                }
+                if (den == 0.0) {
+                    diag += a[q];
+                } else {
+                    for (int p = rp[j]; p < rp[j + 1]; p++) {
+                        const int mm = ci[p];
+                        if (sm[mm] == i && cf[mm] && opposite(akk, a[p]))
+                            num[pos[mm]] += a[q] * a[p] / den;
+                    }
+                }
+            } else {
+                diag += a[q];                    /* weak: lumped */
+            }
+        }
+        if (diag == 0.0) { e = OR_ERR_ZERO_PIVOT; break; }
+        double mx = 0.0, sum_all = 0.0, sum_kept = 0.0;
+        for (int t = 0; t < nci; t++) {
+            num[t] = -num[t] / diag;
+            if (fabs(num[t]) > mx) mx = fabs(num[t]);
+            sum_all += num[t];
+        }
+        for (int t = 0; t < nci; t++)
+            if (fabs(num[t]) >= trunc * mx) sum_kept += num[t];
+        const double scale = sum_kept != 0.0 ? sum_all / sum_kept : 1.0;
+        for (int t = 0; t < nci; t++)
+            if (fabs(num[t]) >= trunc * mx) {
+                pci[m] = cmap[cl[t]];
+                pv[m] = num[t] * scale;
+                m++;
+            }
+        for (int t = 0; t < nci; t++) pos[cl[t]] = -1;
+        prp[i + 1] = m;
+    }
+    free(sm); free(pos); free(cl); free(num); free(cmap);
+    if (e) { free(prp); free(pci); free(pv); return e; }
+    *nc_out = nc; *prp_o = prp; *pci_o = pci; *pv_o = pv;
+    return OR_OK;
+}
+
+static int cmp_int(const void *x, const void *y)
+{
+    const int a = *(const int *)x, b = *(const int *)y;
+    return (a > b) - (a < b);
+}
+
+/* C = A B (row-wise, contributions in ascending order of A's entries);
+ * columns of every row ascending; returns the allocated product */
+static void csr_mult(int n, int k, int m, const int *arp, const int *aci, const double *av,
+                     const int *brp, const int *bci, const double *bv,
+                     int **crp_o, int **cci_o, double **cv_o)
+{
+    (void)k;
+    int *crp = (int *)malloc(sizeof(int) * (size_t)(n + 1));
+    int *stamp = (int *)malloc(sizeof(int) * (size_t)(m + 1));
+    int *list = (int *)malloc(sizeof(int) * (size_t)(m + 1));
+    double *acc = (double *)malloc(sizeof(double) * (size_t)(m + 1));
+    for (int j = 0; j < m; j++) stamp[j] = -1;
+    size_t cap = 1024, nnz = 0;
+    int *cci = (int *)malloc(sizeof(int) * cap);
+    double *cv = (double *)malloc(sizeof(double) * cap);
+    crp[0] = 0;
+    for (int i = 0; i < n; i++) {
+        int len = 0;
+        for (int q = arp[i]; q < arp[i + 1]; q++) {
+            const int kk = aci[q];
+            for (int p = brp[kk]; p < brp[kk + 1]; p++) {
+                const int j = bci[p];
+                if (stamp[j] != i) { stamp[j] = i; acc[j] = 0.0; list[len++] = j; }
+                acc[j] += av[q] * bv[p];
+            }
+        }
+        qsort(list, (size_t)len, sizeof(int), cmp_int);
+        if (nnz + (size_t)len > cap) {
+            while (nnz + (size_t)len > cap) cap *= 2;
+            cci = (int *)realloc(cci, sizeof(int) * cap);
+            cv = (double *)realloc(cv, sizeof(double) * cap);
+        }
+        for (int t = 0; t < len; t++) { cci[nnz] = list[t]; cv[nnz] = acc[list[t]]; nnz++; }
+        crp[i + 1] = (int)nnz;
+    }
+    free(stamp); free(list); free(acc);
+    *crp_o = crp; *cci_o = cci; *cv_o = cv;
+}
+
+/* dense LU with partial pivoting (first largest pivot) */
+static int dense_lu(int n, double *M, int *piv)
+{
+    for (int k = 0; k < n; k++) {
+        int p = k;
+        for (int i = k + 1; i < n; i++)
+            if (fabs(M[(size_t)i * n + k]) > fabs(M[(size_t)p * n + k])) p = i;
+        piv[k] = p;
+        if (M[(size_t)p * n + k] == 0.0) return OR_ERR_ZERO_PIVOT;
+        if (p != k)
+            for (int j = 0; j < n; j++) {
+                double t = M[(size_t)k * n + j];
+                M[(size_t)k * n + j] = M[(size_t)p * n + j];
+                M[(size_t)p * n + j] = t;
+            }
+        for (int i = k + 1; i < n; i++) {
+            const double l = M[(size_t)i * n + k] / M[(size_t)k * n + k];
+            M[(size_t)i * n + k] = l;
+            for (int j = k + 1; j < n; j++) M[(size_t)i * n + j] -= l * M[(size_t)k * n + j];
+        }
+    }
+    return OR_OK;
+}
+
+static void dense_lu_solve(int n, const double *M, const int *piv, double *x)
+{
+    for (int k = 0; k < n; k++)
+        if (piv[k] != k) { double t = x[k]; x[k] = x[piv[k]]; x[piv[k]] = t; }
+    for (int i = 0; i < n; i++)
+        for (int j = 0; j < i; j++) x[i] -= M[(size_t)i * n + j] * x[j];
+    for (int i = n - 1; i >= 0; i--) {
+        for (int j = i + 1; j < n; j++) x[i] -= M[(size_t)i * n + j] * x[j];
+        x[i] /= M[(size_t)i * n + i];
+    }
+}
+
+static void amg_level_free(amg_level *L)
+{
+    free(L->rp); free(L->ci); free(L->a); free(L->cf);
+    free(L->prp); free(L->pci); free(L->pv);
+    free(L->trp); free(L->tci); free(L->tv);
+    free(L->lu); free(L->piv);
+    free(L->x); free(L->b); free(L->r); free(L->t);
+}
+
+void or_amg_destroy(or_amg *M)
+{
+    if (!M) return;
+    for (int l = 0; l < M->nlev; l++) amg_level_free(&M->lev[l]);
+    free(M->lev);
+    free(M);
+}
+
+or_amg *or_amg_create(int n, const int *rp, const int *ci, const double *a,
+                      const or_amg_opts *opts, int *err)
+{
+    or_amg_opts o;
+    if (opts) o = *opts; else or_amg_defaults(&o);
+    int e = OR_OK;
+    if (n < 1 || o.max_levels < 1 || o.num_sweeps < 0) e = OR_ERR_ARG;
+    if (e) { if (err) *err = e; return NULL; }
+    or_amg *M = (or_amg *)calloc(1, sizeof(or_amg));
+    M->o = o;
+    M->lev = (amg_level *)calloc((size_t)o.max_levels, sizeof(amg_level));
+    amg_level *L = &M->lev[0];
+    L->n = n;
+    L->rp = (int *)malloc(sizeof(int) * (size_t)(n + 1));
+    L->ci = (int *)malloc(sizeof(int) * (size_t)(rp[n] + 1));
+    L->a = (double *)malloc(sizeof(double) * (size_t)(rp[n] + 1));
+    memcpy(L->rp, rp, sizeof(int) * (size_t)(n + 1));
+    memcpy(L->ci, ci, sizeof(int) * (size_t)rp[n]);
+    memcpy(L->a, a, sizeof(double) * (size_t)rp[n]);
+    M->nlev = 1;
+    for (int l = 0; !e; l++) {
+        L = &M->lev[l];
+        const int nl = L->n;
+        L->x = (double *)calloc((size_t)nl + 1, sizeof(double));
+        L->b = (double *)calloc((size_t)nl + 1, sizeof(double));
+        L->r = (double *)calloc((size_t)nl + 1, sizeof(double));
+        L->t = (double *)calloc((size_t)nl + 1, sizeof(double));
+        int coarsest = l == o.max_levels - 1 || nl <= o.coarse_size;
+        if (!coarsest) {
+            const int nnz = L->rp[nl];
+            int *srp = (int *)malloc(sizeof(int) * (size_t)(nl + 1));
+            int *sci = (int *)malloc(sizeof(int) * (size_t)(nnz + 1));
+            or_amg_strength(nl, L->rp, L->ci, L->a, o.strength, o.max_row_sum, srp, sci);
+            int *trp = (int *)malloc(sizeof(int) * (size_t)(nl + 1));
+            int *tci = (int *)malloc(sizeof(int) * (size_t)(srp[nl] + 1));
+            pattern_transpose(nl, nl, srp, sci, trp, tci, NULL, NULL);
+            L->cf = (int *)malloc(sizeof(int) * (size_t)(nl + 1));
+            amg_coarsen(nl, srp, sci, trp, tci, L->cf);
+            free(trp); free(tci);
+            e = amg_interp(nl, L->rp, L->ci, L->a, srp, sci, L->cf, o.trunc, &L->nc,
+                           &L->prp, &L->pci, &L->pv);
+            free(srp); free(sci);
+            if (e) break;
+            if (L->nc == 0 || L->nc == nl) {           /* no coarsening */
+                free(L->cf); free(L->prp); free(L->pci); free(L->pv);
+                L->cf = NULL; L->prp = NULL; L->pci = NULL; L->pv = NULL;
+                L->nc = 0;
+                coarsest = 1;
+            }
+        }
+        if (coarsest) {
+            L->lu = (double *)calloc((size_t)nl * nl, sizeof(double));
+            L->piv = (int *)malloc(sizeof(int) * (size_t)nl);
+            for (int i = 0; i < nl; i++)
+                for (int q = L->rp[i]; q < L->rp[i + 1]; q++)
+                    L->lu[(size_t)i * nl + L->ci[q]] = L->a[q];
+            e = dense_lu(nl, L->lu, L->piv);
+            break;
+        }
+        /* R = P^T, A_{l+1} = R (A P) */
+        const int nc = L->nc;
+        L->trp = (int *)malloc(sizeof(int) * (size_t)(nc + 1));
+        L->tci = (int *)malloc(sizeof(int) * (size_t)(L->prp[nl] + 1));
+        L->tv = (double *)malloc(sizeof(double) * (size_t)(L->prp[nl] + 1));
+        pattern_transpose(nl, nc, L->prp, L->pci, L->trp, L->tci, L->pv, L->tv);
+        int *aprp, *apci;
+        double *apv;
+        csr_mult(nl, nl, nc, L->rp, L->ci, L->a, L->prp, L->pci, L->pv, &aprp, &apci, &apv);
+        amg_level *Lc = &M->lev[l + 1];
+        Lc->n = nc;
+        csr_mult(nc, nl, nc, L->trp, L->tci, L->tv, aprp, apci, apv, &Lc->rp, &Lc->ci, &Lc->a);
+        free(aprp); free(apci); free(apv);
+        M->nlev = l + 2;
+    }
+    if (err) *err = e;
+    if (e) { or_amg_destroy(M); return NULL; }
+    return M;
+}
+
+/* one hybrid Gauss-Seidel sweep: xn from xo */
+static void amg_hgs(const amg_level *L, int chunk, const double *b, const double *xo, double *xn)
+{
+    const int n = L->n, c = chunk > 0 ? chunk : n;
+    for (int i = 0; i < n; i++) {
+        const int c0 = i / c * c;
+        double s = b[i], d = 0.0;
+        for (int q = L->rp[i]; q < L->rp[i + 1]; q++) {
+            const int j = L->ci[q];
+            if (j == i) d = L->a[q];
+            else if (j >= c0 && j < i) s -= L->a[q] * xn[j];
+            else s -= L->a[q] * xo[j];
+        }
+        xn[i] = s / d;
+    }
+}
+
+static void amg_smooth(const or_amg *M, amg_level *L)
+{
+    for (int s = 0; s < M->o.num_sweeps; s++) {
+        amg_hgs(L, M->o.gs_chunk, L->b, L->x, L->t);
+        memcpy(L->x, L->t, sizeof(double) * (size_t)L->n);
+    }
+}
+
+static void amg_cycle(or_amg *M, int l)
+{
+    amg_level *L = &M->lev[l];
+    const int n = L->n;
+    if (l == M->nlev - 1) {
+        memcpy(L->x, L->b, sizeof(double) * (size_t)n);
+        dense_lu_solve(n, L->lu, L->piv, L->x);
+        return;
+    }
+    amg_level *Lc = &M->lev[l + 1];
+    for (int i = 0; i < n; i++) L->x[i] = 0.0;
+    amg_smooth(M, L);                                     /* x = S(x, A, b) */
+    for (int i = 0; i < n; i++) {                         /* r = b - A x    */
+        double s = L->b[i];
+        for (int q = L->rp[i]; q < L->rp[i + 1]; q++) s -= L->a[q] * L->x[L->ci[q]];
+        L->r[i] = s;
+    }
+    for (int I = 0; I < L->nc; I++) {                     /* b_c = R r      */
+        double s = 0.0;
+        for (int q = L->trp[I]; q < L->trp[I + 1]; q++) s += L->tv[q] * L->r[L->tci[q]];
+        Lc->b[I] = s;
+    }
+    amg_cycle(M, l + 1);
+    for (int i = 0; i < n; i++) {                         /* x += P x_c     */
+        double s = 0.0;
+        for (int q = L->prp[i]; q < L->prp[i + 1]; q++) s += L->pv[q] * Lc->x[L->pci[q]];
+        L->x[i] += s;
+    }
+    amg_smooth(M, L);                                     /* x = T(x, A, b) */
+}
+
+void or_amg_vcycle(or_amg *M, const double *b, double *x)
+{
+    memcpy(M->lev[0].b, b, sizeof(double) * (size_t)M->lev[0].n);
+    amg_cycle(M, 0);
+    memcpy(x, M->lev[0].x, sizeof(double) * (size_t)M->lev[0].n);
+}
+
+int or_amg_nlevels(const or_amg *M) { return M->nlev; }
+
+/* sizes of level l: rows, entries of A_l, coarse rows and entries of P_l
+ * (0 on the coarsest level) */
+void or_amg_level_size(const or_amg *M, int l, int *n, int *nnz, int *nc, int *pnnz)
+{
+    const amg_level *L = &M->lev[l];
+    *n = L->n;
+    *nnz = L->rp[L->n];
+    *nc = l < M->nlev - 1 ? L->nc : 0;
+    *pnnz = l < M->nlev - 1 ? L->prp[L->n] : 0;
+}
+
+void or_amg_level_get(const or_amg *M, int l, int *rp, int *ci, double *a, int *cf,
+                      int *prp, int *pci, double *pv)
+{
+    const amg_level *L = &M->lev[l];
+    const int n = L->n;
+    memcpy(rp, L->rp, sizeof(int) * (size_t)(n + 1));
+    memcpy(ci, L->ci, sizeof(int) * (size_t)L->rp[n]);
+    memcpy(a, L->a, sizeof(double) * (size_t)L->rp[n]);
+    if (l < M->nlev - 1) {
+        memcpy(cf, L->cf, sizeof(int) * (size_t)n);
+        memcpy(prp, L->prp, sizeof(int) * (size_t)(n + 1));
+        memcpy(pci, L->pci, sizeof(int) * (size_t)L->prp[n]);
+        memcpy(pv, L->pv, sizeof(double) * (size_t)L->prp[n]);
+    }
+}
+
+/* ======================================================================
  * Preconditioner objects (Figure 29)
  * ====================================================================== */
 /* one subdomain of RAS: its number s (it owns the rows r with part[r] =
@@ -406,6 +963,7 @@ struct or_pc {
     double *w, *app, *applu;
     lowp_lu lpp;                /* rounded pressure factor                */
     float *appf, *af;           /* rounded A_pp values, rounded A values  */
+    or_amg *amg;                /* AMG, or CPR's AMG pressure stage       */
     /* learned stage */
     or_pc *base;
     int nx, ny, nz, bf16;
@@ -633,7 +1191,31 @@ void or_pc_destroy(or_pc *pc)
     }
     free(pc->subs);
     free(pc->part);
+    or_amg_destroy(pc->amg);
     free(pc);
+}
+
+or_pc *or_pc_create_amg(int kind, int nb, int bs, const int *rp, const int *ci,
+                        const double *a, const or_amg_opts *o, int *err)
+{
+    const int is_cpr = kind == OR_PC_CPR_PF || kind == OR_PC_CPR_FP ||
+                       kind == OR_PC_CPR_FPF || kind == OR_PC_CPR_FFPF;
+    int e = OR_OK;
+    or_pc *pc = NULL;
+    if (kind == OR_PC_AMG && bs == 1) {
+        pc = (or_pc *)calloc(1, sizeof(or_pc));
+        pc->kind = kind; pc->nb = nb; pc->bs = 1; pc->prec = OR_PREC_F64;
+        pc->rp = rp; pc->ci = ci; pc->a = a;
+        pc->amg = or_amg_create(nb, rp, ci, a, o, &e);
+    } else if (is_cpr && bs == 3) {
+        pc = or_pc_create(kind, nb, bs, rp, ci, a, OR_PREC_F64, 0, &e);
+        if (pc) pc->amg = or_amg_create(nb, rp, ci, pc->app, o, &e);
+    } else {
+        e = OR_ERR_ARG;
+    }
+    if (err) *err = e;
+    if (e) { or_pc_destroy(pc); return NULL; }
+    return pc;
 }
 
 void or_pc_learned_stats(const or_pc *pc, long *applies, long *fallbacks)
@@ -642,10 +1224,15 @@ void or_pc_learned_stats(const or_pc *pc, long *applies, long *fallbacks)
     if (fallbacks) *fallbacks = pc->fallbacks;
 }
 
-/* FP64 pressure stage: p = 0, then s sweeps p <- p + (LU)^-1 (r_p - A_pp p) */
+/* FP64 pressure stage: p = 0, then s sweeps p <- p + (LU)^-1 (r_p - A_pp p);
+ * with AMG, p = one V-cycle on A_pp */
 static void pstage_f64(or_pc *pc, const double *rpv, double *p)
 {
     int nb = pc->nb;
+    if (pc->amg) {
+        or_amg_vcycle(pc->amg, rpv, p);
+        return;
+    }
     double *res = (double *)malloc(sizeof(double) * nb);
     double *d = (double *)malloc(sizeof(double) * nb);
     for (int i = 0; i < nb; i++) p[i] = 0.0;
@@ -796,6 +1383,10 @@ void or_pc_apply(or_pc *pc, const double *v, double *z)
     }
     if (pc->kind == OR_PC_RAS) {
         ras_apply(pc, v, z);
+        return;
+    }
+    if (pc->kind == OR_PC_AMG) {
+        or_amg_vcycle(pc->amg, v, z);
         return;
     }
     if (pc->prec == OR_PREC_F64) {

@@ -55,10 +55,39 @@ void or_bilu0_solve_lower(int nb, int bs, const int *rp, const int *ci,
 void or_bilu0_solve_upper(int nb, int bs, const int *rp, const int *ci,
                           const double *lu, const double *y, double *x);
 
+/* ---- algebraic multigrid (Section 4.2, Algorithms 3-4, Figure 34) ------ */
+typedef struct {
+    double strength;      /* strength threshold theta (0.5)                   */
+    double max_row_sum;   /* rows with |row sum| > this * |diagonal| are weak (0.9) */
+    double trunc;         /* interpolation truncation factor (1e-2)           */
+    int max_levels;       /* levels including the coarsest (8)                */
+    int num_sweeps;       /* smoothing sweeps before and after (2)            */
+    int gs_chunk;         /* rows per Gauss-Seidel chunk; <= 0: all rows (0)  */
+    int coarse_size;      /* a level this small is the coarsest (9)           */
+} or_amg_opts;
+typedef struct or_amg or_amg;
+void or_amg_defaults(or_amg_opts *o);
+/* hierarchy of a scalar CSR matrix (Algorithm 3 on every level) */
+or_amg *or_amg_create(int n, const int *rp, const int *ci, const double *a,
+                      const or_amg_opts *o, int *err);
+/* x = one V-cycle (Algorithm 4) applied to b from x = 0 */
+void or_amg_vcycle(or_amg *M, const double *b, double *x);
+void or_amg_destroy(or_amg *M);
+/* strong dependencies of every row into srp[n+1], sci[<= rp[n]]; returns
+ * their number */
+int or_amg_strength(int n, const int *rp, const int *ci, const double *a,
+                    double theta, double max_row_sum, int *srp, int *sci);
+int or_amg_nlevels(const or_amg *M);
+void or_amg_level_size(const or_amg *M, int l, int *n, int *nnz, int *nc, int *pnnz);
+/* A_l, and (not on the coarsest level) the C/F splitting and P_l */
+void or_amg_level_get(const or_amg *M, int l, int *rp, int *ci, double *a, int *cf,
+                      int *prp, int *pci, double *pv);
+
 /* ---- preconditioner objects (Figure 29: setup / solve / destroy) ------- */
 typedef struct or_pc or_pc;
 enum { OR_PC_NONE = 0, OR_PC_BILU0 = 1, OR_PC_CPR_PF = 2, OR_PC_CPR_FP = 3,
-       OR_PC_LEARNED = 4, OR_PC_CPR_FPF = 5, OR_PC_CPR_FFPF = 6, OR_PC_RAS = 7 };
+       OR_PC_LEARNED = 4, OR_PC_CPR_FPF = 5, OR_PC_CPR_FFPF = 6, OR_PC_RAS = 7,
+       OR_PC_AMG = 8 };
 
 or_pc *or_pc_create(int kind, int nb, int bs, const int *rp, const int *ci,
                     const double *a, int prec, int p_sweeps, int *err);
@@ -85,6 +114,11 @@ or_pc *or_pc_create_ras_sets(int nb, int bs, const int *rp, const int *ci,
 or_pc *or_pc_create_ras(int nb, int bs, const int *rp, const int *ci,
                         const double *a, int nsub, const int *starts,
                         int overlap, int *err);
+/* AMG preconditioners (FP64): kind OR_PC_AMG, one V-cycle on a scalar
+ * matrix (bs = 1); or a CPR kind (bs = 3) whose pressure stage is one
+ * V-cycle on A_pp instead of ILU(0) sweeps */
+or_pc *or_pc_create_amg(int kind, int nb, int bs, const int *rp, const int *ci,
+                        const double *a, const or_amg_opts *o, int *err);
 void or_pc_apply(or_pc *pc, const double *v, double *z);
 void or_pc_destroy(or_pc *pc);
 /* counters of the learned stage: applications and fallbacks */

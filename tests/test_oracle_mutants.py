@@ -7,6 +7,7 @@ import contextlib
 import pytest
 
 import oracle
+from tests import test_oracle_amg as ta
 from tests import test_oracle_cpr_conv as tc
 from tests import test_oracle_krylov as tk
 from tests import test_oracle_linalg as tl
@@ -128,6 +129,53 @@ MUTANTS = [
      "if (n2 < n1) accept = 1;",
      "if (n2 <= n1) accept = 1;",
      [lambda: tc.test_learned_stage_zero_net_falls_back_bit_exactly()]),
+    ("amg_row_sum_rule_ignored",
+     "const int dependent = !(max_row_sum < 1.0 && fabs(rsum) > max_row_sum * fabs(diag));",
+     "const int dependent = 1;",
+     [lambda: ta.test_strength_hand_example()]),
+    ("amg_strength_sign",
+     "if (ci[q] != i && -s * a[q] >= theta * mx) sci[m++] = ci[q];",
+     "if (ci[q] != i && -a[q] >= theta * mx) sci[m++] = ci[q];",
+     [lambda: ta.test_strength_hand_example()]),
+    ("amg_no_second_pass",
+     "        if (cf[i] != FPT) continue;\n        for (int q = srp[i]; q < srp[i + 1]; q++)\n            if (cf[sci[q]] == CPT) mark[sci[q]] = i;",
+     "        continue;\n        for (int q = srp[i]; q < srp[i + 1]; q++)\n            if (cf[sci[q]] == CPT) mark[sci[q]] = i;",
+     [lambda: ta.test_splitting_invariants((8, 7, 6), 2),
+      lambda: ta.test_splitting_invariants((10, 9, 5), 3)]),
+    ("amg_weak_not_lumped",
+     "diag += a[q];                    /* weak: lumped */",
+     "(void)0;                         /* weak: lumped */",
+     [lambda: ta.test_interpolation_keeps_constants_on_zero_row_sums()]),
+    ("amg_distribution_sign",
+     "num[pos[mm]] += a[q] * a[p] / den;",
+     "num[pos[mm]] -= a[q] * a[p] / den;",
+     [lambda: ta.test_interpolation_keeps_constants_on_zero_row_sums()]),
+    ("amg_truncation_not_rescaled",
+     "const double scale = sum_kept != 0.0 ? sum_all / sum_kept : 1.0;",
+     "const double scale = 1.0;",
+     [lambda: ta.test_truncation_drops_small_weights_and_keeps_row_sums()]),
+    ("amg_weight_sign",
+     "num[t] = -num[t] / diag;",
+     "num[t] = num[t] / diag;",
+     [lambda: ta.test_chain_splitting_interpolation_and_galerkin(),
+      lambda: ta.test_vcycle_converges_on_poisson(0)]),
+    ("amg_transpose_values",
+     "if (v) tv[p] = v[q];",
+     "if (v) tv[p] = v[p];",
+     [lambda: ta.test_galerkin_coarse_matrices()]),
+    ("amg_gs_reads_old_inside_chunk",
+     "else if (j >= c0 && j < i) s -= L->a[q] * xn[j];",
+     "else if (j >= c0 && j < i) s -= L->a[q] * xo[j];",
+     [lambda: ta.test_vcycle_matches_dense_algorithm4(4, 2)]),
+    ("amg_no_post_smoothing",
+     "    amg_smooth(M, L);                                     /* x = T(x, A, b) */",
+     "    (void)0;                                              /* x = T(x, A, b) */",
+     [lambda: ta.test_vcycle_matches_dense_algorithm4(0, 2)]),
+    ("amg_coarse_correction_sign",
+     "        L->x[i] += s;",
+     "        L->x[i] -= s;",
+     [lambda: ta.test_vcycle_matches_dense_algorithm4(0, 2),
+      lambda: ta.test_vcycle_converges_on_poisson(0)]),
 ]
 
 
