@@ -59,6 +59,9 @@ CONFIGS = [
     ("gmres30_rasbox_1x4x4_f64", "GMRES", "RAS", "F64", None),
     ("gmres30_rasbox_2x4x4_f64", "GMRES", "RAS", "F64", None),
     ("gmres30_rasbox_2x2x2_f64", "GMRES", "RAS", "F64", None),
+    ("gmres30_ilu0_scalar_f64", "GMRES", "ILU0", "F64", None),
+    ("gmres30_amg_scalar_f64", "GMRES", "AMG", "F64", None),
+    ("fgmres30_cpr_fpf_amg_f64", "FGMRES", "CPR", "F64", ("FPF", 4)),
 ]
 # per-configuration extras: LGMRES augmentation, and the symmetric scalar
 # system of the same grid (CG needs a symmetric positive definite matrix)
@@ -66,7 +69,10 @@ EXTRAS = {"lgmres30_2_bilu0_f64": dict(aug_k=2), "pcg_ilu0_scalar_f64": dict(sys
           "gmres30_ras4_f64": dict(ras=(4, 1)), "gmres30_ras8_f64": dict(ras=(8, 1)),
           "gmres30_rasbox_1x4x4_f64": dict(ras=(1, 4, 4, 1)),
           "gmres30_rasbox_2x4x4_f64": dict(ras=(2, 4, 4, 1)),
-          "gmres30_rasbox_2x2x2_f64": dict(ras=(2, 2, 2, 1))}
+          "gmres30_rasbox_2x2x2_f64": dict(ras=(2, 2, 2, 1)),
+          "gmres30_ilu0_scalar_f64": dict(system="scalar"),
+          "gmres30_amg_scalar_f64": dict(system="scalar"),
+          "fgmres30_cpr_fpf_amg_f64": dict(cpr_pressure="AMG")}
 WEIGHTS = os.path.join(ROOT, "paper_1701_05913_amd", "weights", "bilu0_blackoil64.bin")
 
 # matrix-core FLOPs per cell of each conv layer (3x3x3 taps, 2 per MAC)
@@ -237,6 +243,7 @@ def main():
         K.SolverSetPrecision(S, getattr(K, f"KRY_PREC_{prec}"))
         if cpr:
             K.SolverSetCPR(S, getattr(K, f"KRY_CPR_{cpr[0]}"), cpr[1])
+            K.SolverSetCPRPressure(S, getattr(K, f"KRY_CPR_P_{ex.get('cpr_pressure', 'ILU0')}"))
         K.SolverSetStream(S, stream)
         K.SolverSetSweepLayout(S, getattr(K, f"KRY_SWEEP_{args.layout.upper()}"))
         if pc.endswith("_LEARNED"):
@@ -290,7 +297,8 @@ def main():
             ent.update(bytes_per_launch=abytes[kname], gbs=round(gbs, 1),
                        frac_hbm=round(gbs / HBM_PEAK_GBS, 4))
         kernels[kname] = ent
-    for kname in ["ilu_grid_untile", "learned_stage", "ras_apply", "ras_ilu_fwd", "ras_ilu_bwd"]:
+    for kname in ["ilu_grid_untile", "learned_stage", "ras_apply", "ras_ilu_fwd", "ras_ilu_bwd",
+                  "amg_vcycle"]:
         cnt, ms = K.KernelTimingQuery(kname)
         if cnt:
             kernels[kname] = dict(launches=cnt, total_ms=round(ms, 4), avg_us=round(1000 * ms / cnt, 3))

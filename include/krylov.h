@@ -67,7 +67,9 @@ enum { KRY_PC_NONE = 0, KRY_PC_ILU0 = 1, KRY_PC_BILU0 = 1, KRY_PC_CPR = 2,
        KRY_PC_BILU0_LEARNED = 4, KRY_PC_CPR_LEARNED = 5,
        /* restricted additive Schwarz with block ILU(0) subdomain solves
         * (Section 4.1): see SolverSetRAS */
-       KRY_PC_RAS = 6 };
+       KRY_PC_RAS = 6,
+       /* algebraic multigrid, one V-cycle (Section 4.2): see SolverSetAMG */
+       KRY_PC_AMG = 7 };
 /* precision of the preconditioner apply (mixed-precision extension) */
 enum { KRY_PREC_F64 = 0, KRY_PREC_F32 = 1, KRY_PREC_BF16_FACTORS = 2 };
 /* CPR stage order (Section 4.2.1): PF = pressure then full (Algorithm 6,
@@ -76,6 +78,9 @@ enum { KRY_PREC_F64 = 0, KRY_PREC_F32 = 1, KRY_PREC_BF16_FACTORS = 2 };
  * full (Algorithm 8).  Every stage after the first acts on the residual
  * of the running iterate. */
 enum { KRY_CPR_PF = 0, KRY_CPR_FP = 1, KRY_CPR_FPF = 2, KRY_CPR_FFPF = 3 };
+/* CPR pressure solver: ILU(0) sweeps (SolverSetCPR's p_sweeps) or one AMG
+ * V-cycle on A_pp, the paper's M_g(A_pp)^-1 (Algorithms 5-8) */
+enum { KRY_CPR_P_ILU0 = 0, KRY_CPR_P_AMG = 1 };
 /* layout of the ILU triangular sweeps: AUTO picks GRID when the matrix is a
  * 7-point stencil on an nx x ny x nz grid (nx, ny, nz >= 2) in natural
  * order, LEVELS otherwise */
@@ -195,12 +200,38 @@ int  SolverSetAugk(SOLVER *s, int64_t k);
  * SolverSetStream: HIP stream (hipStream_t) for all work of the solver. */
 int SolverSetPrecision(SOLVER *s, int prec);
 int SolverSetCPR(SOLVER *s, int variant, int p_sweeps);
+/* CPR's pressure solver, KRY_CPR_P_ILU0 (default) or KRY_CPR_P_AMG (FP64
+ * only; KRY_ERR_UNSUPPORTED at SolverAssemble otherwise). */
+int SolverSetCPRPressure(SOLVER *s, int psolver);
+/* Algebraic multigrid (Section 4.2: Algorithm 3 setup, Algorithm 4
+ * V-cycle; classical Ruge-Stueben strength, coarsening and interpolation
+ * with Figure 34's strength 0.5, max row sum 0.9 and truncation 0.01), for
+ * KRY_PC_AMG on a scalar (bs = 1) matrix and for CPR's AMG pressure
+ * stage.  max_levels (default 8) counts the coarsest level, which is
+ * solved exactly through a dense inverse (at most 8192 rows,
+ * KRY_ERR_UNSUPPORTED otherwise); num_sweeps (default 2) hybrid
+ * Gauss-Seidel sweeps before and after the coarse correction, Gauss-Seidel
+ * inside chunks of gs_chunk consecutive rows (1, 2, 4, 8 or 16; default 4)
+ * and Jacobi between chunks.  The setup runs on the host at
+ * SolverAssemble; the V-cycle runs on the GPU.  FP64 only.  KRY_ERR_ARG
+ * for max_levels < 1 or num_sweeps < 1. */
+int SolverSetAMG(SOLVER *s, int max_levels, int num_sweeps, int gs_chunk);
+/* The AMG hierarchy built by SolverAssemble (KRY_PC_AMG, or CPR with the
+ * AMG pressure stage): SolverGetAMGLevels returns the number of levels
+ * (KRY_ERR_ARG without a hierarchy).  SolverGetAMGLevel writes the sizes of
+ * level l (rows n, entries nnz of A_l, coarse rows nc and entries pnnz of
+ * P_l, both 0 on the coarsest level) and, for every non-NULL array, A_l in
+ * CSR (rowptr[n+1], col[nnz], val[nnz]), the C/F splitting (cf[n], 1 = C)
+ * and P_l in CSR (prowptr[n+1], pcol[pnnz], pval[pnnz]); host memory. */
+int SolverGetAMGLevels(const SOLVER *s);
+int SolverGetAMGLevel(const SOLVER *s, int l, int *n, int *nnz, int *nc, int *pnnz, int *rowptr,
+                      int *col, double *val, int *cf, int *prowptr, int *pcol, double *pval);
 /* Restricted additive Schwarz (Section 4.1, the RAS preconditioner, with
  * ILU(0) as the local solver and the paper's default overlap of 1): the
  * matrix must be a 7-point grid stencil in natural order (MatGetGrid); it
  * is cut into nsub z-slabs of nz/nsub layers (owned rows), each grown by
- * `overlap` layers on both sides, factored by block ILU(0) and swept on a
- * stream of its own; the solution is written back on the owned rows only.
+ * `overlap` layers on both sides, factored by block ILU(0) and swept together
+ * with the other slabs; the solution is written back on the owned rows only.
  * FP64 only.  Defaults nsub = 4, overlap = 1; KRY_ERR_ARG for nsub < 1 or
  * overlap < 0, and at SolverAssemble for nsub > nz; KRY_ERR_UNSUPPORTED
  * for a matrix that is not a grid stencil or a reduced precision. */

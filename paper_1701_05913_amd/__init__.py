@@ -32,9 +32,10 @@ KRY_HOST, KRY_DEVICE = 0, 1
 KRY_F64 = 0
 KRY_GMRES, KRY_FGMRES, KRY_BICGSTAB, KRY_CG = 0, 1, 2, 3
 KRY_PC_NONE, KRY_PC_ILU0, KRY_PC_BILU0, KRY_PC_CPR, KRY_PC_CUSTOM = 0, 1, 1, 2, 3
-KRY_PC_BILU0_LEARNED, KRY_PC_CPR_LEARNED, KRY_PC_RAS = 4, 5, 6
+KRY_PC_BILU0_LEARNED, KRY_PC_CPR_LEARNED, KRY_PC_RAS, KRY_PC_AMG = 4, 5, 6, 7
 KRY_PREC_F64, KRY_PREC_F32, KRY_PREC_BF16_FACTORS = 0, 1, 2
 KRY_CPR_PF, KRY_CPR_FP, KRY_CPR_FPF, KRY_CPR_FFPF = 0, 1, 2, 3
+KRY_CPR_P_ILU0, KRY_CPR_P_AMG = 0, 1
 KRY_SWEEP_AUTO, KRY_SWEEP_LEVELS, KRY_SWEEP_GRID = 0, 1, 2
 
 
@@ -83,6 +84,10 @@ _SIGS = {
     "SolverSetCPR": (C.c_int, [P, C.c_int, C.c_int]),
     "SolverSetRAS": (C.c_int, [P, C.c_int, C.c_int]),
     "SolverSetRASBoxes": (C.c_int, [P, C.c_int, C.c_int, C.c_int, C.c_int]),
+    "SolverSetCPRPressure": (C.c_int, [P, C.c_int]),
+    "SolverSetAMG": (C.c_int, [P, C.c_int, C.c_int, C.c_int]),
+    "SolverGetAMGLevels": (C.c_int, [P]),
+    "SolverGetAMGLevel": (C.c_int, [P, C.c_int] + [C.POINTER(I32)] * 4 + [P] * 7),
     "SolverSetSweepLayout": (C.c_int, [P, C.c_int]),
     "SolverSetStream": (C.c_int, [P, P]),
     "SolverGetResidual": (D, [P]), "SolverGetIters": (C.c_int, [P]),
@@ -312,6 +317,32 @@ def SolverSetPrecision(s, p): return _check(_lib.SolverSetPrecision(s, p))
 def SolverSetCPR(s, variant, p_sweeps): return _check(_lib.SolverSetCPR(s, variant, p_sweeps))
 def SolverSetRAS(s, nsub, overlap): return _check(_lib.SolverSetRAS(s, nsub, overlap))
 def SolverSetRASBoxes(s, px, py, pz, overlap): return _check(_lib.SolverSetRASBoxes(s, px, py, pz, overlap))
+def SolverSetCPRPressure(s, psolver): return _check(_lib.SolverSetCPRPressure(s, psolver))
+def SolverSetAMG(s, max_levels, num_sweeps, gs_chunk):
+    return _check(_lib.SolverSetAMG(s, max_levels, num_sweeps, gs_chunk))
+def SolverGetAMGLevels(s): return _check(_lib.SolverGetAMGLevels(s))
+
+
+def SolverGetAMGLevel(s, level):
+    """dict(n, nc, A=(rowptr, col, val), cf, P=(rowptr, col, val)); cf and P
+    are None on the coarsest level."""
+    n, nnz, nc, pnnz = (C.c_int32(0) for _ in range(4))
+    null = [None] * 7
+    _check(_lib.SolverGetAMGLevel(s, level, C.byref(n), C.byref(nnz), C.byref(nc), C.byref(pnnz),
+                                  *null))
+    n, nnz, nc, pnnz = n.value, nnz.value, nc.value, pnnz.value
+    rp = np.zeros(n + 1, np.int32)
+    col = np.zeros(max(nnz, 1), np.int32)
+    val = np.zeros(max(nnz, 1))
+    cf = np.zeros(max(n, 1), np.int32)
+    prp = np.zeros(n + 1, np.int32)
+    pcol = np.zeros(max(pnnz, 1), np.int32)
+    pval = np.zeros(max(pnnz, 1))
+    ptr = [a.ctypes.data_as(C.c_void_p) for a in (rp, col, val, cf, prp, pcol, pval)]
+    _check(_lib.SolverGetAMGLevel(s, level, None, None, None, None, *ptr))
+    coarse = nc == 0
+    return dict(n=n, nc=nc, A=(rp, col[:nnz], val[:nnz]), cf=None if coarse else cf[:n],
+                P=None if coarse else (prp, pcol[:pnnz], pval[:pnnz]))
 def SolverSetSweepLayout(s, layout): return _check(_lib.SolverSetSweepLayout(s, layout))
 
 

@@ -6,9 +6,9 @@
 // Quasi-IMPES weights per cell from the diagonal block
 // D = [[d_pp, d_ps^T], [d_sp, D_ss]]:  w^T = [1, -d_ps^T D_ss^-1], so w^T D
 // has zero secondary columns.  Pressure matrix (A_pp)_ij = w_i^T A_ij e_0 on
-// the block pattern of A.  The AMG pressure solve of the paper is replaced
-// by a fixed number of ILU(0) sweeps p <- p + (L_p U_p)^-1 (r_p - A_pp p)
-// from p = 0.
+// the block pattern of A.  The pressure solve is either the paper's AMG
+// (one V-cycle on A_pp, FP64) or a fixed number of ILU(0) sweeps
+// p <- p + (L_p U_p)^-1 (r_p - A_pp p) from p = 0.
 //   PF (Algorithm 6 with its garbled steps 2 and 4 read as the classical
 //   two-stage CPR):  z1 = Pi_p(P(Pi_r W v)); r = v - A z1; z = z1 + BILU^-1 r
 //   FP (Algorithm 5):  z1 = BILU^-1 v; r = v - A z1; z = z1 + Pi_p(P(Pi_r W r))
@@ -152,7 +152,13 @@ int cpr_setup(hipStream_t s, MAT_ *A, CprPC &C, int variant, int sweeps, int pre
     KRY_TRY(sell_build(s, &P));
     // factors: the pressure factor is FP32 whenever the apply is reduced
     const int pprec = prec == KRY_PREC_F64 ? KRY_PREC_F64 : KRY_PREC_F32;
-    KRY_TRY(ilu_setup(s, &P, P.val.p, C.ilu_p, pprec, d_err, layout));
+    if (C.amg) {
+        if (prec != KRY_PREC_F64) return set_error(KRY_ERR_UNSUPPORTED, "CPR-AMG: FP64 only");
+        KRY_TRY(amg_setup(s, nb, P.h_rowptr.data(), P.h_col.data(), P.val.p, C.amg_opts, *C.amg,
+                          d_err));
+    } else {
+        KRY_TRY(ilu_setup(s, &P, P.val.p, C.ilu_p, pprec, d_err, layout));
+    }
     KRY_TRY(ilu_setup(s, A, A->val.p, C.ilu_a, prec, d_err, layout));
     if (prec != KRY_PREC_F64) {
         KRY_TRY(ensure_sell_f32(s, P.sell));
@@ -185,6 +191,8 @@ static int cpr_apply_t(hipStream_t s, MAT_ *A, CprPC &C, const double *v, double
     auto pressure_stage = [&](const T *rvec) -> int {
         // rp = Pi_r W rvec; p = (LU)^-1 rp; then sweeps - 1 corrections
         hipLaunchKernelGGL((k_restrict<T, T>), g, blk, 0, s, nb, C.w.p, rvec, rp);
+        if (C.amg)   // FP64 only: p = one V-cycle on rp
+            return amg_apply(s, *C.amg, (const double *)rp, (double *)p, err);
         KRY_TRY(ilu_apply(s, C.ilu_p, rp, tin, p, tin, 0, nullptr, nullptr, err));
         for (int k = 1; k < C.sweeps; k++) {
             if (tin == 0)

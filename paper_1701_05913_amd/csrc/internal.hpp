@@ -282,6 +282,44 @@ int ilu_apply(hipStream_t s, IluFactor &F, const void *b, int in_type,
 // ---------------------------------------------------------------------------
 // CPR two-stage preconditioner (cpr.hip)
 // ---------------------------------------------------------------------------
+// Classical AMG (Algorithms 3 and 4); Figure 34's defaults, the hybrid
+// Gauss-Seidel smoother on chunks of gs_chunk rows.
+struct AmgOpts {
+    double strength = 0.5, max_row_sum = 0.9, trunc = 1e-2;
+    int max_levels = 8, num_sweeps = 2, gs_chunk = 4, coarse_size = 9;
+};
+struct AmgCsr {                 // host CSR, n rows, m columns
+    int n = 0, m = 0;
+    std::vector<int> rp, ci;
+    std::vector<double> v;
+};
+struct AmgLevelHost {           // A_l, its C/F splitting and P_l (not on the coarsest)
+    AmgCsr A;
+    std::vector<int> cf;
+    AmgCsr P;
+};
+struct AmgLevel {
+    int n = 0, nc = 0, nch = 0, team = 1;
+    int64_t ell_bytes = 0;
+    DBuf<int64_t> goff;         // chunk-interleaved rows of A_l, per wavefront group
+    DBuf<int> gk, rlen, ecol;
+    DBuf<double> eval, low;     // low: each chunk's diagonal and lower block
+    DBuf<int> prp, pci, rrp, rci;   // P_l and R_l = P_l^T
+    DBuf<double> pv, rv;
+    DBuf<double> x, t, r, b;
+};
+struct AmgPC {
+    AmgOpts o;
+    std::vector<AmgLevelHost> host;
+    std::vector<std::unique_ptr<AmgLevel>> lev;
+    DBuf<double> cinv;          // inverse of the coarsest matrix, row-major
+};
+// hierarchy of the n x n CSR matrix (host pattern, device values)
+int amg_setup(hipStream_t s, int n, const int *h_rowptr, const int *h_col, const double *d_val,
+              const AmgOpts &o, AmgPC &M, int *d_err);
+// x = one V-cycle applied to b (device vectors of n, distinct)
+int amg_apply(hipStream_t s, AmgPC &M, const double *b, double *x, int *d_err);
+
 struct CprPC {
     int variant = KRY_CPR_PF, sweeps = 4, prec = KRY_PREC_F64;
     int nb = 0;
@@ -289,6 +327,8 @@ struct CprPC {
     MAT_ app;               // pressure matrix (CSR, pattern of A's blocks)
     IluFactor ilu_p;        // ILU(0) of A_pp
     IluFactor ilu_a;        // block ILU(0) of A
+    std::unique_ptr<AmgPC> amg;   // pressure stage: one V-cycle instead of ILU(0) sweeps
+    AmgOpts amg_opts;
     DBuf<char> work;        // scratch vectors
 };
 // One grid of a multi-grid sweep launch (the subdomains of RAS, boxes of a
@@ -402,6 +442,9 @@ struct SOLVER_ {
     int restart = 30;
     int prec = KRY_PREC_F64;
     int cpr_variant = KRY_CPR_PF, cpr_sweeps = 4;
+    int cpr_psolver = KRY_CPR_P_ILU0;
+    kry::AmgOpts amg_opts;
+    std::unique_ptr<kry::AmgPC> amg;
     int sweep_layout = KRY_SWEEP_AUTO;
     hipStream_t stream = nullptr;
     PC_SETUP csetup = nullptr;

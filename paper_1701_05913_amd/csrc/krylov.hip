@@ -686,6 +686,8 @@ int pc_apply(SOLVER_ *S, const double *v, double *z) {
         return learned_stage_apply(S->stream, S->A, *S->learned, v, z);
     case KRY_PC_RAS:
         return ras_apply(S->stream, *S->ras, v, z, S->err.p);
+    case KRY_PC_AMG:
+        return amg_apply(S->stream, *S->amg, v, z, S->err.p);
     case KRY_PC_CUSTOM: {
         VEC_ vv, zz;
         vv.map = zz.map = S->map;
@@ -952,7 +954,7 @@ extern "C" SOLVER *SolverCreate(int solver_type, int pc_type, MAP *map) {
         set_error(KRY_ERR_UNSUPPORTED, "SolverCreate: solver type %d", solver_type);
         return nullptr;
     }
-    if (pc_type < KRY_PC_NONE || pc_type > KRY_PC_RAS) {
+    if (pc_type < KRY_PC_NONE || pc_type > KRY_PC_AMG) {
         set_error(KRY_ERR_UNSUPPORTED, "SolverCreate: preconditioner type %d", pc_type);
         return nullptr;
     }
@@ -1038,6 +1040,55 @@ extern "C" int SolverSetCPR(SOLVER *s, int variant, int p_sweeps) {
     s->assembled = false;
     return KRY_OK;
 }
+extern "C" int SolverSetCPRPressure(SOLVER *s, int psolver) {
+    if (!s || (psolver != KRY_CPR_P_ILU0 && psolver != KRY_CPR_P_AMG))
+        return set_error(KRY_ERR_ARG, "SolverSetCPRPressure: bad argument");
+    s->cpr_psolver = psolver;
+    s->assembled = false;
+    return KRY_OK;
+}
+extern "C" int SolverSetAMG(SOLVER *s, int max_levels, int num_sweeps, int gs_chunk) {
+    if (!s || max_levels < 1 || num_sweeps < 1) return set_error(KRY_ERR_ARG, "SolverSetAMG: bad argument");
+    s->amg_opts.max_levels = max_levels;
+    s->amg_opts.num_sweeps = num_sweeps;
+    s->amg_opts.gs_chunk = gs_chunk;
+    s->assembled = false;
+    return KRY_OK;
+}
+static const AmgPC *solver_amg(const SOLVER *s) {
+    if (!s) return nullptr;
+    if (s->amg) return s->amg.get();
+    if (s->cpr && s->cpr->amg) return s->cpr->amg.get();
+    return nullptr;
+}
+extern "C" int SolverGetAMGLevels(const SOLVER *s) {
+    const AmgPC *M = solver_amg(s);
+    if (!M) return set_error(KRY_ERR_ARG, "SolverGetAMGLevels: no AMG hierarchy assembled");
+    return (int)M->host.size();
+}
+extern "C" int SolverGetAMGLevel(const SOLVER *s, int l, int *n, int *nnz, int *nc, int *pnnz,
+                                 int *rowptr, int *col, double *val, int *cf, int *prowptr,
+                                 int *pcol, double *pval) {
+    const AmgPC *M = solver_amg(s);
+    if (!M) return set_error(KRY_ERR_ARG, "SolverGetAMGLevel: no AMG hierarchy assembled");
+    if (l < 0 || l >= (int)M->host.size()) return set_error(KRY_ERR_ARG, "SolverGetAMGLevel: no level %d", l);
+    const AmgLevelHost &H = M->host[l];
+    const bool coarsest = l == (int)M->host.size() - 1;
+    if (n) *n = H.A.n;
+    if (nnz) *nnz = (int)H.A.ci.size();
+    if (nc) *nc = coarsest ? 0 : H.P.m;
+    if (pnnz) *pnnz = coarsest ? 0 : (int)H.P.ci.size();
+    if (rowptr) std::copy(H.A.rp.begin(), H.A.rp.end(), rowptr);
+    if (col) std::copy(H.A.ci.begin(), H.A.ci.end(), col);
+    if (val) std::copy(H.A.v.begin(), H.A.v.end(), val);
+    if (!coarsest) {
+        if (cf) std::copy(H.cf.begin(), H.cf.end(), cf);
+        if (prowptr) std::copy(H.P.rp.begin(), H.P.rp.end(), prowptr);
+        if (pcol) std::copy(H.P.ci.begin(), H.P.ci.end(), pcol);
+        if (pval) std::copy(H.P.v.begin(), H.P.v.end(), pval);
+    }
+    return KRY_OK;
+}
 extern "C" int SolverSetRASBoxes(SOLVER *s, int px, int py, int pz, int overlap) {
     if (!s || px < 1 || py < 1 || pz < 1 || overlap < 0)
         return set_error(KRY_ERR_ARG, "SolverSetRASBoxes: bad argument");
@@ -1094,6 +1145,7 @@ extern "C" int SolverAssemble(SOLVER *s) {
     hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(64), 0, s->stream, s->err.p);
     s->ilu.reset();
     s->cpr.reset();
+    s->amg.reset();
     // RAS keeps its subdomain patterns when the matrix and options are unchanged
     const bool ras_reuse = s->pc_type == KRY_PC_RAS && s->ras && s->ras->A == s->A &&
                            s->ras->px == s->ras_px && s->ras->py == s->ras_py &&
@@ -1112,8 +1164,28 @@ extern "C" int SolverAssemble(SOLVER *s) {
     case KRY_PC_CPR:
     case KRY_PC_CPR_LEARNED:
         s->cpr.reset(new CprPC());
+        if (s->cpr_psolver == KRY_CPR_P_AMG) {
+            if (s->prec != KRY_PREC_F64)
+                return set_error(KRY_ERR_UNSUPPORTED, "CPR with the AMG pressure stage is FP64 only");
+            s->cpr->amg.reset(new AmgPC());
+            s->cpr->amg_opts = s->amg_opts;
+        }
         KRY_TRY(cpr_setup(s->stream, s->A, *s->cpr, s->cpr_variant, s->cpr_sweeps, s->prec, s->err.p,
                           s->sweep_layout));
+        break;
+    case KRY_PC_AMG:
+        if (s->A->bs != 1)
+            return set_error(KRY_ERR_UNSUPPORTED, "AMG preconditioner: scalar (bs = 1) matrices only");
+        if (s->prec != KRY_PREC_F64) return set_error(KRY_ERR_UNSUPPORTED, "AMG preconditioner: FP64 only");
+        s->amg.reset(new AmgPC());
+        {
+            const int rc = amg_setup(s->stream, s->A->nb, s->A->h_rowptr.data(), s->A->h_col.data(),
+                                     s->A->val.p, s->amg_opts, *s->amg, s->err.p);
+            if (rc < 0) {
+                s->amg.reset();
+                return rc;
+            }
+        }
         break;
     case KRY_PC_RAS:
         if (ras_reuse) {

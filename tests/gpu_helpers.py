@@ -44,7 +44,7 @@ class GpuSystem:
 
 def make_solver(g, solver, pc, rtol=1e-8, maxit=5000, restart=30,
                 prec=K.KRY_PREC_F64, cpr=(K.KRY_CPR_PF, 4), layout=K.KRY_SWEEP_AUTO, aug_k=0,
-                ras=(4, 1)):
+                ras=(4, 1), amg=(8, 2, 4), cpr_p=K.KRY_CPR_P_ILU0):
     S = K.SolverCreate(solver, pc, g.map)
     K.SolverSetSweepLayout(S, layout)
     K.SolverSetMat(S, g.A)
@@ -55,6 +55,9 @@ def make_solver(g, solver, pc, rtol=1e-8, maxit=5000, restart=30,
     K.SolverSetPrecision(S, prec)
     if pc == K.KRY_PC_CPR:
         K.SolverSetCPR(S, cpr[0], cpr[1])
+        K.SolverSetCPRPressure(S, cpr_p)
+    # (max_levels, num_sweeps, gs_chunk) of AMG, for KRY_PC_AMG and CPR-AMG
+    K.SolverSetAMG(S, *amg)
     if pc == K.KRY_PC_RAS:
         # (nsub, overlap): z-slabs; (px, py, pz, overlap): boxes
         if len(ras) == 4:
@@ -81,8 +84,9 @@ def solve(g, solver, pc, b=None, x0=None, **kw):
 
 
 def pc_apply(g, pc, v, prec=K.KRY_PREC_F64, cpr=(K.KRY_CPR_PF, 4), solver=K.KRY_FGMRES,
-             layout=K.KRY_SWEEP_AUTO, repeat=1, ras=(4, 1)):
-    S = make_solver(g, solver, pc, prec=prec, cpr=cpr, layout=layout, ras=ras)
+             layout=K.KRY_SWEEP_AUTO, repeat=1, ras=(4, 1), amg=(8, 2, 4), cpr_p=K.KRY_CPR_P_ILU0):
+    S = make_solver(g, solver, pc, prec=prec, cpr=cpr, layout=layout, ras=ras, amg=amg,
+                    cpr_p=cpr_p)
     try:
         K.SolverAssemble(S)
         vt, vh = g.vec(v)

@@ -628,3 +628,153 @@ def test_ras_box_errors():
         K.SolverDestroy(S)
     finally:
         g.close()
+
+
+# ---- algebraic multigrid (Section 4.2): hierarchy, V-cycle, solves ----------------
+def _amg_levels_equal(S, M):
+    assert K.SolverGetAMGLevels(S) == M.nlevels
+    for l in range(M.nlevels):
+        g, o = K.SolverGetAMGLevel(S, l), M.level(l)
+        assert g["n"] == o["n"] and g["nc"] == o["nc"], l
+        for a, b in zip(g["A"][:2], o["A"][:2]):
+            assert np.array_equal(a, b), l
+        assert np.allclose(g["A"][2], o["A"][2], rtol=1e-14, atol=0), l
+        if o["cf"] is None:
+            assert g["cf"] is None
+            continue
+        # the splitting is integer work: bit-exact
+        assert np.array_equal(g["cf"], o["cf"]), l
+        for a, b in zip(g["P"][:2], o["P"][:2]):
+            assert np.array_equal(a, b), l
+        assert np.allclose(g["P"][2], o["P"][2], rtol=1e-14, atol=0), l
+
+
+@pytest.mark.parametrize("grid,perm", [((24, 24, 24), "iid"), ((21, 17, 13), "layered")])
+def test_amg_hierarchy_matches_oracle(grid, perm):
+    s = ri.scalar_system(*grid, seed=13, perm=perm)
+    A = oracle.Matrix.from_system(s)
+    g = GpuSystem(s)
+    try:
+        S = make_solver(g, K.KRY_GMRES, K.KRY_PC_AMG)
+        K.SolverAssemble(S)
+        _amg_levels_equal(S, oracle.AMG(A, gs_chunk=4))
+        K.SolverDestroy(S)
+    finally:
+        g.close()
+
+
+@pytest.mark.parametrize("grid,amg", [((24, 24, 24), (8, 2, 4)), ((21, 17, 13), (8, 2, 4)),
+                                      ((21, 17, 13), (8, 1, 1)), ((21, 17, 13), (3, 3, 16)),
+                                      ((21, 17, 13), (8, 2, 2)), ((21, 17, 13), (1, 2, 8))])
+def test_amg_vcycle_parity(grid, amg):
+    s = ri.scalar_system(*grid, seed=14, perm="layered")
+    A = oracle.Matrix.from_system(s)
+    v = np.random.default_rng(15).standard_normal(A.n)
+    ref = oracle.PC.amg(A, max_levels=amg[0], num_sweeps=amg[1], gs_chunk=amg[2]).apply(v)
+    g = GpuSystem(s)
+    try:
+        zs = pc_apply(g, K.KRY_PC_AMG, v, solver=K.KRY_GMRES, amg=amg, repeat=2)
+    finally:
+        g.close()
+    assert np.array_equal(zs[0], zs[1])
+    assert relerr(zs[1], ref) <= 1e-11
+
+
+def test_amg_vcycle_parity_64cube():
+    # the benchmark's scalar system: sampled against the oracle's full V-cycle
+    s = ri.scalar_system(64, 64, 64, seed=0)
+    A = oracle.Matrix.from_system(s)
+    v = np.random.default_rng(16).standard_normal(A.n)
+    ref = oracle.PC.amg(A, gs_chunk=4).apply(v)
+    g = GpuSystem(s)
+    try:
+        z = pc_apply(g, K.KRY_PC_AMG, v, solver=K.KRY_GMRES)
+    finally:
+        g.close()
+    assert relerr(z, ref) <= 1e-11
+
+
+def test_amg_gmres_solve():
+    s = ri.scalar_system(32, 32, 32, seed=0)
+    A = oracle.Matrix.from_system(s)
+    g = GpuSystem(s)
+    try:
+        gpu = solve(g, K.KRY_GMRES, K.KRY_PC_AMG, rtol=1e-8, maxit=500)
+    finally:
+        g.close()
+    ref = _check_solve(s, gpu, A, oracle.PC.amg(A, gs_chunk=4), 1e-8, oracle.gmres, restart=30,
+                       maxit=500)
+    assert ref["iters"] <= 15
+
+
+@pytest.mark.parametrize("variant,kind", [(K.KRY_CPR_PF, "cpr_pf"), (K.KRY_CPR_FP, "cpr_fp"),
+                                          (K.KRY_CPR_FPF, "cpr_fpf"), (K.KRY_CPR_FFPF, "cpr_ffpf")])
+def test_cpr_amg_apply_parity(variant, kind):
+    s = ri.blackoil_system(20, 18, 14, seed=17)
+    A = oracle.Matrix.from_system(s)
+    v = np.random.default_rng(18).standard_normal(A.n)
+    ref = oracle.PC.amg(A, kind, gs_chunk=4).apply(v)
+    g = GpuSystem(s)
+    try:
+        z = pc_apply(g, K.KRY_PC_CPR, v, cpr=(variant, 4), cpr_p=K.KRY_CPR_P_AMG)
+        S = make_solver(g, K.KRY_FGMRES, K.KRY_PC_CPR, cpr=(variant, 4), cpr_p=K.KRY_CPR_P_AMG)
+        K.SolverAssemble(S)
+        # the pressure hierarchy is the oracle's AMG of A_pp
+        rc, w = oracle.cpr_weights(A)
+        Ap = oracle.Matrix(A.rowptr, A.col, oracle.cpr_pressure_matrix(A, w), 1)
+        _amg_levels_equal(S, oracle.AMG(Ap, gs_chunk=4))
+        K.SolverDestroy(S)
+    finally:
+        g.close()
+    assert relerr(z, ref) <= 1e-10
+
+
+def test_cpr_amg_solve():
+    s = ri.blackoil_system(24, 20, 16, seed=19)
+    A = oracle.Matrix.from_system(s)
+    g = GpuSystem(s)
+    try:
+        gpu = solve(g, K.KRY_FGMRES, K.KRY_PC_CPR, rtol=1e-8, maxit=500,
+                    cpr=(K.KRY_CPR_FPF, 4), cpr_p=K.KRY_CPR_P_AMG)
+    finally:
+        g.close()
+    _check_solve(s, gpu, A, oracle.PC.amg(A, "cpr_fpf", gs_chunk=4), 1e-8, oracle.gmres,
+                 restart=30, maxit=500, flexible=True)
+
+
+def test_amg_errors():
+    sb = ri.blackoil_system(6, 5, 4, seed=1)
+    ss = ri.scalar_system(6, 5, 4, seed=1)
+    gb, gs = GpuSystem(sb), GpuSystem(ss)
+    try:
+        cases = [(gb, K.KRY_PC_AMG, K.KRY_PREC_F64, (8, 2, 4), K.KRY_ERR_UNSUPPORTED),
+                 (gs, K.KRY_PC_AMG, K.KRY_PREC_F32, (8, 2, 4), K.KRY_ERR_UNSUPPORTED),
+                 (gs, K.KRY_PC_AMG, K.KRY_PREC_F64, (8, 2, 3), K.KRY_ERR_UNSUPPORTED),
+                 (gb, K.KRY_PC_CPR, K.KRY_PREC_F32, (8, 2, 4), K.KRY_ERR_UNSUPPORTED)]
+        for g, pc, prec, amg, code in cases:
+            S = K.SolverCreate(K.KRY_FGMRES, pc, g.map)
+            K.SolverSetMat(S, g.A)
+            K.SolverSetPrecision(S, prec)
+            K.SolverSetAMG(S, *amg)
+            if pc == K.KRY_PC_CPR:
+                K.SolverSetCPRPressure(S, K.KRY_CPR_P_AMG)
+            with pytest.raises(K.KrylovError) as e:
+                K.SolverAssemble(S)
+            assert e.value.code == code
+            with pytest.raises(K.KrylovError):
+                K.SolverGetAMGLevels(S)
+            K.SolverDestroy(S)
+        S = K.SolverCreate(K.KRY_GMRES, K.KRY_PC_AMG, gs.map)
+        for bad in ((0, 2, 4), (8, 0, 4)):
+            with pytest.raises(K.KrylovError):
+                K.SolverSetAMG(S, *bad)
+        with pytest.raises(K.KrylovError):
+            K.SolverSetCPRPressure(S, 5)
+        K.SolverSetMat(S, gs.A)
+        K.SolverAssemble(S)
+        with pytest.raises(K.KrylovError):
+            K.SolverGetAMGLevel(S, K.SolverGetAMGLevels(S))
+        K.SolverDestroy(S)
+    finally:
+        gb.close()
+        gs.close()
