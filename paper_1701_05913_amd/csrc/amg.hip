@@ -139,23 +139,39 @@ void split_cf(int n, const std::vector<int> &srp, const std::vector<int> &sci,
     constexpr int UND = -1;
     std::vector<int> meas(n);
     cf.assign(n, UND);
-    // (measure, -index): the top is the largest measure, then the smallest
-    // index; an entry is stale once its point is decided or its measure moved
-    std::priority_queue<std::pair<int, int>> open;
+    // one min-heap of indices per measure value; the next point is the
+    // smallest index in the largest non-empty bucket.  An entry is stale
+    // once its point is decided or its measure has moved.
+    int mmax = 0;
     for (int i = 0; i < n; i++) {
         meas[i] = drp[i + 1] - drp[i];
+        mmax = std::max(mmax, meas[i]);
+    }
+    // a measure grows by at most the points depending on it: bounded by
+    // twice the longest column of the strong pattern
+    std::vector<std::vector<int>> bucket(2 * (mmax + 1) + 1);
+    auto push = [&](int i) {
+        auto &h = bucket[meas[i]];
+        h.push_back(i);
+        std::push_heap(h.begin(), h.end(), std::greater<int>());
+    };
+    for (int i = 0; i < n; i++) {
         if (srp[i + 1] == srp[i] && meas[i] == 0) cf[i] = 0;
-        else open.push({meas[i], -i});
+        else push(i);
     }
     auto shift = [&](int k, int d) {
         meas[k] += d;
-        open.push({meas[k], -k});
+        push(k);
     };
-    while (!open.empty()) {
-        const auto top = open.top();
-        open.pop();
-        const int i = -top.second;
-        if (cf[i] != UND || top.first != meas[i]) continue;
+    int top = (int)bucket.size() - 1;
+    for (;;) {
+        while (top >= 0 && bucket[top].empty()) top--;
+        if (top < 0) break;
+        auto &h = bucket[top];
+        std::pop_heap(h.begin(), h.end(), std::greater<int>());
+        const int i = h.back();
+        h.pop_back();
+        if (cf[i] != UND || meas[i] != top) continue;
         if (meas[i] == 0) {
             cf[i] = 0;
             continue;
@@ -166,7 +182,10 @@ void split_cf(int n, const std::vector<int> &srp, const std::vector<int> &sci,
             if (cf[j] != UND) continue;
             cf[j] = 0;
             for (int p = srp[j]; p < srp[j + 1]; p++)
-                if (cf[sci[p]] == UND) shift(sci[p], +1);
+                if (cf[sci[p]] == UND) {
+                    shift(sci[p], +1);
+                    top = std::max(top, meas[sci[p]]);
+                }
         }
         for (int q = srp[i]; q < srp[i + 1]; q++)
             if (cf[sci[q]] == UND) shift(sci[q], -1);
