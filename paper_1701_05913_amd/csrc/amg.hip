@@ -559,11 +559,11 @@ constexpr int AMG_DENSE_MAX = 8192;
 
 }  // namespace
 
-// team size for a level: rows of ~8 entries per lane
+// team size for a level: about 4 entries of a row per lane
 static int team_size(const AmgCsr &A) {
     const double mean = A.n ? (double)A.ci.size() / A.n : 0.0;
     int T = 1;
-    while (T < 8 && mean > 8.0 * T) T *= 2;
+    while (T < 32 && mean > 4.0 * T) T *= 2;
     return T;
 }
 
@@ -748,7 +748,9 @@ static void launch_team(hipStream_t s, bool sm, const AmgLevel &L, const double 
     case 1: launch_pair<CH, 1>(s, sm, L, b, xin, out); break;
     case 2: launch_pair<CH, 2>(s, sm, L, b, xin, out); break;
     case 4: launch_pair<CH, 4>(s, sm, L, b, xin, out); break;
-    default: launch_pair<CH, 8>(s, sm, L, b, xin, out); break;
+    case 8: launch_pair<CH, 8>(s, sm, L, b, xin, out); break;
+    case 16: launch_pair<CH, 16>(s, sm, L, b, xin, out); break;
+    default: launch_pair<CH, 32>(s, sm, L, b, xin, out); break;
     }
 }
 
