@@ -312,6 +312,38 @@ def test_blackoil64_bilu0(solver):
         _check_bicgstab(s, gpu, A, pc, 1e-8, 5000)
 
 
+def test_blackoil128x128x64_cpr_mixed_precision():
+    # the 128x128x64 configuration at full size (3,145,728 unknowns): the
+    # oracle's solve is too slow here, so the checks are ones that hold at
+    # any size: the whole SpMV against the oracle, FGMRES(30) + CPR-PF in
+    # FP64, FP32 and with BF16 factors each reaching a true FP64 residual of
+    # 1e-8 recomputed by the oracle, and the reduced-precision iteration
+    # counts within 10% of the FP64 run's
+    s = ri.blackoil_system(128, 128, 64, seed=0)
+    A = oracle.Matrix.from_system(s)
+    g = GpuSystem(s)
+    res = {}
+    try:
+        x = np.random.default_rng(21).standard_normal(A.n)
+        xt, xh = g.vec(x)
+        yt, yh = g.vec()
+        K.MatVecMXY(g.A, xh, yh)
+        torch.cuda.synchronize()
+        assert relerr(yt.cpu().numpy(), oracle.spmv(A, x)) <= 1e-12
+        for prec in (K.KRY_PREC_F64, K.KRY_PREC_F32, K.KRY_PREC_BF16_FACTORS):
+            res[prec] = solve(g, K.KRY_FGMRES, K.KRY_PC_CPR, rtol=1e-8, maxit=5000, prec=prec,
+                              cpr=(K.KRY_CPR_PF, 4))
+    finally:
+        g.close()
+    nb = np.linalg.norm(s["b"])
+    for prec, r in res.items():
+        assert r["status"] == K.KRY_OK, (prec, r["status"])
+        assert np.linalg.norm(s["b"] - oracle.spmv(A, r["x"])) <= 1e-8 * nb * (1 + 1e-9)
+    it64 = res[K.KRY_PREC_F64]["iters"]
+    for prec in (K.KRY_PREC_F32, K.KRY_PREC_BF16_FACTORS):
+        assert abs(res[prec]["iters"] - it64) <= max(1, 0.1 * it64), (prec, res[prec]["iters"], it64)
+
+
 # ---- LGMRES (aug_k > 0) and preconditioned CG (Algorithm 2) ------------------------
 @pytest.mark.parametrize("grid", [SMALL_BLOCK, (32, 32, 16)])
 def test_lgmres_solve(grid):
