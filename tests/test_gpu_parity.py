@@ -810,3 +810,63 @@ def test_amg_errors():
     finally:
         gb.close()
         gs.close()
+
+
+def test_amg_degenerate_hierarchies():
+    rng = np.random.default_rng(22)
+    # no off-diagonal entries: nothing is strong, nothing coarsens, the one
+    # level is solved exactly
+    D = np.diag(1.0 + rng.random(50))
+    g = GpuSystem(bsr_from_dense(D, 1))
+    try:
+        v = rng.standard_normal(50)
+        S = make_solver(g, K.KRY_GMRES, K.KRY_PC_AMG)
+        K.SolverAssemble(S)
+        assert K.SolverGetAMGLevels(S) == 1
+        K.SolverDestroy(S)
+        z = pc_apply(g, K.KRY_PC_AMG, v, solver=K.KRY_GMRES)
+        assert relerr(z, v / np.diag(D)) <= 1e-14
+    finally:
+        g.close()
+    # a 1D chain of 40 points: several levels, against the oracle
+    n = 40
+    C = 2.5 * np.eye(n) - np.eye(n, k=1) - np.eye(n, k=-1)
+    sc = bsr_from_dense(C, 1)
+    A = oracle.Matrix.from_system(sc)
+    v = rng.standard_normal(n)
+    g = GpuSystem(sc)
+    try:
+        S = make_solver(g, K.KRY_GMRES, K.KRY_PC_AMG)
+        K.SolverAssemble(S)
+        M = oracle.AMG(A, gs_chunk=4)
+        assert M.nlevels >= 3
+        _amg_levels_equal(S, M)
+        K.SolverDestroy(S)
+        z = pc_apply(g, K.KRY_PC_AMG, v, solver=K.KRY_GMRES)
+        assert relerr(z, oracle.PC.amg(A, gs_chunk=4).apply(v)) <= 1e-12
+    finally:
+        g.close()
+
+
+def test_amg_single_level_is_a_direct_solve():
+    # max_levels = 1: the whole matrix is the coarsest level; one GMRES step
+    s = ri.scalar_system(12, 10, 9, seed=23)
+    A = oracle.Matrix.from_system(s)
+    g = GpuSystem(s)
+    try:
+        gpu = solve(g, K.KRY_GMRES, K.KRY_PC_AMG, rtol=1e-10, maxit=50, amg=(1, 2, 4))
+    finally:
+        g.close()
+    assert gpu["status"] == K.KRY_OK and gpu["iters"] == 1
+    assert np.linalg.norm(s["b"] - oracle.spmv(A, gpu["x"])) <= 1e-10 * np.linalg.norm(s["b"])
+    # a coarsest level beyond the dense limit is refused
+    big = ri.scalar_system(24, 24, 16, seed=23)
+    g = GpuSystem(big)
+    try:
+        S = make_solver(g, K.KRY_GMRES, K.KRY_PC_AMG, amg=(1, 2, 4))
+        with pytest.raises(K.KrylovError) as e:
+            K.SolverAssemble(S)
+        assert e.value.code == K.KRY_ERR_UNSUPPORTED
+        K.SolverDestroy(S)
+    finally:
+        g.close()
