@@ -387,10 +387,13 @@ void or_cpr_extract_pressure(int nb, const int *rp, const int *ci,
  *   strength       j is a strong dependency of i when
  *                  -s a_ij >= theta max_{k != i} (-s a_ik), s = sign(a_ii);
  *                  a row with |sum_j a_ij| > max_row_sum |a_ii| has none
- *   coarse points  Ruge-Stueben first pass (the undecided point on which
- *                  most undecided points strongly depend becomes C, ties to
- *                  the smallest index; the points depending on it become F)
- *                  and second pass (a strong F-F pair shares a C point)
+ *   coarse points  Ruge-Stueben first pass (the undecided point of largest
+ *                  measure becomes C, ties to the smallest index, and the
+ *                  undecided points depending on it become F; a measure
+ *                  starts at the number of points depending on the point,
+ *                  +1 when one of them becomes F that way, -1 when one
+ *                  becomes C; a point taken with measure 0 becomes F) and
+ *                  second pass (a strong F-F pair shares a C point)
  *   interpolation  classical: an F point interpolates from its strong C
  *                  points; its strong F neighbours are distributed over
  *                  them through their entries of sign opposite to their

@@ -7,10 +7,13 @@
 //                 -s a_ij >= theta max_{k != i} (-s a_ik), s = sign(a_ii);
 //                 a row with |sum_j a_ij| > max_row_sum |a_ii| has none
 //   coarse points Ruge-Stueben: first pass takes the undecided point with
-//                 the largest measure (undecided points depending on it, F
-//                 points counted twice), ties to the smallest index, as C
-//                 and the points depending on it as F; the second pass makes
-//                 sure a strong F-F pair shares a C point
+//                 the largest measure, ties to the smallest index, as C and
+//                 the undecided points depending on it as F.  A measure
+//                 starts at the number of points depending on the point,
+//                 rises by one when one of those becomes F beside a new C
+//                 point and falls by one when one becomes C; a point taken
+//                 with measure 0 becomes F.  The second pass makes sure a
+//                 strong F-F pair shares a C point.
 //   interpolation classical: strong F neighbours distributed over the C
 //                 points through their entries of sign opposite to their
 //                 diagonal, weak neighbours lumped into the diagonal;
