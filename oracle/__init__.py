@@ -91,6 +91,8 @@ def load(path: str):
     L.or_amg_level_get.argtypes = [P, I, P, P, P, P, P, P, P]
     L.or_pc_create_amg.argtypes = [I, I, I, P, P, P, P, C.POINTER(I)]
     L.or_pc_create_amg.restype = P
+    L.or_pc_create_cpr.argtypes = [I, I, P, P, P, P, I, P, C.POINTER(I)]
+    L.or_pc_create_cpr.restype = P
     L.or_gelu.argtypes = [D]
     L.or_gelu.restype = D
     L.or_bf16_round.argtypes = [C.c_float]
@@ -331,6 +333,27 @@ class PC:
         obj.err = err.value
         if not obj.h:
             raise RuntimeError(f"oracle AMG setup failed: {obj.err}")
+        return obj
+
+    @classmethod
+    def cpr(cls, A: "Matrix", kind="cpr_fpf", amg=None, p_sweeps=4, full=None):
+        """FP64 CPR whose pressure stage is one AMG V-cycle (amg = dict of
+        AMG options, {} for the defaults) or p_sweeps ILU(0) sweeps, and
+        whose full-system stage R(A)^-1 is the preconditioner `full` (a PC,
+        e.g. RAS; it is taken over) or block ILU(0)."""
+        obj = cls.__new__(cls)
+        obj.A = A
+        obj._opts = None if amg is None else AmgOpts.make(**amg)
+        fh = None
+        if full is not None:
+            fh, full.h = full.h, None      # ownership moves to the CPR object
+        err = C.c_int(0)
+        obj.h = lib().or_pc_create_cpr(PC_KIND[kind], A.nb, _p(A.rowptr), _p(A.col), _p(A.val),
+                                       None if obj._opts is None else C.byref(obj._opts),
+                                       int(p_sweeps), fh, C.byref(err))
+        obj.err = err.value
+        if not obj.h:
+            raise RuntimeError(f"oracle CPR setup failed: {obj.err}")
         return obj
 
     @classmethod

@@ -967,6 +967,7 @@ struct or_pc {
     lowp_lu lpp;                /* rounded pressure factor                */
     float *appf, *af;           /* rounded A_pp values, rounded A values  */
     or_amg *amg;                /* AMG, or CPR's AMG pressure stage       */
+    or_pc *full;                /* CPR's full-system stage when not BILU(0) */
     /* learned stage */
     or_pc *base;
     int nx, ny, nz, bf16;
@@ -1195,7 +1196,23 @@ void or_pc_destroy(or_pc *pc)
     free(pc->subs);
     free(pc->part);
     or_amg_destroy(pc->amg);
+    if (pc->full) or_pc_destroy(pc->full);
     free(pc);
+}
+
+or_pc *or_pc_create_cpr(int kind, int nb, const int *rp, const int *ci, const double *a,
+                        const or_amg_opts *amg, int p_sweeps, or_pc *full, int *err)
+{
+    const int is_cpr = kind == OR_PC_CPR_PF || kind == OR_PC_CPR_FP ||
+                       kind == OR_PC_CPR_FPF || kind == OR_PC_CPR_FFPF;
+    int e = is_cpr ? OR_OK : OR_ERR_ARG;
+    or_pc *pc = NULL;
+    if (!e) pc = amg ? or_pc_create_amg(kind, nb, 3, rp, ci, a, amg, &e)
+                     : or_pc_create(kind, nb, 3, rp, ci, a, OR_PREC_F64, p_sweeps, &e);
+    if (pc) pc->full = full;
+    else if (full) or_pc_destroy(full);
+    if (err) *err = e;
+    return pc;
 }
 
 or_pc *or_pc_create_amg(int kind, int nb, int bs, const int *rp, const int *ci,
@@ -1276,11 +1293,19 @@ static void cpr_resid_f64(or_pc *pc, const double *f, const double *x, double *r
     or_bsr_amxpby(pc->nb, 3, pc->rp, pc->ci, pc->a, -1.0, x, 1.0, r);
 }
 
+/* the full-system solve R(A)^-1 of Algorithms 5-8: block ILU(0), or the
+ * preconditioner given as the full stage (RAS) */
+static void full_solve_f64(or_pc *pc, const double *r, double *t)
+{
+    if (pc->full) or_pc_apply(pc->full, r, t);
+    else or_bilu0_solve(pc->nb, 3, pc->rp, pc->ci, pc->lu, r, t);
+}
+
 static void cpr_full_f64(or_pc *pc, const double *r, double *x)
 {
     const size_t n = 3 * (size_t)pc->nb;
     double *t = (double *)malloc(sizeof(double) * n);
-    or_bilu0_solve(pc->nb, 3, pc->rp, pc->ci, pc->lu, r, t);
+    full_solve_f64(pc, r, t);
     for (size_t i = 0; i < n; i++) x[i] += t[i];
     free(t);
 }
@@ -1415,12 +1440,12 @@ void or_pc_apply(or_pc *pc, const double *v, double *z)
             for (int i = 0; i < nb; i++) { z[3 * i] = p[i]; z[3 * i + 1] = 0.0; z[3 * i + 2] = 0.0; }
             memcpy(r, v, sizeof(double) * n);
             or_bsr_amxpby(nb, 3, pc->rp, pc->ci, pc->a, -1.0, z, 1.0, r);
-            or_bilu0_solve(nb, 3, pc->rp, pc->ci, pc->lu, r, t);
+            full_solve_f64(pc, r, t);
             for (size_t i = 0; i < n; i++) z[i] += t[i];
         } else {
             /* Algorithm 5: z1 = BILU^-1 v; r = v - A z1;
              * z = z1 + Pi_p(P-stage(Pi_r W r)) */
-            or_bilu0_solve(nb, 3, pc->rp, pc->ci, pc->lu, v, z);
+            full_solve_f64(pc, v, z);
             memcpy(r, v, sizeof(double) * n);
             or_bsr_amxpby(nb, 3, pc->rp, pc->ci, pc->a, -1.0, z, 1.0, r);
             for (int i = 0; i < nb; i++)

@@ -119,6 +119,12 @@ or_pc *or_pc_create_ras(int nb, int bs, const int *rp, const int *ci,
  * V-cycle on A_pp instead of ILU(0) sweeps */
 or_pc *or_pc_create_amg(int kind, int nb, int bs, const int *rp, const int *ci,
                         const double *a, const or_amg_opts *o, int *err);
+/* FP64 CPR (a CPR kind, bs = 3) with the pressure stage one AMG V-cycle
+ * (amg != NULL) or p_sweeps ILU(0) sweeps, and the full-system stage R(A)^-1
+ * the preconditioner `full` (e.g. RAS; ownership passes, also on failure)
+ * or, when NULL, block ILU(0) */
+or_pc *or_pc_create_cpr(int kind, int nb, const int *rp, const int *ci, const double *a,
+                        const or_amg_opts *amg, int p_sweeps, or_pc *full, int *err);
 void or_pc_apply(or_pc *pc, const double *v, double *z);
 void or_pc_destroy(or_pc *pc);
 /* counters of the learned stage: applications and fallbacks */

@@ -65,8 +65,8 @@ MUTANTS = [
      "app[p] = w[3 * i] * B[0] + w[3 * i + 1] * B[1] + w[3 * i + 2] * B[2];",
      [lambda: tc.test_pressure_matrix_is_decoupled_operator_on_pressure_vectors()]),
     ("cpr_pf_second_stage_on_v",
-     "or_bsr_amxpby(nb, 3, pc->rp, pc->ci, pc->a, -1.0, z, 1.0, r);\n            or_bilu0_solve(nb, 3, pc->rp, pc->ci, pc->lu, r, t);",
-     "or_bilu0_solve(nb, 3, pc->rp, pc->ci, pc->lu, r, t);",
+     "or_bsr_amxpby(nb, 3, pc->rp, pc->ci, pc->a, -1.0, z, 1.0, r);\n            full_solve_f64(pc, r, t);",
+     "full_solve_f64(pc, r, t);",
      [lambda: tc.test_cpr_exact_when_stages_are_exact("cpr_pf")]),
     ("cpr_ffpf_skips_second_full_stage",
      "if (pc->kind == OR_PC_CPR_FFPF) {\n        cpr_resid_f64(pc, f, x, r);",
@@ -171,6 +171,10 @@ MUTANTS = [
      "    amg_smooth(M, L);                                     /* x = T(x, A, b) */",
      "    (void)0;                                              /* x = T(x, A, b) */",
      [lambda: ta.test_vcycle_matches_dense_algorithm4(0, 2)]),
+    ("cpr_full_stage_ignored",
+     "    if (pc->full) or_pc_apply(pc->full, r, t);",
+     "    if (0) or_pc_apply(pc->full, r, t);",
+     [lambda: tr.test_cpr_with_ras_full_stage_converges()]),
     ("amg_coarse_correction_sign",
      "        L->x[i] += s;",
      "        L->x[i] -= s;",

@@ -191,3 +191,32 @@ def test_ras_sets_rejects_bad_sets():
     bad_part[0] = 2
     with pytest.raises(RuntimeError):
         oracle.PC.ras_sets(A, bad_part, sets)
+
+
+# ---- RAS as CPR's full-system stage R(A)^-1 (Algorithms 5-8) -----------------
+@pytest.mark.parametrize("kind", ["cpr_pf", "cpr_fp", "cpr_fpf", "cpr_ffpf"])
+def test_cpr_with_one_ras_subdomain_is_block_ilu_cpr(kind):
+    # one subdomain is the whole matrix: its local block ILU(0) solve is the
+    # global one, so the CPR operator is unchanged, bit for bit
+    s = ri.blackoil_system(6, 5, 4, seed=21)
+    A = oracle.Matrix.from_system(s)
+    v = np.random.default_rng(22).standard_normal(A.n)
+    one = oracle.PC.ras(A, [0, A.nb], 1)
+    assert np.array_equal(oracle.PC.cpr(A, kind, full=one).apply(v), oracle.PC(A, kind).apply(v))
+    one = oracle.PC.ras(A, [0, A.nb], 1)
+    assert np.array_equal(oracle.PC.cpr(A, kind, amg={"gs_chunk": 4}, full=one).apply(v),
+                          oracle.PC.amg(A, kind, gs_chunk=4).apply(v))
+
+
+def test_cpr_with_ras_full_stage_converges():
+    s = ri.blackoil_system(12, 10, 8, seed=23)
+    A = oracle.Matrix.from_system(s)
+    v = np.random.default_rng(24).standard_normal(A.n)
+    part, sets = box_partition((12, 10, 8), (1, 2, 2), 1)
+    z_ras = oracle.PC.cpr(A, "cpr_fpf", full=oracle.PC.ras_sets(A, part, sets)).apply(v)
+    z_ilu = oracle.PC(A, "cpr_fpf").apply(v)
+    assert 1e-8 < relerr(z_ras, z_ilu) < 0.5
+    for amg in (None, {"gs_chunk": 4}):
+        pc = oracle.PC.cpr(A, "cpr_fpf", amg=amg, full=oracle.PC.ras_sets(A, part, sets))
+        r = oracle.gmres(A, pc, s["b"], restart=30, maxit=500, rtol=1e-8, flexible=True)
+        assert r["status"] == 0 and r["relres"] <= 1e-8
