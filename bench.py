@@ -62,6 +62,8 @@ CONFIGS = [
     ("gmres30_ilu0_scalar_f64", "GMRES", "ILU0", "F64", None),
     ("gmres30_amg_scalar_f64", "GMRES", "AMG", "F64", None),
     ("fgmres30_cpr_fpf_amg_f64", "FGMRES", "CPR", "F64", ("FPF", 4)),
+    ("fgmres30_cpr_fpf_ras_f64", "FGMRES", "CPR", "F64", ("FPF", 4)),
+    ("fgmres30_cpr_fpf_ras_amg_f64", "FGMRES", "CPR", "F64", ("FPF", 4)),
 ]
 # per-configuration extras: LGMRES augmentation, and the symmetric scalar
 # system of the same grid (CG needs a symmetric positive definite matrix)
@@ -72,7 +74,11 @@ EXTRAS = {"lgmres30_2_bilu0_f64": dict(aug_k=2), "pcg_ilu0_scalar_f64": dict(sys
           "gmres30_rasbox_2x2x2_f64": dict(ras=(2, 2, 2, 1)),
           "gmres30_ilu0_scalar_f64": dict(system="scalar"),
           "gmres30_amg_scalar_f64": dict(system="scalar"),
-          "fgmres30_cpr_fpf_amg_f64": dict(cpr_pressure="AMG")}
+          "fgmres30_cpr_fpf_amg_f64": dict(cpr_pressure="AMG"),
+          # the paper's CPR: full stage R(A)^-1 = RAS (1x4x4 boxes, overlap 1)
+          "fgmres30_cpr_fpf_ras_f64": dict(cpr_full="RAS", ras=(1, 4, 4, 1)),
+          "fgmres30_cpr_fpf_ras_amg_f64": dict(cpr_full="RAS", ras=(1, 4, 4, 1),
+                                               cpr_pressure="AMG")}
 WEIGHTS = os.path.join(ROOT, "paper_1701_05913_amd", "weights", "bilu0_blackoil64.bin")
 
 # matrix-core FLOPs per cell of each conv layer (3x3x3 taps, 2 per MAC)
@@ -244,6 +250,7 @@ def main():
         if cpr:
             K.SolverSetCPR(S, getattr(K, f"KRY_CPR_{cpr[0]}"), cpr[1])
             K.SolverSetCPRPressure(S, getattr(K, f"KRY_CPR_P_{ex.get('cpr_pressure', 'ILU0')}"))
+            K.SolverSetCPRFull(S, getattr(K, f"KRY_CPR_F_{ex.get('cpr_full', 'BILU0')}"))
         K.SolverSetStream(S, stream)
         K.SolverSetSweepLayout(S, getattr(K, f"KRY_SWEEP_{args.layout.upper()}"))
         if pc.endswith("_LEARNED"):

@@ -81,6 +81,10 @@ enum { KRY_CPR_PF = 0, KRY_CPR_FP = 1, KRY_CPR_FPF = 2, KRY_CPR_FFPF = 3 };
 /* CPR pressure solver: ILU(0) sweeps (SolverSetCPR's p_sweeps) or one AMG
  * V-cycle on A_pp, the paper's M_g(A_pp)^-1 (Algorithms 5-8) */
 enum { KRY_CPR_P_ILU0 = 0, KRY_CPR_P_AMG = 1 };
+/* CPR full-system stage R(A)^-1 of Algorithms 5-8: block ILU(0) of A, or
+ * RAS with block ILU(0) subdomain solves (the paper's R(A)^-1) on the
+ * solver's RAS subdomains (SolverSetRAS / SolverSetRASBoxes) */
+enum { KRY_CPR_F_BILU0 = 0, KRY_CPR_F_RAS = 1 };
 /* layout of the ILU triangular sweeps: AUTO picks GRID when the matrix is a
  * 7-point stencil on an nx x ny x nz grid (nx, ny, nz >= 2) in natural
  * order, LEVELS otherwise */
@@ -203,6 +207,10 @@ int SolverSetCPR(SOLVER *s, int variant, int p_sweeps);
 /* CPR's pressure solver, KRY_CPR_P_ILU0 (default) or KRY_CPR_P_AMG (FP64
  * only; KRY_ERR_UNSUPPORTED at SolverAssemble otherwise). */
 int SolverSetCPRPressure(SOLVER *s, int psolver);
+/* CPR's full-system stage, KRY_CPR_F_BILU0 (default) or KRY_CPR_F_RAS (FP64
+ * and a 7-point grid matrix; KRY_ERR_UNSUPPORTED at SolverAssemble
+ * otherwise). */
+int SolverSetCPRFull(SOLVER *s, int fsolver);
 /* Algebraic multigrid (Section 4.2: Algorithm 3 setup, Algorithm 4
  * V-cycle; classical Ruge-Stueben strength, coarsening and interpolation
  * with Figure 34's strength 0.5, max row sum 0.9 and truncation 0.01), for

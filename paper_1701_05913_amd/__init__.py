@@ -36,6 +36,7 @@ KRY_PC_BILU0_LEARNED, KRY_PC_CPR_LEARNED, KRY_PC_RAS, KRY_PC_AMG = 4, 5, 6, 7
 KRY_PREC_F64, KRY_PREC_F32, KRY_PREC_BF16_FACTORS = 0, 1, 2
 KRY_CPR_PF, KRY_CPR_FP, KRY_CPR_FPF, KRY_CPR_FFPF = 0, 1, 2, 3
 KRY_CPR_P_ILU0, KRY_CPR_P_AMG = 0, 1
+KRY_CPR_F_BILU0, KRY_CPR_F_RAS = 0, 1
 KRY_SWEEP_AUTO, KRY_SWEEP_LEVELS, KRY_SWEEP_GRID = 0, 1, 2
 
 
@@ -85,6 +86,7 @@ _SIGS = {
     "SolverSetRAS": (C.c_int, [P, C.c_int, C.c_int]),
     "SolverSetRASBoxes": (C.c_int, [P, C.c_int, C.c_int, C.c_int, C.c_int]),
     "SolverSetCPRPressure": (C.c_int, [P, C.c_int]),
+    "SolverSetCPRFull": (C.c_int, [P, C.c_int]),
     "SolverSetAMG": (C.c_int, [P, C.c_int, C.c_int, C.c_int]),
     "SolverGetAMGLevels": (C.c_int, [P]),
     "SolverGetAMGLevel": (C.c_int, [P, C.c_int] + [C.POINTER(I32)] * 4 + [P] * 7),
@@ -318,6 +320,7 @@ def SolverSetCPR(s, variant, p_sweeps): return _check(_lib.SolverSetCPR(s, varia
 def SolverSetRAS(s, nsub, overlap): return _check(_lib.SolverSetRAS(s, nsub, overlap))
 def SolverSetRASBoxes(s, px, py, pz, overlap): return _check(_lib.SolverSetRASBoxes(s, px, py, pz, overlap))
 def SolverSetCPRPressure(s, psolver): return _check(_lib.SolverSetCPRPressure(s, psolver))
+def SolverSetCPRFull(s, fsolver): return _check(_lib.SolverSetCPRFull(s, fsolver))
 def SolverSetAMG(s, max_levels, num_sweeps, gs_chunk):
     return _check(_lib.SolverSetAMG(s, max_levels, num_sweeps, gs_chunk))
 def SolverGetAMGLevels(s): return _check(_lib.SolverGetAMGLevels(s))

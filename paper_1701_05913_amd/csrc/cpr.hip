@@ -109,6 +109,15 @@ __global__ void k_inject_add(int nb, const T *__restrict__ z1, const T *__restri
     z[b + 2] = static_cast<double>(z1[b + 2]);
 }
 
+// out = a + b
+template <typename T>
+__global__ void k_add_vec(int64_t n, const T *__restrict__ a, const T *__restrict__ b,
+                          T *__restrict__ out) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        out[i] = a[i] + b[i];
+}
+
 template <typename T>
 __global__ void k_cast(int64_t n, const double *__restrict__ x, T *__restrict__ y) {
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
@@ -159,7 +168,13 @@ int cpr_setup(hipStream_t s, MAT_ *A, CprPC &C, int variant, int sweeps, int pre
     } else {
         KRY_TRY(ilu_setup(s, &P, P.val.p, C.ilu_p, pprec, d_err, layout));
     }
-    KRY_TRY(ilu_setup(s, A, A->val.p, C.ilu_a, prec, d_err, layout));
+    if (C.ras) {
+        if (prec != KRY_PREC_F64) return set_error(KRY_ERR_UNSUPPORTED, "CPR-RAS: FP64 only");
+        KRY_TRY(ras_setup(s, A, *C.ras, C.ras_box[0], C.ras_box[1], C.ras_box[2], C.ras_box[3], prec,
+                          d_err, layout));
+    } else {
+        KRY_TRY(ilu_setup(s, A, A->val.p, C.ilu_a, prec, d_err, layout));
+    }
     if (prec != KRY_PREC_F64) {
         KRY_TRY(ensure_sell_f32(s, P.sell));
         if (variant == KRY_CPR_PF) KRY_TRY(ensure_col0_f32(s, A));
@@ -206,6 +221,21 @@ static int cpr_apply_t(hipStream_t s, MAT_ *A, CprPC &C, const double *v, double
         }
         return KRY_OK;
     };
+    // the full-system stage R(A)^-1 with ilu_apply's add modes: 0 out = R^-1 in
+    // (in xs_out); 1 add_out = add_in + R^-1 in; 2 add_out = Pi_p add_in +
+    // R^-1 in.  RAS (FP64 only) solves into xs_out and adds afterwards.
+    auto full = [&](const T *in, T *xs_out, int mode, const T *add_in, double *add_out) -> int {
+        if (!C.ras)
+            return ilu_apply(s, C.ilu_a, in, tin, xs_out, tin, mode, add_in, add_out, err);
+        KRY_TRY(ras_apply(s, *C.ras, (const double *)in, (double *)xs_out, err));
+        if (mode == 1)
+            hipLaunchKernelGGL(k_add_vec<double>, dim3(2048), blk, 0, s, n, (const double *)add_in,
+                               (const double *)xs_out, add_out);
+        if (mode == 2)
+            hipLaunchKernelGGL(k_inject_add<double>, g, blk, 0, s, nb, (const double *)xs_out,
+                               (const double *)add_in, add_out);
+        return KRY_OK;
+    };
     // r2 = v - A x over the full blocks
     auto residual = [&](const T *x) -> int {
         if (tin == 0)
@@ -215,10 +245,10 @@ static int cpr_apply_t(hipStream_t s, MAT_ *A, CprPC &C, const double *v, double
                              (float *)r2);
     };
     if (C.variant == KRY_CPR_FPF || C.variant == KRY_CPR_FFPF) {
-        KRY_TRY(ilu_apply(s, C.ilu_a, vin, tin, z1, tin, 0, nullptr, nullptr, err));
+        KRY_TRY(full(vin, z1, 0, nullptr, nullptr));
         if (C.variant == KRY_CPR_FFPF) {
             KRY_TRY(residual(z1));
-            KRY_TRY(ilu_apply(s, C.ilu_a, r2, tin, xs, tin, 1, z1, z2, err));
+            KRY_TRY(full(r2, xs, 1, z1, (double *)z2));
             std::swap(z1, z2);
         }
         KRY_TRY(residual(z1));
@@ -226,7 +256,7 @@ static int cpr_apply_t(hipStream_t s, MAT_ *A, CprPC &C, const double *v, double
         hipLaunchKernelGGL(k_inject_inplace<T>, g, blk, 0, s, nb, p, z1);
         KRY_TRY(residual(z1));
         if (tin == 0) {
-            KRY_TRY(ilu_apply(s, C.ilu_a, r2, tin, xs, tin, 1, z1, z, err));
+            KRY_TRY(full(r2, xs, 1, z1, z));
         } else {
             KRY_TRY(ilu_apply(s, C.ilu_a, r2, tin, xs, tin, 1, z1, z2, err));
             hipLaunchKernelGGL(k_widen, dim3(2048), blk, 0, s, n, (const float *)z2, z);
@@ -237,9 +267,9 @@ static int cpr_apply_t(hipStream_t s, MAT_ *A, CprPC &C, const double *v, double
             KRY_TRY(spmv_col0_residual_f64(s, A, (const double *)vin, (const double *)p, (double *)r2));
         else
             KRY_TRY(spmv_col0_residual_f32(s, A, (const float *)vin, (const float *)p, (float *)r2));
-        KRY_TRY(ilu_apply(s, C.ilu_a, r2, tin, xs, tin, 2, p, z, err));
+        KRY_TRY(full(r2, xs, 2, p, z));
     } else {
-        KRY_TRY(ilu_apply(s, C.ilu_a, vin, tin, z1, tin, 0, nullptr, nullptr, err));
+        KRY_TRY(full(vin, z1, 0, nullptr, nullptr));
         if (tin == 0)
             KRY_TRY(spmv_f64(s, A, -1.0, (const double *)z1, 1.0, v, (double *)r2, 0, nullptr,
                              nullptr, nullptr));

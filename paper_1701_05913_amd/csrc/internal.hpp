@@ -320,6 +320,7 @@ int amg_setup(hipStream_t s, int n, const int *h_rowptr, const int *h_col, const
 // x = one V-cycle applied to b (device vectors of n, distinct)
 int amg_apply(hipStream_t s, AmgPC &M, const double *b, double *x, int *d_err);
 
+struct RasPC;
 struct CprPC {
     int variant = KRY_CPR_PF, sweeps = 4, prec = KRY_PREC_F64;
     int nb = 0;
@@ -329,6 +330,8 @@ struct CprPC {
     IluFactor ilu_a;        // block ILU(0) of A
     std::unique_ptr<AmgPC> amg;   // pressure stage: one V-cycle instead of ILU(0) sweeps
     AmgOpts amg_opts;
+    std::unique_ptr<RasPC> ras;   // full-system stage: RAS instead of block ILU(0)
+    int ras_box[4] = {1, 1, 4, 1};   // px, py, pz, overlap
     DBuf<char> work;        // scratch vectors
 };
 // One grid of a multi-grid sweep launch (the subdomains of RAS, boxes of a
@@ -442,7 +445,7 @@ struct SOLVER_ {
     int restart = 30;
     int prec = KRY_PREC_F64;
     int cpr_variant = KRY_CPR_PF, cpr_sweeps = 4;
-    int cpr_psolver = KRY_CPR_P_ILU0;
+    int cpr_psolver = KRY_CPR_P_ILU0, cpr_full = KRY_CPR_F_BILU0;
     kry::AmgOpts amg_opts;
     std::unique_ptr<kry::AmgPC> amg;
     int sweep_layout = KRY_SWEEP_AUTO;

@@ -1047,6 +1047,13 @@ extern "C" int SolverSetCPRPressure(SOLVER *s, int psolver) {
     s->assembled = false;
     return KRY_OK;
 }
+extern "C" int SolverSetCPRFull(SOLVER *s, int fsolver) {
+    if (!s || (fsolver != KRY_CPR_F_BILU0 && fsolver != KRY_CPR_F_RAS))
+        return set_error(KRY_ERR_ARG, "SolverSetCPRFull: bad argument");
+    s->cpr_full = fsolver;
+    s->assembled = false;
+    return KRY_OK;
+}
 extern "C" int SolverSetAMG(SOLVER *s, int max_levels, int num_sweeps, int gs_chunk) {
     if (!s || max_levels < 1 || num_sweeps < 1) return set_error(KRY_ERR_ARG, "SolverSetAMG: bad argument");
     s->amg_opts.max_levels = max_levels;
@@ -1169,6 +1176,13 @@ extern "C" int SolverAssemble(SOLVER *s) {
                 return set_error(KRY_ERR_UNSUPPORTED, "CPR with the AMG pressure stage is FP64 only");
             s->cpr->amg.reset(new AmgPC());
             s->cpr->amg_opts = s->amg_opts;
+        }
+        if (s->cpr_full == KRY_CPR_F_RAS) {
+            if (s->prec != KRY_PREC_F64)
+                return set_error(KRY_ERR_UNSUPPORTED, "CPR with the RAS full stage is FP64 only");
+            s->cpr->ras.reset(new RasPC());
+            const int box[4] = {s->ras_px, s->ras_py, s->ras_pz, s->ras_overlap};
+            std::copy(box, box + 4, s->cpr->ras_box);
         }
         KRY_TRY(cpr_setup(s->stream, s->A, *s->cpr, s->cpr_variant, s->cpr_sweeps, s->prec, s->err.p,
                           s->sweep_layout));

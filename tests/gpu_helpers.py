@@ -44,7 +44,7 @@ class GpuSystem:
 
 def make_solver(g, solver, pc, rtol=1e-8, maxit=5000, restart=30,
                 prec=K.KRY_PREC_F64, cpr=(K.KRY_CPR_PF, 4), layout=K.KRY_SWEEP_AUTO, aug_k=0,
-                ras=(4, 1), amg=(8, 2, 4), cpr_p=K.KRY_CPR_P_ILU0):
+                ras=(4, 1), amg=(8, 2, 4), cpr_p=K.KRY_CPR_P_ILU0, cpr_f=K.KRY_CPR_F_BILU0):
     S = K.SolverCreate(solver, pc, g.map)
     K.SolverSetSweepLayout(S, layout)
     K.SolverSetMat(S, g.A)
@@ -56,9 +56,10 @@ def make_solver(g, solver, pc, rtol=1e-8, maxit=5000, restart=30,
     if pc == K.KRY_PC_CPR:
         K.SolverSetCPR(S, cpr[0], cpr[1])
         K.SolverSetCPRPressure(S, cpr_p)
+        K.SolverSetCPRFull(S, cpr_f)
     # (max_levels, num_sweeps, gs_chunk) of AMG, for KRY_PC_AMG and CPR-AMG
     K.SolverSetAMG(S, *amg)
-    if pc == K.KRY_PC_RAS:
+    if pc == K.KRY_PC_RAS or cpr_f == K.KRY_CPR_F_RAS:
         # (nsub, overlap): z-slabs; (px, py, pz, overlap): boxes
         if len(ras) == 4:
             K.SolverSetRASBoxes(S, *ras)
@@ -84,9 +85,10 @@ def solve(g, solver, pc, b=None, x0=None, **kw):
 
 
 def pc_apply(g, pc, v, prec=K.KRY_PREC_F64, cpr=(K.KRY_CPR_PF, 4), solver=K.KRY_FGMRES,
-             layout=K.KRY_SWEEP_AUTO, repeat=1, ras=(4, 1), amg=(8, 2, 4), cpr_p=K.KRY_CPR_P_ILU0):
+             layout=K.KRY_SWEEP_AUTO, repeat=1, ras=(4, 1), amg=(8, 2, 4), cpr_p=K.KRY_CPR_P_ILU0,
+             cpr_f=K.KRY_CPR_F_BILU0):
     S = make_solver(g, solver, pc, prec=prec, cpr=cpr, layout=layout, ras=ras, amg=amg,
-                    cpr_p=cpr_p)
+                    cpr_p=cpr_p, cpr_f=cpr_f)
     try:
         K.SolverAssemble(S)
         vt, vh = g.vec(v)

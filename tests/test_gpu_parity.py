@@ -870,3 +870,59 @@ def test_amg_single_level_is_a_direct_solve():
         K.SolverDestroy(S)
     finally:
         g.close()
+
+
+# ---- CPR with the paper's full-system stage R(A)^-1 = RAS (Algorithms 5-8) --------
+@pytest.mark.parametrize("variant,kind", [(K.KRY_CPR_PF, "cpr_pf"), (K.KRY_CPR_FP, "cpr_fp"),
+                                          (K.KRY_CPR_FPF, "cpr_fpf"), (K.KRY_CPR_FFPF, "cpr_ffpf")])
+@pytest.mark.parametrize("pressure", ["ilu", "amg"])
+def test_cpr_ras_full_stage_apply_parity(variant, kind, pressure):
+    grid, ras = (20, 18, 14), (1, 2, 2, 1)
+    s = ri.blackoil_system(*grid, seed=25)
+    A = oracle.Matrix.from_system(s)
+    v = np.random.default_rng(26).standard_normal(A.n)
+    full = oracle.PC.ras_sets(A, *box_partition(grid, ras[:3], ras[3]))
+    ref = oracle.PC.cpr(A, kind, amg={"gs_chunk": 4} if pressure == "amg" else None,
+                        full=full).apply(v)
+    g = GpuSystem(s)
+    try:
+        zs = pc_apply(g, K.KRY_PC_CPR, v, cpr=(variant, 4), ras=ras, cpr_f=K.KRY_CPR_F_RAS,
+                      cpr_p=K.KRY_CPR_P_AMG if pressure == "amg" else K.KRY_CPR_P_ILU0, repeat=2)
+    finally:
+        g.close()
+    assert np.array_equal(zs[0], zs[1])
+    assert relerr(zs[1], ref) <= 1e-10
+
+
+def test_cpr_ras_amg_solve():
+    # the paper's CPR-FPF: RAS full stage (8 z-slabs, overlap 1) and AMG pressure stage
+    grid = (24, 20, 16)
+    s = ri.blackoil_system(*grid, seed=27)
+    A = oracle.Matrix.from_system(s)
+    g = GpuSystem(s)
+    try:
+        gpu = solve(g, K.KRY_FGMRES, K.KRY_PC_CPR, rtol=1e-8, maxit=500, cpr=(K.KRY_CPR_FPF, 4),
+                    ras=(8, 1), cpr_f=K.KRY_CPR_F_RAS, cpr_p=K.KRY_CPR_P_AMG)
+    finally:
+        g.close()
+    starts = [q * 16 // 8 * 24 * 20 for q in range(9)]
+    pc = oracle.PC.cpr(A, "cpr_fpf", amg={"gs_chunk": 4}, full=oracle.PC.ras(A, starts, 1))
+    _check_solve(s, gpu, A, pc, 1e-8, oracle.gmres, restart=30, maxit=500, flexible=True)
+
+
+def test_cpr_ras_full_stage_errors():
+    s = ri.blackoil_system(6, 5, 4, seed=1)
+    g = GpuSystem(s)
+    try:
+        S = K.SolverCreate(K.KRY_FGMRES, K.KRY_PC_CPR, g.map)
+        K.SolverSetMat(S, g.A)
+        K.SolverSetPrecision(S, K.KRY_PREC_F32)
+        K.SolverSetCPRFull(S, K.KRY_CPR_F_RAS)
+        with pytest.raises(K.KrylovError) as e:
+            K.SolverAssemble(S)
+        assert e.value.code == K.KRY_ERR_UNSUPPORTED
+        with pytest.raises(K.KrylovError):
+            K.SolverSetCPRFull(S, 7)
+        K.SolverDestroy(S)
+    finally:
+        g.close()
