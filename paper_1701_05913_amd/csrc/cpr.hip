@@ -170,8 +170,13 @@ int cpr_setup(hipStream_t s, MAT_ *A, CprPC &C, int variant, int sweeps, int pre
     }
     if (C.ras) {
         if (prec != KRY_PREC_F64) return set_error(KRY_ERR_UNSUPPORTED, "CPR-RAS: FP64 only");
-        KRY_TRY(ras_setup(s, A, *C.ras, C.ras_box[0], C.ras_box[1], C.ras_box[2], C.ras_box[3], prec,
-                          d_err, layout));
+        const int rc = C.ras_reuse ? ras_refactor(s, A, *C.ras, d_err)
+                                   : ras_setup(s, A, *C.ras, C.ras_box[0], C.ras_box[1],
+                                               C.ras_box[2], C.ras_box[3], prec, d_err, layout);
+        if (rc < 0) {   // a half-built subdomain set is never reused
+            C.ras.reset();
+            return rc;
+        }
     } else {
         KRY_TRY(ilu_setup(s, A, A->val.p, C.ilu_a, prec, d_err, layout));
     }

@@ -332,6 +332,7 @@ struct CprPC {
     AmgOpts amg_opts;
     std::unique_ptr<RasPC> ras;   // full-system stage: RAS instead of block ILU(0)
     int ras_box[4] = {1, 1, 4, 1};   // px, py, pz, overlap
+    bool ras_reuse = false;          // ras holds this matrix's subdomains: refactor only
     DBuf<char> work;        // scratch vectors
 };
 // One grid of a multi-grid sweep launch (the subdomains of RAS, boxes of a

@@ -1151,6 +1151,8 @@ extern "C" int SolverAssemble(SOLVER *s) {
     if (!s->err.p) KRY_TRY(s->err.alloc(1));
     hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(64), 0, s->stream, s->err.p);
     s->ilu.reset();
+    // CPR's RAS full stage keeps its subdomain patterns like RAS does
+    std::unique_ptr<RasPC> cpr_ras = s->cpr ? std::move(s->cpr->ras) : nullptr;
     s->cpr.reset();
     s->amg.reset();
     // RAS keeps its subdomain patterns when the matrix and options are unchanged
@@ -1180,9 +1182,14 @@ extern "C" int SolverAssemble(SOLVER *s) {
         if (s->cpr_full == KRY_CPR_F_RAS) {
             if (s->prec != KRY_PREC_F64)
                 return set_error(KRY_ERR_UNSUPPORTED, "CPR with the RAS full stage is FP64 only");
-            s->cpr->ras.reset(new RasPC());
             const int box[4] = {s->ras_px, s->ras_py, s->ras_pz, s->ras_overlap};
             std::copy(box, box + 4, s->cpr->ras_box);
+            const RasPC *R = cpr_ras.get();
+            s->cpr->ras_reuse = R && R->A == s->A && R->px == box[0] && R->py == box[1] &&
+                                R->pz == box[2] && R->overlap == box[3] &&
+                                R->layout == s->sweep_layout;
+            if (s->cpr->ras_reuse) s->cpr->ras = std::move(cpr_ras);
+            else s->cpr->ras.reset(new RasPC());
         }
         KRY_TRY(cpr_setup(s->stream, s->A, *s->cpr, s->cpr_variant, s->cpr_sweeps, s->prec, s->err.p,
                           s->sweep_layout));

@@ -926,3 +926,34 @@ def test_cpr_ras_full_stage_errors():
         K.SolverDestroy(S)
     finally:
         g.close()
+
+
+def test_cpr_ras_reassemble_after_value_update():
+    # a second SolverAssemble reuses CPR's RAS subdomains and refactors them
+    grid, ras = (16, 12, 12), (1, 2, 2, 1)
+    s = ri.blackoil_system(*grid, seed=28)
+    A = oracle.Matrix.from_system(s)
+    v = np.random.default_rng(29).standard_normal(A.n)
+    sets = box_partition(grid, ras[:3], ras[3])
+    g = GpuSystem(s)
+    try:
+        S = make_solver(g, K.KRY_FGMRES, K.KRY_PC_CPR, cpr=(K.KRY_CPR_FPF, 4), ras=ras,
+                        cpr_f=K.KRY_CPR_F_RAS)
+        vt, vh = g.vec(v)
+        zt, zh = g.vec()
+        K.SolverAssemble(S)
+        K.SolverPCApply(S, vh, zh)
+        torch.cuda.synchronize()
+        ref = oracle.PC.cpr(A, "cpr_fpf", full=oracle.PC.ras_sets(A, *sets)).apply(v)
+        assert relerr(zt.cpu().numpy(), ref) <= 1e-10
+        val2 = s["val"].reshape(-1, 9).copy() * 1.25
+        K.MatUpdateValues(g.A, val2.reshape(-1))
+        K.SolverAssemble(S)
+        K.SolverPCApply(S, vh, zh)
+        torch.cuda.synchronize()
+        A2 = oracle.Matrix(s["rowptr"], s["col"], val2.reshape(-1), 3)
+        ref2 = oracle.PC.cpr(A2, "cpr_fpf", full=oracle.PC.ras_sets(A2, *sets)).apply(v)
+        assert relerr(zt.cpu().numpy(), ref2) <= 1e-10
+        K.SolverDestroy(S)
+    finally:
+        g.close()
