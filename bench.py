@@ -49,6 +49,7 @@ CONFIGS = [
     ("fgmres30_bilu0_bf16", "FGMRES", "BILU0", "BF16_FACTORS", None),
     ("fgmres30_cpr_f64", "FGMRES", "CPR", "F64", ("PF", 4)),
     ("fgmres30_cpr_f32", "FGMRES", "CPR", "F32", ("PF", 4)),
+    ("fgmres30_cpr_bf16", "FGMRES", "CPR", "BF16_FACTORS", ("PF", 4)),
     ("fgmres30_cpr_fpf_f64", "FGMRES", "CPR", "F64", ("FPF", 4)),
     ("fgmres30_cpr_ffpf_f64", "FGMRES", "CPR", "F64", ("FFPF", 4)),
     ("fgmres30_bilu0_learned", "FGMRES", "BILU0_LEARNED", "F64", None),
