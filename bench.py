@@ -37,6 +37,10 @@ WORKLOADS = {
     "blackoil128x128x64": dict(grid=(128, 128, 64), perm="layered", sigma2=2.0,
                                desc="128x128x64 3x3-block black-oil system "
                                     "(3,145,728 unknowns), seed 0"),
+    "channelized256x256x128": dict(grid=(256, 256, 128), perm="channelized", sigma2=3.0,
+                                   desc="256x256x128 3x3-block black-oil system (25,165,824 "
+                                        "unknowns, 58,458,112 blocks), channelized log-normal "
+                                        "permeability (20% channels at 1000x), seed 0"),
     "blackoil32": dict(grid=(32, 32, 32), perm="layered", sigma2=2.0,
                        desc="32^3 3x3-block black-oil system (quick check)"),
 }
@@ -273,6 +277,7 @@ def main():
                    true_relres=K.SolverGetResidual(S), status=rc)
         if name.endswith("_learned"):
             out["stage_applies"], out["stage_fallbacks"] = K.SolverGetLearnedStats(S)
+        print(f"[bench] {name}: {dt:.4f} s, {out['iters']} iterations", file=sys.stderr, flush=True)
         return out
 
     for _ in range(args.warmup):
