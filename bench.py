@@ -191,7 +191,7 @@ def main():
         print(json.dumps({"copy_probe_bytes": src.numel() * 8}))
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py: this build measures one GPU holding one rank's share; "
+        print("bench.py measures one GPU holding one rank's share; "
               "multi-GPU runs are not supported (use --gpus 1)", file=sys.stderr)
         sys.exit(2)
 
