@@ -473,6 +473,7 @@ struct SOLVER_ {
     kry::DBuf<double> V, Z, wrk, H, small, partial;
     kry::DBuf<double> AUG;       // LGMRES: stored corrections (aug_k columns)
     double *h_pinned = nullptr;  // host-visible readback slots
+    hipEvent_t step_ev[2] = {nullptr, nullptr};   // Arnoldi steps' read-backs (slots 8, 16)
 };
 
 namespace kry {

@@ -581,6 +581,8 @@ static int ensure_workspace(SOLVER_ *S) {
                                         (size_t)spmv_blocks(S->A) * 2});
     KRY_TRY(S->partial.alloc(np));
     if (!S->h_pinned) KRY_HIP(hipHostMalloc(reinterpret_cast<void **>(&S->h_pinned), 64 * sizeof(double)));
+    for (auto &ev : S->step_ev)
+        if (!ev) KRY_HIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
     KRY_HIP(hipMemsetAsync(S->small.p, 0, S->small.bytes(), S->stream));
     return KRY_OK;
 }
@@ -737,6 +739,10 @@ static int gmres_solve(SOLVER_ *S, const double *b, double *x) {
     int status = KRY_NOT_CONVERGED;
     double relres = 0.0;
     int nstored = 0, head = 0;   // corrections: the i-th newest in AUG slot (head + i) % k
+    // the next Arnoldi step may run ahead of the host's convergence test
+    // unless the preconditioner calls back into host code or counts its uses
+    const bool speculate = S->pc_type != KRY_PC_CUSTOM && S->pc_type != KRY_PC_BILU0_LEARNED &&
+                           S->pc_type != KRY_PC_CPR_LEARNED;
     for (;;) {
         double beta = 0.0;
         KRY_TRY(true_residual(S, b, x, S->V.p, &beta));
@@ -749,7 +755,16 @@ static int gmres_solve(SOLVER_ *S, const double *b, double *x) {
         KRY_TRY(vec_scale_copy(S->stream, n, dc(sc + SC_INVBETA), S->V.p, S->V.p));
         int jend = 0;
         const int steps = m + nstored;
-        for (int j = 0; j < steps; j++) {
+        // step j: z_j = M^-1 v_j (or the stored correction), w = A z_j, CGS2
+        // against v_0..v_j with the Hessenberg column and Givens update, then
+        // an asynchronous read-back of (h_{j+1,j}, 1/h_{j+1,j}, estimate) into
+        // pinned slot j % 2 and an event.  When the preconditioner runs no
+        // host code and keeps no counters, step j+1 is issued before step
+        // j's estimate is read, so the GPU never waits for the host; if step
+        // j ends the cycle, step j+1's results (column j+2 of V, column j+1
+        // of H and its rotation) are never used: the least-squares solve
+        // takes columns 0..j only.
+        auto issue = [&](int j) -> int {
             double *vj = S->V.p + (size_t)j * S->ldv;
             double *zj = flexible ? S->Z.p + (size_t)j * S->ldv : ztmp;
             double *w = S->V.p + (size_t)(j + 1) * S->ldv;
@@ -760,16 +775,36 @@ static int gmres_solve(SOLVER_ *S, const double *b, double *x) {
                                        sizeof(double) * n, hipMemcpyDeviceToDevice, S->stream));
             KRY_TRY(spmv_f64(S->stream, S->A, 1.0, zj, 0.0, nullptr, w, 0, nullptr, nullptr, nullptr));
             KRY_TRY(cgs2_step(S, j, w));
-            double hv[3];                                  // SC_HN, SC_INVHN, SC_EST
-            KRY_TRY(readback(S, sc + SC_HN, 3, hv));
-            const double est = hv[2];
+            KRY_HIP(hipMemcpyAsync(S->h_pinned + 8 + 8 * (j & 1), sc + SC_HN, 3 * sizeof(double),
+                                   hipMemcpyDeviceToHost, S->stream));
+            KRY_HIP(hipEventRecord(S->step_ev[j & 1], S->stream));
+            return KRY_OK;
+        };
+        // v_{j+1} = w / h_{j+1,j}: reads this step's 1/h before step j+1 overwrites it
+        auto normalize = [&](int j) -> int {
+            double *w = S->V.p + (size_t)(j + 1) * S->ldv;
+            return vec_scale_copy(S->stream, n, dc(sc + SC_INVHN), w, w);
+        };
+        KRY_TRY(issue(0));
+        for (int j = 0; j < steps; j++) {
+            const bool ahead = speculate && j + 1 < steps;
+            if (ahead) {
+                KRY_TRY(normalize(j));
+                KRY_TRY(issue(j + 1));
+            }
+            KRY_HIP(hipEventSynchronize(S->step_ev[j & 1]));
+            const double hn = S->h_pinned[8 + 8 * (j & 1)];        // SC_HN
+            const double est = S->h_pinned[8 + 8 * (j & 1) + 2];   // SC_EST
             nits++;
             jend = j + 1;
             S->hist.push_back(est);
             if (nits >= S->maxit) break;
-            if (hv[0] == 0.0) break;                      // lucky breakdown
+            if (hn == 0.0) break;                         // lucky breakdown
             if (est <= tol) break;
-            KRY_TRY(vec_scale_copy(S->stream, n, dc(sc + SC_INVHN), w, w));
+            if (!ahead) {
+                KRY_TRY(normalize(j));
+                if (j + 1 < steps) KRY_TRY(issue(j + 1));
+            }
         }
         hipLaunchKernelGGL(k_ls_solve, dim3(1), dim3(64), 0, S->stream, small, L, jend);
         if (k > 0) {
@@ -976,6 +1011,8 @@ extern "C" int SolverDestroy(SOLVER **sp) {
     SOLVER *s = *sp;
     if (s->pc_type == KRY_PC_CUSTOM && s->cdestroy) s->cdestroy(s->cdata);
     if (s->h_pinned) (void)hipHostFree(s->h_pinned);
+    for (auto &ev : s->step_ev)
+        if (ev) (void)hipEventDestroy(ev);
     delete s;
     *sp = nullptr;
     return KRY_OK;
