@@ -60,7 +60,7 @@ namespace {
 template <typename F>
 void for_ranges(int n, int &nw, F f) {
     const unsigned hw = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
-    nw = std::max(1, std::min((int)hw, n / 4096));
+    nw = std::max(1, std::min((int)hw, n / 1024));
     if (nw == 1) {
         f(0, n, 0);
         return;
@@ -127,6 +127,45 @@ void find_strong(const AmgCsr &A, double theta, double mrs, std::vector<int> &sr
     join_pieces(A.n, pc, srp, sci, nullptr);
 }
 
+// set of indices in [0, n) as a 64-ary tree of bit words: leaves hold one
+// bit per index, each upper word one bit per non-empty word below; insert,
+// erase and the smallest element cost one word per level
+struct IndexSet {
+    std::vector<std::vector<uint64_t>> lv;   // lv[0]: leaves ... lv.back(): one word
+    void init(int n) {
+        lv.clear();
+        size_t bits = (size_t)std::max(n, 1);
+        do {
+            const size_t words = (bits + 63) / 64;
+            lv.emplace_back(words, 0);
+            bits = words;
+        } while (lv.back().size() > 1);
+    }
+    void insert(int i) {
+        size_t x = (size_t)i;
+        for (auto &w : lv) {
+            const bool had = w[x >> 6] != 0;
+            w[x >> 6] |= 1ull << (x & 63);
+            if (had) break;
+            x >>= 6;
+        }
+    }
+    void erase(int i) {
+        size_t x = (size_t)i;
+        for (auto &w : lv) {
+            w[x >> 6] &= ~(1ull << (x & 63));
+            if (w[x >> 6] != 0) break;
+            x >>= 6;
+        }
+    }
+    bool empty() const { return lv.back()[0] == 0; }
+    int first() const {
+        size_t x = 0;
+        for (int l = (int)lv.size() - 1; l >= 0; l--) x = (x << 6) | (size_t)__builtin_ctzll(lv[l][x]);
+        return (int)x;
+    }
+};
+
 // C/F splitting: cf[i] = 1 for C, 0 for F
 void split_cf(int n, const std::vector<int> &srp, const std::vector<int> &sci,
               std::vector<int> &cf) {
@@ -142,9 +181,9 @@ void split_cf(int n, const std::vector<int> &srp, const std::vector<int> &sci,
     constexpr int UND = -1;
     std::vector<int> meas(n);
     cf.assign(n, UND);
-    // one min-heap of indices per measure value; the next point is the
-    // smallest index in the largest non-empty bucket.  An entry is stale
-    // once its point is decided or its measure has moved.
+    // one ordered index set per measure value; the next point is the
+    // smallest index in the largest non-empty set.  Every undecided point
+    // sits in the set of its current measure.
     int mmax = 0;
     for (int i = 0; i < n; i++) {
         meas[i] = drp[i + 1] - drp[i];
@@ -152,29 +191,23 @@ void split_cf(int n, const std::vector<int> &srp, const std::vector<int> &sci,
     }
     // a measure grows by at most the points depending on it: bounded by
     // twice the longest column of the strong pattern
-    std::vector<std::vector<int>> bucket(2 * (mmax + 1) + 1);
-    auto push = [&](int i) {
-        auto &h = bucket[meas[i]];
-        h.push_back(i);
-        std::push_heap(h.begin(), h.end(), std::greater<int>());
-    };
+    std::vector<IndexSet> bucket(2 * (mmax + 1) + 1);
+    for (auto &b : bucket) b.init(n);
     for (int i = 0; i < n; i++) {
         if (srp[i + 1] == srp[i] && meas[i] == 0) cf[i] = 0;
-        else push(i);
+        else bucket[meas[i]].insert(i);
     }
     auto shift = [&](int k, int d) {
+        bucket[meas[k]].erase(k);
         meas[k] += d;
-        push(k);
+        bucket[meas[k]].insert(k);
     };
     int top = (int)bucket.size() - 1;
     for (;;) {
         while (top >= 0 && bucket[top].empty()) top--;
         if (top < 0) break;
-        auto &h = bucket[top];
-        std::pop_heap(h.begin(), h.end(), std::greater<int>());
-        const int i = h.back();
-        h.pop_back();
-        if (cf[i] != UND || meas[i] != top) continue;
+        const int i = bucket[top].first();
+        bucket[top].erase(i);
         if (meas[i] == 0) {
             cf[i] = 0;
             continue;
@@ -183,6 +216,7 @@ void split_cf(int n, const std::vector<int> &srp, const std::vector<int> &sci,
         for (int q = drp[i]; q < drp[i + 1]; q++) {
             const int j = dci[q];
             if (cf[j] != UND) continue;
+            bucket[meas[j]].erase(j);
             cf[j] = 0;
             for (int p = srp[j]; p < srp[j + 1]; p++)
                 if (cf[sci[p]] == UND) {
@@ -362,15 +396,20 @@ AmgCsr multiply(const AmgCsr &X, const AmgCsr &Y) {
                     acc[j] += X.v[q] * Y.v[p];
                 }
             }
-            // insertion sort: rows hold tens of entries
-            for (size_t a = 1; a < cols.size(); a++) {
-                const int c = cols[a];
-                size_t b = a;
-                while (b > 0 && cols[b - 1] > c) {
-                    cols[b] = cols[b - 1];
-                    b--;
+            // insertion sort for short rows, std::sort for the long rows of
+            // coarse levels
+            if (cols.size() > 32) {
+                std::sort(cols.begin(), cols.end());
+            } else {
+                for (size_t a = 1; a < cols.size(); a++) {
+                    const int c = cols[a];
+                    size_t b = a;
+                    while (b > 0 && cols[b - 1] > c) {
+                        cols[b] = cols[b - 1];
+                        b--;
+                    }
+                    cols[b] = c;
                 }
-                cols[b] = c;
             }
             for (int j : cols) {
                 out.ci.push_back(j);
