@@ -124,7 +124,9 @@ def test_grid_detection():
                                        # off-diagonal blocks), not the grid factorization
                                        ("block", (2, 6, 5)), ("block", (7, 2, 6)),
                                        ("scalar", (2, 9, 7)),
-                                       ("block", (40, 1, 1)), ("block", (1, 1, 1))])
+                                       ("block", (40, 1, 1)), ("block", (1, 1, 1)),
+                                       # more tiles than CUs (272 and 306)
+                                       ("block", (4, 136, 128)), ("scalar", (3, 144, 129))])
 def test_ilu_apply_parity_fp64(kind, grid, layout):
     s = _sys(kind, grid, seed=2)
     if layout == K.KRY_SWEEP_GRID and min(grid) < 2:
@@ -155,7 +157,7 @@ def test_grid_layout_requires_grid_stencil():
 @pytest.mark.parametrize("layout", LAYOUTS)
 @pytest.mark.parametrize("prec,tol", [(K.KRY_PREC_F32, 1e-5), (K.KRY_PREC_BF16_FACTORS, 1e-4)])
 @pytest.mark.parametrize("kind,grid", [("scalar", SMALL_SCALAR), ("block", SMALL_BLOCK),
-                                       ("block", (64, 64, 64))])
+                                       ("block", (64, 64, 64)), ("block", (4, 136, 128))])
 def test_ilu_apply_parity_reduced(kind, grid, prec, tol, layout):
     s = _sys(kind, grid, seed=3)
     A = oracle.Matrix.from_system(s)
@@ -1056,3 +1058,15 @@ def test_absolute_tolerance_stop():
     assert gpu["status"] == K.KRY_OK and ref["status"] == 0
     assert abs(gpu["iters"] - ref["iters"]) <= 1
     assert np.linalg.norm(s["b"] - oracle.spmv(A, gpu["x"])) <= atol * (1 + 1e-9)
+
+
+def test_many_tiles_gmres_solve():
+    # GMRES(30) + BILU(0) on a grid of 17 x 17 = 289 tiles, more than CUs
+    s = ri.blackoil_system(6, 136, 130, seed=36)
+    A = oracle.Matrix.from_system(s)
+    g = GpuSystem(s)
+    try:
+        gpu = solve(g, K.KRY_GMRES, K.KRY_PC_BILU0, rtol=1e-8, maxit=2000)
+    finally:
+        g.close()
+    _check_solve(s, gpu, A, oracle.PC(A, "bilu0"), 1e-8, oracle.gmres, restart=30, maxit=2000)
