@@ -10,7 +10,9 @@
 // gfx950 design: the Gram-Schmidt of Algorithm 1's Arnoldi step (modified,
 // j dependent dot products per step) becomes classical Gram-Schmidt with
 // one reorthogonalization (CGS2): two passes of h = V^T w, w -= V h, each a
-// tall-skinny GEMV that streams V once.  All scalars (Hessenberg column,
+// tall-skinny GEMV that streams V once.  The second pass also sums ||w||^2,
+// so h_{j+1,j} = sqrt(||w||^2 - ||h2||^2) is known before the last update,
+// which writes the normalized next basis vector.  All scalars (Hessenberg column,
 // Givens rotations, residual estimate) stay in device memory; the host
 // reads back one estimate per step, which is the only per-step sync.
 // Reductions use fixed grids and fixed summation order, so two runs give
@@ -184,9 +186,11 @@ __global__ __launch_bounds__(256) void k_cgs_update_dots(int n, const double *__
     __shared__ double tl[CGS_CH];
     __shared__ double lds[256];
     __shared__ double hs[MAXC];
+    __shared__ double nl[4];
     if (threadIdx.x < MAXC) hs[threadIdx.x] = (int)threadIdx.x < nc ? h[threadIdx.x] : 0.0;
     __syncthreads();
     const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    double nacc = 0.0;   // ||w - V h||^2 of this thread's rows
     double acc[CPW];
 #pragma unroll
     for (int c = 0; c < CPW; c++) acc[c] = 0.0;
@@ -211,6 +215,7 @@ __global__ __launch_bounds__(256) void k_cgs_update_dots(int n, const double *__
                 t -= pre[k] * hs[k];
             }
         if (base + (int)threadIdx.x < n) w[base + threadIdx.x] = t;
+        nacc += t * t;   // rows past n carry t = 0
         tl[threadIdx.x] = t;
         __syncthreads();
         if (base + stride < n) load(base + stride);
@@ -230,21 +235,25 @@ __global__ __launch_bounds__(256) void k_cgs_update_dots(int n, const double *__
         const double s = wave_sum(acc[c]);
         if (lane == 0) lds[wv * CPW + c] = s;
     }
+    nacc = wave_sum(nacc);
+    if (lane == 0) nl[wv] = nacc;
     __syncthreads();
     if ((int)threadIdx.x < nc) partial[(size_t)blockIdx.x * MAXCOL + threadIdx.x] = lds[threadIdx.x];
+    // column nc (free: nc <= MAXCOL - 1) holds the block's ||w||^2
+    if (threadIdx.x == 0) partial[(size_t)blockIdx.x * MAXCOL + nc] = nl[0] + nl[1] + nl[2] + nl[3];
 }
 
-// pass 3: w -= V h and partials of ||w||^2
+// pass 3: w = (w - V h) / h_{j+1,j}, the next basis vector (the scale
+// 1/h_{j+1,j} is read from the step's scalars, 0 after a breakdown)
 template <int MAXC>
-__global__ __launch_bounds__(256) void k_cgs_update_norm(int n, const double *__restrict__ V,
-                                                         int64_t ldv, int nc, const double *h,
-                                                         double *__restrict__ w,
-                                                         double *__restrict__ partial) {
-    __shared__ double lds[256];
+__global__ __launch_bounds__(256) void k_cgs_update_scale(int n, const double *__restrict__ V,
+                                                          int64_t ldv, int nc, const double *h,
+                                                          const double *inv_hn,
+                                                          double *__restrict__ w) {
     __shared__ double hs[MAXC];
     if (threadIdx.x < MAXC) hs[threadIdx.x] = (int)threadIdx.x < nc ? h[threadIdx.x] : 0.0;
     __syncthreads();
-    double acc = 0.0;
+    const double sc = *inv_hn;
     const int nq = n / CGS_ROWS;
     for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < nq; q += gridDim.x * blockDim.x) {
         const unsigned off = (unsigned)q * CGS_ROWS;
@@ -260,9 +269,12 @@ __global__ __launch_bounds__(256) void k_cgs_update_norm(int n, const double *__
                 t1.x -= b.x * hs[k];
                 t1.y -= b.y * hs[k];
             }
+        t0.x *= sc;
+        t0.y *= sc;
+        t1.x *= sc;
+        t1.y *= sc;
         *reinterpret_cast<double2 *>(w + off) = t0;
         *reinterpret_cast<double2 *>(w + off + 2) = t1;
-        acc += t0.x * t0.x + t0.y * t0.y + t1.x * t1.x + t1.y * t1.y;
     }
     if (blockIdx.x == 0 && (int)threadIdx.x < n - nq * CGS_ROWS) {
         const int r = nq * CGS_ROWS + threadIdx.x;
@@ -270,17 +282,14 @@ __global__ __launch_bounds__(256) void k_cgs_update_norm(int n, const double *__
 #pragma unroll
         for (int k = 0; k < MAXC; k++)
             if (k < nc) t -= V[k * ldv + r] * hs[k];
-        w[r] = t;
-        acc += t * t;
+        w[r] = t * sc;
     }
-    acc = wave_sum(acc);
-    if ((threadIdx.x & 63) == 0) lds[threadIdx.x >> 6] = acc;
-    __syncthreads();
-    if (threadIdx.x == 0) partial[(size_t)blockIdx.x * MAXCOL] = lds[0] + lds[1] + lds[2] + lds[3];
 }
 
-// Finish Arnoldi step j: ||w||^2 from the pass-3 partials (block sum in a
-// fixed order); column j of H = h1 + h2 and h_{j+1,j} = ||w||; apply the
+// Finish Arnoldi step j: column j of H = h1 + h2; h_{j+1,j} = ||w - V h2||,
+// taken as sqrt(||w||^2 - ||h2||^2) from pass 2's norm partials (column
+// j + 1 of each block's row, summed in a fixed order): h2 = V^T w with V
+// orthonormal, so the second correction removes exactly ||h2||^2; apply the
 // previous Givens rotations, form rotation j, update g and the residual
 // estimate |g_{j+1}|.  The operands are loaded into LDS by all threads; the
 // rotation sweep itself is serial on thread 0.
@@ -290,7 +299,7 @@ __global__ __launch_bounds__(256) void k_arnoldi_finish(const double *__restrict
     __shared__ double lds[4];
     __shared__ double col[MAXCOL + 1], cs[MAXCOL], sn[MAXCOL];
     double s = 0.0;
-    for (int b = threadIdx.x; b < nblocks; b += blockDim.x) s += partial[(size_t)b * MAXCOL];
+    for (int b = threadIdx.x; b < nblocks; b += blockDim.x) s += partial[(size_t)b * MAXCOL + j + 1];
     const double *h1 = small + L.h1, *h2 = small + L.h2;
     if ((int)threadIdx.x <= j) col[threadIdx.x] = h1[threadIdx.x] + h2[threadIdx.x];
     if ((int)threadIdx.x < j) {
@@ -300,7 +309,9 @@ __global__ __launch_bounds__(256) void k_arnoldi_finish(const double *__restrict
     s = block_sum<256>(s, lds);
     if (threadIdx.x != 0) return;
     double *H = small + L.H + (size_t)j * (m + 1), *g = small + L.g, *sc = small + L.sc;
-    const double hn = sqrt(s);
+    double h2sq = 0.0;
+    for (int k = 0; k <= j; k++) h2sq += h2[k] * h2[k];
+    const double hn = sqrt(fmax(s - h2sq, 0.0));
     col[j + 1] = hn;
     sc[SC_HN] = hn;
     sc[SC_INVHN] = hn != 0.0 ? 1.0 / hn : 0.0;
@@ -612,9 +623,9 @@ static void launch_cgs(hipStream_t st, int n, const double *V, int64_t ldv, int 
                        partial);
     hipLaunchKernelGGL((k_sum_cols<MAXC, 1024>), dim3(1), dim3(1024), 0, st, partial, g2, nc,
                        small + L.h2);
-    hipLaunchKernelGGL(k_cgs_update_norm<MAXC>, dim3(g3), b, 0, st, n, V, ldv, nc, small + L.h2, w,
-                       partial);
-    hipLaunchKernelGGL(k_arnoldi_finish, dim3(1), b, 0, st, partial, g3, j, m, small, L);
+    hipLaunchKernelGGL(k_arnoldi_finish, dim3(1), b, 0, st, partial, g2, j, m, small, L);
+    hipLaunchKernelGGL(k_cgs_update_scale<MAXC>, dim3(g3), b, 0, st, n, V, ldv, nc, small + L.h2,
+                       small + L.sc + SC_INVHN, w);
 }
 
 static int cgs2_step(SOLVER_ *S, int j, double *w) {
@@ -756,7 +767,8 @@ static int gmres_solve(SOLVER_ *S, const double *b, double *x) {
         int jend = 0;
         const int steps = m + nstored;
         // step j: z_j = M^-1 v_j (or the stored correction), w = A z_j, CGS2
-        // against v_0..v_j with the Hessenberg column and Givens update, then
+        // against v_0..v_j with the Hessenberg column and Givens update and
+        // w normalized in place into v_{j+1}, then
         // an asynchronous read-back of (h_{j+1,j}, 1/h_{j+1,j}, estimate) into
         // pinned slot j % 2 and an event.  When the preconditioner runs no
         // host code and keeps no counters, step j+1 is issued before step
@@ -780,18 +792,10 @@ static int gmres_solve(SOLVER_ *S, const double *b, double *x) {
             KRY_HIP(hipEventRecord(S->step_ev[j & 1], S->stream));
             return KRY_OK;
         };
-        // v_{j+1} = w / h_{j+1,j}: reads this step's 1/h before step j+1 overwrites it
-        auto normalize = [&](int j) -> int {
-            double *w = S->V.p + (size_t)(j + 1) * S->ldv;
-            return vec_scale_copy(S->stream, n, dc(sc + SC_INVHN), w, w);
-        };
         KRY_TRY(issue(0));
         for (int j = 0; j < steps; j++) {
             const bool ahead = speculate && j + 1 < steps;
-            if (ahead) {
-                KRY_TRY(normalize(j));
-                KRY_TRY(issue(j + 1));
-            }
+            if (ahead) KRY_TRY(issue(j + 1));
             KRY_HIP(hipEventSynchronize(S->step_ev[j & 1]));
             const double hn = S->h_pinned[8 + 8 * (j & 1)];        // SC_HN
             const double est = S->h_pinned[8 + 8 * (j & 1) + 2];   // SC_EST
@@ -801,10 +805,7 @@ static int gmres_solve(SOLVER_ *S, const double *b, double *x) {
             if (nits >= S->maxit) break;
             if (hn == 0.0) break;                         // lucky breakdown
             if (est <= tol) break;
-            if (!ahead) {
-                KRY_TRY(normalize(j));
-                if (j + 1 < steps) KRY_TRY(issue(j + 1));
-            }
+            if (!ahead && j + 1 < steps) KRY_TRY(issue(j + 1));
         }
         hipLaunchKernelGGL(k_ls_solve, dim3(1), dim3(64), 0, S->stream, small, L, jend);
         if (k > 0) {
