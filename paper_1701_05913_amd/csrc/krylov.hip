@@ -286,31 +286,48 @@ __global__ __launch_bounds__(256) void k_cgs_update_scale(int n, const double *_
     }
 }
 
-// Finish Arnoldi step j: column j of H = h1 + h2; h_{j+1,j} = ||w - V h2||,
-// taken as sqrt(||w||^2 - ||h2||^2) from pass 2's norm partials (column
-// j + 1 of each block's row, summed in a fixed order): h2 = V^T w with V
-// orthonormal, so the second correction removes exactly ||h2||^2; apply the
-// previous Givens rotations, form rotation j, update g and the residual
-// estimate |g_{j+1}|.  The operands are loaded into LDS by all threads; the
+// Finish Arnoldi step j in one block: h2 from pass 2's partials (columns
+// 0..j, block sums in a fixed order, also stored for pass 3) and ||w||^2
+// (column j + 1); column j of H = h1 + h2; h_{j+1,j} = ||w - V h2|| taken as
+// sqrt(||w||^2 - ||h2||^2): h2 = V^T w with V orthonormal, so the second
+// correction removes exactly ||h2||^2; apply the previous Givens rotations,
+// form rotation j, update g and the residual estimate |g_{j+1}|.  The
 // rotation sweep itself is serial on thread 0.
-__global__ __launch_bounds__(256) void k_arnoldi_finish(const double *__restrict__ partial,
-                                                        int nblocks, int j, int m, double *small,
-                                                        SmallLayout L) {
-    __shared__ double lds[4];
-    __shared__ double col[MAXCOL + 1], cs[MAXCOL], sn[MAXCOL];
+template <int MAXC>
+__global__ __launch_bounds__(1024) void k_arnoldi_finish(const double *__restrict__ partial,
+                                                         int nblocks, int j, int m, double *small,
+                                                         SmallLayout L) {
+    constexpr int NT = 1024, G = NT / MAXC;
+    __shared__ double lds[NT];
+    __shared__ double red[NT / 64];
+    __shared__ double col[MAXCOL + 1], h2s[MAXCOL], cs[MAXCOL], sn[MAXCOL];
+    const int nc = j + 1;
+    {
+        const int k = threadIdx.x % MAXC, gq = threadIdx.x / MAXC;
+        double a = 0.0;
+        if (k < nc)
+            for (int b = gq; b < nblocks; b += G) a += partial[(size_t)b * MAXCOL + k];
+        lds[threadIdx.x] = a;
+    }
     double s = 0.0;
-    for (int b = threadIdx.x; b < nblocks; b += blockDim.x) s += partial[(size_t)b * MAXCOL + j + 1];
-    const double *h1 = small + L.h1, *h2 = small + L.h2;
-    if ((int)threadIdx.x <= j) col[threadIdx.x] = h1[threadIdx.x] + h2[threadIdx.x];
+    for (int b = threadIdx.x; b < nblocks; b += NT) s += partial[(size_t)b * MAXCOL + nc];
     if ((int)threadIdx.x < j) {
         cs[threadIdx.x] = small[L.cs + threadIdx.x];
         sn[threadIdx.x] = small[L.sn + threadIdx.x];
     }
-    s = block_sum<256>(s, lds);
+    __syncthreads();
+    if ((int)threadIdx.x < nc) {
+        double r = 0.0;
+        for (int q = 0; q < G; q++) r += lds[q * MAXC + threadIdx.x];
+        h2s[threadIdx.x] = r;
+        small[L.h2 + threadIdx.x] = r;
+        col[threadIdx.x] = small[L.h1 + threadIdx.x] + r;
+    }
+    s = block_sum<NT>(s, red);
     if (threadIdx.x != 0) return;
     double *H = small + L.H + (size_t)j * (m + 1), *g = small + L.g, *sc = small + L.sc;
     double h2sq = 0.0;
-    for (int k = 0; k <= j; k++) h2sq += h2[k] * h2[k];
+    for (int k = 0; k <= j; k++) h2sq += h2s[k] * h2s[k];
     const double hn = sqrt(fmax(s - h2sq, 0.0));
     col[j + 1] = hn;
     sc[SC_HN] = hn;
@@ -621,9 +638,8 @@ static void launch_cgs(hipStream_t st, int n, const double *V, int64_t ldv, int 
                        small + L.h1);
     hipLaunchKernelGGL(k_cgs_update_dots<MAXC>, dim3(g2), b, 0, st, n, V, ldv, nc, small + L.h1, w,
                        partial);
-    hipLaunchKernelGGL((k_sum_cols<MAXC, 1024>), dim3(1), dim3(1024), 0, st, partial, g2, nc,
-                       small + L.h2);
-    hipLaunchKernelGGL(k_arnoldi_finish, dim3(1), b, 0, st, partial, g2, j, m, small, L);
+    hipLaunchKernelGGL(k_arnoldi_finish<MAXC>, dim3(1), dim3(1024), 0, st, partial, g2, j, m,
+                       small, L);
     hipLaunchKernelGGL(k_cgs_update_scale<MAXC>, dim3(g3), b, 0, st, n, V, ldv, nc, small + L.h2,
                        small + L.sc + SC_INVHN, w);
 }
