@@ -60,5 +60,25 @@ def test_host_side_argument_errors_without_gpu():
     K.SolverSetAugk(s, 2)                        # LGMRES(30, 2)
     with pytest.raises(K.KrylovError):
         K.SolverAssemble(s)                      # no matrix
+    # the RAS, AMG and CPR-stage setters check their arguments on the host
+    for bad in ((0, 1, 1, 1), (1, 0, 1, 1), (1, 1, 0, 1), (1, 1, 1, -1)):
+        with pytest.raises(K.KrylovError):
+            K.SolverSetRASBoxes(s, *bad)
+    for bad in ((0, 1), (2, -1)):
+        with pytest.raises(K.KrylovError):
+            K.SolverSetRAS(s, *bad)
+    for bad in ((0, 2, 4), (8, 0, 4)):
+        with pytest.raises(K.KrylovError):
+            K.SolverSetAMG(s, *bad)
+    with pytest.raises(K.KrylovError):
+        K.SolverSetCPRPressure(s, 2)
+    with pytest.raises(K.KrylovError):
+        K.SolverSetCPRFull(s, 2)
+    K.SolverSetRASBoxes(s, 2, 2, 2, 1)
+    K.SolverSetAMG(s, 6, 1, 8)
+    K.SolverSetCPRPressure(s, K.KRY_CPR_P_AMG)
+    K.SolverSetCPRFull(s, K.KRY_CPR_F_RAS)
+    with pytest.raises(K.KrylovError):
+        K.SolverGetAMGLevels(s)                  # nothing assembled
     K.SolverDestroy(s)
     K.MapDestroy(m)
