@@ -58,9 +58,9 @@ namespace {
 // f(lo, hi, w) for worker w; rows are independent, so the result does not
 // depend on the cut
 template <typename F>
-void for_ranges(int n, int &nw, F f) {
+void for_ranges(int n, int &nw, F f, int grain = 1024) {
     const unsigned hw = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
-    nw = std::max(1, std::min((int)hw, n / 1024));
+    nw = std::max(1, std::min((int)hw, n / grain));
     if (nw == 1) {
         f(0, n, 0);
         return;
@@ -72,35 +72,47 @@ void for_ranges(int n, int &nw, F f) {
 }
 
 // rows computed in pieces: per piece its row lengths and entries, then
-// concatenated in order
+// concatenated in order (each piece copied by its own thread once the
+// offsets are known)
 struct Piece {
     std::vector<int> len, ci;
     std::vector<double> v;
     int err = 0, err_row = -1;
 };
-void join_pieces(int n, std::vector<Piece> &pc, std::vector<int> &rp, std::vector<int> &ci,
-                 std::vector<double> *v) {
-    rp.assign(n + 1, 0);
-    size_t total = 0;
-    for (auto &p : pc) total += p.ci.size();
-    ci.resize(total);
-    if (v) v->resize(total);
-    int r = 0;
-    size_t at = 0;
-    for (auto &p : pc) {
-        for (int L : p.len) {
-            rp[r + 1] = rp[r] + L;
-            r++;
-        }
-        std::copy(p.ci.begin(), p.ci.end(), ci.begin() + at);
-        if (v) std::copy(p.v.begin(), p.v.end(), v->begin() + at);
-        at += p.ci.size();
+void join_pieces(int n, std::vector<Piece> &pc, HVec<int> &rp, HVec<int> &ci, HVec<double> *v) {
+    const int np = (int)pc.size();
+    std::vector<size_t> at(np + 1, 0);
+    std::vector<int> r0(np + 1, 0);
+    for (int w = 0; w < np; w++) {
+        at[w + 1] = at[w] + pc[w].ci.size();
+        r0[w + 1] = r0[w] + (int)pc[w].len.size();
     }
+    rp.resize(n + 1);
+    rp[0] = 0;
+    ci.resize(at[np]);
+    if (v) v->resize(at[np]);
+    auto copy = [&](int w) {
+        const Piece &p = pc[w];
+        size_t off = at[w];
+        int r = r0[w];
+        for (int L : p.len) {
+            off += L;
+            rp[++r] = (int)off;
+        }
+        std::copy(p.ci.begin(), p.ci.end(), ci.begin() + at[w]);
+        if (v) std::copy(p.v.begin(), p.v.end(), v->begin() + at[w]);
+    };
+    if (np == 1 || at[np] < 65536) {
+        for (int w = 0; w < np; w++) copy(w);
+        return;
+    }
+    std::vector<std::thread> th;
+    for (int w = 0; w < np; w++) th.emplace_back(copy, w);
+    for (auto &x : th) x.join();
 }
 
 // strong dependencies of each row (ascending)
-void find_strong(const AmgCsr &A, double theta, double mrs, std::vector<int> &srp,
-                 std::vector<int> &sci) {
+void find_strong(const AmgCsr &A, double theta, double mrs, HVec<int> &srp, HVec<int> &sci) {
     std::vector<Piece> pc(16);
     int nw = 1;
     for_ranges(A.n, nw, [&](int lo, int hi, int w) {
@@ -167,7 +179,7 @@ struct IndexSet {
 };
 
 // C/F splitting: cf[i] = 1 for C, 0 for F
-void split_cf(int n, const std::vector<int> &srp, const std::vector<int> &sci,
+void split_cf(int n, const HVec<int> &srp, const HVec<int> &sci,
               std::vector<int> &cf) {
     // who depends on i: the transpose of the strong pattern
     std::vector<int> drp(n + 1, 0), dci(sci.size());
@@ -255,7 +267,7 @@ void split_cf(int n, const std::vector<int> &srp, const std::vector<int> &sci,
 
 inline bool signs_differ(double d, double x) { return (d > 0.0 && x < 0.0) || (d < 0.0 && x > 0.0); }
 
-int build_prolongation(const AmgCsr &A, const std::vector<int> &srp, const std::vector<int> &sci,
+int build_prolongation(const AmgCsr &A, const HVec<int> &srp, const HVec<int> &sci,
                        const std::vector<int> &cf, double trunc, AmgCsr &P) {
     const int n = A.n;
     std::vector<int> cnum(n, -1);
@@ -382,6 +394,13 @@ AmgCsr multiply(const AmgCsr &X, const AmgCsr &Y) {
         Piece &out = pc[wk];
         std::vector<double> acc(Y.m, 0.0);
         std::vector<int> seen(Y.m, -1), cols;
+        // room for the products of this range's entries (an upper bound on
+        // its output when every product lands in a new column)
+        size_t est = 0;
+        for (int q = X.rp[lo]; q < X.rp[hi]; q++) est += Y.rp[X.ci[q] + 1] - Y.rp[X.ci[q]];
+        out.ci.reserve(est);
+        out.v.reserve(est);
+        out.len.reserve(hi - lo);
         for (int i = lo; i < hi; i++) {
             cols.clear();
             for (int q = X.rp[i]; q < X.rp[i + 1]; q++) {
@@ -609,58 +628,94 @@ static int team_size(const AmgCsr &A) {
     return T;
 }
 
-// chunk-interleaved rows of A (see the head of the file)
-static int upload_level(hipStream_t s, const AmgCsr &A, int ch, AmgLevel &L) {
+// chunk-interleaved rows of A (see the head of the file), built on the
+// host: every wavefront group owns its own ranges of the arrays, so the
+// groups are filled in parallel
+struct EllHost {
+    int n = 0, nch = 0, team = 1, ngrp = 0;
+    std::vector<int64_t> goff;
+    std::vector<int> gk;
+    HVec<int> rlen, ecol;
+    HVec<double> eval, low;
+};
+static void build_ell(const AmgCsr &A, int ch, EllHost &E) {
     const int n = A.n, T = team_size(A), cpw = 64 / T, nl = ch * (ch + 1) / 2;
     const int nch = (n + ch - 1) / ch, ngrp = (nch + cpw - 1) / cpw;
+    const int gr = cpw * ch;   // rows per group
     // an entry (r, j) is "lower" when j lies in r's chunk at or before r
     auto lower = [&](int r, int j) { return j <= r && j >= r / ch * ch; };
-    std::vector<int> rest(n, 0);
-    for (int r = 0; r < n; r++)
-        for (int q = A.rp[r]; q < A.rp[r + 1]; q++) rest[r] += !lower(r, A.ci[q]);
-    std::vector<int64_t> goff(ngrp + 1, 0);
-    std::vector<int> gk(ngrp, 0), rlen((size_t)ngrp * ch * cpw, 0);
-    for (int g = 0; g < ngrp; g++) {
-        int K = 0;
-        for (int r = g * cpw * ch; r < std::min(n, (g + 1) * cpw * ch); r++) K = std::max(K, rest[r]);
-        gk[g] = (K + T - 1) / T;
-        goff[g + 1] = goff[g] + (int64_t)ch * gk[g] * 64;
-    }
-    std::vector<int> ecol(std::max<int64_t>(goff[ngrp], 1), -1);
-    std::vector<double> eval(ecol.size(), 0.0);
-    std::vector<double> low((size_t)ngrp * nl * cpw, 0.0);
-    for (int r = 0; r < n; r++) {
-        const int q = r / ch, t = r % ch, g = q / cpw, c = q % cpw;
-        rlen[((size_t)g * ch + t) * cpw + c] = rest[r];
-        int e = 0;
-        for (int k = A.rp[r]; k < A.rp[r + 1]; k++) {
-            const int j = A.ci[k];
-            if (lower(r, j)) {
-                low[((size_t)g * nl + t * (t + 1) / 2 + (j - q * ch)) * cpw + c] += A.v[k];
-                continue;
+    E.n = n;
+    E.nch = nch;
+    E.team = T;
+    E.ngrp = ngrp;
+    E.goff.assign(ngrp + 1, 0);
+    E.gk.assign(ngrp, 0);
+    int nw = 1;
+    for_ranges(ngrp, nw, [&](int glo, int ghi, int) {
+        for (int g = glo; g < ghi; g++) {
+            int K = 0;
+            for (int r = g * gr; r < std::min(n, (g + 1) * gr); r++) {
+                int rest = 0;
+                for (int q = A.rp[r]; q < A.rp[r + 1]; q++) rest += !lower(r, A.ci[q]);
+                K = std::max(K, rest);
             }
-            const int64_t p = goff[g] + (int64_t)(t * gk[g] + e / T) * 64 + c * T + e % T;
-            ecol[p] = j;
-            eval[p] = A.v[k];
-            e++;
+            E.gk[g] = (K + T - 1) / T;
         }
+    }, 64);
+    for (int g = 0; g < ngrp; g++) E.goff[g + 1] = E.goff[g] + (int64_t)ch * E.gk[g] * 64;
+    const size_t ne = std::max<int64_t>(E.goff[ngrp], 1);
+    E.rlen.resize((size_t)ngrp * ch * cpw);
+    E.ecol.resize(ne);
+    E.eval.resize(ne);
+    E.low.resize((size_t)ngrp * nl * cpw);
+    if (E.goff[ngrp] == 0) {
+        E.ecol[0] = -1;
+        E.eval[0] = 0.0;
     }
-    L.n = n;
-    L.nch = nch;
-    L.team = T;
+    for_ranges(ngrp, nw, [&](int glo, int ghi, int) {
+        std::fill(E.ecol.begin() + E.goff[glo], E.ecol.begin() + E.goff[ghi], -1);
+        std::fill(E.eval.begin() + E.goff[glo], E.eval.begin() + E.goff[ghi], 0.0);
+        std::fill(E.rlen.begin() + (size_t)glo * ch * cpw, E.rlen.begin() + (size_t)ghi * ch * cpw, 0);
+        std::fill(E.low.begin() + (size_t)glo * nl * cpw, E.low.begin() + (size_t)ghi * nl * cpw, 0.0);
+        for (int r = glo * gr; r < std::min(n, ghi * gr); r++) {
+            const int q = r / ch, t = r % ch, g = q / cpw, c = q % cpw;
+            int e = 0;
+            for (int k = A.rp[r]; k < A.rp[r + 1]; k++) {
+                const int j = A.ci[k];
+                if (lower(r, j)) {
+                    E.low[((size_t)g * nl + t * (t + 1) / 2 + (j - q * ch)) * cpw + c] += A.v[k];
+                    continue;
+                }
+                const int64_t p = E.goff[g] + (int64_t)(t * E.gk[g] + e / T) * 64 + c * T + e % T;
+                E.ecol[p] = j;
+                E.eval[p] = A.v[k];
+                e++;
+            }
+            E.rlen[((size_t)g * ch + t) * cpw + c] = e;
+        }
+    }, 64);
+}
+
+static int upload_level(hipStream_t s, const AmgCsr &A, int ch, AmgLevel &L) {
+    EllHost E;
+    build_ell(A, ch, E);
+    const int ngrp = E.ngrp;
+    L.n = E.n;
+    L.nch = E.nch;
+    L.team = E.team;
     KRY_TRY(L.goff.alloc(ngrp));
     KRY_TRY(L.gk.alloc(ngrp));
-    KRY_TRY(L.rlen.alloc(rlen.size()));
-    KRY_TRY(L.ecol.alloc(ecol.size()));
-    KRY_TRY(L.eval.alloc(eval.size()));
-    KRY_TRY(L.low.alloc(low.size()));
-    KRY_HIP(hipMemcpyAsync(L.low.p, low.data(), sizeof(double) * low.size(), hipMemcpyHostToDevice, s));
-    KRY_HIP(hipMemcpyAsync(L.goff.p, goff.data(), sizeof(int64_t) * ngrp, hipMemcpyHostToDevice, s));
-    KRY_HIP(hipMemcpyAsync(L.gk.p, gk.data(), sizeof(int) * ngrp, hipMemcpyHostToDevice, s));
-    KRY_HIP(hipMemcpyAsync(L.rlen.p, rlen.data(), sizeof(int) * rlen.size(), hipMemcpyHostToDevice, s));
-    KRY_HIP(hipMemcpyAsync(L.ecol.p, ecol.data(), sizeof(int) * ecol.size(), hipMemcpyHostToDevice, s));
-    KRY_HIP(hipMemcpyAsync(L.eval.p, eval.data(), sizeof(double) * eval.size(), hipMemcpyHostToDevice, s));
-    L.ell_bytes = (int64_t)ecol.size() * (sizeof(int) + sizeof(double));
+    KRY_TRY(L.rlen.alloc(E.rlen.size()));
+    KRY_TRY(L.ecol.alloc(E.ecol.size()));
+    KRY_TRY(L.eval.alloc(E.eval.size()));
+    KRY_TRY(L.low.alloc(E.low.size()));
+    KRY_HIP(hipMemcpyAsync(L.low.p, E.low.data(), sizeof(double) * E.low.size(), hipMemcpyHostToDevice, s));
+    KRY_HIP(hipMemcpyAsync(L.goff.p, E.goff.data(), sizeof(int64_t) * ngrp, hipMemcpyHostToDevice, s));
+    KRY_HIP(hipMemcpyAsync(L.gk.p, E.gk.data(), sizeof(int) * ngrp, hipMemcpyHostToDevice, s));
+    KRY_HIP(hipMemcpyAsync(L.rlen.p, E.rlen.data(), sizeof(int) * E.rlen.size(), hipMemcpyHostToDevice, s));
+    KRY_HIP(hipMemcpyAsync(L.ecol.p, E.ecol.data(), sizeof(int) * E.ecol.size(), hipMemcpyHostToDevice, s));
+    KRY_HIP(hipMemcpyAsync(L.eval.p, E.eval.data(), sizeof(double) * E.eval.size(), hipMemcpyHostToDevice, s));
+    L.ell_bytes = (int64_t)E.ecol.size() * (sizeof(int) + sizeof(double));
     KRY_HIP(hipStreamSynchronize(s));   // the host vectors go out of scope
     return KRY_OK;
 }
@@ -703,7 +758,7 @@ int amg_setup(hipStream_t s, int n, const int *h_rowptr, const int *h_col, const
         AmgLevelHost &H = M.host[l];
         bool last = l == o.max_levels - 1 || H.A.n <= o.coarse_size;
         if (!last) {
-            std::vector<int> srp, sci;
+            HVec<int> srp, sci;
             find_strong(H.A, o.strength, o.max_row_sum, srp, sci);
             split_cf(H.A.n, srp, sci, H.cf);
             KRY_TRY(build_prolongation(H.A, srp, sci, H.cf, o.trunc, H.P));

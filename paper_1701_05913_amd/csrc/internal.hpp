@@ -8,6 +8,7 @@
 #include <cstdio>
 #include <cstring>
 #include <memory>
+#include <utility>
 #include <string>
 #include <vector>
 
@@ -288,10 +289,32 @@ struct AmgOpts {
     double strength = 0.5, max_row_sum = 0.9, trunc = 1e-2;
     int max_levels = 8, num_sweeps = 2, gs_chunk = 4, coarse_size = 9;
 };
+// host vectors whose resize leaves new elements uninitialised, so that the
+// threads that fill them are the first to touch their pages
+template <typename T>
+struct NoInitAlloc : std::allocator<T> {
+    template <typename U>
+    struct rebind {
+        using other = NoInitAlloc<U>;
+    };
+    NoInitAlloc() = default;
+    template <typename U>
+    NoInitAlloc(const NoInitAlloc<U> &) noexcept {}
+    template <typename U>
+    void construct(U *p) noexcept {
+        ::new (static_cast<void *>(p)) U;
+    }
+    template <typename U, typename... A>
+    void construct(U *p, A &&...a) {
+        ::new (static_cast<void *>(p)) U(std::forward<A>(a)...);
+    }
+};
+template <typename T>
+using HVec = std::vector<T, NoInitAlloc<T>>;
 struct AmgCsr {                 // host CSR, n rows, m columns
     int n = 0, m = 0;
-    std::vector<int> rp, ci;
-    std::vector<double> v;
+    HVec<int> rp, ci;
+    HVec<double> v;
 };
 struct AmgLevelHost {           // A_l, its C/F splitting and P_l (not on the coarsest)
     AmgCsr A;
