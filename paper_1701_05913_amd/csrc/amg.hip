@@ -54,7 +54,8 @@ namespace {
 // ---------------------------------------------------------------------------
 // host setup
 // ---------------------------------------------------------------------------
-// [0, n) cut into contiguous ranges, one per worker thread (at most 16):
+// [0, n) cut into contiguous ranges, one per worker thread (at most 16, and
+// at least grain items each):
 // f(lo, hi, w) for worker w; rows are independent, so the result does not
 // depend on the cut
 template <typename F>
@@ -134,7 +135,7 @@ void find_strong(const AmgCsr &A, double theta, double mrs, HVec<int> &srp, HVec
                     if (A.ci[q] != i && -sg * A.v[q] >= theta * big) P.ci.push_back(A.ci[q]);
             P.len.push_back((int)(P.ci.size() - before));
         }
-    });
+    }, 128);
     pc.resize(nw);
     join_pieces(A.n, pc, srp, sci, nullptr);
 }
@@ -354,7 +355,7 @@ int build_prolongation(const AmgCsr &A, const HVec<int> &srp, const HVec<int> &s
             }
             out.len.push_back((int)(out.ci.size() - before));
         }
-    });
+    }, 128);
     pc.resize(nw);
     for (auto &p : pc)
         if (p.err) return set_error(p.err, "AMG: zero interpolation diagonal in row %d", p.err_row);
@@ -436,7 +437,7 @@ AmgCsr multiply(const AmgCsr &X, const AmgCsr &Y) {
             }
             out.len.push_back((int)cols.size());
         }
-    });
+    }, 128);
     pc.resize(nw);
     join_pieces(X.n, pc, Z.rp, Z.ci, &Z.v);
     return Z;

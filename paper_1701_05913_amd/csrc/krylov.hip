@@ -175,8 +175,10 @@ __global__ __launch_bounds__(256) void k_cgs_dots(int n, const double *__restric
 // nc columns, so each block stages a tile of CGS_CH rows of V in LDS: the
 // threads form t row by row, then every wavefront takes MAXC / 4 columns
 // of the tile for the dot products.  The next tile's V is loaded into
-// registers while the current tile's products run.
-template <int MAXC>
+// registers while the current tile's products run.  With UPD = false the
+// same tiling serves pass 1 on many columns: t = w, nothing is written back
+// and no norm is formed.
+template <int MAXC, bool UPD = true>
 __global__ __launch_bounds__(256) void k_cgs_update_dots(int n, const double *__restrict__ V,
                                                          int64_t ldv, int nc, const double *h,
                                                          double *__restrict__ w,
@@ -187,7 +189,7 @@ __global__ __launch_bounds__(256) void k_cgs_update_dots(int n, const double *__
     __shared__ double lds[256];
     __shared__ double hs[MAXC];
     __shared__ double nl[4];
-    if (threadIdx.x < MAXC) hs[threadIdx.x] = (int)threadIdx.x < nc ? h[threadIdx.x] : 0.0;
+    if (threadIdx.x < MAXC) hs[threadIdx.x] = UPD && (int)threadIdx.x < nc ? h[threadIdx.x] : 0.0;
     __syncthreads();
     const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
     double nacc = 0.0;   // ||w - V h||^2 of this thread's rows
@@ -212,10 +214,12 @@ __global__ __launch_bounds__(256) void k_cgs_update_dots(int n, const double *__
         for (int k = 0; k < MAXC; k++)
             if (k < nc) {
                 tile[k][threadIdx.x] = pre[k];
-                t -= pre[k] * hs[k];
+                if (UPD) t -= pre[k] * hs[k];
             }
-        if (base + (int)threadIdx.x < n) w[base + threadIdx.x] = t;
-        nacc += t * t;   // rows past n carry t = 0
+        if (UPD) {
+            if (base + (int)threadIdx.x < n) w[base + threadIdx.x] = t;
+            nacc += t * t;   // rows past n carry t = 0
+        }
         tl[threadIdx.x] = t;
         __syncthreads();
         if (base + stride < n) load(base + stride);
@@ -235,12 +239,15 @@ __global__ __launch_bounds__(256) void k_cgs_update_dots(int n, const double *__
         const double s = wave_sum(acc[c]);
         if (lane == 0) lds[wv * CPW + c] = s;
     }
-    nacc = wave_sum(nacc);
-    if (lane == 0) nl[wv] = nacc;
+    if (UPD) {
+        nacc = wave_sum(nacc);
+        if (lane == 0) nl[wv] = nacc;
+    }
     __syncthreads();
     if ((int)threadIdx.x < nc) partial[(size_t)blockIdx.x * MAXCOL + threadIdx.x] = lds[threadIdx.x];
     // column nc (free: nc <= MAXCOL - 1) holds the block's ||w||^2
-    if (threadIdx.x == 0) partial[(size_t)blockIdx.x * MAXCOL + nc] = nl[0] + nl[1] + nl[2] + nl[3];
+    if (UPD && threadIdx.x == 0)
+        partial[(size_t)blockIdx.x * MAXCOL + nc] = nl[0] + nl[1] + nl[2] + nl[3];
 }
 
 // pass 3: w = (w - V h) / h_{j+1,j}, the next basis vector (the scale
@@ -629,11 +636,17 @@ template <int MAXC>
 static void launch_cgs(hipStream_t st, int n, const double *V, int64_t ldv, int nc, double *w,
                        double *small, SmallLayout L, double *partial, int j, int m) {
     const dim3 b(256);
-    const int g1 = MAXC >= 32 ? 256 : 512;
     const int g2 = MAXC == 64 ? 256 : MAXC == 16 ? 1024 : 512;
+    const int g1 = MAXC >= 32 ? g2 : 512;
     const int g3 = 512;
     static_assert(CGS_MAXBLK >= 1024, "partials sized for the largest grid");
-    hipLaunchKernelGGL(k_cgs_dots<MAXC>, dim3(g1), b, 0, st, n, V, ldv, nc, w, partial);
+    // pass 1: row-parallel dot products up to 16 columns, the LDS tiling of
+    // pass 2 beyond
+    if constexpr (MAXC >= 32)
+        hipLaunchKernelGGL((k_cgs_update_dots<MAXC, false>), dim3(g1), b, 0, st, n, V, ldv, nc,
+                           nullptr, w, partial);
+    else
+        hipLaunchKernelGGL(k_cgs_dots<MAXC>, dim3(g1), b, 0, st, n, V, ldv, nc, w, partial);
     hipLaunchKernelGGL((k_sum_cols<MAXC, 1024>), dim3(1), dim3(1024), 0, st, partial, g1, nc,
                        small + L.h1);
     hipLaunchKernelGGL(k_cgs_update_dots<MAXC>, dim3(g2), b, 0, st, n, V, ldv, nc, small + L.h1, w,
