@@ -597,23 +597,83 @@ __global__ __launch_bounds__(256) void k_amg_dense(int n, const double *__restri
 }
 
 // step k of in-place Gauss-Jordan inversion without pivoting, M -> Mn:
-// pivot row divided by the pivot, pivot column negated and divided, the
-// rest reduced; the pivot becomes its reciprocal
-__global__ __launch_bounds__(256) void k_amg_gj_step(int n, int k, const double *__restrict__ M,
-                                                     double *__restrict__ Mn, int *err) {
+// Gauss-Jordan inversion of the coarsest matrix in panels of GJ_RB pivots.
+// One pivot k: the pivot row is divided by the pivot, the pivot column
+// negated and divided, the rest reduced, and the pivot becomes its
+// reciprocal.  A panel K of rb pivots does rb such steps at once: with
+// P = M_KK^-1 (the steps applied to the diagonal block alone) and
+// W = P M_KR, the new matrix is M_KK = P, M_KR = W, M_RK = -M_RK P and
+// M_RR = M_RR - M_RK W.
+constexpr int GJ_RB = 32;
+
+// P = inverse of the rb x rb diagonal block at (k0, k0), one thread per
+// entry; err is set if a pivot is zero or not finite
+__global__ __launch_bounds__(1024) void k_amg_gj_panel(int n, int k0, int rb,
+                                                       const double *__restrict__ M,
+                                                       double *__restrict__ P, int *err) {
+    __shared__ double a[2][GJ_RB][GJ_RB];
+    __shared__ int bad;
+    const int t = threadIdx.x, i = t / GJ_RB, j = t % GJ_RB;
+    const bool in = i < rb && j < rb;
+    if (t == 0) bad = 0;
+    a[0][i][j] = in ? M[(int64_t)(k0 + i) * n + k0 + j] : 0.0;
+    __syncthreads();
+    int c = 0;
+    for (int k = 0; k < rb; k++) {
+        const double piv = a[c][k][k];
+        const bool ok = std::fabs(piv) > 0.0 && std::isfinite(piv);
+        if (!ok && t == 0) bad = 1;
+        double val = 0.0;
+        if (in && ok) {
+            if (i == k) val = j == k ? 1.0 / piv : a[c][k][j] / piv;
+            else if (j == k) val = -a[c][i][k] / piv;
+            else val = a[c][i][j] - a[c][i][k] * a[c][k][j] / piv;
+        }
+        a[c ^ 1][i][j] = val;
+        __syncthreads();
+        c ^= 1;
+    }
+    if (in) P[i * GJ_RB + j] = a[c][i][j];
+    if (t == 0 && bad) *err = 1;
+}
+
+// W = P M_K., rb rows of n (row b at W + b n)
+__global__ __launch_bounds__(256) void k_amg_gj_w(int n, int k0, int rb, const double *__restrict__ M,
+                                                  const double *__restrict__ P,
+                                                  double *__restrict__ W) {
+    const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (e >= (int64_t)rb * n) return;
+    const int b = (int)(e / n), j = (int)(e - (int64_t)b * n);
+    double s = 0.0;
+    for (int c = 0; c < rb; c++) s += P[b * GJ_RB + c] * M[(int64_t)(k0 + c) * n + j];
+    W[e] = s;
+}
+
+// the matrix after the panel's rb steps, out of place (Mn from M)
+__global__ __launch_bounds__(256) void k_amg_gj_update(int n, int k0, int rb,
+                                                       const double *__restrict__ M,
+                                                       const double *__restrict__ P,
+                                                       const double *__restrict__ W,
+                                                       double *__restrict__ Mn) {
     const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (e >= (int64_t)n * n) return;
     const int i = (int)(e / n), j = (int)(e - (int64_t)i * n);
-    const double piv = M[(int64_t)k * n + k];
-    if (!(std::fabs(piv) > 0.0) || !std::isfinite(piv)) {
-        if (e == 0) *err = 1;
-        Mn[e] = 0.0;
-        return;
-    }
+    const bool ik = i >= k0 && i < k0 + rb, jk = j >= k0 && j < k0 + rb;
+    const double *mi = M + (int64_t)i * n + k0;   // row i of the panel's columns
     double val;
-    if (i == k) val = j == k ? 1.0 / piv : M[(int64_t)k * n + j] / piv;
-    else if (j == k) val = -M[(int64_t)i * n + k] / piv;
-    else val = M[e] - M[(int64_t)i * n + k] * M[(int64_t)k * n + j] / piv;
+    if (ik && jk) {
+        val = P[(i - k0) * GJ_RB + (j - k0)];
+    } else if (ik) {
+        val = W[(int64_t)(i - k0) * n + j];
+    } else if (jk) {
+        double s = 0.0;
+        for (int b = 0; b < rb; b++) s += mi[b] * P[b * GJ_RB + (j - k0)];
+        val = -s;
+    } else {
+        double s = M[e];
+        for (int b = 0; b < rb; b++) s -= mi[b] * W[(int64_t)b * n + j];
+        val = s;
+    }
     Mn[e] = val;
 }
 
@@ -801,16 +861,23 @@ int amg_setup(hipStream_t s, int n, const int *h_rowptr, const int *h_col, const
         std::vector<double> dense((size_t)nl * nl, 0.0);
         for (int i = 0; i < nl; i++)
             for (int q = C.rp[i]; q < C.rp[i + 1]; q++) dense[(size_t)i * nl + C.ci[q]] += C.v[q];
-        DBuf<double> tmp;
+        DBuf<double> tmp, pb, wb;
         KRY_TRY(M.cinv.alloc((size_t)nl * nl));
         KRY_TRY(tmp.alloc((size_t)nl * nl));
+        KRY_TRY(pb.alloc((size_t)GJ_RB * GJ_RB));
+        KRY_TRY(wb.alloc((size_t)GJ_RB * nl));
         KRY_HIP(hipMemcpyAsync(M.cinv.p, dense.data(), sizeof(double) * dense.size(),
                                hipMemcpyHostToDevice, s));
         const int64_t ne = (int64_t)nl * nl;
         const dim3 g((unsigned)((ne + 255) / 256)), blk(256);
         double *cur = M.cinv.p, *nxt = tmp.p;
-        for (int k = 0; k < nl; k++) {
-            hipLaunchKernelGGL(k_amg_gj_step, g, blk, 0, s, nl, k, cur, nxt, d_err);
+        for (int k0 = 0; k0 < nl; k0 += GJ_RB) {
+            const int rb = std::min(GJ_RB, nl - k0);
+            hipLaunchKernelGGL(k_amg_gj_panel, dim3(1), dim3(GJ_RB * GJ_RB), 0, s, nl, k0, rb, cur,
+                               pb.p, d_err);
+            hipLaunchKernelGGL(k_amg_gj_w, dim3((unsigned)(((int64_t)rb * nl + 255) / 256)), blk, 0,
+                               s, nl, k0, rb, cur, pb.p, wb.p);
+            hipLaunchKernelGGL(k_amg_gj_update, g, blk, 0, s, nl, k0, rb, cur, pb.p, wb.p, nxt);
             std::swap(cur, nxt);
         }
         KRY_HIP(hipGetLastError());
