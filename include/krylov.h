@@ -357,8 +357,14 @@ int LearnedLoad(LEARNED *L, const char *path);
  * step: both Gram-Schmidt passes, the norm and the Givens update),
  * "learned_stage" (one learned-stage apply after the base preconditioner),
  * "conv_l<k>_fwd" (layer k of the network), "conv_wgrad", "conv_dgrad"
- * (weight and input gradients). */
+ * (weight and input gradients).  Each event adds a few microseconds
+ * between the launches it separates, so a caller that times a whole solve
+ * can restrict the events to the families it needs: KernelTimingSelect
+ * takes a comma-separated list of the names above (NULL or "" selects
+ * every family) and applies to launches issued after the call; the list is
+ * copied, the call never fails. */
 int KernelTimingEnable(int on);
+int KernelTimingSelect(const char *names);
 int KernelTimingReset(void);
 int KernelTimingQuery(const char *name, int64_t *launches, double *total_ms);
 

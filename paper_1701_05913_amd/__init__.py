@@ -97,6 +97,7 @@ _SIGS = {
     "SolverGetHistory": (C.c_int, [P, P, C.c_int]),
     "SolverSetPC": (C.c_int, [P, P, P, P, P]),
     "KernelTimingEnable": (C.c_int, [C.c_int]), "KernelTimingReset": (C.c_int, []),
+    "KernelTimingSelect": (C.c_int, [C.c_char_p]),
     "KernelTimingQuery": (C.c_int, [C.c_char_p, C.POINTER(I64), C.POINTER(D)]),
     "KrylovSetStream": (C.c_int, [P]), "LastError": (C.c_char_p, []),
     "SolverSetLearned": (C.c_int, [P, C.c_char_p, P]),
@@ -499,6 +500,14 @@ def LearnedLoad(L, path):
 # ---- timing and stream ---------------------------------------------------------
 def KernelTimingEnable(on=True):
     return _check(_lib.KernelTimingEnable(int(bool(on))))
+
+
+def KernelTimingSelect(names=None):
+    """Time only the named kernel families (a comma-separated string or a
+    list of names); None times every family."""
+    if names is not None and not isinstance(names, str):
+        names = ",".join(names)
+    return _check(_lib.KernelTimingSelect(None if names is None else names.encode()))
 
 
 def KernelTimingReset():

@@ -124,6 +124,9 @@ hipStream_t global_stream();
 // kernel timing registry (HIP events around selected launches)
 // ---------------------------------------------------------------------------
 bool timing_on();
+// timing is on and the scope name is among the selected ones (all when
+// none are selected)
+bool timing_wanted(const char *name);
 void timing_begin(const char *name, hipStream_t s);
 void timing_end(const char *name, hipStream_t s);
 
@@ -131,7 +134,7 @@ struct TimedScope {
     const char *name;
     hipStream_t s;
     bool on;
-    TimedScope(const char *n, hipStream_t st) : name(n), s(st), on(timing_on()) {
+    TimedScope(const char *n, hipStream_t st) : name(n), s(st), on(timing_wanted(n)) {
         if (on) timing_begin(name, s);
     }
     ~TimedScope() {

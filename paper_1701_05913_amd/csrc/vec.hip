@@ -36,8 +36,18 @@ struct TimingEntry {
 static std::mutex g_tmu;
 static std::map<std::string, TimingEntry> g_timing;
 static bool g_timing_on = false;
+static std::vector<std::string> g_timing_only;   // empty: every scope
 
 bool timing_on() { return g_timing_on; }
+
+bool timing_wanted(const char *name) {
+    if (!g_timing_on) return false;
+    std::lock_guard<std::mutex> lk(g_tmu);
+    if (g_timing_only.empty()) return true;
+    for (const auto &x : g_timing_only)
+        if (x == name) return true;
+    return false;
+}
 
 void timing_begin(const char *name, hipStream_t s) {
     std::lock_guard<std::mutex> lk(g_tmu);
@@ -216,6 +226,23 @@ extern "C" int KrylovSetStream(void *stream) {
 
 extern "C" int KernelTimingEnable(int on) {
     g_timing_on = on != 0;
+    return KRY_OK;
+}
+
+extern "C" int KernelTimingSelect(const char *names) {
+    std::lock_guard<std::mutex> lk(g_tmu);
+    g_timing_only.clear();
+    if (!names) return KRY_OK;
+    std::string cur;
+    for (const char *c = names;; c++) {
+        if (*c == ',' || *c == '\0') {
+            if (!cur.empty()) g_timing_only.push_back(cur);
+            cur.clear();
+            if (*c == '\0') break;
+        } else {
+            cur += *c;
+        }
+    }
     return KRY_OK;
 }
 

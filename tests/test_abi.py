@@ -80,5 +80,9 @@ def test_host_side_argument_errors_without_gpu():
     K.SolverSetCPRFull(s, K.KRY_CPR_F_RAS)
     with pytest.raises(K.KrylovError):
         K.SolverGetAMGLevels(s)                  # nothing assembled
+    # the timing selection is host state only
+    K.KernelTimingSelect("ilu_bwd_bsr3_f64,spmv_bsr3")
+    K.KernelTimingSelect(["cgs2"])
+    K.KernelTimingSelect(None)
     K.SolverDestroy(s)
     K.MapDestroy(m)
