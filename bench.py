@@ -94,6 +94,7 @@ HEADLINE = "gmres30_bilu0_f64"
 # the headline's dominant kernel (the backward block ILU(0) sweep, FP64):
 # the only launches the timed region brackets with HIP events
 ROOF_KERNEL = "ilu_bwd_bsr3_f64"
+ROOF_SAMPLE = 8
 
 
 def algorithmic_bytes(nb, nnzb):
@@ -287,10 +288,12 @@ def main():
         for name, *_ in configs:
             run_one(name)
 
-    # timed region: HIP events bracket only the launches of the headline's
-    # dominant kernel (every event adds a few microseconds between launches)
+    # timed region: HIP events bracket only the headline's dominant kernel,
+    # one launch in every ROOF_SAMPLE (every event adds a few microseconds
+    # between the launches it separates)
     K.KernelTimingReset()
     K.KernelTimingSelect(ROOF_KERNEL)
+    K.KernelTimingSample(ROOF_SAMPLE)
     K.KernelTimingEnable(True)
     results = {name: [] for name, *_ in configs}
     torch.cuda.synchronize()
@@ -307,6 +310,7 @@ def main():
     # every instrumented launch bracketed
     K.KernelTimingReset()
     K.KernelTimingSelect(None)
+    K.KernelTimingSample(1)
     K.KernelTimingEnable(True)
     for name, *_ in configs:
         run_one(name)

@@ -362,9 +362,13 @@ int LearnedLoad(LEARNED *L, const char *path);
  * can restrict the events to the families it needs: KernelTimingSelect
  * takes a comma-separated list of the names above (NULL or "" selects
  * every family) and applies to launches issued after the call; the list is
- * copied, the call never fails. */
+ * copied, the call never fails.  KernelTimingSample(k) brackets only the
+ * first of every k launches of each family (k = 1, the default, brackets
+ * all; KRY_ERR_ARG for k < 1); it restarts the per-family launch counts,
+ * as does KernelTimingReset. */
 int KernelTimingEnable(int on);
 int KernelTimingSelect(const char *names);
+int KernelTimingSample(int every);
 int KernelTimingReset(void);
 int KernelTimingQuery(const char *name, int64_t *launches, double *total_ms);
 

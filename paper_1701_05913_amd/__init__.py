@@ -97,7 +97,7 @@ _SIGS = {
     "SolverGetHistory": (C.c_int, [P, P, C.c_int]),
     "SolverSetPC": (C.c_int, [P, P, P, P, P]),
     "KernelTimingEnable": (C.c_int, [C.c_int]), "KernelTimingReset": (C.c_int, []),
-    "KernelTimingSelect": (C.c_int, [C.c_char_p]),
+    "KernelTimingSelect": (C.c_int, [C.c_char_p]), "KernelTimingSample": (C.c_int, [C.c_int]),
     "KernelTimingQuery": (C.c_int, [C.c_char_p, C.POINTER(I64), C.POINTER(D)]),
     "KrylovSetStream": (C.c_int, [P]), "LastError": (C.c_char_p, []),
     "SolverSetLearned": (C.c_int, [P, C.c_char_p, P]),
@@ -508,6 +508,11 @@ def KernelTimingSelect(names=None):
     if names is not None and not isinstance(names, str):
         names = ",".join(names)
     return _check(_lib.KernelTimingSelect(None if names is None else names.encode()))
+
+
+def KernelTimingSample(every=1):
+    """Bracket only the first of every `every` launches of each family."""
+    return _check(_lib.KernelTimingSample(int(every)))
 
 
 def KernelTimingReset():

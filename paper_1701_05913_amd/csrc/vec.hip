@@ -37,16 +37,18 @@ static std::mutex g_tmu;
 static std::map<std::string, TimingEntry> g_timing;
 static bool g_timing_on = false;
 static std::vector<std::string> g_timing_only;   // empty: every scope
+static int g_timing_every = 1;                   // time one launch in every g_timing_every
+static std::map<std::string, int64_t> g_timing_seen;
 
 bool timing_on() { return g_timing_on; }
 
 bool timing_wanted(const char *name) {
     if (!g_timing_on) return false;
     std::lock_guard<std::mutex> lk(g_tmu);
-    if (g_timing_only.empty()) return true;
-    for (const auto &x : g_timing_only)
-        if (x == name) return true;
-    return false;
+    bool sel = g_timing_only.empty();
+    for (const auto &x : g_timing_only) sel = sel || x == name;
+    if (!sel) return false;
+    return g_timing_seen[name]++ % g_timing_every == 0;
 }
 
 void timing_begin(const char *name, hipStream_t s) {
@@ -246,8 +248,17 @@ extern "C" int KernelTimingSelect(const char *names) {
     return KRY_OK;
 }
 
+extern "C" int KernelTimingSample(int every) {
+    if (every < 1) return set_error(KRY_ERR_ARG, "KernelTimingSample: every must be >= 1");
+    std::lock_guard<std::mutex> lk(g_tmu);
+    g_timing_every = every;
+    g_timing_seen.clear();
+    return KRY_OK;
+}
+
 extern "C" int KernelTimingReset(void) {
     std::lock_guard<std::mutex> lk(g_tmu);
+    g_timing_seen.clear();
     for (auto &kv : g_timing) {
         for (auto &pr : kv.second.ev) {
             (void)hipEventDestroy(pr.first);

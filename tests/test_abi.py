@@ -84,5 +84,9 @@ def test_host_side_argument_errors_without_gpu():
     K.KernelTimingSelect("ilu_bwd_bsr3_f64,spmv_bsr3")
     K.KernelTimingSelect(["cgs2"])
     K.KernelTimingSelect(None)
+    K.KernelTimingSample(4)
+    K.KernelTimingSample(1)
+    with pytest.raises(K.KrylovError):
+        K.KernelTimingSample(0)
     K.SolverDestroy(s)
     K.MapDestroy(m)
