@@ -11,6 +11,7 @@ from tests import test_oracle_amg as ta
 from tests import test_oracle_cpr_conv as tc
 from tests import test_oracle_krylov as tk
 from tests import test_oracle_linalg as tl
+from tests import test_oracle_precision as tp
 from tests import test_oracle_ras as tr
 
 # (name, exact text in oracle.c, replacement, pins expected to fail)
@@ -180,6 +181,41 @@ MUTANTS = [
      "        L->x[i] -= s;",
      [lambda: ta.test_vcycle_matches_dense_algorithm4(0, 2),
       lambda: ta.test_vcycle_converges_on_poisson(0)]),
+    # reduced-precision emulation (mixed-precision extension)
+    ("lowp_forward_double_accumulator",
+     "                float s = 0.0f;\n                for (int c = 0; c < bs; c++) s += blk[r * bs + c] * yk[c];\n                t[r] -= s;",
+     "                double s = 0.0;\n                for (int c = 0; c < bs; c++) s += (double)blk[r * bs + c] * yk[c];\n                t[r] = (float)((double)t[r] - s);",
+     [lambda: tp.test_forward_sweep_accumulates_in_float()]),
+    ("lowp_backward_double_accumulator",
+     "                float s = 0.0f;\n                for (int c = 0; c < bs; c++) s += blk[r * bs + c] * xj[c];\n                t[r] -= s;",
+     "                double s = 0.0;\n                for (int c = 0; c < bs; c++) s += (double)blk[r * bs + c] * xj[c];\n                t[r] = (float)((double)t[r] - s);",
+     [lambda: tp.test_backward_sweep_accumulates_in_float()]),
+    ("pstage_f32_double_residual",
+     "            float t = 0.0f;\n            for (int q = pc->rp[i]; q < pc->rp[i + 1]; q++) t += pc->appf[q] * p[pc->ci[q]];\n            res[i] = rpv[i] - t;",
+     "            double t = 0.0;\n            for (int q = pc->rp[i]; q < pc->rp[i + 1]; q++) t += (double)pc->appf[q] * p[pc->ci[q]];\n            res[i] = (float)((double)rpv[i] - t);",
+     [lambda: tp.test_cpr_pf_pressure_stage_in_float()]),
+    ("bf16_variant_rounds_diagonal_inverse",
+     "for (int e = 0; e < b2; e++) L->f[(size_t)p * b2 + e] = (float)inv[e];",
+     "for (int e = 0; e < b2; e++) L->f[(size_t)p * b2 + e] = (prec == OR_PREC_BF16) ? or_bf16_round((float)inv[e]) : (float)inv[e];",
+     [lambda: tp.test_diagonal_inverse_kept_in_float_for_bf16_factors()]),
+    ("bf16_variant_keeps_float_off_diagonals",
+     "L->f[(size_t)p * b2 + e] = (prec == OR_PREC_BF16) ? or_bf16_round(v) : v;",
+     "L->f[(size_t)p * b2 + e] = v;",
+     [lambda: tp.test_forward_sweep_accumulates_in_float(),
+      lambda: tp.test_bf16_rounds_off_diagonal_blocks_of_3x3_factors()]),
+    ("conv_bf16_activations_not_rounded",
+     "round_copy(cells * cout, act, h[l + 1], bf16);",
+     "round_copy(cells * cout, act, h[l + 1], 0);",
+     [lambda: tp.test_conv_bf16_emulation_rounds_input_and_activations()]),
+    ("conv_bf16_input_not_rounded",
+     "round_copy(cells * CONV_C[0], in, h[0], bf16);",
+     "round_copy(cells * CONV_C[0], in, h[0], 0);",
+     [lambda: tp.test_conv_bf16_emulation_rounds_input_and_activations()]),
+    ("conv_bf16_weights_not_rounded",
+     "round_copy(nw, pp, W, bf16);",
+     "round_copy(nw, pp, W, 0);",
+     [lambda: tp.test_conv_bf16_emulation_rounds_weights()]),
+
 ]
 
 
