@@ -267,6 +267,14 @@ int    SolverGetTimes(const SOLVER *s, double *setup_s, double *solve_s);
  * the recurrence residual norm (BiCGSTAB) after iteration k; returns the
  * number of entries written (at most cap). */
 int    SolverGetHistory(const SOLVER *s, double *hist, int cap);
+/* Krylov basis of the last Arnoldi cycle (Algorithm 1: the orthonormal
+ * v_1 ... v_{m+1} of GMRES / FGMRES / LGMRES): copies columns
+ * [first, first + ncols) of V, each n = nb * bs values, into dst (column
+ * after column, n apart; dst on `where`).  Column 0 holds the next cycle's
+ * unnormalized residual once a solve has ended.  KRY_ERR_ARG if the solver
+ * has no basis (BiCGSTAB, CG, no solve yet) or the range exceeds its
+ * columns.  Synchronizes the solver's stream. */
+int    SolverGetKrylovBasis(const SOLVER *s, int first, int ncols, double *dst, int where);
 
 /* Custom preconditioner (Figure 29): setup(data, A) once in
  * SolverAssemble, solve(data, x, b) computes x = M^-1 b on the solver's

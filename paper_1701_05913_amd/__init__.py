@@ -95,6 +95,7 @@ _SIGS = {
     "SolverGetResidual": (D, [P]), "SolverGetIters": (C.c_int, [P]),
     "SolverGetTimes": (C.c_int, [P, C.POINTER(D), C.POINTER(D)]),
     "SolverGetHistory": (C.c_int, [P, P, C.c_int]),
+    "SolverGetKrylovBasis": (C.c_int, [P, C.c_int, C.c_int, P, C.c_int]),
     "SolverSetPC": (C.c_int, [P, P, P, P, P]),
     "KernelTimingEnable": (C.c_int, [C.c_int]), "KernelTimingReset": (C.c_int, []),
     "KernelTimingSelect": (C.c_int, [C.c_char_p]), "KernelTimingSample": (C.c_int, [C.c_int]),
@@ -374,6 +375,14 @@ def SolverGetHistory(s, cap=100000):
     buf = np.zeros(cap)
     k = _check(_lib.SolverGetHistory(s, buf.ctypes.data_as(C.c_void_p), cap))
     return buf[:k].copy()
+
+
+def SolverGetKrylovBasis(s, first, ncols, n):
+    """Columns [first, first + ncols) of the last cycle's basis as a host
+    array of shape (ncols, n)."""
+    buf = np.zeros((ncols, n))
+    _check(_lib.SolverGetKrylovBasis(s, first, ncols, buf.ctypes.data_as(C.c_void_p), KRY_HOST))
+    return buf
 
 
 PC_SETUP = C.CFUNCTYPE(C.c_int, C.c_void_p, C.c_void_p)

@@ -12,11 +12,15 @@
 // one reorthogonalization (CGS2): two passes of h = V^T w, w -= V h, each a
 // tall-skinny GEMV that streams V once.  The second pass also sums ||w||^2,
 // so h_{j+1,j} = sqrt(||w||^2 - ||h2||^2) is known before the last update,
-// which writes the normalized next basis vector.  All scalars (Hessenberg column,
+// which writes the normalized next basis vector.  When ||h2||^2 is not small
+// against ||w||^2 (w nearly in span V, close to a lucky breakdown) that
+// difference cancels; the last update then writes w - V h2 unscaled with
+// its norm taken explicitly, and a follow-up kernel scales it.  All scalars (Hessenberg column,
 // Givens rotations, residual estimate) stay in device memory; the host
 // reads back one estimate per step, which is the only per-step sync.
 // Reductions use fixed grids and fixed summation order, so two runs give
 // bitwise identical iterates.
+#include <cfloat>
 #include <chrono>
 #include <cmath>
 
@@ -31,7 +35,7 @@ constexpr int MAXCOL = 64;   // restart length limit (columns of V)
 enum {
     SC_BETA = 0, SC_INVBETA, SC_HN, SC_INVHN, SC_EST, SC_BREAK,
     SC_RHO, SC_RHO0, SC_ALPHA, SC_OMEGA, SC_BETAB, SC_RV, SC_TT, SC_TS,
-    SC_SNORM, SC_RNORM, SC_FLAGS, SC_RHN, SC_NONE, SC_COUNT = 32
+    SC_SNORM, SC_RNORM, SC_FLAGS, SC_RHN, SC_NONE, SC_RENORM, SC_WN2, SC_COUNT = 32
 };
 
 struct SmallLayout {
@@ -251,16 +255,23 @@ __global__ __launch_bounds__(256) void k_cgs_update_dots(int n, const double *__
 }
 
 // pass 3: w = (w - V h) / h_{j+1,j}, the next basis vector (the scale
-// 1/h_{j+1,j} is read from the step's scalars, 0 after a breakdown)
+// 1/h_{j+1,j} is read from the step's scalars, 0 after a breakdown).  When
+// the step's scalars ask for an explicit norm (renorm != 0, scale 1), each
+// block also writes its partial of ||w - V h||^2 to partial[block * MAXCOL].
 template <int MAXC>
 __global__ __launch_bounds__(256) void k_cgs_update_scale(int n, const double *__restrict__ V,
                                                           int64_t ldv, int nc, const double *h,
                                                           const double *inv_hn,
-                                                          double *__restrict__ w) {
+                                                          const double *renorm,
+                                                          double *__restrict__ w,
+                                                          double *__restrict__ partial) {
     __shared__ double hs[MAXC];
+    __shared__ double red[4];
     if (threadIdx.x < MAXC) hs[threadIdx.x] = (int)threadIdx.x < nc ? h[threadIdx.x] : 0.0;
     __syncthreads();
     const double sc = *inv_hn;
+    const bool want_norm = *renorm != 0.0;
+    double nacc = 0.0;
     const int nq = n / CGS_ROWS;
     for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < nq; q += gridDim.x * blockDim.x) {
         const unsigned off = (unsigned)q * CGS_ROWS;
@@ -276,6 +287,7 @@ __global__ __launch_bounds__(256) void k_cgs_update_scale(int n, const double *_
                 t1.x -= b.x * hs[k];
                 t1.y -= b.y * hs[k];
             }
+        if (want_norm) nacc += t0.x * t0.x + t0.y * t0.y + t1.x * t1.x + t1.y * t1.y;
         t0.x *= sc;
         t0.y *= sc;
         t1.x *= sc;
@@ -289,17 +301,93 @@ __global__ __launch_bounds__(256) void k_cgs_update_scale(int n, const double *_
 #pragma unroll
         for (int k = 0; k < MAXC; k++)
             if (k < nc) t -= V[k * ldv + r] * hs[k];
+        if (want_norm) nacc += t * t;
         w[r] = t * sc;
     }
+    if (want_norm) {   // uniform across the grid
+        nacc = block_sum<256>(nacc, red);
+        if (threadIdx.x == 0) partial[(size_t)blockIdx.x * MAXCOL] = nacc;
+    }
+}
+
+// Hessenberg column j from col[0..j] = h1 + h2 and h_{j+1,j} = hn: apply the
+// previous Givens rotations, form rotation j, update g and the residual
+// estimate |g_{j+1}| (one thread; cs, sn = the previous rotations, staged
+// in LDS by the caller)
+__device__ void arnoldi_column(double *small, const SmallLayout &L, int j, int m, double *col,
+                               const double *cs, const double *sn, double hn) {
+    double *H = small + L.H + (size_t)j * (m + 1), *g = small + L.g, *sc = small + L.sc;
+    col[j + 1] = hn;
+    sc[SC_HN] = hn;
+    sc[SC_INVHN] = hn != 0.0 ? 1.0 / hn : 0.0;
+    sc[SC_BREAK] = hn == 0.0 ? 1.0 : 0.0;
+    for (int k = 0; k < j; k++) {
+        const double t = cs[k] * col[k] + sn[k] * col[k + 1];
+        col[k + 1] = -sn[k] * col[k] + cs[k] * col[k + 1];
+        col[k] = t;
+    }
+    const double r = hypot(col[j], col[j + 1]);
+    double c = 1.0, sv = 0.0;
+    if (r != 0.0) {
+        c = col[j] / r;
+        sv = col[j + 1] / r;
+    }
+    small[L.cs + j] = c;
+    small[L.sn + j] = sv;
+    col[j] = r;
+    col[j + 1] = 0.0;
+    for (int k = 0; k <= j + 1; k++) H[k] = col[k];
+    const double gj = g[j];
+    g[j + 1] = -sv * gj;
+    g[j] = c * gj;
+    sc[SC_EST] = fabs(sv * gj);
+}
+
+// After pass 3 of a step that asked for an explicit norm: every block sums
+// pass 3's partials in the same order (so all see the same h_{j+1,j}),
+// scales its rows of w by 1/h_{j+1,j}, and block 0 finishes the Hessenberg
+// column.  Such a step has ||w - V h1|| at the rounding level of the first
+// projection, so what the second leaves is either a new direction, kept if
+// its norm exceeds the rounding level 8 eps (j + 2) ||w|| of two
+// projections, or rounding noise, taken as h_{j+1,j} = 0 (a lucky
+// breakdown: w lies in span V).  Exits at once on the usual path.
+__global__ __launch_bounds__(256) void k_cgs_renorm(int n, const double *__restrict__ partial,
+                                                    int nblocks, double *__restrict__ w, int j,
+                                                    int m, double *small, SmallLayout L) {
+    __shared__ double red[4];
+    __shared__ double hsh;
+    __shared__ double col[MAXCOL + 1], cs[MAXCOL], sn[MAXCOL];
+    if (small[L.sc + SC_RENORM] == 0.0) return;
+    double s = 0.0;
+    for (int b = threadIdx.x; b < nblocks; b += 256) s += partial[(size_t)b * MAXCOL];
+    s = block_sum<256>(s, red);
+    if (threadIdx.x == 0) {
+        const double hn = sqrt(s);
+        const double floor_ = 8.0 * DBL_EPSILON * (j + 2) * sqrt(small[L.sc + SC_WN2]);
+        hsh = hn > floor_ ? hn : 0.0;
+    }
+    __syncthreads();
+    const double hn = hsh;
+    const double inv = hn != 0.0 ? 1.0 / hn : 0.0;
+    for (int r = blockIdx.x * 256 + threadIdx.x; r < n; r += gridDim.x * 256) w[r] *= inv;
+    if (blockIdx.x != 0) return;
+    if ((int)threadIdx.x <= j) col[threadIdx.x] = small[L.h1 + threadIdx.x] + small[L.h2 + threadIdx.x];
+    if ((int)threadIdx.x < j) {
+        cs[threadIdx.x] = small[L.cs + threadIdx.x];
+        sn[threadIdx.x] = small[L.sn + threadIdx.x];
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) arnoldi_column(small, L, j, m, col, cs, sn, hn);
 }
 
 // Finish Arnoldi step j in one block: h2 from pass 2's partials (columns
 // 0..j, block sums in a fixed order, also stored for pass 3) and ||w||^2
-// (column j + 1); column j of H = h1 + h2; h_{j+1,j} = ||w - V h2|| taken as
-// sqrt(||w||^2 - ||h2||^2): h2 = V^T w with V orthonormal, so the second
-// correction removes exactly ||h2||^2; apply the previous Givens rotations,
-// form rotation j, update g and the residual estimate |g_{j+1}|.  The
-// rotation sweep itself is serial on thread 0.
+// (column j + 1); column j of H = h1 + h2.  h_{j+1,j} = ||w - V h2|| is
+// taken as sqrt(||w||^2 - ||h2||^2) (h2 = V^T w with V orthonormal, so the
+// second correction removes exactly ||h2||^2) when ||h2||^2 <= ||w||^2 / 2,
+// where the difference keeps all but a few bits; otherwise the step is
+// marked for an explicit norm (pass 3 writes w - V h2 unscaled and
+// k_cgs_renorm finishes the column).
 template <int MAXC>
 __global__ __launch_bounds__(1024) void k_arnoldi_finish(const double *__restrict__ partial,
                                                          int nblocks, int j, int m, double *small,
@@ -332,34 +420,20 @@ __global__ __launch_bounds__(1024) void k_arnoldi_finish(const double *__restric
     }
     s = block_sum<NT>(s, red);
     if (threadIdx.x != 0) return;
-    double *H = small + L.H + (size_t)j * (m + 1), *g = small + L.g, *sc = small + L.sc;
+    double *sc = small + L.sc;
     double h2sq = 0.0;
     for (int k = 0; k <= j; k++) h2sq += h2s[k] * h2s[k];
-    const double hn = sqrt(fmax(s - h2sq, 0.0));
-    col[j + 1] = hn;
-    sc[SC_HN] = hn;
-    sc[SC_INVHN] = hn != 0.0 ? 1.0 / hn : 0.0;
-    sc[SC_BREAK] = hn == 0.0 ? 1.0 : 0.0;
-    for (int k = 0; k < j; k++) {
-        const double t = cs[k] * col[k] + sn[k] * col[k + 1];
-        col[k + 1] = -sn[k] * col[k] + cs[k] * col[k + 1];
-        col[k] = t;
+    if (h2sq <= 0.5 * s) {
+        sc[SC_RENORM] = 0.0;
+        arnoldi_column(small, L, j, m, col, cs, sn, sqrt(s - h2sq));
+    } else {
+        // ||w||^2 = ||h1||^2 + ||w - V h1||^2 for the breakdown test
+        double h1sq = 0.0;
+        for (int k = 0; k <= j; k++) h1sq += small[L.h1 + k] * small[L.h1 + k];
+        sc[SC_WN2] = h1sq + s;
+        sc[SC_RENORM] = 1.0;
+        sc[SC_INVHN] = 1.0;
     }
-    const double r = hypot(col[j], col[j + 1]);
-    double c = 1.0, sv = 0.0;
-    if (r != 0.0) {
-        c = col[j] / r;
-        sv = col[j + 1] / r;
-    }
-    small[L.cs + j] = c;
-    small[L.sn + j] = sv;
-    col[j] = r;
-    col[j + 1] = 0.0;
-    for (int k = 0; k <= j + 1; k++) H[k] = col[k];
-    const double gj = g[j];
-    g[j + 1] = -sv * gj;
-    g[j] = c * gj;
-    sc[SC_EST] = fabs(sv * gj);
 }
 
 // g = beta e_1 and the first basis vector scale factor
@@ -654,7 +728,8 @@ static void launch_cgs(hipStream_t st, int n, const double *V, int64_t ldv, int 
     hipLaunchKernelGGL(k_arnoldi_finish<MAXC>, dim3(1), dim3(1024), 0, st, partial, g2, j, m,
                        small, L);
     hipLaunchKernelGGL(k_cgs_update_scale<MAXC>, dim3(g3), b, 0, st, n, V, ldv, nc, small + L.h2,
-                       small + L.sc + SC_INVHN, w);
+                       small + L.sc + SC_INVHN, small + L.sc + SC_RENORM, w, partial);
+    hipLaunchKernelGGL(k_cgs_renorm, dim3(256), b, 0, st, n, partial, g3, w, j, m, small, L);
 }
 
 static int cgs2_step(SOLVER_ *S, int j, double *w) {
@@ -1380,6 +1455,23 @@ extern "C" int SolverGetTimes(const SOLVER *s, double *setup_s, double *solve_s)
     if (!s) return set_error(KRY_ERR_ARG, "SolverGetTimes: NULL solver");
     if (setup_s) *setup_s = s->t_setup;
     if (solve_s) *solve_s = s->t_solve;
+    return KRY_OK;
+}
+
+extern "C" int SolverGetKrylovBasis(const SOLVER *s, int first, int ncols, double *dst, int where) {
+    if (!s || (!dst && ncols > 0) || first < 0 || ncols < 0)
+        return set_error(KRY_ERR_ARG, "SolverGetKrylovBasis: bad argument");
+    if (!s->V.p || s->ldv == 0)
+        return set_error(KRY_ERR_ARG, "SolverGetKrylovBasis: the solver holds no Krylov basis");
+    const int64_t n = (int64_t)s->A->nb * s->A->bs;
+    if ((int64_t)(first + ncols) * s->ldv > (int64_t)s->V.n)
+        return set_error(KRY_ERR_ARG, "SolverGetKrylovBasis: columns [%d, %d) exceed the basis", first,
+                         first + ncols);
+    const hipMemcpyKind kind = where == KRY_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+    for (int c = 0; c < ncols; c++)
+        KRY_HIP(hipMemcpyAsync(dst + (size_t)c * n, s->V.p + (size_t)(first + c) * s->ldv,
+                               sizeof(double) * n, kind, s->stream));
+    KRY_HIP(hipStreamSynchronize(s->stream));
     return KRY_OK;
 }
 
