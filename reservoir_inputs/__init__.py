@@ -19,8 +19,17 @@ Box-Muller.  Every draw is a pure function of (seed, field, index, sub), so
 any subset of cells can be regenerated independently.
 
 Cell numbering is natural lexicographic: cell = i + nx*(j + ny*k).
+
+Bulk draws go through philox.c (the same generator in C, compiled on first
+use into libphilox.so next to it, threads by OpenMP); the numpy
+implementation below gives the same values bit for bit and serves when the
+compiler is missing.
 """
 from __future__ import annotations
+
+import ctypes as _C
+import os
+import subprocess
 
 import numpy as np
 
@@ -75,6 +84,54 @@ def philox4x32_10(c0, c1, c2, c3, k0: int, k1: int):
             c2.astype(np.uint32), c3.astype(np.uint32))
 
 
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SO = os.path.join(_HERE, "libphilox.so")
+_clib = None
+
+
+def build(force: bool = True) -> str:
+    """Compile philox.c into libphilox.so."""
+    if force or not os.path.exists(_SO):
+        tmp = _SO + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-std=c99", "-fPIC", "-shared", "-fopenmp",
+                               "-Wall", "-o", tmp, os.path.join(_HERE, "philox.c")])
+        os.replace(tmp, _SO)
+    return _SO
+
+
+def _lib():
+    global _clib
+    if _clib is None:
+        try:
+            if not os.path.exists(_SO):
+                build()
+            L = _C.CDLL(_SO)
+            P, U32, I64, U64 = _C.c_void_p, _C.c_uint32, _C.c_int64, _C.c_uint64
+            L.philox_uniforms.argtypes = [U32, U32, P, U64, I64, U32, P, P]
+            L.philox_words.argtypes = [U32, U32, P, I64, U32, P]
+            _clib = L
+        except (OSError, subprocess.CalledProcessError):
+            _clib = False
+    return _clib
+
+
+def _uniform_pair(seed: int, field: int, idx, sub: int, both: bool):
+    """The two 53-bit uniforms of each index (second one None unless both)."""
+    L = _lib()
+    if not L:
+        w0, w1, w2, w3 = _words(seed, field, idx, sub)
+        return _u53(w0, w1), (_u53(w2, w3) if both else None)
+    idx = np.ascontiguousarray(np.asarray(idx, dtype=np.uint64).ravel())
+    n = idx.size
+    u1 = np.empty(n)
+    u2 = np.empty(n) if both else None
+    L.philox_uniforms(int(seed) & 0xFFFFFFFF, int(field) & 0xFFFFFFFF,
+                      idx.ctypes.data_as(_C.c_void_p), 0, n, int(sub) & 0xFFFFFFFF,
+                      u1.ctypes.data_as(_C.c_void_p),
+                      u2.ctypes.data_as(_C.c_void_p) if both else None)
+    return u1, u2
+
+
 def _words(seed: int, field: int, idx, sub: int = 0):
     idx = np.asarray(idx, dtype=np.uint64)
     return philox4x32_10(idx & _MASK32, idx >> np.uint64(32),
@@ -91,15 +148,14 @@ def _u53(a, b):
 
 
 def uniform01(seed: int, field: int, idx, sub: int = 0):
-    w0, w1, _, _ = _words(seed, field, idx, sub)
-    return _u53(w0, w1)
+    shape = np.shape(idx)
+    return _uniform_pair(seed, field, idx, sub, False)[0].reshape(shape)
 
 
 def normal01(seed: int, field: int, idx, sub: int = 0):
-    w0, w1, w2, w3 = _words(seed, field, idx, sub)
-    u1 = _u53(w0, w1)
-    u2 = _u53(w2, w3)
-    return np.sqrt(-2.0 * np.log(u1)) * np.cos(2.0 * np.pi * u2)
+    shape = np.shape(idx)
+    u1, u2 = _uniform_pair(seed, field, idx, sub, True)
+    return (np.sqrt(-2.0 * np.log(u1)) * np.cos(2.0 * np.pi * u2)).reshape(shape)
 
 
 # ---------------------------------------------------------------------------

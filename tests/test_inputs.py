@@ -103,3 +103,15 @@ def test_determinism_by_seed():
     c = ri.blackoil_system(4, 3, 2, seed=6)
     assert np.array_equal(a["val"], b["val"]) and np.array_equal(a["b"], b["b"])
     assert not np.array_equal(a["val"], c["val"])
+
+
+def test_c_philox_matches_numpy_bit_for_bit():
+    # the bulk draws of philox.c against the module's numpy Philox-4x32-10
+    if not ri._lib():
+        pytest.skip("libphilox.so could not be built")
+    idx = np.random.default_rng(0).integers(0, 2 ** 40, size=50000).astype(np.uint64)
+    for seed, field, sub in ((0, 1, 0), (3, 7, 5), (2 ** 31 + 5, 3, 8)):
+        u1, u2 = ri._uniform_pair(seed, field, idx, sub, True)
+        w = ri._words(seed, field, idx, sub)
+        assert np.array_equal(u1, ri._u53(w[0], w[1]))
+        assert np.array_equal(u2, ri._u53(w[2], w[3]))
