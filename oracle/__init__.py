@@ -33,9 +33,44 @@ def build(force: bool = True) -> str:
         tmp = _SO + ".tmp"
         subprocess.check_call(
             ["gcc", "-O2", "-std=c99", "-fPIC", "-shared", "-ffp-contract=off",
-             "-fno-fast-math", "-Wall", "-o", tmp, _SRC, "-lm"])
+             "-fno-fast-math", "-Wall", "-Wno-unknown-pragmas", "-o", tmp, _SRC, "-lm"])
         os.replace(tmp, _SO)
     return _SO
+
+
+_SO_OMP = os.path.join(_HERE, "liboracle_omp.so")
+
+
+def build_omp(force: bool = True) -> str:
+    """The same source with OpenMP on (parallel SpMV, dot products and the
+    vector loops of GMRES; serial sweeps and factorization): the
+    multi-threaded CPU timing leg, never a parity reference."""
+    if force or not os.path.exists(_SO_OMP):
+        tmp = _SO_OMP + ".tmp"
+        subprocess.check_call(
+            ["gcc", "-O2", "-std=c99", "-fPIC", "-shared", "-ffp-contract=off",
+             "-fno-fast-math", "-fopenmp", "-Wall", "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _SO_OMP)
+    return _SO_OMP
+
+
+class using:
+    """Context manager: route this module's calls through another compiled
+    oracle library (e.g. load(build_omp(False)))."""
+
+    def __init__(self, lib_):
+        self.lib = lib_
+
+    def __enter__(self):
+        global _lib
+        self.saved = _lib
+        _lib = self.lib
+        return self.lib
+
+    def __exit__(self, *exc):
+        global _lib
+        _lib = self.saved
+        return False
 
 
 _lib = None

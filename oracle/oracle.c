@@ -99,6 +99,7 @@ static int blk_inverse(int bs, const double *A, double *Ainv)
 static double dot(int n, const double *x, const double *y)
 {
     double s = 0.0;
+#pragma omp parallel for reduction(+ : s) schedule(static)
     for (int i = 0; i < n; i++) s += x[i] * y[i];
     return s;
 }
@@ -132,12 +133,17 @@ float or_bf16_round(float f)
 
 static double bf16d(double x) { return (double)or_bf16_round((float)x); }
 
-/* ======================================================================
+/* The SpMV row loops, dot products and the vector loops of GMRES carry
+ * OpenMP pragmas, as the paper's kernels carry USE_OMP loops; a plain
+ * build (no -fopenmp, the correctness reference) ignores them.  The
+ * triangular sweeps and the factorization stay serial.
+ * ======================================================================
  * C1. SpMV -- Figures 20 and 21: y_i = sum_j a_ij x_j row by row.
  * ====================================================================== */
 void or_bsr_spmv(int nb, int bs, const int *rp, const int *ci,
                  const double *a, const double *x, double *y)
 {
+#pragma omp parallel for schedule(static)
     for (int i = 0; i < nb; i++) {
         for (int r = 0; r < bs; r++) {
             double t = 0.0;
@@ -156,6 +162,7 @@ void or_bsr_amxpby(int nb, int bs, const int *rp, const int *ci,
                    const double *a, double alpha, const double *x,
                    double beta, double *y)
 {
+#pragma omp parallel for schedule(static)
     for (int i = 0; i < nb; i++) {
         for (int r = 0; r < bs; r++) {
             double t = 0.0;
@@ -1583,12 +1590,15 @@ int or_gmres(int nb, int bs, const int *rp, const int *ci, const double *a,
             for (int k = 0; k <= j; k++) {           /* MGS */
                 double h = dot((int)n, w, V + n * k);
                 HH(k, j) = h;
+#pragma omp parallel for schedule(static)
                 for (size_t i = 0; i < n; i++) w[i] -= h * V[n * k + i];
             }
             double hn = nrm2((int)n, w);
             HH(j + 1, j) = hn;
-            if (hn != 0.0)
+            if (hn != 0.0) {
+#pragma omp parallel for schedule(static)
                 for (size_t i = 0; i < n; i++) V[n * (j + 1) + i] = w[i] / hn;
+            }
             for (int k = 0; k < j; k++) {            /* old rotations */
                 double t = cs[k] * HH(k, j) + sn[k] * HH(k + 1, j);
                 HH(k + 1, j) = -sn[k] * HH(k, j) + cs[k] * HH(k + 1, j);
@@ -1615,12 +1625,16 @@ int or_gmres(int nb, int bs, const int *rp, const int *ci, const double *a,
             y[i] = HH(i, i) != 0.0 ? s / HH(i, i) : 0.0;
         }
         if (o->flexible && !o->left) {
-            for (int k = 0; k < jend; k++)
+            for (int k = 0; k < jend; k++) {
+#pragma omp parallel for schedule(static)
                 for (size_t i = 0; i < n; i++) x[i] += y[k] * Z[n * k + i];
+            }
         } else {
             for (size_t i = 0; i < n; i++) w[i] = 0.0;
-            for (int k = 0; k < jend; k++)
+            for (int k = 0; k < jend; k++) {
+#pragma omp parallel for schedule(static)
                 for (size_t i = 0; i < n; i++) w[i] += y[k] * V[n * k + i];
+            }
             if (o->left) {
                 for (size_t i = 0; i < n; i++) x[i] += w[i];
             } else {
