@@ -124,6 +124,17 @@ int     VecAXPBY(double alpha, VEC *x, double beta, VEC *y); /* Figure 10: y = a
 int     VecAXPBYZ(double alpha, VEC *x, double beta, VEC *y, VEC *z); /* Figure 11 */
 double  VecDot(VEC *x, VEC *y);                              /* Figure 12 (NaN on error) */
 double  VecNorm2(VEC *x);
+/* VecDotNoAlloc: for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc).
+ * Writes <x, y> to result_dev (one double in device memory, caller-owned),
+ * asynchronously on the library stream; no allocation, no host sync.  The
+ * value equals VecDot's bit for bit (same kernels, same reduction order).
+ * The reduction's partial sums live in a static device array of 1024
+ * doubles (8 KiB per GPU, held until the process ends); any vector length
+ * fits.  All calls on one GPU share that array: calls that overlap on one
+ * GPU (other streams, other threads) race.  KRY_ERR_ARG / KRY_ERR_DIM on
+ * bad arguments, KRY_ERR_HIP if the array's address cannot be found. */
+int     VecDotNoAlloc(VEC *x, VEC *y, double *result_dev);
 
 /* ---- MAT: sparse matrix (Section 2.3, Figures 15-21) ---------------------
  * Built in one call from CSR (bs = 1) or block CSR with bs x bs row-major

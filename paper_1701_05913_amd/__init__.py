@@ -95,6 +95,7 @@ _SIGS = {
     "SolverGetResidual": (D, [P]), "SolverGetIters": (C.c_int, [P]),
     "SolverGetTimes": (C.c_int, [P, C.POINTER(D), C.POINTER(D)]),
     "SolverGetHistory": (C.c_int, [P, P, C.c_int]),
+    "VecDotNoAlloc": (C.c_int, [P, P, P]),
     "SolverGetKrylovBasis": (C.c_int, [P, C.c_int, C.c_int, P, C.c_int]),
     "SolverSetPC": (C.c_int, [P, P, P, P, P]),
     "KernelTimingEnable": (C.c_int, [C.c_int]), "KernelTimingReset": (C.c_int, []),
@@ -229,6 +230,12 @@ def VecDot(x, y):
 
 def VecNorm2(x):
     return _lib.VecNorm2(x)
+
+
+def VecDotNoAlloc(x, y, result):
+    """<x, y> into `result`, a CUDA float64 tensor (its first element),
+    asynchronously on the library stream, without allocating."""
+    return _check(_lib.VecDotNoAlloc(x, y, _dptr(result)))
 
 
 # ---- MAT -----------------------------------------------------------------

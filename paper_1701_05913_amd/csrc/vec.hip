@@ -420,6 +420,55 @@ extern "C" double VecDot(VEC *x, VEC *y) {
     return r;
 }
 
+// ---------------------------------------------------------------------------
+// Allocation-free dot product.  The partial sums of its reduction live in a
+// file-scope device array (one copy per GPU, held until the process ends);
+// host code reaches it only through the address hipGetSymbolAddress gives
+// on each device (the array's name is a host-side stand-in there).
+// ---------------------------------------------------------------------------
+constexpr int NOALLOC_MAX_PARTS = 2 * RED_BLOCKS;   // doubles of partial sums
+static __device__ __align__(256) double scratch[NOALLOC_MAX_PARTS];
+constexpr int NOALLOC_MAX_DEVICES = 64;
+static double *g_scratch_dev[NOALLOC_MAX_DEVICES];
+static std::mutex g_scratch_mu;
+
+// the scratch array's device address on the current device (looked up once
+// per device, with that device current)
+static int scratch_ptr(double **out) {
+    int dev = 0;
+    KRY_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= NOALLOC_MAX_DEVICES)
+        return set_error(KRY_ERR_ARG, "VecDotNoAlloc: device %d beyond the %d supported", dev,
+                         NOALLOC_MAX_DEVICES);
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_dev[dev]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return set_error(KRY_ERR_HIP, "VecDotNoAlloc: hipGetSymbolAddress failed: %s",
+                             hipGetErrorString(e));
+        g_scratch_dev[dev] = static_cast<double *>(p);
+    }
+    *out = g_scratch_dev[dev];
+    return KRY_OK;
+}
+
+extern "C" int VecDotNoAlloc(VEC *x, VEC *y, double *result_dev) {
+    if (!x || !y || !result_dev) return set_error(KRY_ERR_ARG, "VecDotNoAlloc: NULL argument");
+    if (x->n != y->n) return set_error(KRY_ERR_DIM, "VecDotNoAlloc: sizes differ");
+    // the reduction's partials: RED_BLOCKS slots of stride 2, every slot
+    // written by its block before the final sum reads it (nothing to clear)
+    constexpr int parts = 2 * RED_BLOCKS;
+    static_assert(parts <= NOALLOC_MAX_PARTS, "scratch holds the reduction's partials");
+    if (parts > NOALLOC_MAX_PARTS)
+        return set_error(KRY_ERR_ARG, "VecDotNoAlloc: %d partials exceed the scratch of %d",
+                         parts, NOALLOC_MAX_PARTS);
+    double *part = nullptr;
+    KRY_TRY(scratch_ptr(&part));
+    KRY_TRY(vec_dot_partial(g_stream, x->n, x->data, y->data, nullptr, nullptr, part));
+    return sum_partials(g_stream, part, RED_BLOCKS, 2, 1, result_dev, SUM_PLAIN);
+}
+
 extern "C" double VecNorm2(VEC *x) {
     double d = VecDot(x, x);
     return std::isnan(d) ? d : std::sqrt(d);
