@@ -43,8 +43,8 @@
 
 namespace kry {
 
-constexpr int NLOAD = 4;       // factor loader wavefronts per workgroup
-constexpr int GWG = 64 * (2 + NLOAD);
+constexpr int NLOAD = 2;       // DMA loader wavefronts per workgroup
+constexpr int GWG = 64 * (2 + NLOAD);   // one wavefront per SIMD
 constexpr int NFACE = 40;      // >= TJ + TK for every tiling used
 constexpr int DB = 16;         // boundary ring depth (steps)
 
@@ -368,8 +368,10 @@ static int grid_finish(hipStream_t s, const MAT_ *A, IluFactor &F) {
             hipLaunchKernelGGL(k_grid_round_f32, dim3(2048), blk, 0, s, nlu, F.lt64.p, F.lt32.p);
             hipLaunchKernelGGL(k_grid_round_f32, dim3(2048), blk, 0, s, nlu, F.ut64.p, F.ut32.p);
         } else {
-            KRY_TRY(F.lt16.alloc(nlu));
-            KRY_TRY(F.ut16.alloc(nlu));
+            // 128 elements of slack: the sweeps' DMA of a step's planes
+            // rounds up to 256 bytes
+            KRY_TRY(F.lt16.alloc(nlu + 128));
+            KRY_TRY(F.ut16.alloc(nlu + 128));
             hipLaunchKernelGGL(k_grid_round_bf16, dim3(2048), blk, 0, s, nlu, F.lt64.p, F.lt16.p);
             hipLaunchKernelGGL(k_grid_round_bf16, dim3(2048), blk, 0, s, nlu, F.ut64.p, F.ut16.p);
         }
@@ -514,23 +516,165 @@ int ilu_grid_factor_setup(hipStream_t s, const MAT_ *A, const double *d_val, Ilu
 //                     and publishes the face cells; it issues no loads
 //   wave 1            boundary: polls the face buffers of the two upstream
 //                     tiles and stages the values in LDS
-//   waves 2..         loaders: stream each step's factor planes and
-//                     right-hand side into an LDS ring, two steps in flight
-//                     per wavefront; when a tile is done they re-arm the
-//                     other sweep's face slots of that tile
+//   waves 2, 3        loaders: copy each step's factor planes (and the
+//                     forward's right-hand side, the backward's diagonal
+//                     inverses and forward result) straight from global
+//                     memory into an LDS ring with the gfx950 global-to-LDS
+//                     DMA loads, several steps in flight per wavefront and
+//                     no register staging; when a tile is done they re-arm
+//                     the other sweep's face slots of that tile
 // Ring slots carry the step's stamp (a running step count of the
-// workgroup), so no slot is ever reset.
+// workgroup), so no slot is ever reset.  Four wavefronts per workgroup and
+// one workgroup per CU (the ring fills the LDS) give every role a SIMD of
+// its own: a spinning wavefront never takes issue slots from another.
 // ---------------------------------------------------------------------------
-template <typename TC, typename TF>
-__device__ __forceinline__ TC gld(const TF *p) { return static_cast<TC>(*p); }
-template <>
-__device__ __forceinline__ float gld<float, uint16_t>(const uint16_t *p) { return bf16_to_f32(*p); }
+// ring slots for steps of SB bytes (120 KiB of ring, 2 to 8 slots)
+template <int SB>
+constexpr int ring_slots() {
+    return (122880 / SB) > 8 ? 8 : (122880 / SB) < 2 ? 2 : (122880 / SB);
+}
 
-template <int NV, typename TC>
-constexpr int ring_depth() {
-    return (122880 / (NV * 64 * (int)sizeof(TC))) > 8 ? 8
-         : (122880 / (NV * 64 * (int)sizeof(TC))) < 2 ? 2
-         : (122880 / (NV * 64 * (int)sizeof(TC)));
+typedef __attribute__((address_space(3))) void lds_void_t;
+
+// global-to-LDS DMA of a contiguous block of BYTES (a multiple of 256) by
+// one wavefront: whole 1 KiB pieces as 16 bytes per lane, then 256-byte
+// pieces as 4 bytes per lane.  Lane l of a piece at offset o copies
+// src + o + w l to dst + o + w l (w its width; the LDS address of a lane is
+// the wave-uniform base plus w l).  Every instruction runs on the whole
+// wavefront: the LDS base of an instruction must be wave-uniform, so none
+// sits under a lane-dependent branch.  A block of BF16 planes with an odd
+// plane count ends 128 bytes short of a multiple of 256: its DMA rounds up
+// (pad256), reading 128 bytes past the block (the planes are allocated with
+// that much slack) into a ring region sized for the rounded length.
+constexpr int pad256(int bytes) { return (bytes + 255) / 256 * 256; }
+constexpr int dma_count(int bytes) { return bytes / 1024 + (bytes % 1024) / 256; }
+template <int BYTES>
+__device__ __forceinline__ void dma_block(const void *src, char *dst, int lane) {
+    static_assert(BYTES % 256 == 0, "256-byte pieces");
+    const char *g = static_cast<const char *>(src);
+    constexpr int N16 = BYTES / 1024, N4 = (BYTES % 1024) / 256;
+#pragma unroll
+    for (int q = 0; q < N16; q++)
+        __builtin_amdgcn_global_load_lds(g + q * 1024 + lane * 16, (lds_void_t *)(dst + q * 1024),
+                                         16, 0, 0);
+#pragma unroll
+    for (int q = 0; q < N4; q++) {
+        const int o = N16 * 1024 + q * 256;
+        __builtin_amdgcn_global_load_lds(g + o + lane * 4, (lds_void_t *)(dst + o), 4, 0, 0);
+    }
+}
+// W bytes per lane (4 or 12) from each lane's own address into dst + S l,
+// S = 4 for dwords and 16 for three-dword pieces (the DMA keeps a 16-byte
+// stride per lane for those)
+template <int W>
+__device__ __forceinline__ void dma_piece(const void *src, char *dst) {
+    static_assert(W == 4 || W == 12, "dword or three-dword pieces");
+    if constexpr (W == 4)
+        __builtin_amdgcn_global_load_lds(src, (lds_void_t *)(dst), 4, 0, 0);
+    else
+        __builtin_amdgcn_global_load_lds(src, (lds_void_t *)(dst), 12, 0, 0);
+}
+// wait until at most N vector memory instructions of this wavefront are
+// outstanding (they complete in order, so every older one has landed)
+template <int N>
+__device__ __forceinline__ void wait_vm() {
+    static_assert(N >= 0 && N < 64, "vmcnt range");
+    __builtin_amdgcn_s_waitcnt((N & 15) | ((N >> 4) << 14) | (7 << 4) | (15 << 8));
+}
+
+// value types of the ring: factor storage TF read as the compute type TC
+template <typename TC, typename TF>
+__device__ __forceinline__ TC cvt(TF v) { return static_cast<TC>(v); }
+template <>
+__device__ __forceinline__ float cvt<float, uint16_t>(uint16_t v) { return bf16_to_f32(v); }
+
+// A cell's right-hand side (BS values of TIN, CB bytes) gathered by DMA in
+// pieces of W bytes per lane: piece p of lane l at p 64 LS + l LS (LS the
+// lane stride of the piece).  Component r of lane `lane` from those pieces.
+template <typename TIN, int BS>
+struct RhsStage {
+    static constexpr int CB = BS * (int)sizeof(TIN);
+    static constexpr int W = CB % 12 == 0 ? 12 : 4;
+    static constexpr int LS = W == 12 ? 16 : 4;
+    static constexpr int NP = CB / W;            // DMA instructions per step
+    static constexpr int BYTES = NP * 64 * LS;
+    static __device__ __forceinline__ uint32_t dword(const char *rb, int lane, int d) {
+        const int off = 4 * d;
+        return *reinterpret_cast<const uint32_t *>(rb + (off / W) * 64 * LS + lane * LS + off % W);
+    }
+    template <typename TC>
+    static __device__ __forceinline__ TC value(const char *rb, int lane, int r) {
+        if constexpr (sizeof(TIN) == 8) {
+            const uint64_t u = (static_cast<uint64_t>(dword(rb, lane, 2 * r + 1)) << 32) |
+                               dword(rb, lane, 2 * r);
+            return static_cast<TC>(__longlong_as_double(static_cast<long long>(u)));
+        } else {
+            return static_cast<TC>(__uint_as_float(dword(rb, lane, r)));
+        }
+    }
+    static __device__ __forceinline__ void load(const TIN *cell, char *dst) {
+#pragma unroll
+        for (int q = 0; q < NP; q++)
+            dma_piece<W>(reinterpret_cast<const char *>(cell) + q * W, dst + q * 64 * LS);
+    }
+};
+
+// LDS flag access from a wavefront with DMA loads in flight.  The
+// compiler treats any LDS access as possibly aliasing the DMA's LDS writes
+// and would drain every outstanding DMA first; these two touch only the
+// flag word, so they are written as single LDS instructions (the read waits
+// for its own result inside the same statement).
+__device__ __forceinline__ int lds_flag_get(const int *p) {
+    const unsigned a = (unsigned)(size_t)((const __attribute__((address_space(3))) int *)p);
+    int v;
+    asm volatile("ds_read_b32 %0, %1\n\ts_waitcnt lgkmcnt(0)" : "=v"(v) : "v"(a) : "memory");
+    return v;
+}
+__device__ __forceinline__ void lds_flag_put(int *p, int v) {
+    const unsigned a = (unsigned)(size_t)((__attribute__((address_space(3))) int *)p);
+    asm volatile("ds_write_b32 %0, %1\n\ts_waitcnt lgkmcnt(0)" : : "v"(a), "v"(v) : "memory");
+}
+
+// Loader loop of one tile: steps t = w, w + NLOAD, ... of S; issue(t) starts
+// the DMA of step t into ring slot t % D (P instructions); at most K steps of
+// this wavefront in flight; a step is stamped in full[] once its DMA landed.
+// Slot t % D is free once the compute wavefront has consumed step t - D.
+// The wait counts assume no other vector memory operation of the wavefront
+// is outstanding when the loop starts.
+template <int D, int P, int K, typename F>
+__device__ __forceinline__ void loader_loop(int w, int S, int base, int *cons, int *full, int lane,
+                                            int *err, F &&issue) {
+    // the wave's vector memory counter holds at most 63 outstanding
+    // instructions: every DMA of the K steps in flight must fit in it
+    static_assert(K >= 1 && K <= 4 && K * P <= 63, "in-flight DMA within the vmcnt range");
+    int next = w, done = w;
+    uint32_t idle = 0;
+    wait_vm<0>();
+    while (done < S) {
+        while (next < S && next - done < K * NLOAD &&
+               __builtin_amdgcn_readfirstlane(lds_flag_get(cons)) >= base + next - D + 1) {
+            issue(next);
+            next += NLOAD;
+        }
+        const int inflight = (next - done) / NLOAD;
+        if (inflight == 0) {   // the ring is full: wait for the compute wavefront
+            if (++idle > 4 * SPIN_LIMIT) {
+                __hip_atomic_store(err, ERR_STALL_FLAG, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                break;
+            }
+            __builtin_amdgcn_s_sleep(1);
+            continue;
+        }
+        idle = 0;
+        // the oldest step's DMA has landed once at most (inflight - 1) * P
+        // newer instructions are outstanding
+        if constexpr (K >= 4) { if (inflight == 4) wait_vm<(K >= 4 ? 3 * P : 0)>(); }
+        if constexpr (K >= 3) { if (inflight == 3) wait_vm<(K >= 3 ? 2 * P : 0)>(); }
+        if constexpr (K >= 2) { if (inflight == 2) wait_vm<(K >= 2 ? P : 0)>(); }
+        if (inflight == 1) wait_vm<0>();
+        if (lane == 0) lds_flag_put(&full[done % D], base + done);
+        done += NLOAD;
+    }
 }
 
 // acc -= B y for block b of the planes in v
@@ -664,8 +808,15 @@ __device__ __forceinline__ void grid_fwd_body(const GridTiles &G, const TF *__re
                                               int *ctr, int *other_ctr, int *err, int blk,
                                               int64_t vsJ, int64_t vsK) {
     constexpr int B2 = BS * BS, NM = 3 * B2, NV = NM + BS;
-    constexpr int D = ring_depth<NV, TC>();
-    __shared__ TC ring[D][NV][64];
+    // ring step: NM factor planes of TF, then the step's right-hand-side
+    // cells as gathered by the DMA pieces of RhsStage
+    using RS = RhsStage<TIN, BS>;
+    constexpr int PB = pad256(NM * 64 * (int)sizeof(TF));
+    constexpr int SB = (PB + RS::BYTES + 15) / 16 * 16;
+    constexpr int D = ring_slots<SB>();
+    constexpr int P = dma_count(PB) + RS::NP;                  // DMA instructions per step
+    constexpr int K = (D / NLOAD) < (63 / P) ? (D / NLOAD) : (63 / P);
+    __shared__ __attribute__((aligned(16))) char ringb[D * SB];
     __shared__ TC bring[DB][NFACE][BS];
     __shared__ int full[D], bfull[DB], cons, bcons, tile;
     // wave-uniform role index (an SGPR), so the roles are real branches
@@ -692,6 +843,24 @@ __device__ __forceinline__ void grid_fwd_body(const GridTiles &G, const TF *__re
             if (T < 0) break;
             TC *yrow = yt + (int64_t)T * S * BS * 64 + lane;
             TC *frow = ff + (int64_t)T * S * NF * BS;
+            // the right-hand side of a lane outside the grid, or of a step
+            // outside its line, is zero (its staged words are not loaded)
+            const int JK = G.order[T];
+            const bool lane_ok = lane < TJ * TK && (JK & 0xffff) * TJ + jj < G.ny &&
+                                 (JK >> 16) * TK + kk < G.nz;
+            auto read_step = [&](int t, TC (&v)[NV]) {
+                const char *sl = ringb + (t % D) * SB;
+                const TF *pl = reinterpret_cast<const TF *>(sl);
+#pragma unroll
+                for (int e = 0; e < NM; e++) v[e] = cvt<TC, TF>(pl[e * 64 + lane]);
+                const int i = t - jj - kk;
+                const bool ok = lane_ok && i >= 0 && i < nx;
+#pragma unroll
+                for (int r = 0; r < BS; r++) {
+                    const TC x = RS::template value<TC>(sl + PB, lane, r);
+                    v[NM + r] = ok ? x : TC(0);
+                }
+            };
             TC yp[BS];
 #pragma unroll
             for (int r = 0; r < BS; r++) yp[r] = TC(0);
@@ -715,10 +884,7 @@ __device__ __forceinline__ void grid_fwd_body(const GridTiles &G, const TF *__re
                     if (jj == 0) yj[r] = bj;
                     if (kk == 0) yk[r] = bk;
                 }
-                if (more) {
-#pragma unroll
-                    for (int e = 0; e < NV; e++) vn[e] = ring[(t + 1) % D][e][lane];
-                }
+                if (more) read_step(t + 1, vn);
                 pa = lds_get(&bfull[(t + 1) % DB]);
                 pb = t + 2 < S ? lds_get(&full[(t + 2) % D]) : -1;
                 TC acc[BS];
@@ -748,8 +914,7 @@ __device__ __forceinline__ void grid_fwd_body(const GridTiles &G, const TF *__re
             };
             TC va[NV], vb[NV];
             lds_wait_eq(&full[0], base, err);
-#pragma unroll
-            for (int e = 0; e < NV; e++) va[e] = ring[0][e][lane];
+            read_step(0, va);
             int t = 0;
             for (; t + 1 < S; t += 2) {
                 step(t, va, vb);
@@ -780,7 +945,7 @@ __device__ __forceinline__ void grid_fwd_body(const GridTiles &G, const TF *__re
             boundary_role<TC, BS>(S, nx, base, lane, NF, src, lag, bring, bfull, &bcons, err);
         }
     } else {
-        // ---- loaders: planes of steps w, w + NLOAD, ... ----
+        // ---- loaders: DMA of steps w, w + NLOAD, ... ----
         const int w = wave - 2;
         for (int base = 0;; base += S) {
             const int T = next_tile(G, ctr, &tile, false, blk);
@@ -789,33 +954,18 @@ __device__ __forceinline__ void grid_fwd_body(const GridTiles &G, const TF *__re
             const int j = (JK & 0xffff) * TJ + jj, k = (JK >> 16) * TK + kk;
             const bool lane_ok = lane < TJ * TK && j < G.ny && k < G.nz;
             const int64_t cl = lane_ok ? vsJ * j + vsK * k : 0;
-            const TF *lb = Lt + (int64_t)T * S * NM * 64 + lane;
-            auto load_step = [&](int t, TC (&v)[NV]) {
-#pragma unroll
-                for (int e = 0; e < NM; e++) v[e] = gld<TC, TF>(lb + ((int64_t)t * NM + e) * 64);
+            const TF *lb = Lt + (int64_t)T * S * NM * 64;
+            // every step issues the same P instructions (the wait counts
+            // assume it): a lane with no cell loads b[0], which the compute
+            // wavefront discards
+            auto issue = [&](int t) {
+                char *sl = ringb + (t % D) * SB;
+                dma_block<PB>(lb + (int64_t)t * NM * 64, sl, lane);
                 const int i = t - jj - kk;
                 const bool ok = lane_ok && i >= 0 && i < nx;
-                const int64_t c = ok ? cl + i : 0;
-#pragma unroll
-                for (int r = 0; r < BS; r++) v[NM + r] = ok ? static_cast<TC>(b[c * BS + r]) : TC(0);
+                RS::load(b + (ok ? (cl + i) * BS : 0), sl + PB);
             };
-            // store step t (held in cur) while step t + NLOAD loads into nxt
-            auto put_step = [&](int t, const TC (&cur)[NV], TC (&nxt)[NV]) {
-                if (t + NLOAD < S) load_step(t + NLOAD, nxt);
-                lds_wait_ge(&cons, base + t - D + 1, err);
-#pragma unroll
-                for (int e = 0; e < NV; e++) ring[t % D][e][lane] = cur[e];
-                lds_release();
-                if (lane == 0) lds_put(&full[t % D], base + t);
-            };
-            TC ca[NV], cb[NV];
-            if (w < S) load_step(w, ca);
-            int t = w;
-            for (; t + NLOAD < S; t += 2 * NLOAD) {
-                put_step(t, ca, cb);
-                put_step(t + NLOAD, cb, ca);
-            }
-            if (t < S) put_step(t, ca, cb);
+            loader_loop<D, P, K>(w, S, base, &cons, full, lane, err, issue);
             // the backward sweep's face slots of this tile start unwritten
             TC *fr = fb + (int64_t)T * S * NF * BS;
             for (int64_t e = w * 64 + lane; e < (int64_t)S * NF * BS; e += NLOAD * 64)
@@ -829,8 +979,15 @@ __device__ __forceinline__ void grid_bwd_body(const GridTiles &G, const TF *__re
                                               const TD *__restrict__ Dt, TC *yt, TC *fb, TC *ff,
                                               int *ctr, int *other_ctr, int *err, int blk) {
     constexpr int B2 = BS * BS, NM = 3 * B2, NV = NM + B2 + BS;
-    constexpr int D = ring_depth<NV, TC>();
-    __shared__ TC ring[D][NV][64];
+    // ring step: NM factor planes of TF, B2 diagonal-inverse planes of TD,
+    // BS forward-result planes of TC
+    constexpr int PB = pad256(NM * 64 * (int)sizeof(TF)), DBY = B2 * 64 * (int)sizeof(TD);
+    constexpr int YB = BS * 64 * (int)sizeof(TC);
+    constexpr int SB = PB + DBY + YB;
+    constexpr int D = ring_slots<SB>();
+    constexpr int P = dma_count(PB) + dma_count(DBY) + dma_count(YB);
+    constexpr int K = (D / NLOAD) < (63 / P) ? (D / NLOAD) : (63 / P);
+    __shared__ __attribute__((aligned(16))) char ringb[D * SB];
     __shared__ TC bring[DB][NFACE][BS];
     __shared__ int full[D], bfull[DB], cons, bcons, tile;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -855,6 +1012,18 @@ __device__ __forceinline__ void grid_bwd_body(const GridTiles &G, const TF *__re
             if (T < 0) break;
             TC *yrow = yt + (int64_t)T * S * BS * 64 + lane;
             TC *frow = fb + (int64_t)T * S * NF * BS;
+            auto read_step = [&](int t, TC (&v)[NV]) {
+                const char *sl = ringb + (t % D) * SB;
+                const TF *pu = reinterpret_cast<const TF *>(sl);
+                const TD *pd = reinterpret_cast<const TD *>(sl + PB);
+                const TC *py = reinterpret_cast<const TC *>(sl + PB + DBY);
+#pragma unroll
+                for (int e = 0; e < NM; e++) v[e] = cvt<TC, TF>(pu[e * 64 + lane]);
+#pragma unroll
+                for (int e = 0; e < B2; e++) v[NM + e] = static_cast<TC>(pd[e * 64 + lane]);
+#pragma unroll
+                for (int r = 0; r < BS; r++) v[NM + B2 + r] = py[r * 64 + lane];
+            };
             TC xp[BS];
 #pragma unroll
             for (int r = 0; r < BS; r++) xp[r] = TC(0);
@@ -874,10 +1043,7 @@ __device__ __forceinline__ void grid_bwd_body(const GridTiles &G, const TF *__re
                     if (jj == TJ - 1) xj[r] = bj;
                     if (kk == TK - 1) xk[r] = bk;
                 }
-                if (more) {
-#pragma unroll
-                    for (int e = 0; e < NV; e++) vn[e] = ring[(t + 1) % D][e][lane];
-                }
+                if (more) read_step(t + 1, vn);
                 pa = lds_get(&bfull[(t + 1) % DB]);
                 pb = t + 2 < S ? lds_get(&full[(t + 2) % D]) : -1;
                 TC acc[BS];
@@ -915,8 +1081,7 @@ __device__ __forceinline__ void grid_bwd_body(const GridTiles &G, const TF *__re
             };
             TC va[NV], vb[NV];
             lds_wait_eq(&full[0], base, err);
-#pragma unroll
-            for (int e = 0; e < NV; e++) va[e] = ring[0][e][lane];
+            read_step(0, va);
             int t = 0;
             for (; t + 1 < S; t += 2) {
                 step(t, va, vb);
@@ -947,39 +1112,22 @@ __device__ __forceinline__ void grid_bwd_body(const GridTiles &G, const TF *__re
             boundary_role<TC, BS>(S, nx, base, lane, NF, src, lag, bring, bfull, &bcons, err);
         }
     } else {
-        // ---- loaders: U blocks, diagonal inverse, forward result ----
+        // ---- loaders: DMA of U blocks, diagonal inverses, forward result ----
         const int w = wave - 2;
         for (int base = 0;; base += S) {
             const int T = next_tile(G, ctr, &tile, true, blk);
             if (T < 0) break;
-            const TF *ub = Ut + (int64_t)T * S * NM * 64 + lane;
-            const TD *db = Dt + (int64_t)T * S * B2 * 64 + lane;
-            const TC *yb = yt + (int64_t)T * S * BS * 64 + lane;
-            auto load_step = [&](int t, TC (&v)[NV]) {
-#pragma unroll
-                for (int e = 0; e < NM; e++) v[e] = gld<TC, TF>(ub + ((int64_t)t * NM + e) * 64);
-#pragma unroll
-                for (int e = 0; e < B2; e++) v[NM + e] = static_cast<TC>(db[((int64_t)t * B2 + e) * 64]);
+            const TF *ub = Ut + (int64_t)T * S * NM * 64;
+            const TD *db = Dt + (int64_t)T * S * B2 * 64;
+            const TC *yb = yt + (int64_t)T * S * BS * 64;
+            auto issue = [&](int t) {
+                char *sl = ringb + (t % D) * SB;
+                dma_block<PB>(ub + (int64_t)t * NM * 64, sl, lane);
+                dma_block<DBY>(db + (int64_t)t * B2 * 64, sl + PB, lane);
                 // the forward result of the same cells: forward step S - 1 - t
-#pragma unroll
-                for (int r = 0; r < BS; r++) v[NM + B2 + r] = yb[((int64_t)(S - 1 - t) * BS + r) * 64];
+                dma_block<YB>(yb + (int64_t)(S - 1 - t) * BS * 64, sl + PB + DBY, lane);
             };
-            auto put_step = [&](int t, const TC (&cur)[NV], TC (&nxt)[NV]) {
-                if (t + NLOAD < S) load_step(t + NLOAD, nxt);
-                lds_wait_ge(&cons, base + t - D + 1, err);
-#pragma unroll
-                for (int e = 0; e < NV; e++) ring[t % D][e][lane] = cur[e];
-                lds_release();
-                if (lane == 0) lds_put(&full[t % D], base + t);
-            };
-            TC ca[NV], cb[NV];
-            if (w < S) load_step(w, ca);
-            int t = w;
-            for (; t + NLOAD < S; t += 2 * NLOAD) {
-                put_step(t, ca, cb);
-                put_step(t + NLOAD, cb, ca);
-            }
-            if (t < S) put_step(t, ca, cb);
+            loader_loop<D, P, K>(w, S, base, &cons, full, lane, err, issue);
             // the forward sweep's face slots of this tile start unwritten
             TC *fr = ff + (int64_t)T * S * NF * BS;
             for (int64_t e = w * 64 + lane; e < (int64_t)S * NF * BS; e += NLOAD * 64)
