@@ -384,9 +384,13 @@ def SolverGetHistory(s, cap=100000):
     return buf[:k].copy()
 
 
-def SolverGetKrylovBasis(s, first, ncols, n):
-    """Columns [first, first + ncols) of the last cycle's basis as a host
-    array of shape (ncols, n)."""
+def SolverGetKrylovBasis(s, first, ncols, n, out=None):
+    """Columns [first, first + ncols) of the last cycle's basis: into `out`
+    (a contiguous CUDA float64 tensor of ncols * n values) when given, else
+    as a host array of shape (ncols, n)."""
+    if out is not None:
+        _check(_lib.SolverGetKrylovBasis(s, first, ncols, _dptr(out), KRY_DEVICE))
+        return out
     buf = np.zeros((ncols, n))
     _check(_lib.SolverGetKrylovBasis(s, first, ncols, buf.ctypes.data_as(C.c_void_p), KRY_HOST))
     return buf

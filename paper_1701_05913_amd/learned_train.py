@@ -1,11 +1,14 @@
 """Train the learned preconditioner stage on the GPU and evaluate it.
 
-Harvest: for each training system (seeded black-oil generator, known
-x_true with b = A x_true), FGMRES(m)+BILU(0) runs from x = 0 one restart
-cycle at a time; after every cycle the current residual v = b - A x gives
-the stage's input r1 = v - A z1 (z1 = BILU(0)^-1 v) and its exact target
-A^-1 r1 = (x_true - x) - z1.  Each pair is normalised by s = ||r1|| /
-sqrt(n) (LearnedMakePair) and kept in device memory.
+Harvest (default, "arnoldi"): for each training system (seeded black-oil
+generator), FGMRES(30)+BILU(0) runs three restart cycles from x = 0; a
+seeded subset of the cycles' Krylov basis vectors v_j (the vectors the
+stage is applied to inside FGMRES) gives inputs r1 = v_j - A z1 with
+z1 = BILU(0)^-1 v_j.  Trained with the residual loss, which needs no
+target.  ("residual": after every cycle the current residual v = b - A x
+gives r1 and its exact target A^-1 r1 = (x_true - x) - z1.)  Each input is
+normalised by s = ||r1|| / sqrt(n) (LearnedMakePair) and kept in device
+memory.
 
 Train: Adam, one pair per step, cosine learning-rate decay, seeded
 shuffling, on one of two losses:
@@ -58,13 +61,12 @@ class System:
         self.lnk = torch.from_numpy(np.asarray(s["lnk"], np.float32)).to(DEV)
         self.At = None
         if transpose:
-            import scipy.sparse as sp
-            T = sp.bsr_matrix((np.asarray(s["val"]).reshape(-1, 3, 3), np.asarray(s["col"]),
-                               np.asarray(s["rowptr"])), shape=(self.n, self.n)).T.tobsr(blocksize=(3, 3))
-            T.sort_indices()
-            self.At = K.MatCreateBSR(self.map, self.nb, 3, T.indptr.astype(np.int32),
-                                     T.indices.astype(np.int32),
-                                     np.ascontiguousarray(T.data.reshape(-1), dtype=np.float64))
+            # the generator shares one block between A_ij and A_ji, so A^T has
+            # A's pattern with every block transposed in place
+            tv = np.ascontiguousarray(np.asarray(s["val"], np.float64).reshape(-1, 3, 3)
+                                      .transpose(0, 2, 1).reshape(-1))
+            self.At = K.MatCreateBSR(self.map, self.nb, 3, np.asarray(s["rowptr"], np.int32),
+                                     np.asarray(s["col"], np.int32), tv)
         self._vecs = []
 
     def vec(self, t):
@@ -123,6 +125,42 @@ def harvest(sys_, restart, cycles, stop_relres=1e-10):
         tgt = torch.empty(3 * cells, dtype=torch.float32, device=DEV)
         K.LearnedMakePair(cells, r1, d, sys_.lnk, inp, tgt)
         pairs.append((inp, tgt))
+    K.SolverDestroy(S)
+    return pairs
+
+
+def harvest_arnoldi(sys_, npairs, seed, restart=30, cycles=3):
+    """Stage inputs from the vectors the stage is applied to: the Krylov
+    basis vectors v_j of FGMRES(restart)+BILU(0) cycles from x = 0, each
+    turned into r1 = v_j - A BILU(0)^-1 v_j (the residual loss needs no
+    target).  A seeded subset of npairs of the cycles' vectors is kept."""
+    K.KrylovSetStream(torch.cuda.current_stream())
+    S = sys_.solver(K.KRY_PC_BILU0, restart=restart, rtol=0.0, maxit=restart)
+    n, cells = sys_.n, sys_.nb
+    x = torch.zeros(n, dtype=torch.float64, device=DEV)
+    v = torch.empty_like(x)
+    z1 = torch.empty_like(x)
+    r1 = torch.empty_like(x)
+    zero = torch.zeros_like(x)
+    hb, hx, hv, hz, hr = (sys_.vec(t) for t in (sys_.b, x, v, z1, r1))
+    rng = np.random.default_rng(seed)
+    cand = [(c, j) for c in range(cycles) for j in range(1, restart + 1)]
+    keep = set(map(tuple, np.array(cand)[rng.choice(len(cand), min(npairs, len(cand)), replace=False)]))
+    tgt = torch.zeros(3 * cells, dtype=torch.float32, device=DEV)   # unused by the residual loss
+    pairs = []
+    for c in range(cycles):
+        K.SolverSolve(S, hb, hx)                     # one FGMRES cycle from x
+        cols = [j for j in range(1, restart + 1) if (c, j) in keep]
+        if not cols:
+            continue
+        for j in cols:
+            K.SolverGetKrylovBasis(S, j, 1, n, out=v)
+            K.SolverPCApply(S, hv, hz)               # z1 = BILU(0)^-1 v_j
+            r1.copy_(v)
+            K.MatVecAMXPBY(-1.0, sys_.A, hz, 1.0, hr)    # r1 = v_j - A z1
+            inp = torch.empty(4 * cells, dtype=torch.float32, device=DEV)
+            K.LearnedMakePair(cells, r1, zero, sys_.lnk, inp, tgt)
+            pairs.append((inp, tgt))
     K.SolverDestroy(S)
     return pairs
 
@@ -225,6 +263,10 @@ def main(argv=None):
     ap.add_argument("--eval-seeds", default="10000:10004")
     ap.add_argument("--eval-grids", default="64,64,64;128,128,64",
                     help="grids of the held-out systems, ';'-separated")
+    ap.add_argument("--harvest", choices=("arnoldi", "residual"), default="arnoldi",
+                    help="stage inputs from FGMRES(30) basis vectors (residual loss only) or "
+                         "from restart-cycle residuals with exact targets")
+    ap.add_argument("--pairs-per-system", type=int, default=78)
     ap.add_argument("--restart", type=int, default=10, help="FGMRES restart during harvest")
     ap.add_argument("--cycles", type=int, default=40, help="restart cycles harvested per system")
     ap.add_argument("--epochs", type=int, default=4)
@@ -233,6 +275,8 @@ def main(argv=None):
     ap.add_argument("--loss", choices=("mse", "residual"), default="residual")
     ap.add_argument("--init", default=None, help="checkpoint to start from")
     ap.add_argument("--report", default=None, help="JSON summary file")
+    ap.add_argument("--eval-only", action="store_true",
+                    help="no harvest or training: evaluate the checkpoint given by --init")
     a = ap.parse_args(argv)
     # torch's CUDA context first, then the library (see the binding's notes)
     torch.zeros(1, device=DEV)
@@ -240,11 +284,31 @@ def main(argv=None):
     t0, t1 = (int(v) for v in a.train_seeds.split(":"))
     e0, e1 = (int(v) for v in a.eval_seeds.split(":"))
 
+    if a.eval_only:
+        if not a.init:
+            ap.error("--eval-only needs --init")
+        Li = K.LearnedCreate(*grid, False)
+        K.LearnedLoad(Li, a.init)
+        params = K.LearnedGetParams(Li)
+        K.LearnedDestroy(Li)
+        rows = []
+        for eg in a.eval_grids.split(";"):
+            rows += evaluate(tuple(int(v) for v in eg.split(",")), range(e0, e1), params)
+        summary = {"checkpoint": a.init, "eval_seeds": [e0, e1], "eval": rows}
+        if a.report:
+            with open(a.report, "w") as f:
+                json.dump(summary, f, indent=1)
+        return
     keep = a.loss == "residual"
     pairs, systems, th = [], [], time.perf_counter()
+    if a.harvest == "arnoldi" and a.loss != "residual":
+        ap.error("--harvest arnoldi has no targets: use --loss residual")
     for seed in range(t0, t1):
         sys_ = System(grid, seed, transpose=keep)
-        p = harvest(sys_, a.restart, a.cycles)
+        if a.harvest == "arnoldi":
+            p = harvest_arnoldi(sys_, a.pairs_per_system, seed)
+        else:
+            p = harvest(sys_, a.restart, a.cycles)
         pairs += [(inp, tgt, len(systems)) for inp, tgt in p]
         if keep:
             systems.append(sys_)
@@ -276,6 +340,7 @@ def main(argv=None):
     for eg in a.eval_grids.split(";"):
         rows += evaluate(tuple(int(v) for v in eg.split(",")), range(e0, e1), params)
     summary = {"grid": list(grid), "train_seeds": [t0, t1], "eval_seeds": [e0, e1],
+               "harvest": a.harvest, "pairs_per_system": a.pairs_per_system,
                "restart_harvest": a.restart, "cycles": a.cycles, "epochs": a.epochs, "lr": a.lr,
                "loss": a.loss, "init": a.init,
                "pairs": npairs, "harvest_s": round(t_harvest, 1),

@@ -115,3 +115,14 @@ def test_c_philox_matches_numpy_bit_for_bit():
         w = ri._words(seed, field, idx, sub)
         assert np.array_equal(u1, ri._u53(w[0], w[1]))
         assert np.array_equal(u2, ri._u53(w[2], w[3]))
+
+
+def test_blockwise_transpose_is_the_operator_transpose():
+    # the learned-stage training builds A^T by transposing every block in
+    # place; that is A^T because the generator shares A_ij and A_ji
+    s = ri.blackoil_system(5, 4, 3, seed=17)
+    nb = s["nb"]
+    B = sp.bsr_matrix((s["val"], s["col"], s["rowptr"]), shape=(3 * nb, 3 * nb))
+    T = sp.bsr_matrix((np.asarray(s["val"]).transpose(0, 2, 1), s["col"], s["rowptr"]),
+                      shape=(3 * nb, 3 * nb))
+    assert abs(B.T.toarray() - T.toarray()).max() == 0.0
