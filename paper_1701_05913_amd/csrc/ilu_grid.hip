@@ -1197,13 +1197,57 @@ __global__ __launch_bounds__(GWG) void k_grid_bwd(GridTiles G, const TF *__restr
     grid_bwd_body<BS, TF, TD, TC, TO>(G, Ut, Dt, yt, fb, ff, ctr, other_ctr, err, blockIdx.x);
 }
 
+// Natural-order copy of a whole grid's tile-step result with the epilogue
+// of ilu_apply.  A block takes UNT_CH consecutive steps of one tile: it reads
+// them as contiguous rows into LDS, line by line (line = lane of the tile),
+// then writes each line's UNT_CH cells as one contiguous run, so a wavefront
+// stores 512 contiguous bytes instead of 64 scattered cells.  Blocks b,
+// b + 8, b + 16, ... run on one XCD; the chunks of one tile are given to
+// consecutive blocks of the same XCD, so the cache line that two chunks of
+// a line share is completed in that XCD's L2 before it is written back.
+constexpr int UNT_CH = 32;
+
 template <int BS, typename TC, typename TO, int ADD, typename TAI, typename TAO>
 __global__ __launch_bounds__(256) void k_grid_untile(GridTiles G, const TC *__restrict__ yt,
                                                      TO *__restrict__ xo,
                                                      const TAI *__restrict__ add_in,
                                                      TAO *__restrict__ add_out) {
-    const UntileBox all{0, G.nx, 0, G.ny, 0, G.nz, G.nx, (int64_t)G.nx * G.ny};
-    grid_untile_body<BS, TC, TO, ADD, TAI, TAO>(G, yt, xo, add_in, add_out, all, blockIdx.x);
+    constexpr int LV = UNT_CH * BS;   // values of one line in a chunk
+    constexpr int LS = LV + 1;        // odd LDS stride: the row writes hit distinct banks
+    __shared__ TC lds[64 * LS];
+    const int nchunk = (G.S + UNT_CH - 1) / UNT_CH;
+    const int xcd = blockIdx.x % 8, idx = blockIdx.x / 8;
+    const int T = 8 * (idx / nchunk) + xcd, c = idx % nchunk;
+    if (T >= G.ntiles) return;
+    const int t0 = c * UNT_CH, nt = min(UNT_CH, G.S - t0);
+    const TC *src = yt + ((int64_t)T * G.S + t0) * BS * 64;
+    for (int e = threadIdx.x; e < nt * BS * 64; e += 256) {
+        const int tl = e / (BS * 64), r = (e / 64) % BS, ln = e % 64;
+        lds[ln * LS + tl * BS + r] = src[e];
+    }
+    __syncthreads();
+    const int JK = G.order[T];
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int64_t vsK = (int64_t)G.nx * G.ny;
+    for (int l = wv; l < G.TJ * G.TK; l += 4) {
+        const int jj = l % G.TJ, kk = l / G.TJ;
+        const int j = (JK & 0xffff) * G.TJ + jj, k = (JK >> 16) * G.TK + kk;
+        if (j >= G.ny || k >= G.nz) continue;
+        const int xs = t0 - jj - kk;   // x of the line's first cell in this chunk
+        const int64_t cl = vsK * k + (int64_t)G.nx * j;
+        for (int e = lane; e < nt * BS; e += 64) {
+            const int x = xs + e / BS, r = e % BS;
+            if (x < 0 || x >= G.nx) continue;
+            const TC v = lds[l * LS + e];
+            const int64_t o = (cl + x) * BS + r;
+            if (ADD == 0) xo[o] = static_cast<TO>(v);
+            if (ADD == 1) add_out[o] = static_cast<TAO>(add_in[o]) + static_cast<TAO>(v);
+            if (ADD == 2) {
+                const TC base0 = (r == 0) ? static_cast<TC>(add_in[cl + x]) : TC(0);
+                add_out[o] = static_cast<TAO>(base0 + v);
+            }
+        }
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -1329,8 +1373,9 @@ static int grid_pair(hipStream_t s, IluFactor &F, const TF *lt, const TF *ut, co
     }
     {
         TimedScope t("ilu_grid_untile", s);
-        const int nchunk = (F.G.S + 7) / 8;
-        hipLaunchKernelGGL((k_grid_untile<BS, TC, TO, ADD, TAI, TAO>), dim3(F.G.ntiles * nchunk),
+        const int nchunk = (F.G.S + UNT_CH - 1) / UNT_CH;
+        hipLaunchKernelGGL((k_grid_untile<BS, TC, TO, ADD, TAI, TAO>),
+                           dim3(8 * ((F.G.ntiles + 7) / 8) * nchunk),
                            dim3(256), 0, s, F.G, yt, xo, add_in, add_out);
     }
     KRY_HIP(hipGetLastError());
