@@ -713,10 +713,16 @@ __device__ __forceinline__ double lane_shift1(double v) {
 // The face cell of step t lies at offset t - lag along the lane's line.
 //
 // The wave is cut into G = 64 / NF groups of NF lanes; group g stages
-// steps g, g + G, g + 2G, ... .  Every round polls each group's current
-// step once; a group whose NF cells are all published (and whose ring
-// slot has been consumed) stages them and moves on, the others poll again,
-// so a step is handed over one poll after its last cell appears.
+// steps g, g + G, g + 2G, ... .  Every round probes each group's current
+// step: its first lane (a j-face entry, from the J - 1 tile) and its last
+// lane (a k-face entry, from the K - 1 tile) read the last word of their
+// entry.  Only a group whose probes both show published values reads its
+// NF entries in full; a group whose NF cells are all published (and whose
+// ring slot has been consumed) stages them and moves on, the others probe
+// again.  A waiting round thus costs two words per group instead of the
+// NF * BS values of a full read: these agent-scope loads bypass the L2,
+// and with every tile's boundary wavefront polling, full reads cost 11 to
+// 14% of the sweep time at 256 x 256 x 128.
 template <typename TC, int BS>
 __device__ void boundary_role(int S, int nx, int base, int lane, int NF, const TC *src, int lag,
                               TC (&bring)[DB][NFACE][BS], int *bfull, int *bcons, int *err) {
@@ -737,7 +743,18 @@ __device__ void boundary_role(int S, int nx, int base, int lane, int NF, const T
         TC vals[BS];
 #pragma unroll
         for (int r = 0; r < BS; r++) vals[r] = TC(0);
-        if (active) {
+        bool pr = true;
+        if (active && (f == 0 || f == NF - 1) && !failed) {
+            const int off = ts - lag;
+            if (q != nullptr && off >= 0 && off < nx)
+                pr = __hip_atomic_load(const_cast<U *>(q) + ts * stride + (BS - 1),
+                                       __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_AGENT) != Bits<TC>::sentinel;
+        }
+        const uint64_t pb = __ballot(pr);
+        const bool probed = lane_ok && ((pb >> (g * NF)) & 1ull) && ((pb >> (g * NF + NF - 1)) & 1ull);
+        if (active && !probed) ready = false;
+        if (active && probed) {
             const int off = ts - lag;
             if (q != nullptr && off >= 0 && off < nx) {
 #pragma unroll
@@ -1198,14 +1215,17 @@ __global__ __launch_bounds__(GWG) void k_grid_bwd(GridTiles G, const TF *__restr
 }
 
 // Natural-order copy of a whole grid's tile-step result with the epilogue
-// of ilu_apply.  A block takes UNT_CH consecutive steps of one tile: it reads
+// of ilu_apply.  A block takes UNT_CH consecutive steps of one tile (16: a
+// 25 KB LDS tile, six blocks per CU; 32 steps, three blocks per CU, took
+// 50% longer at 256 x 256 x 128): it reads
 // them as contiguous rows into LDS, line by line (line = lane of the tile),
 // then writes each line's UNT_CH cells as one contiguous run, so a wavefront
-// stores 512 contiguous bytes instead of 64 scattered cells.  Blocks b,
+// store covers one line's 16 cells (384 contiguous bytes in FP64) instead
+// of one cell of 64 different lines.  Blocks b,
 // b + 8, b + 16, ... run on one XCD; the chunks of one tile are given to
 // consecutive blocks of the same XCD, so the cache line that two chunks of
 // a line share is completed in that XCD's L2 before it is written back.
-constexpr int UNT_CH = 32;
+constexpr int UNT_CH = 16;
 
 template <int BS, typename TC, typename TO, int ADD, typename TAI, typename TAO>
 __global__ __launch_bounds__(256) void k_grid_untile(GridTiles G, const TC *__restrict__ yt,

@@ -142,11 +142,14 @@ __global__ __launch_bounds__(256) void k_sell_spmv(
             T xv[BS];
 #pragma unroll
             for (int k = 0; k < BS; k++) xv[k] = x[(int64_t)c * BS + k];
+            // the matrix planes stream through once: non-temporal loads
+            // leave the L2 to x, whose neighbour rows are read again
             const TA *v = val + (int64_t)t * B2 * 64 + lane;
 #pragma unroll
             for (int r = 0; r < BS; r++)
 #pragma unroll
-                for (int k = 0; k < BS; k++) acc[r] += static_cast<T>(v[(r * BS + k) * 64]) * xv[k];
+                for (int k = 0; k < BS; k++)
+                    acc[r] += static_cast<T>(__builtin_nontemporal_load(v + (r * BS + k) * 64)) * xv[k];
         }
     }
     double d0 = 0.0, d1 = 0.0;
