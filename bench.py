@@ -63,6 +63,9 @@ CONFIGS = [
     ("fgmres30_cpr_fpf_f64", "FGMRES", "CPR", "F64", ("FPF", 4)),
     ("fgmres30_cpr_ffpf_f64", "FGMRES", "CPR", "F64", ("FFPF", 4)),
     ("fgmres30_bilu0_learned", "FGMRES", "BILU0_LEARNED", "F64", None),
+    ("fgmres30_bilu0_f64_heldout", "FGMRES", "BILU0", "F64", None),
+    ("fgmres30_cpr_f32_learned", "FGMRES", "CPR_LEARNED", "F32", ("PF", 4)),
+    ("fgmres30_cpr_f32_heldout", "FGMRES", "CPR", "F32", ("PF", 4)),
     ("lgmres30_2_bilu0_f64", "GMRES", "BILU0", "F64", None),
     ("pcg_ilu0_scalar_f64", "CG", "ILU0", "F64", None),
     ("gmres30_ras4_f64", "GMRES", "RAS", "F64", None),
@@ -78,7 +81,14 @@ CONFIGS = [
 ]
 # per-configuration extras: LGMRES augmentation, and the symmetric scalar
 # system of the same grid (CG needs a symmetric positive definite matrix)
+# The learned variants run on a system of the same workload drawn with a seed
+# that no training run used (HELDOUT_SEED), each beside the same solve
+# without the stage (the *_heldout rows).
 EXTRAS = {"lgmres30_2_bilu0_f64": dict(aug_k=2), "pcg_ilu0_scalar_f64": dict(system="scalar"),
+          "fgmres30_bilu0_learned": dict(system="heldout"),
+          "fgmres30_bilu0_f64_heldout": dict(system="heldout"),
+          "fgmres30_cpr_f32_learned": dict(system="heldout", weights="cpr_f32_channelized128.bin"),
+          "fgmres30_cpr_f32_heldout": dict(system="heldout"),
           "gmres30_ras4_f64": dict(ras=(4, 1)), "gmres30_ras8_f64": dict(ras=(8, 1)),
           "gmres30_rasbox_1x4x4_f64": dict(ras=(1, 4, 4, 1)),
           "gmres30_rasbox_2x4x4_f64": dict(ras=(2, 4, 4, 1)),
@@ -94,13 +104,16 @@ HEADLINE = "gmres30_bilu0_f64"
 # variants run once after the timed region unless --variants says otherwise
 DEFAULT_VARIANTS = {
     "channelized256x256x128": ["fgmres30_bilu0_f32", "fgmres30_bilu0_bf16", "fgmres30_cpr_f32",
-                               "fgmres30_cpr_fpf_f64"],
+                               "fgmres30_cpr_fpf_f64", "fgmres30_cpr_f32_heldout",
+                               "fgmres30_cpr_f32_learned"],
     "blackoil128x128x64": ["fgmres30_bilu0_f32", "fgmres30_bilu0_bf16", "fgmres30_cpr_f64",
                            "fgmres30_cpr_f32", "fgmres30_cpr_bf16", "fgmres30_cpr_fpf_f64"],
     "blackoil64": [c[0] for c in CONFIGS if c[0] != HEADLINE],
     "blackoil32": ["fgmres30_bilu0_f32"],
 }
-WEIGHTS = os.path.join(ROOT, "paper_1701_05913_amd", "weights", "bilu0_blackoil64.bin")
+WEIGHTS_DIR = os.path.join(ROOT, "paper_1701_05913_amd", "weights")
+WEIGHTS = "bilu0_blackoil64.bin"
+HELDOUT_SEED = 10000
 
 # matrix-core FLOPs per cell of each conv layer (3x3x3 taps, 2 per MAC)
 CONV_FLOPS_PER_CELL = {"conv_l1_fwd": 2 * 27 * 4 * 32, "conv_l2_fwd": 2 * 27 * 32 * 32,
@@ -266,7 +279,7 @@ def build_solver(K, name, st, pc, prec, cpr, ex, mm, AA, rtol, maxit, stream, ln
         K.SolverSetCPRFull(S, getattr(K, f"KRY_CPR_F_{ex.get('cpr_full', 'BILU0')}"))
     K.SolverSetStream(S, stream)
     if pc.endswith("_LEARNED"):
-        K.SolverSetLearned(S, ex.get("weights", WEIGHTS), lnk)
+        K.SolverSetLearned(S, os.path.join(WEIGHTS_DIR, ex.get("weights", WEIGHTS)), lnk)
     return S
 
 
@@ -349,7 +362,26 @@ def main():
     configs = [known[HEADLINE]] + [known[v] for v in vnames if v != HEADLINE]
 
     # the scalar system, built only when a configuration needs it
-    sys_vecs = {"blackoil": (m, A, bh, xh, x)}
+    sys_vecs = {"blackoil": (m, A, bh, xh, x, lnk)}
+    # learned variants without their weights file are skipped
+    for c in list(configs):
+        w = EXTRAS.get(c[0], {}).get("weights", WEIGHTS)
+        if c[2].endswith("_LEARNED") and not os.path.exists(os.path.join(WEIGHTS_DIR, w)):
+            print(f"[bench] {c[0]}: no weights file {w}, skipped", file=sys.stderr, flush=True)
+            configs.remove(c)
+    if any(EXTRAS.get(c[0], {}).get("system") == "heldout" for c in configs):
+        sh = ri.blackoil_system(*wl["grid"], seed=HELDOUT_SEED, perm=wl["perm"],
+                                sigma2=wl["sigma2"])
+        m2 = K.MapCreateLocal(n)
+        A2 = K.MatCreateBSR(m2, nb, 3,
+                            torch.from_numpy(np.ascontiguousarray(sh["rowptr"], dtype=np.int32)).to(dev),
+                            torch.from_numpy(np.ascontiguousarray(sh["col"], dtype=np.int32)).to(dev),
+                            torch.from_numpy(np.ascontiguousarray(sh["val"].reshape(-1))).to(dev))
+        b2 = torch.from_numpy(sh["b"]).to(dev)
+        x2 = torch.zeros(n, dtype=torch.float64, device=dev)
+        lnk2 = torch.from_numpy(np.asarray(sh["lnk"], dtype=np.float32)).to(dev)
+        sys_vecs["heldout"] = (m2, A2, K.VecWrap(m2, b2), K.VecWrap(m2, x2), x2, lnk2)
+        del sh
     if any(EXTRAS.get(c[0], {}).get("system") == "scalar" for c in configs):
         ss = ri.scalar_system(*wl["grid"], seed=0)
         ns = len(ss["rowptr"]) - 1
@@ -359,13 +391,13 @@ def main():
                             torch.from_numpy(np.ascontiguousarray(ss["val"].reshape(-1))).to(dev))
         b1 = torch.from_numpy(ss["b"]).to(dev)
         x1 = torch.zeros(ns, dtype=torch.float64, device=dev)
-        sys_vecs["scalar"] = (m1, A1, K.VecWrap(m1, b1), K.VecWrap(m1, x1), x1)
+        sys_vecs["scalar"] = (m1, A1, K.VecWrap(m1, b1), K.VecWrap(m1, x1), x1, None)
     solvers = {}
     for name, st, pc, prec, cpr in configs:
         ex = EXTRAS.get(name, {})
         mm, AA = sys_vecs[ex.get("system", "blackoil")][:2]
         solvers[name] = build_solver(K, name, st, pc, prec, cpr, ex, mm, AA, args.rtol,
-                                     wl["maxit"], stream, lnk)
+                                     wl["maxit"], stream, sys_vecs[ex.get("system", "blackoil")][5])
 
     flush_buf = None
     if args.flush:
@@ -373,7 +405,7 @@ def main():
 
     def run_one(name, quiet=False):
         S = solvers[name]
-        _, _, bv, xv, xt = sys_vecs[EXTRAS.get(name, {}).get("system", "blackoil")]
+        _, _, bv, xv, xt, _ = sys_vecs[EXTRAS.get(name, {}).get("system", "blackoil")]
         xt.zero_()
         if flush_buf is not None:
             flush_buf.fill_(1.0)
@@ -513,12 +545,13 @@ def main():
     K.VecDestroy(xh)
     K.MatDestroy(A)
     K.MapDestroy(m)
-    if "scalar" in sys_vecs:
-        m1, A1, b1h, x1h, _ = sys_vecs["scalar"]
-        K.VecDestroy(b1h)
-        K.VecDestroy(x1h)
-        K.MatDestroy(A1)
-        K.MapDestroy(m1)
+    for key in ("scalar", "heldout"):
+        if key in sys_vecs:
+            m1, A1, b1h, x1h = sys_vecs[key][:4]
+            K.VecDestroy(b1h)
+            K.VecDestroy(x1h)
+            K.MatDestroy(A1)
+            K.MapDestroy(m1)
 
     cpu = None
     if not args.no_cpu:

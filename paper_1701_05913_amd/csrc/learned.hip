@@ -239,6 +239,157 @@ __global__ __launch_bounds__(256) void k_conv(int nx, int ny, int nz, int cout,
 }
 
 // ---------------------------------------------------------------------------
+// 32-channel convolutions (hidden layers 2 and 3, the output layer and the
+// input gradients of layers 2 and 3): persistent workgroups, one per CU.
+// The packed weights are staged in LDS once per launch; each workgroup
+// then walks the bricks b = blockIdx.x, b + gridDim.x, ...  The next
+// brick's input (with halo) is loaded into registers while the current
+// brick's MFMAs run, and written to LDS after them.  The taps are taken
+// by (dz, dx) pairs: the ten halo rows y0 - 1 .. y0 + 8 of that pair are
+// read once and serve the three dy taps (row r of tap dy is halo row
+// r + dy + 1), so a pair costs 10 A-fragment and 3 NT B-fragment reads
+// for 24 NT MFMAs.  Same MODEs and epilogues as k_conv; in MODE 2 the
+// bias-gradient partial is one per workgroup (bricks summed in order).
+// ---------------------------------------------------------------------------
+constexpr int CONV_PERSIST_WG = 256;
+constexpr int PRE_U4 = (HCELLS * 4 + 255) / 256;   // 16-byte input pieces per thread
+
+template <int NT, int MODE>
+__global__ __launch_bounds__(256) void k_conv32(int nx, int ny, int nz, int cout,
+                                                const uint16_t *__restrict__ in,
+                                                const uint16_t *__restrict__ wp,
+                                                const float *__restrict__ bias,
+                                                uint16_t *__restrict__ out_h,
+                                                float *__restrict__ out_f,
+                                                const float *__restrict__ zprev,
+                                                float *__restrict__ dbpart) {
+    constexpr int CST = CSTRIDE32;
+    constexpr int NW = 27 * NT * 64 * 8;
+    __shared__ __attribute__((aligned(16))) uint16_t sh_in[HCELLS * CST];
+    __shared__ __attribute__((aligned(16))) uint16_t sh_w[NW];
+    __shared__ float sh_db[4][32];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int nbx = (nx + BX - 1) / BX, nby = (ny + BY - 1) / BY, nbz = (nz + BZ - 1) / BZ;
+    const int nbricks = nbx * nby * nbz;
+    const int64_t sy = nx, sz = (int64_t)nx * ny;
+
+    for (int c = tid; c < NW / 8; c += 256)
+        *reinterpret_cast<uint4 *>(sh_w + c * 8) = *reinterpret_cast<const uint4 *>(wp + c * 8);
+
+    // the 16-byte pieces of a brick's halo cells: piece q of thread tid is
+    // c = q * 256 + tid, halo cell c / 4, channels (c % 4) * 8 .. + 7
+    uint4 pre[PRE_U4];
+    auto load = [&](int b) {
+        const int x0 = (b % nbx) * BX, y0 = ((b / nbx) % nby) * BY, z0 = (b / (nbx * nby)) * BZ;
+#pragma unroll
+        for (int q = 0; q < PRE_U4; q++) {
+            const int c = q * 256 + tid;
+            const int hc = c >> 2, part = c & 3;
+            const int hx = hc % HX, hy = (hc / HX) % HY, hz = hc / (HX * HY);
+            const int gx = x0 + hx - 1, gy = y0 + hy - 1, gz = z0 + hz - 1;
+            uint4 v = make_uint4(0, 0, 0, 0);
+            if (c < HCELLS * 4 && gx >= 0 && gx < nx && gy >= 0 && gy < ny && gz >= 0 && gz < nz)
+                v = *reinterpret_cast<const uint4 *>(in + (gx + gy * sy + gz * sz) * 32 + part * 8);
+            pre[q] = v;
+        }
+    };
+    float dbs[NT];
+#pragma unroll
+    for (int t = 0; t < NT; t++) dbs[t] = 0.0f;
+    const int xl = lane & 15, g = lane >> 4;
+    int b = blockIdx.x;
+    if (b < nbricks) load(b);
+    for (; b < nbricks; b += gridDim.x) {
+        __syncthreads();   // the previous brick's fragments have been read
+#pragma unroll
+        for (int q = 0; q < PRE_U4; q++) {
+            const int c = q * 256 + tid;
+            if (c < HCELLS * 4) *reinterpret_cast<uint4 *>(sh_in + (c >> 2) * CST + (c & 3) * 8) = pre[q];
+        }
+        __syncthreads();
+        if (b + (int)gridDim.x < nbricks) load(b + gridDim.x);
+
+        f32x4 acc[BY][NT];
+#pragma unroll
+        for (int r = 0; r < BY; r++)
+#pragma unroll
+            for (int t = 0; t < NT; t++) acc[r][t] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll 1
+        for (int pz = 0; pz < 3; pz++) {
+#pragma unroll 1
+            for (int px = 0; px < 3; px++) {
+                const int hb = (wave + pz) * HY * HX + xl + px;
+                bf16x8 a[BY + 2];
+#pragma unroll
+                for (int rr = 0; rr < BY + 2; rr++)
+                    a[rr] = *reinterpret_cast<const bf16x8 *>(sh_in + (hb + rr * HX) * CST + g * 8);
+#pragma unroll
+                for (int py = 0; py < 3; py++) {
+                    const int kb = pz * 9 + py * 3 + px;
+                    bf16x8 bfr[NT];
+#pragma unroll
+                    for (int t = 0; t < NT; t++)
+                        bfr[t] = *reinterpret_cast<const bf16x8 *>(sh_w + ((kb * NT + t) * 64 + lane) * 8);
+#pragma unroll
+                    for (int r = 0; r < BY; r++)
+#pragma unroll
+                        for (int t = 0; t < NT; t++)
+                            acc[r][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[r + py], bfr[t], acc[r][t], 0, 0, 0);
+                }
+            }
+        }
+
+        // epilogue: lane holds channel n = t*16 + lane%16 of cells x = 4g + i
+        const int x0 = (b % nbx) * BX, y0 = ((b / nbx) % nby) * BY, z0 = (b / (nbx * nby)) * BZ;
+        const int gz = z0 + wave;
+#pragma unroll
+        for (int r = 0; r < BY; r++) {
+            const int gy = y0 + r;
+#pragma unroll
+            for (int i = 0; i < 4; i++) {
+                const int gx = x0 + 4 * g + i;
+                const bool ok = gx < nx && gy < ny && gz < nz;
+                const int64_t cell = gx + gy * sy + gz * sz;
+#pragma unroll
+                for (int t = 0; t < NT; t++) {
+                    const int n = t * 16 + xl;
+                    const float y = acc[r][t][i];
+                    if (MODE == 0) {
+                        if (ok) {
+                            const float v = y + bias[n];
+                            out_h[cell * 32 + n] = f2bf(gelu(v));
+                            if (out_f) out_f[cell * 32 + n] = v;
+                        }
+                    } else if (MODE == 1) {
+                        if (ok && n < cout) out_f[cell * cout + n] = y + bias[n];
+                    } else {
+                        if (ok) {
+                            const float gv = y * gelu_grad(zprev[cell * 32 + n]);
+                            out_h[cell * 32 + n] = f2bf(gv);
+                            dbs[t] += gv;
+                        }
+                    }
+                }
+            }
+        }
+    }
+    if (MODE == 2) {
+#pragma unroll
+        for (int t = 0; t < NT; t++) {
+            float v = dbs[t];
+            v += __shfl_xor(v, 16, 64);
+            v += __shfl_xor(v, 32, 64);
+            if (lane < 16) sh_db[wave][t * 16 + lane] = v;
+        }
+        __syncthreads();
+        if (tid < 32) {
+            const float v = sh_db[0][tid] + sh_db[1][tid] + sh_db[2][tid] + sh_db[3][tid];
+            dbpart[(size_t)blockIdx.x * 32 + tid] = v;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
 // weight gradient: part[wg][m][n] = sum over the bricks of workgroup wg of
 // dz[cell][m] * h[cell + tap][c], n = tap * CINP + c (M = MT*16 output
 // channels, N = 27*CINP columns in tiles of 16).  K runs over 32 cells at a
@@ -540,6 +691,9 @@ struct ConvNet {
 static int conv_blocks(const ConvNet &N) {
     return ((N.nx + BX - 1) / BX) * ((N.ny + BY - 1) / BY) * ((N.nz + BZ - 1) / BZ);
 }
+static int conv_persist_blocks(const ConvNet &N) {
+    return std::min(conv_blocks(N), CONV_PERSIST_WG);
+}
 static int wgrad_blocks(const ConvNet &N) {
     const int nb = ((N.nx + DWX - 1) / DWX) * ((N.ny + DWY - 1) / DWY) * ((N.nz + DWZ - 1) / DWZ);
     return std::min(nb, DW_WG);
@@ -615,15 +769,16 @@ static int net_forward(hipStream_t s, ConvNet &N) {
                            N.params.p + NET_OFF[0] + 32 * 4 * 27, N.h[0].p, keep ? N.z[0].p : nullptr,
                            nullptr, nullptr);
     }
+    const dim3 gp(conv_persist_blocks(N));
     for (int l = 1; l <= 2; l++) {
         TimedScope t(l == 1 ? "conv_l2_fwd" : "conv_l3_fwd", s);
-        hipLaunchKernelGGL((k_conv<32, 2, 0>), g, b, 0, s, N.nx, N.ny, N.nz, 32, N.h[l - 1].p,
+        hipLaunchKernelGGL((k_conv32<2, 0>), gp, b, 0, s, N.nx, N.ny, N.nz, 32, N.h[l - 1].p,
                            N.wf[l].p, N.params.p + NET_OFF[l] + 32 * 32 * 27, N.h[l].p,
                            keep ? N.z[l].p : nullptr, nullptr, nullptr);
     }
     {
         TimedScope t("conv_l4_fwd", s);
-        hipLaunchKernelGGL((k_conv<32, 1, 1>), g, b, 0, s, N.nx, N.ny, N.nz, 3, N.h[2].p, N.wf[3].p,
+        hipLaunchKernelGGL((k_conv32<1, 1>), gp, b, 0, s, N.nx, N.ny, N.nz, 3, N.h[2].p, N.wf[3].p,
                            N.params.p + NET_OFF[3] + 3 * 32 * 27, nullptr, N.out.p, nullptr, nullptr);
     }
     KRY_HIP(hipGetLastError());
@@ -684,9 +839,10 @@ static int net_backward_from_dz4(hipStream_t s, ConvNet &N) {
         }
         {
             TimedScope t("conv_dgrad", s);
-            hipLaunchKernelGGL((k_conv<32, 2, 2>), g, b, 0, s, N.nx, N.ny, N.nz, 32, dcur, N.wt[l].p,
+            const dim3 gp(conv_persist_blocks(N));
+            hipLaunchKernelGGL((k_conv32<2, 2>), gp, b, 0, s, N.nx, N.ny, N.nz, 32, dcur, N.wt[l].p,
                                nullptr, dnext, nullptr, N.z[l - 1].p, N.part.p);
-            hipLaunchKernelGGL(k_bgrad_reduce, dim3(1), dim3(64), 0, s, N.part.p, (int)g.x, 32, 32,
+            hipLaunchKernelGGL(k_bgrad_reduce, dim3(1), dim3(64), 0, s, N.part.p, (int)gp.x, 32, 32,
                                N.grad.p + NET_OFF[l - 1] + (l - 1 == 0 ? 32 * 4 * 27 : 32 * 32 * 27));
         }
         std::swap(dcur, dnext);

@@ -45,11 +45,18 @@ import reservoir_inputs as ri
 DEV = "cuda:0"
 
 
+# base preconditioners of the stage: (plain kind, learned kind)
+BASES = {"bilu0": (K.KRY_PC_BILU0, K.KRY_PC_BILU0_LEARNED),
+         "cpr_f32": (K.KRY_PC_CPR, K.KRY_PC_CPR_LEARNED)}
+
+
 class System:
     """One generated system uploaded through the C ABI."""
 
     def __init__(self, grid, seed, perm="layered", transpose=False):
-        s = ri.blackoil_system(*grid, seed=seed, perm=perm)
+        # layered fields with variance 2, channelized ones with variance 3
+        s = ri.blackoil_system(*grid, seed=seed, perm=perm,
+                               sigma2=3.0 if perm == "channelized" else 2.0)
         self.grid, self.seed = grid, seed
         self.nb, self.n = s["nb"], s["n"]
         self.map = K.MapCreateLocal(self.n)
@@ -74,10 +81,15 @@ class System:
         self._vecs.append(h)
         return h
 
-    def solver(self, pc, restart=30, rtol=1e-8, maxit=2000, params=None):
+    def solver(self, pc, restart=30, rtol=1e-8, maxit=2000, params=None, base="bilu0"):
+        """FGMRES with the base preconditioner `base` (BASES), plain (pc =
+        its plain kind) or with the learned stage (its learned kind)."""
         S = K.SolverCreate(K.KRY_FGMRES, pc, self.map)
         K.SolverSetMat(S, self.A)
         K.SolverSetStream(S, torch.cuda.current_stream())
+        if base == "cpr_f32":
+            K.SolverSetPrecision(S, K.KRY_PREC_F32)
+            K.SolverSetCPR(S, K.KRY_CPR_PF, 4)
         K.SolverSetRestart(S, restart)
         K.SolverSetRtol(S, rtol)
         K.SolverSetMaxit(S, maxit)
@@ -129,13 +141,14 @@ def harvest(sys_, restart, cycles, stop_relres=1e-10):
     return pairs
 
 
-def harvest_arnoldi(sys_, npairs, seed, restart=30, cycles=3):
+def harvest_arnoldi(sys_, npairs, seed, restart=30, cycles=3, base="bilu0"):
     """Stage inputs from the vectors the stage is applied to: the Krylov
-    basis vectors v_j of FGMRES(restart)+BILU(0) cycles from x = 0, each
-    turned into r1 = v_j - A BILU(0)^-1 v_j (the residual loss needs no
-    target).  A seeded subset of npairs of the cycles' vectors is kept."""
+    basis vectors v_j of FGMRES(restart) cycles from x = 0 with the base
+    preconditioner M, each turned into r1 = v_j - A M^-1 v_j (the residual
+    loss needs no target).  A seeded subset of npairs of the cycles'
+    vectors is kept."""
     K.KrylovSetStream(torch.cuda.current_stream())
-    S = sys_.solver(K.KRY_PC_BILU0, restart=restart, rtol=0.0, maxit=restart)
+    S = sys_.solver(BASES[base][0], restart=restart, rtol=0.0, maxit=restart, base=base)
     n, cells = sys_.n, sys_.nb
     x = torch.zeros(n, dtype=torch.float64, device=DEV)
     v = torch.empty_like(x)
@@ -155,7 +168,7 @@ def harvest_arnoldi(sys_, npairs, seed, restart=30, cycles=3):
             continue
         for j in cols:
             K.SolverGetKrylovBasis(S, j, 1, n, out=v)
-            K.SolverPCApply(S, hv, hz)               # z1 = BILU(0)^-1 v_j
+            K.SolverPCApply(S, hv, hz)               # z1 = M^-1 v_j_j
             r1.copy_(v)
             K.MatVecAMXPBY(-1.0, sys_.A, hz, 1.0, hr)    # r1 = v_j - A z1
             inp = torch.empty(4 * cells, dtype=torch.float32, device=DEV)
@@ -193,12 +206,19 @@ def zero_loss(pairs, grid, loss):
     return tot / max(len(pairs), 1)
 
 
-def train(pairs, grid, epochs, lr, seed, loss="mse", systems=None, init=None, log_every=500):
+def train(pairs, grid, epochs, lr, seed, loss="mse", systems=None, init=None, log_every=500,
+          save_path=None, resume=None, start_epoch=0, last_scale=0.1):
     """pairs: (input, target, system index); systems: needed for the
-    residual loss."""
+    residual loss.  save_path: checkpoint written after every epoch.
+    resume, start_epoch: continue a run from the checkpoint it wrote after
+    epoch start_epoch - 1 (parameters, Adam moments and step count), with
+    the same shuffles and learning-rate schedule as an uninterrupted run."""
     L = K.LearnedCreate(*grid, True)
     K.LearnedSetStream(L, torch.cuda.current_stream())
-    K.LearnedSetParams(L, init_params(seed) if init is None else init)
+    if resume is not None:
+        K.LearnedLoad(L, resume)
+    else:
+        K.LearnedSetParams(L, init_params(seed, last_scale) if init is None else init)
     cells = grid[0] * grid[1] * grid[2]
     out = torch.empty(3 * cells, dtype=torch.float32, device=DEV)
     dout = torch.empty_like(out)
@@ -207,6 +227,9 @@ def train(pairs, grid, epochs, lr, seed, loss="mse", systems=None, init=None, lo
     step, curve, t0 = 0, [], time.perf_counter()
     for ep in range(epochs):
         order = rng.permutation(len(pairs))
+        if ep < start_epoch:
+            step += len(pairs)
+            continue
         acc = 0.0
         for i in order:
             inp, tgt, k = pairs[i]
@@ -224,17 +247,19 @@ def train(pairs, grid, epochs, lr, seed, loss="mse", systems=None, init=None, lo
                 print(f"  step {step}/{total} loss {lv:.4e}", flush=True)
         curve.append(acc / len(pairs))
         print(f"epoch {ep}: mean loss {curve[-1]:.4e} ({time.perf_counter() - t0:.1f} s)", flush=True)
+        if save_path:
+            K.LearnedSave(L, save_path)
     return L, curve, time.perf_counter() - t0
 
 
-def evaluate(grid, seeds, params, rtol=1e-8, restart=30):
+def evaluate(grid, seeds, params, rtol=1e-8, restart=30, perm="layered", base="bilu0"):
     rows = []
     for seed in seeds:
-        sys_ = System(grid, seed)
-        row = {"seed": seed, "grid": list(grid)}
-        for name, pc, prm in [("bilu0", K.KRY_PC_BILU0, None),
-                              ("bilu0_learned", K.KRY_PC_BILU0_LEARNED, params)]:
-            S = sys_.solver(pc, restart=restart, rtol=rtol, params=prm)
+        sys_ = System(grid, seed, perm=perm)
+        row = {"seed": seed, "grid": list(grid), "perm": perm, "base": base}
+        for name, pc, prm in [(base, BASES[base][0], None),
+                              (base + "_learned", BASES[base][1], params)]:
+            S = sys_.solver(pc, restart=restart, rtol=rtol, params=prm, base=base)
             x = torch.zeros(sys_.n, dtype=torch.float64, device=DEV)
             hb, hx = sys_.vec(sys_.b), sys_.vec(x)
             torch.cuda.synchronize()
@@ -271,9 +296,19 @@ def main(argv=None):
     ap.add_argument("--cycles", type=int, default=40, help="restart cycles harvested per system")
     ap.add_argument("--epochs", type=int, default=4)
     ap.add_argument("--lr", type=float, default=1e-3)
+    ap.add_argument("--last-scale", type=float, default=0.1,
+                    help="scale of the output layer's initial weights (0: the first "
+                         "corrections are zero)")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--loss", choices=("mse", "residual"), default="residual")
     ap.add_argument("--init", default=None, help="checkpoint to start from")
+    ap.add_argument("--resume", default=None,
+                    help="checkpoint this run wrote after epoch --start-epoch - 1")
+    ap.add_argument("--start-epoch", type=int, default=0)
+    ap.add_argument("--grid-perm", default="layered", choices=("layered", "channelized"),
+                    help="permeability field of the training and evaluation systems")
+    ap.add_argument("--base", default="bilu0", choices=sorted(BASES),
+                    help="base preconditioner the stage corrects (harvest and evaluation)")
     ap.add_argument("--report", default=None, help="JSON summary file")
     ap.add_argument("--eval-only", action="store_true",
                     help="no harvest or training: evaluate the checkpoint given by --init")
@@ -293,7 +328,8 @@ def main(argv=None):
         K.LearnedDestroy(Li)
         rows = []
         for eg in a.eval_grids.split(";"):
-            rows += evaluate(tuple(int(v) for v in eg.split(",")), range(e0, e1), params)
+            rows += evaluate(tuple(int(v) for v in eg.split(",")), range(e0, e1), params,
+                         perm=a.grid_perm, base=a.base)
         summary = {"checkpoint": a.init, "eval_seeds": [e0, e1], "eval": rows}
         if a.report:
             with open(a.report, "w") as f:
@@ -303,10 +339,12 @@ def main(argv=None):
     pairs, systems, th = [], [], time.perf_counter()
     if a.harvest == "arnoldi" and a.loss != "residual":
         ap.error("--harvest arnoldi has no targets: use --loss residual")
+    if a.harvest == "residual" and a.base != "bilu0":
+        ap.error("--harvest residual supports --base bilu0 only")
     for seed in range(t0, t1):
-        sys_ = System(grid, seed, transpose=keep)
+        sys_ = System(grid, seed, perm=a.grid_perm, transpose=keep)
         if a.harvest == "arnoldi":
-            p = harvest_arnoldi(sys_, a.pairs_per_system, seed)
+            p = harvest_arnoldi(sys_, a.pairs_per_system, seed, base=a.base)
         else:
             p = harvest(sys_, a.restart, a.cycles)
         pairs += [(inp, tgt, len(systems)) for inp, tgt in p]
@@ -325,9 +363,11 @@ def main(argv=None):
         K.LearnedDestroy(Li)
     loss0 = zero_loss(pairs, grid, a.loss)
     print(f"zero-network {a.loss} loss {loss0:.4e} over {len(pairs)} pairs", flush=True)
+    if a.resume and not a.start_epoch:
+        ap.error("--resume needs --start-epoch")
     L, curve, t_train = train(pairs, grid, a.epochs, a.lr, a.seed, loss=a.loss, systems=systems,
-                              init=init)
-    K.LearnedSave(L, a.out)
+                              init=init, save_path=a.out, resume=a.resume,
+                              start_epoch=a.start_epoch, last_scale=a.last_scale)
     params = K.LearnedGetParams(L)
     K.LearnedDestroy(L)
     npairs = len(pairs)
@@ -338,12 +378,14 @@ def main(argv=None):
 
     rows = []
     for eg in a.eval_grids.split(";"):
-        rows += evaluate(tuple(int(v) for v in eg.split(",")), range(e0, e1), params)
+        rows += evaluate(tuple(int(v) for v in eg.split(",")), range(e0, e1), params,
+                         perm=a.grid_perm, base=a.base)
     summary = {"grid": list(grid), "train_seeds": [t0, t1], "eval_seeds": [e0, e1],
                "harvest": a.harvest, "pairs_per_system": a.pairs_per_system,
                "restart_harvest": a.restart, "cycles": a.cycles, "epochs": a.epochs, "lr": a.lr,
-               "loss": a.loss, "init": a.init,
-               "pairs": npairs, "harvest_s": round(t_harvest, 1),
+               "loss": a.loss, "init": a.init, "perm": a.grid_perm, "base": a.base,
+               "last_scale": a.last_scale,
+               "resume": a.resume, "start_epoch": a.start_epoch, "pairs": npairs, "harvest_s": round(t_harvest, 1),
                "train_s": round(t_train, 1), "zero_network_loss": loss0,
                "loss_per_epoch": curve, "eval": rows}
     if a.report:

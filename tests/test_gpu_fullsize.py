@@ -11,6 +11,8 @@ fixed-iteration prefix of plain GMRES(30) + BILU(0): one full restart cycle
 of 30 steps (the measurement plan names 60; 30 keeps the oracle's share
 of the test near two minutes), comparing the residual estimate after every
 step and the iterate x with the oracle's run of the same length."""
+import os
+
 import numpy as np
 import pytest
 
@@ -88,3 +90,57 @@ def test_256_gmres_bilu0_fixed_prefix(big):
     # the true residual after the prefix, recomputed by the oracle
     r = np.linalg.norm(s["b"] - oracle.spmv(A, gpu["x"])) / np.linalg.norm(s["b"])
     assert abs(r - gpu["relres"]) <= 1e-6 * r
+
+
+CPR_WEIGHTS = os.path.join(os.path.dirname(K.__file__), "weights", "cpr_f32_channelized128.bin")
+
+
+def _cpr_f32_fgmres(g, lnk, steps, weights=None, params=None):
+    pc = K.KRY_PC_CPR if weights is None and params is None else K.KRY_PC_CPR_LEARNED
+    S = K.SolverCreate(K.KRY_FGMRES, pc, g.map)
+    try:
+        K.SolverSetMat(S, g.A)
+        K.SolverSetRtol(S, 0.0)
+        K.SolverSetMaxit(S, steps)
+        K.SolverSetRestart(S, 30)
+        K.SolverSetPrecision(S, K.KRY_PREC_F32)
+        K.SolverSetCPR(S, K.KRY_CPR_PF, 4)
+        K.SolverSetStream(S, torch.cuda.current_stream())
+        if weights is not None:
+            K.SolverSetLearned(S, weights, lnk)
+        elif params is not None:
+            K.SolverSetLearnedParams(S, params, lnk)
+        K.SolverAssemble(S)
+        bt, bh = g.vec(g.s["b"])
+        xt, xh = g.vec()
+        rc = K.SolverSolve(S, bh, xh)
+        torch.cuda.synchronize()
+        stats = K.SolverGetLearnedStats(S) if pc == K.KRY_PC_CPR_LEARNED else None
+        return dict(status=rc, x=xt.cpu().numpy(), iters=K.SolverGetIters(S),
+                    hist=np.asarray(K.SolverGetHistory(S)), stats=stats)
+    finally:
+        K.SolverDestroy(S)
+
+
+@pytest.mark.skipif(not os.path.exists(CPR_WEIGHTS),
+                    reason="trained 128^3 CPR network not present")
+def test_256_cpr_f32_learned_stage_fallback(big):
+    """The learned stage on FP32 CPR-PF at 256x256x128, one restart cycle:
+    with a NaN network every application falls back and the run equals plain
+    CPR-FGMRES bit for bit; with the shipped network (trained on 128^3
+    channelized systems) the counters are consistent and the history finite.
+    Its fallback count over the cycle is reported."""
+    s, A, g = big
+    lnk = torch.from_numpy(np.asarray(s["lnk"], dtype=np.float32)).to("cuda:0")
+    plain = _cpr_f32_fgmres(g, lnk, PREFIX)
+    nan = _cpr_f32_fgmres(g, lnk, PREFIX, params=np.full(K.LearnedNumParams(), np.nan, np.float32))
+    net = _cpr_f32_fgmres(g, lnk, PREFIX, weights=CPR_WEIGHTS)
+    assert plain["iters"] == nan["iters"] == net["iters"] == PREFIX
+    a, f = nan["stats"]
+    assert a >= PREFIX and f == a
+    assert np.array_equal(nan["x"], plain["x"]) and np.array_equal(nan["hist"], plain["hist"])
+    a, f = net["stats"]
+    assert a >= PREFIX and 0 <= f <= a
+    assert np.all(np.isfinite(net["hist"])) and np.all(np.isfinite(net["x"]))
+    print(f"256x256x128 CPR-PF FP32 + learned stage, {PREFIX} steps: residual estimate "
+          f"{net['hist'][-1]:.3e} (plain {plain['hist'][-1]:.3e}), {f} of {a} applications fell back")

@@ -386,41 +386,49 @@ WEIGHTS = os.path.join(os.path.dirname(K.__file__), "weights", "bilu0_blackoil64
 
 
 @pytest.mark.skipif(not os.path.exists(WEIGHTS), reason="trained weights not present")
-def test_trained_stage_against_plain_bilu0_on_a_held_out_system():
-    """What the trained network gains over BILU(0)-FGMRES(30) alone on an
-    unseen 64^3 system (seed 10000): both must reach the FP64 true
-    residual 1e-8; the iteration counts, times and fallback fraction are
-    reported, not pinned (the gain is a measured property of the trained
-    weights)."""
-    import time
-    s = ri.blackoil_system(64, 64, 64, seed=10000)
-    G = GpuSystem(s)
-    lnk = torch.from_numpy(np.asarray(s["lnk"], dtype=np.float32)).to(DEV)
-    res = {}
-    try:
-        for name, pc in [("plain", K.KRY_PC_BILU0), ("learned", K.KRY_PC_BILU0_LEARNED)]:
-            S = K.SolverCreate(K.KRY_FGMRES, pc, G.map)
-            K.SolverSetMat(S, G.A)
-            K.SolverSetStream(S, torch.cuda.current_stream())
-            K.SolverSetRtol(S, 1e-8)
-            K.SolverSetMaxit(S, 2000)
-            if pc == K.KRY_PC_BILU0_LEARNED:
-                K.SolverSetLearned(S, WEIGHTS, lnk)
-            K.SolverAssemble(S)
-            bt, bh = G.vec(s["b"])
-            xt, xh = G.vec()
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            rc = K.SolverSolve(S, bh, xh)
-            torch.cuda.synchronize()
-            res[name] = dict(rc=rc, iters=K.SolverGetIters(S), relres=K.SolverGetResidual(S),
-                             time=time.perf_counter() - t0,
-                             stats=K.SolverGetLearnedStats(S) if pc == K.KRY_PC_BILU0_LEARNED else None)
-            K.SolverDestroy(S)
-    finally:
-        G.close()
-    print(f"\nheld-out 64^3: plain {res['plain']}, learned {res['learned']}")
-    for r in res.values():
-        assert r["rc"] == 0 and r["relres"] <= 1e-8
-    applies, falls = res["learned"]["stats"]
-    assert applies >= res["learned"]["iters"] and 0 <= falls <= applies
+def test_trained_stage_against_plain_bilu0_on_held_out_systems():
+    """What the shipped network gains or loses against BILU(0)-FGMRES(30)
+    alone on 32 unseen 64^3 systems (seeds 10000-10031; training used
+    seeds 0-255): every solve must reach the FP64 true residual 1e-8 and
+    the stage's counters must be consistent; the iteration counts, the
+    mean gain and the fallback fraction are reported, not pinned (they are
+    measured properties of the trained weights)."""
+    rows = []
+    for seed in range(10000, 10032):
+        s = ri.blackoil_system(64, 64, 64, seed=seed)
+        G = GpuSystem(s)
+        lnk = torch.from_numpy(np.asarray(s["lnk"], dtype=np.float32)).to(DEV)
+        res = {}
+        try:
+            for name, pc in [("plain", K.KRY_PC_BILU0), ("learned", K.KRY_PC_BILU0_LEARNED)]:
+                S = K.SolverCreate(K.KRY_FGMRES, pc, G.map)
+                K.SolverSetMat(S, G.A)
+                K.SolverSetStream(S, torch.cuda.current_stream())
+                K.SolverSetRtol(S, 1e-8)
+                K.SolverSetMaxit(S, 2000)
+                if pc == K.KRY_PC_BILU0_LEARNED:
+                    K.SolverSetLearned(S, WEIGHTS, lnk)
+                K.SolverAssemble(S)
+                bt, bh = G.vec(s["b"])
+                xt, xh = G.vec()
+                rc = K.SolverSolve(S, bh, xh)
+                torch.cuda.synchronize()
+                res[name] = dict(rc=rc, iters=K.SolverGetIters(S), relres=K.SolverGetResidual(S),
+                                 stats=K.SolverGetLearnedStats(S) if name == "learned" else None)
+                K.SolverDestroy(S)
+        finally:
+            G.close()
+        for r in res.values():
+            assert r["rc"] == 0 and r["relres"] <= 1e-8, (seed, r)
+        applies, falls = res["learned"]["stats"]
+        assert applies >= res["learned"]["iters"] and 0 <= falls <= applies, (seed, res)
+        rows.append((seed, res["plain"]["iters"], res["learned"]["iters"], applies, falls))
+    plain = np.array([r[1] for r in rows], float)
+    learned = np.array([r[2] for r in rows], float)
+    fb = sum(r[4] for r in rows) / max(1, sum(r[3] for r in rows))
+    print(f"\nheld-out 64^3, 32 seeds: iterations plain {plain.mean():.1f} learned "
+          f"{learned.mean():.1f} (mean ratio {np.mean(learned / plain):.3f}; fewer on "
+          f"{int(np.sum(learned < plain))}, more on {int(np.sum(learned > plain))}); "
+          f"fallback fraction {fb:.3f}")
+    for r in rows:
+        print(f"  seed {r[0]}: plain {r[1]}, learned {r[2]}, stage applies {r[3]}, fallbacks {r[4]}")
