@@ -43,10 +43,27 @@ constexpr int DWX = 16, DWY = 4, DWZ = 2;                    // weight-gradient 
 constexpr int DWROWX = 24;                                   // padded x extent of its halo rows
 constexpr int DW_WG = 256;                                   // persistent weight-gradient workgroups
 
-__device__ __forceinline__ uint16_t f2bf(float f) { return f32_to_bf16_rne(f); }
-__device__ __forceinline__ float gelu(float x) { return 0.5f * x * (1.0f + erff(x * 0.70710678118654752f)); }
+// FP32 -> BF16 round to nearest even in one instruction (v_cvt_pk_bf16_f32
+// on gfx950); equal to f32_to_bf16_rne for every non-NaN input
+__device__ __forceinline__ uint16_t f2bf(float f) { return __builtin_bit_cast(uint16_t, static_cast<__bf16>(f)); }
+// erf by the rational approximation of Abramowitz & Stegun (1964),
+// formula 7.1.26: for x >= 0, erf x = 1 - t (a1 + t (a2 + t (a3 + t (a4 +
+// t a5)))) exp(-x^2) with t = 1 / (1 + p x), absolute error below 1.5e-7
+// (about one FP32 ulp of erf near 1; the activations are rounded to BF16
+// afterwards); odd in x.  Branch-free: one reciprocal, one exponential and
+// five FMAs instead of the library's piecewise erff.
+__device__ __forceinline__ float erf_as(float x) {
+    const float ax = fabsf(x);
+    const float t = __builtin_amdgcn_rcpf(fmaf(0.3275911f, ax, 1.0f));
+    float q = fmaf(t, 1.061405429f, -1.453152027f);
+    q = fmaf(t, q, 1.421413741f);
+    q = fmaf(t, q, -0.284496736f);
+    q = fmaf(t, q, 0.254829592f);
+    return copysignf(1.0f - t * q * __expf(-ax * ax), x);
+}
+__device__ __forceinline__ float gelu(float x) { return 0.5f * x * (1.0f + erf_as(x * 0.70710678118654752f)); }
 __device__ __forceinline__ float gelu_grad(float x) {
-    return 0.5f * (1.0f + erff(x * 0.70710678118654752f)) + x * expf(-0.5f * x * x) * 0.39894228040143268f;
+    return 0.5f * (1.0f + erf_as(x * 0.70710678118654752f)) + x * __expf(-0.5f * x * x) * 0.39894228040143268f;
 }
 
 // ---------------------------------------------------------------------------
@@ -339,37 +356,84 @@ __global__ __launch_bounds__(256) void k_conv32(int nx, int ny, int nz, int cout
             }
         }
 
-        // epilogue: lane holds channel n = t*16 + lane%16 of cells x = 4g + i
+        // epilogue: lane holds channel n = t*16 + lane%16 of brick cells
+        // x = 4g + i, y = r, z = wave.  The results go through LDS (the
+        // brick's input is no longer needed) so that global stores are
+        // whole 16-byte pieces of consecutive cells instead of 2-byte
+        // scattered ones.
         const int x0 = (b % nbx) * BX, y0 = ((b / nbx) % nby) * BY, z0 = (b / (nbx * nby)) * BZ;
-        const int gz = z0 + wave;
+        __syncthreads();
+        // staging strides 80 and 144 bytes per cell: the four cell groups of
+        // a store instruction land on different banks, pieces stay aligned
+        constexpr int SH = CST, SF = 36;
+        static_assert(BX * BY * BZ * SF * 4 <= HCELLS * CST * 2, "staging fits the input tile");
+        uint16_t *st_h = sh_in;                              // [512 cells][SH] BF16
+        float *st_f = reinterpret_cast<float *>(sh_in);      // [512 cells][SF or 4] FP32
 #pragma unroll
         for (int r = 0; r < BY; r++) {
-            const int gy = y0 + r;
 #pragma unroll
             for (int i = 0; i < 4; i++) {
-                const int gx = x0 + 4 * g + i;
-                const bool ok = gx < nx && gy < ny && gz < nz;
-                const int64_t cell = gx + gy * sy + gz * sz;
+                const int cl = (wave * BY + r) * BX + 4 * g + i;
 #pragma unroll
                 for (int t = 0; t < NT; t++) {
                     const int n = t * 16 + xl;
                     const float y = acc[r][t][i];
                     if (MODE == 0) {
-                        if (ok) {
-                            const float v = y + bias[n];
-                            out_h[cell * 32 + n] = f2bf(gelu(v));
-                            if (out_f) out_f[cell * 32 + n] = v;
-                        }
+                        st_h[cl * SH + n] = f2bf(gelu(y + bias[n]));
                     } else if (MODE == 1) {
-                        if (ok && n < cout) out_f[cell * cout + n] = y + bias[n];
+                        if (n < 4) st_f[cl * 4 + n] = y + bias[n < cout ? n : 0];
                     } else {
-                        if (ok) {
-                            const float gv = y * gelu_grad(zprev[cell * 32 + n]);
-                            out_h[cell * 32 + n] = f2bf(gv);
-                            dbs[t] += gv;
-                        }
+                        const int gx = x0 + 4 * g + i, gy = y0 + r, gz = z0 + wave;
+                        float gv = 0.0f;
+                        if (gx < nx && gy < ny && gz < nz)
+                            gv = y * gelu_grad(zprev[(gx + gy * sy + gz * sz) * 32 + n]);
+                        st_h[cl * SH + n] = f2bf(gv);
+                        dbs[t] += gv;
                     }
                 }
+            }
+        }
+        __syncthreads();
+        if (MODE == 1) {
+            // one thread per cell: its cout (<= 4) values
+            for (int cl = tid; cl < BX * BY * BZ; cl += 256) {
+                const int gx = x0 + cl % BX, gy = y0 + (cl / BX) % BY, gz = z0 + cl / (BX * BY);
+                if (gx < nx && gy < ny && gz < nz) {
+                    const int64_t cell = gx + gy * sy + gz * sz;
+                    for (int c = 0; c < cout; c++) out_f[cell * cout + c] = st_f[cl * 4 + c];
+                }
+            }
+        } else {
+            // 16-byte pieces: piece q = cell * 4 + part, eight channels each
+            for (int q = tid; q < BX * BY * BZ * 4; q += 256) {
+                const int cl = q >> 2, part = q & 3;
+                const int gx = x0 + cl % BX, gy = y0 + (cl / BX) % BY, gz = z0 + cl / (BX * BY);
+                if (gx < nx && gy < ny && gz < nz)
+                    *reinterpret_cast<uint4 *>(out_h + (gx + gy * sy + gz * sz) * 32 + part * 8) =
+                        *reinterpret_cast<const uint4 *>(st_h + cl * SH + part * 8);
+            }
+        }
+        if (MODE == 0 && out_f) {
+            // pre-activations for training, in a second round through LDS
+            __syncthreads();
+#pragma unroll
+            for (int r = 0; r < BY; r++)
+#pragma unroll
+                for (int i = 0; i < 4; i++) {
+                    const int cl = (wave * BY + r) * BX + 4 * g + i;
+#pragma unroll
+                    for (int t = 0; t < NT; t++) {
+                        const int n = t * 16 + xl;
+                        st_f[cl * SF + n] = acc[r][t][i] + bias[n];
+                    }
+                }
+            __syncthreads();
+            for (int q = tid; q < BX * BY * BZ * 8; q += 256) {
+                const int cl = q >> 3, part = q & 7;
+                const int gx = x0 + cl % BX, gy = y0 + (cl / BX) % BY, gz = z0 + cl / (BX * BY);
+                if (gx < nx && gy < ny && gz < nz)
+                    *reinterpret_cast<float4 *>(out_f + (gx + gy * sy + gz * sz) * 32 + part * 4) =
+                        *reinterpret_cast<const float4 *>(st_f + cl * SF + part * 4);
             }
         }
     }
