@@ -331,9 +331,9 @@ __global__ __launch_bounds__(256) void k_conv32(int nx, int ny, int nz, int cout
         for (int r = 0; r < BY; r++)
 #pragma unroll
             for (int t = 0; t < NT; t++) acc[r][t] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
-#pragma unroll 1
+#pragma unroll
         for (int pz = 0; pz < 3; pz++) {
-#pragma unroll 1
+#pragma unroll
             for (int px = 0; px < 3; px++) {
                 const int hb = (wave + pz) * HY * HX + xl + px;
                 bf16x8 a[BY + 2];
