@@ -6,11 +6,14 @@ seeded input, in the launch configuration the benchmark times.
 The oracle cannot solve this system to 1e-8 within a test (about 3.6 s per
 GMRES iteration on one host core, some 2 000 iterations), so the checks
 are the whole SpMV (1e-12), one FP64 block ILU(0) apply (1e-10), one FP32
-CPR-PF apply against the oracle's FP32 emulation (1e-5), and a
+and one BF16-factor block ILU(0) apply and one FP32 CPR-PF apply against
+the oracle's emulation of the same rounding (1e-5, 1e-4, 1e-5), and a
 fixed-iteration prefix of plain GMRES(30) + BILU(0): one full restart cycle
 of 30 steps (the measurement plan names 60; 30 keeps the oracle's share
 of the test near two minutes), comparing the residual estimate after every
-step and the iterate x with the oracle's run of the same length."""
+step and the iterate x with the oracle's run of the same length.  The
+learned stage on FP32 CPR-PF is checked on the same grid for its fallback
+(a NaN network reproduces plain CPR-FGMRES bit for bit)."""
 import os
 
 import numpy as np
@@ -59,6 +62,23 @@ def test_256_bilu0_apply_f64(big):
     err = relerr(z, ref)
     print(f"256x256x128 BILU(0) FP64 apply: relerr {err:.2e}")
     assert err <= 1e-10
+
+
+@pytest.mark.parametrize("prec,name,tol", [(K.KRY_PREC_F32, "f32", 1e-5),
+                                           (K.KRY_PREC_BF16_FACTORS, "bf16", 1e-4)])
+def test_256_bilu0_apply_reduced(big, prec, name, tol):
+    # the mixed-precision variants' preconditioner at full size, against the
+    # oracle's emulation of the same rounding, and visibly not FP64
+    s, A, g = big
+    v = np.random.default_rng(34).standard_normal(A.n)
+    z = pc_apply(g, K.KRY_PC_BILU0, v, prec=prec)
+    ref = oracle.PC(A, "bilu0", name).apply(v)
+    ref64 = oracle.PC(A, "bilu0").apply(v)
+    err, err64 = relerr(z, ref), relerr(z, ref64)
+    print(f"256x256x128 BILU(0) {name} apply: relerr {err:.2e} against the oracle's {name}, "
+          f"{err64:.2e} against FP64")
+    assert err <= tol
+    assert err64 > 1e-9
 
 
 def test_256_cpr_pf_apply_f32(big):
