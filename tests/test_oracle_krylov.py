@@ -272,3 +272,26 @@ def test_pcg_reports_breakdown_on_indefinite_matrix():
     # b along the negative-curvature direction: (p, A p) < 0 at the first step
     got = oracle.pcg(A, oracle.PC(A, "none"), np.array([0.0, 1.0, 0.0, 0.0]), maxit=10, rtol=1e-12)
     assert got["status"] == oracle.ERR_BREAKDOWN
+
+
+def test_openmp_build_solves_like_the_serial_oracle():
+    # the OpenMP build times the CPU leg of the benchmark: its parallel sums
+    # round differently, so it must reach the same solve, not the same bits
+    import shutil
+    if shutil.which("gcc") is None:
+        pytest.skip("no gcc")
+    try:
+        lib_omp = oracle.load(oracle.build_omp(force=False))
+    except Exception as e:       # no OpenMP runtime in this toolchain
+        pytest.skip(f"OpenMP build unavailable: {e}")
+    s = ri.blackoil_system(16, 12, 10, seed=5)
+    A = oracle.Matrix.from_system(s)
+    ref = oracle.gmres(A, oracle.PC(A, "bilu0"), s["b"], restart=30, maxit=1000, rtol=1e-10)
+    with oracle.using(lib_omp):
+        A2 = oracle.Matrix.from_system(s)
+        got = oracle.gmres(A2, oracle.PC(A2, "bilu0"), s["b"], restart=30, maxit=1000, rtol=1e-10)
+    assert ref["status"] == got["status"] == 0
+    assert abs(got["iters"] - ref["iters"]) <= 1
+    assert np.linalg.norm(got["x"] - ref["x"]) <= 1e-8 * np.linalg.norm(ref["x"])
+    r = s["b"] - oracle.spmv(A, got["x"])
+    assert np.linalg.norm(r) <= 1e-10 * np.linalg.norm(s["b"]) * (1 + 1e-9)
