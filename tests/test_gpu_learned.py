@@ -56,7 +56,10 @@ def test_num_params():
     assert K.LearnedNumParams() == NP == oracle.conv_nparams()
 
 
-@pytest.mark.parametrize("grid", [(16, 8, 4), (20, 18, 9), (5, 3, 2)])
+# (17, 9, 260): 260 bricks of 16 x 8 x 4 cells, more than the 256 persistent
+# workgroups, so some workgroups take a second brick (the prefetched input
+# and, in the gradient, bias partials summed over bricks); partial bricks in x, y
+@pytest.mark.parametrize("grid", [(16, 8, 4), (20, 18, 9), (5, 3, 2), (17, 9, 260)])
 def test_forward_matches_oracle(grid):
     nx, ny, nz = grid
     cells = nx * ny * nz
@@ -106,7 +109,7 @@ def test_forward_delta_kernels_are_identity():
     assert np.array_equal(got, inp[:3 * cells])
 
 
-@pytest.mark.parametrize("grid", [(12, 10, 6), (17, 5, 3)])
+@pytest.mark.parametrize("grid", [(12, 10, 6), (17, 5, 3), (17, 9, 260)])
 def test_loss_gradient_matches_oracle(grid):
     nx, ny, nz = grid
     cells = nx * ny * nz
