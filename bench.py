@@ -156,15 +156,24 @@ def cgs2_step_bytes(n, nc):
     return (3 * nc + 5) * n * 8
 
 
-def cgs2_avg_bytes(n, iters, launches, restart=RESTART):
-    """Average algorithmic bytes per CGS2 step over a GMRES(restart) solve
-    of `iters` Arnoldi steps; steps issued past the converged one (at most
+def dcgs2_step_bytes(n, nc):
+    """Algorithmic bytes of one step of the lagged CGS2 against nc basis
+    columns (the last one the once-projected vector u): pass A reads them
+    and w, pass B reads them and w again and writes the final v_j and the
+    next once-projected vector (its norm fused): (2 nc + 4) n doubles."""
+    return (2 * nc + 4) * n * 8
+
+
+def cgs2_avg_bytes(n, iters, launches, restart=RESTART, step_bytes=cgs2_step_bytes):
+    """Average algorithmic bytes per Arnoldi step (CGS2, or with
+    step_bytes=dcgs2_step_bytes the lagged form) over a GMRES(restart)
+    solve of `iters` steps; steps issued past the converged one (at most
     one per solve) are counted with the next column count."""
     full, rem = divmod(iters, restart)
-    tot = full * sum(cgs2_step_bytes(n, c) for c in range(1, restart + 1))
-    tot += sum(cgs2_step_bytes(n, c) for c in range(1, rem + 1))
+    tot = full * sum(step_bytes(n, c) for c in range(1, restart + 1))
+    tot += sum(step_bytes(n, c) for c in range(1, rem + 1))
     extra = max(0, launches - iters)
-    tot += extra * cgs2_step_bytes(n, min(rem + 1, restart))
+    tot += extra * step_bytes(n, min(rem + 1, restart))
     return tot / max(1, launches)
 
 
@@ -456,7 +465,8 @@ def main():
     K.KernelTimingEnable(False)
     abytes = algorithmic_bytes(nb, nnzb)
     kernels = {}
-    for kname in list(abytes) + ["cgs2", "ilu_grid_untile", "ilu_grid_factor", "spmv_csr"]:
+    for kname in list(abytes) + ["cgs2", "dcgs2", "ilu_grid_untile",
+                                 "ilu_grid_factor", "spmv_csr"]:
         cnt, ms = K.KernelTimingQuery(kname)
         if cnt == 0:
             continue
@@ -464,6 +474,8 @@ def main():
         bpl = abytes.get(kname)
         if kname == "cgs2":
             bpl = int(cgs2_avg_bytes(n, prof["iters"], cnt))
+        elif kname == "dcgs2":
+            bpl = int(cgs2_avg_bytes(n, prof["iters"], cnt, step_bytes=dcgs2_step_bytes))
         if bpl:
             gbs = bpl / (ms / cnt * 1e-3) / 1e9
             ent.update(bytes_per_launch=bpl, gbs=round(gbs, 1), frac_hbm=round(gbs / HBM_PEAK_GBS, 4))

@@ -268,6 +268,17 @@ int SolverSetRASBoxes(SOLVER *s, int px, int py, int pz, int overlap);
  * fails with KRY_ERR_ARG if the matrix is not a 7-point grid stencil).
  * Both layouts apply the same factor. */
 int SolverSetSweepLayout(SOLVER *s, int layout);
+/* SolverSetOrthog: Gram-Schmidt of the Arnoldi step (Algorithm 1, whose
+ * modified Gram-Schmidt both kinds equal in exact arithmetic).
+ * KRY_ORTHO_AUTO (default): GMRES with a fixed preconditioner (not custom or
+ * learned, no augmentation, restart m <= 31) takes the lagged CGS2 (DCGS2)
+ * of Swirydowicz, Langou, Ananthan, Yang and Thomas (2020), two passes over
+ * V per step: each step's second projection is applied during the next
+ * step, whose residual estimate uses the once-projected column (it differs
+ * from the final one by rounding).  Every other solver, and KRY_ORTHO_CGS2,
+ * takes CGS2: three passes per step.  KRY_ERR_ARG for another kind. */
+enum { KRY_ORTHO_AUTO = 0, KRY_ORTHO_CGS2 = 1 };
+int SolverSetOrthog(SOLVER *s, int kind);
 int SolverSetStream(SOLVER *s, void *hip_stream);
 
 /* results (Figure 22: residual, nits) */

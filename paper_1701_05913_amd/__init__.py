@@ -38,6 +38,7 @@ KRY_CPR_PF, KRY_CPR_FP, KRY_CPR_FPF, KRY_CPR_FFPF = 0, 1, 2, 3
 KRY_CPR_P_ILU0, KRY_CPR_P_AMG = 0, 1
 KRY_CPR_F_BILU0, KRY_CPR_F_RAS = 0, 1
 KRY_SWEEP_AUTO, KRY_SWEEP_LEVELS, KRY_SWEEP_GRID = 0, 1, 2
+KRY_ORTHO_AUTO, KRY_ORTHO_CGS2 = 0, 1
 
 
 class KrylovError(RuntimeError):
@@ -91,6 +92,7 @@ _SIGS = {
     "SolverGetAMGLevels": (C.c_int, [P]),
     "SolverGetAMGLevel": (C.c_int, [P, C.c_int] + [C.POINTER(I32)] * 4 + [P] * 7),
     "SolverSetSweepLayout": (C.c_int, [P, C.c_int]),
+    "SolverSetOrthog": (C.c_int, [P, C.c_int]),
     "SolverSetStream": (C.c_int, [P, P]),
     "SolverGetResidual": (D, [P]), "SolverGetIters": (C.c_int, [P]),
     "SolverGetTimes": (C.c_int, [P, C.POINTER(D), C.POINTER(D)]),
@@ -356,6 +358,7 @@ def SolverGetAMGLevel(s, level):
     return dict(n=n, nc=nc, A=(rp, col[:nnz], val[:nnz]), cf=None if coarse else cf[:n],
                 P=None if coarse else (prp, pcol[:pnnz], pval[:pnnz]))
 def SolverSetSweepLayout(s, layout): return _check(_lib.SolverSetSweepLayout(s, layout))
+def SolverSetOrthog(s, kind): return _check(_lib.SolverSetOrthog(s, kind))
 
 
 def SolverSetStream(s, stream):

@@ -476,6 +476,7 @@ struct SOLVER_ {
     kry::AmgOpts amg_opts;
     std::unique_ptr<kry::AmgPC> amg;
     int sweep_layout = KRY_SWEEP_AUTO;
+    int ortho = KRY_ORTHO_AUTO;
     hipStream_t stream = nullptr;
     PC_SETUP csetup = nullptr;
     PC_SOLVE csolve = nullptr;

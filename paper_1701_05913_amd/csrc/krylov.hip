@@ -30,17 +30,22 @@
 namespace kry {
 
 constexpr int MAXCOL = 64;   // restart length limit (columns of V)
+constexpr int DCGS_MAXM = 31; // longest restart of the lagged Gram-Schmidt
 
 // slots of the small scalar area
 enum {
     SC_BETA = 0, SC_INVBETA, SC_HN, SC_INVHN, SC_EST, SC_BREAK,
     SC_RHO, SC_RHO0, SC_ALPHA, SC_OMEGA, SC_BETAB, SC_RV, SC_TT, SC_TS,
-    SC_SNORM, SC_RNORM, SC_FLAGS, SC_RHN, SC_NONE, SC_RENORM, SC_WN2, SC_COUNT = 32
+    SC_SNORM, SC_RNORM, SC_FLAGS, SC_RHN, SC_NONE, SC_RENORM, SC_WN2,
+    SC_ETA, SC_CU, SC_HH, SC_GSAVE, SC_COUNT = 32
 };
 
+// H holds the rotated columns (R); the lagged Gram-Schmidt also keeps the
+// unrotated final columns (Hu), the provisional column (hp), the update
+// coefficients of its second pass (sa, dv) and the sums of its first (ab)
 struct SmallLayout {
     int m;
-    size_t H, cs, sn, g, y, h1, h2, sc, total;
+    size_t H, cs, sn, g, y, h1, h2, sc, Hu, hp, sa, dv, ab, total;
     explicit SmallLayout(int m_) : m(m_) {
         H = 0;
         cs = H + (size_t)(m + 1) * m;
@@ -50,7 +55,12 @@ struct SmallLayout {
         h1 = y + m;
         h2 = h1 + MAXCOL;
         sc = h2 + MAXCOL;
-        total = sc + SC_COUNT;
+        Hu = sc + SC_COUNT;
+        hp = Hu + (size_t)(m + 1) * m;
+        sa = hp + MAXCOL + 1;
+        dv = sa + MAXCOL;
+        ab = dv + MAXCOL + 1;
+        total = ab + 2 * MAXCOL;
     }
 };
 
@@ -436,6 +446,257 @@ __global__ __launch_bounds__(1024) void k_arnoldi_finish(const double *__restric
     }
 }
 
+// ---------------------------------------------------------------------------
+// Lagged CGS2 for GMRES with a fixed preconditioner (DCGS2 of Swirydowicz,
+// Langou, Ananthan, Yang and Thomas, "Low synchronization Gram-Schmidt and
+// GMRES algorithms", 2020): the second projection of a step's new vector is
+// taken during the next step, in the same pass that projects that step's w,
+// so an Arnoldi step streams V twice instead of three times.
+//
+// Entering step j, columns 0..j-1 of V are final and column j holds u, the
+// once-projected vector of step j - 1 (norm eta, not normalized), with the
+// provisional Hessenberg column hp (unrotated, rows 0..j-1; h_{j,j-1} =
+// eta).  Column j + 1 holds w = A M^-1 u.
+//  pass A  a_k = v_k . u and b_k = v_k . w (k < j), u . u and u . w;
+//  finish  u / eta = V s + alpha v_j with s = a / eta and alpha^2 =
+//          u.u / eta^2 - |s|^2, so column j - 1 of H becomes hp + eta s with
+//          h_{j,j-1} = eta alpha (its rotation and g are final from here on).
+//          With A M^-1 V = V H over the final columns, the w of v_j is
+//          y = (w / eta - V H s) / alpha, and h_k = v_k . y follows from a,
+//          b and H alone;
+//  pass B  v_j = u / (eta alpha) - V s / alpha into column j and
+//          u' = w / (eta alpha) - V d - v_j d_j, d = H s / alpha + h, into
+//          column j + 1, row by row (v_j stays in registers), with |u'|^2;
+//  norm    eta' = |u'| (0 at the rounding level of the projection: a lucky
+//          breakdown); the provisional column h, h_{j+1,j} = eta' (which
+//          differs from the final one only by the O(eps) second projection
+//          the next step applies) is rotated into H with its Givens rotation,
+//          g and the residual estimate, g_j saved for the next finish.
+// A cycle's least-squares solve takes its last column in that provisional
+// form, and its last basis vector u / eta (normalized, projected once).  A
+// step whose alpha^2 keeps less than half of u.u / eta^2 (the
+// once-projected vector mostly in span V, which the breakdown floor of the
+// norm excludes) ends the cycle as a breakdown: every coefficient of the
+// step is zero.
+// ---------------------------------------------------------------------------
+
+// pass A: partials of v_k . u and v_k . w for the nc = j + 1 columns
+// k = 0..j of V (column j is u), in partial[b * MAXCOL + k] and
+// partial[b * MAXCOL + nc + k]; the LDS tiling of pass 2 with u's rows
+// staged beside w's
+template <int MAXC>
+__global__ __launch_bounds__(256) void k_dcgs_dots(int n, const double *__restrict__ V,
+                                                   int64_t ldv, int nc,
+                                                   const double *__restrict__ w,
+                                                   double *__restrict__ partial) {
+    constexpr int CPW = MAXC / 4;
+    __shared__ double tile[MAXC][CGS_CH];
+    __shared__ double tw[CGS_CH];
+    __shared__ double lds[2 * MAXC];
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int ju = nc - 1;
+    double au[CPW], aw[CPW];
+#pragma unroll
+    for (int c = 0; c < CPW; c++) au[c] = aw[c] = 0.0;
+    double pre[MAXC], wpre = 0.0;
+    const int stride = gridDim.x * CGS_CH;
+    auto load = [&](int b) {
+        const int r = b + threadIdx.x;
+        const bool ok = r < n;
+        wpre = ok ? w[r] : 0.0;
+#pragma unroll
+        for (int k = 0; k < MAXC; k++)
+            if (k < nc) pre[k] = ok ? V[k * ldv + r] : 0.0;
+    };
+    int base = blockIdx.x * CGS_CH;
+    if (base < n) load(base);
+    for (; base < n; base += stride) {
+#pragma unroll
+        for (int k = 0; k < MAXC; k++)
+            if (k < nc) tile[k][threadIdx.x] = pre[k];
+        tw[threadIdx.x] = wpre;
+        __syncthreads();
+        if (base + stride < n) load(base + stride);
+#pragma unroll
+        for (int c = 0; c < CPW; c++) {
+            const int k = wv * CPW + c;
+            if (k < nc) {
+#pragma unroll
+                for (int q = 0; q < CGS_CH / 64; q++) {
+                    const double x = tile[k][lane + 64 * q];
+                    au[c] += x * tile[ju][lane + 64 * q];
+                    aw[c] += x * tw[lane + 64 * q];
+                }
+            }
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int c = 0; c < CPW; c++) {
+        const double su = wave_sum(au[c]);
+        const double sw = wave_sum(aw[c]);
+        if (lane == 0) {
+            lds[wv * CPW + c] = su;
+            lds[MAXC + wv * CPW + c] = sw;
+        }
+    }
+    __syncthreads();
+    if ((int)threadIdx.x < nc) {
+        partial[(size_t)blockIdx.x * MAXCOL + threadIdx.x] = lds[threadIdx.x];
+        partial[(size_t)blockIdx.x * MAXCOL + nc + threadIdx.x] = lds[MAXC + threadIdx.x];
+    }
+}
+
+// pass B: column j = cu u - V sa and column j + 1 = cu w - V d - v_j d_j,
+// with its partial |.|^2 in partial[b * MAXCOL]; sa over the j final
+// columns, d over j + 1 values, cu = 1 / (eta alpha)
+template <int MAXC>
+__global__ __launch_bounds__(256) void k_dcgs_update(int n, double *V, int64_t ldv, int j,
+                                                     const double *__restrict__ sa,
+                                                     const double *__restrict__ dv,
+                                                     const double *__restrict__ cu_p,
+                                                     double *__restrict__ partial) {
+    __shared__ double ss[MAXC], ds[MAXC];
+    __shared__ double red[4];
+    if (threadIdx.x < MAXC) {
+        ss[threadIdx.x] = (int)threadIdx.x < j ? sa[threadIdx.x] : 0.0;
+        ds[threadIdx.x] = (int)threadIdx.x <= j ? dv[threadIdx.x] : 0.0;
+    }
+    __syncthreads();
+    const double cu = *cu_p, dj = ds[j];
+    double *u = V + (int64_t)j * ldv;
+    double *w = u + ldv;
+    double nacc = 0.0;
+    const int nq = n / CGS_ROWS;
+    for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < nq; q += gridDim.x * blockDim.x) {
+        const unsigned off = (unsigned)q * CGS_ROWS;
+        double2 v0 = *reinterpret_cast<const double2 *>(u + off);
+        double2 v1 = *reinterpret_cast<const double2 *>(u + off + 2);
+        double2 t0 = *reinterpret_cast<const double2 *>(w + off);
+        double2 t1 = *reinterpret_cast<const double2 *>(w + off + 2);
+        v0.x *= cu;
+        v0.y *= cu;
+        v1.x *= cu;
+        v1.y *= cu;
+        t0.x *= cu;
+        t0.y *= cu;
+        t1.x *= cu;
+        t1.y *= cu;
+#pragma unroll
+        for (int k = 0; k < MAXC; k++)
+            if (k < j) {
+                const double2 *col = reinterpret_cast<const double2 *>(V + k * ldv + off);
+                const double2 a = col[0], b = col[1];
+                v0.x -= a.x * ss[k];
+                v0.y -= a.y * ss[k];
+                v1.x -= b.x * ss[k];
+                v1.y -= b.y * ss[k];
+                t0.x -= a.x * ds[k];
+                t0.y -= a.y * ds[k];
+                t1.x -= b.x * ds[k];
+                t1.y -= b.y * ds[k];
+            }
+        t0.x -= v0.x * dj;
+        t0.y -= v0.y * dj;
+        t1.x -= v1.x * dj;
+        t1.y -= v1.y * dj;
+        *reinterpret_cast<double2 *>(u + off) = v0;
+        *reinterpret_cast<double2 *>(u + off + 2) = v1;
+        *reinterpret_cast<double2 *>(w + off) = t0;
+        *reinterpret_cast<double2 *>(w + off + 2) = t1;
+        nacc += t0.x * t0.x + t0.y * t0.y + t1.x * t1.x + t1.y * t1.y;
+    }
+    if (blockIdx.x == 0 && (int)threadIdx.x < n - nq * CGS_ROWS) {
+        const int r = nq * CGS_ROWS + threadIdx.x;
+        double v = u[r] * cu, t = w[r] * cu;
+#pragma unroll
+        for (int k = 0; k < MAXC; k++)
+            if (k < j) {
+                const double a = V[k * ldv + r];
+                v -= a * ss[k];
+                t -= a * ds[k];
+            }
+        t -= v * dj;
+        u[r] = v;
+        w[r] = t;
+        nacc += t * t;
+    }
+    nacc = block_sum<256>(nacc, red);
+    if (threadIdx.x == 0) partial[(size_t)blockIdx.x * MAXCOL] = nacc;
+}
+
+// finish of step j (one thread) from pass A's sums ab = [a_0..a_j, b_0..b_j]:
+// column j - 1 of H made final (unrotated into Hu, rotated into H, with its
+// Givens rotation and g, replacing its provisional form), the coefficients
+// sa, cu of v_j, the provisional column j (hp) and d of u'
+__global__ void k_dcgs_finish(int j, int m, double *small, SmallLayout L) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    double *sc = small + L.sc, *Hu = small + L.Hu, *hp = small + L.hp;
+    double *sa = small + L.sa, *dv = small + L.dv;
+    const double *a = small + L.ab, *b = a + (j + 1);
+    const double eta = sc[SC_ETA];
+    double s[MAXCOL], col[MAXCOL + 1];
+    bool ok = eta > 0.0 && isfinite(eta);
+    double ss = 0.0;
+    for (int k = 0; k < j; k++) {
+        s[k] = ok ? a[k] / eta : 0.0;
+        ss += s[k] * s[k];
+    }
+    const double sig = ok ? a[j] / (eta * eta) : 0.0;
+    const double al2 = sig - ss;
+    ok = ok && isfinite(al2) && al2 > 0.5 * sig;
+    const double al = ok ? sqrt(al2) : 0.0;
+    if (!ok)
+        for (int k = 0; k < j; k++) s[k] = 0.0;
+    if (j >= 1) {
+        for (int k = 0; k < j; k++) col[k] = hp[k] + (ok ? eta * s[k] : 0.0);
+        col[j] = ok ? eta * al : 0.0;
+        for (int k = 0; k <= j; k++) Hu[(size_t)(j - 1) * (m + 1) + k] = col[k];
+        small[L.g + j - 1] = sc[SC_GSAVE];   // g_{j-1} before the provisional rotation
+        arnoldi_column(small, L, j - 1, m, col, small + L.cs, small + L.sn, col[j]);
+    }
+    sc[SC_CU] = ok ? 1.0 / (eta * al) : 0.0;
+    for (int k = 0; k < j; k++) sa[k] = ok ? s[k] / al : 0.0;
+    if (!ok) {
+        for (int k = 0; k <= j; k++) hp[k] = dv[k] = 0.0;
+        sc[SC_HH] = 0.0;
+        return;
+    }
+    double sb = 0.0;
+    for (int k = 0; k < j; k++) sb += s[k] * b[k];
+    const double bwj = (b[j] / eta - sb) / al;   // v_j . w
+    double hh = 0.0;
+    for (int i = 0; i <= j; i++) {
+        double hs = 0.0;   // (H s)_i over the final columns k >= i - 1
+        for (int k = i > 0 ? i - 1 : 0; k < j; k++) hs += Hu[(size_t)k * (m + 1) + i] * s[k];
+        const double h = ((i < j ? b[i] : bwj) / eta - hs) / al;
+        hp[i] = h;
+        dv[i] = hs / al + h;
+        hh += h * h;
+    }
+    sc[SC_HH] = hh;
+}
+
+// norm of step j: eta' from pass B's partials (fixed order), then the
+// provisional column j rotated into H (rotation j, g, residual estimate,
+// h_{j+1,j} and its inverse in the step's scalars), g_j saved first
+__global__ __launch_bounds__(256) void k_dcgs_norm(const double *__restrict__ partial, int nblocks,
+                                                   int j, int m, double *small, SmallLayout L) {
+    __shared__ double red[4];
+    double s = 0.0;
+    for (int b = threadIdx.x; b < nblocks; b += 256) s += partial[(size_t)b * MAXCOL];
+    s = block_sum<256>(s, red);
+    if (threadIdx.x != 0) return;
+    double *sc = small + L.sc;
+    double eta = sqrt(s);
+    if (eta <= 8.0 * DBL_EPSILON * (j + 2) * sqrt(sc[SC_HH] + s)) eta = 0.0;
+    sc[SC_ETA] = eta;
+    sc[SC_GSAVE] = small[L.g + j];
+    double col[MAXCOL + 1];
+    for (int k = 0; k <= j; k++) col[k] = small[L.hp + k];
+    arnoldi_column(small, L, j, m, col, small + L.cs, small + L.sn, eta);
+}
+
 // g = beta e_1 and the first basis vector scale factor
 __global__ void k_cycle_start(double *small, SmallLayout L) {
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
@@ -444,6 +705,7 @@ __global__ void k_cycle_start(double *small, SmallLayout L) {
     for (int k = 0; k <= L.m; k++) g[k] = 0.0;
     g[0] = beta;
     sc[SC_INVBETA] = beta != 0.0 ? 1.0 / beta : 0.0;
+    sc[SC_ETA] = 1.0;   // the lagged Gram-Schmidt's v_0 = r / beta
 }
 
 // R y = g(0:jend) by back substitution
@@ -746,6 +1008,36 @@ static int cgs2_step(SOLVER_ *S, int j, double *w) {
     return KRY_OK;
 }
 
+// one step of the lagged Gram-Schmidt
+template <int MAXC>
+static void launch_dcgs(hipStream_t st, int n, double *V, int64_t ldv, int j, double *small,
+                        SmallLayout L, double *partial, int m) {
+    const dim3 b(256);
+    const int ga = MAXC == 16 ? 1024 : 512, gb = 512;
+    static_assert(2 * MAXC <= MAXCOL, "pass A's sums of a block fit one partial row");
+    const int nc = j + 1;
+    double *u = V + (int64_t)j * ldv;
+    hipLaunchKernelGGL(k_dcgs_dots<MAXC>, dim3(ga), b, 0, st, n, V, ldv, nc, u + ldv, partial);
+    hipLaunchKernelGGL((k_sum_cols<2 * MAXC, 1024>), dim3(1), dim3(1024), 0, st, partial, ga,
+                       2 * nc, small + L.ab);
+    hipLaunchKernelGGL(k_dcgs_finish, dim3(1), dim3(64), 0, st, j, m, small, L);
+    hipLaunchKernelGGL(k_dcgs_update<MAXC>, dim3(gb), b, 0, st, n, V, ldv, j,
+                       small + L.sa, small + L.dv, small + L.sc + SC_CU, partial);
+    hipLaunchKernelGGL(k_dcgs_norm, dim3(1), b, 0, st, partial, gb, j, m, small, L);
+}
+
+static int dcgs_step(SOLVER_ *S, int j) {
+    const int n = S->A->nb * S->A->bs;
+    const SmallLayout L = layout_of(S);
+    TimedScope ts("dcgs2", S->stream);
+    double *sm = S->small.p, *pt = S->partial.p;
+    if (j + 1 <= 8) launch_dcgs<8>(S->stream, n, S->V.p, S->ldv, j, sm, L, pt, L.m);
+    else if (j + 1 <= 16) launch_dcgs<16>(S->stream, n, S->V.p, S->ldv, j, sm, L, pt, L.m);
+    else launch_dcgs<32>(S->stream, n, S->V.p, S->ldv, j, sm, L, pt, L.m);
+    KRY_HIP(hipGetLastError());
+    return KRY_OK;
+}
+
 static int gemvn_acc(SOLVER_ *S, const double *Z, int nc, const double *y, double beta, double *x) {
     const int64_t n = (int64_t)S->A->nb * S->A->bs;
     const dim3 g(2048), b(256);
@@ -858,6 +1150,10 @@ static int gmres_solve(SOLVER_ *S, const double *b, double *x) {
     // unless the preconditioner calls back into host code or counts its uses
     const bool speculate = S->pc_type != KRY_PC_CUSTOM && S->pc_type != KRY_PC_BILU0_LEARNED &&
                            S->pc_type != KRY_PC_CPR_LEARNED;
+    // the lagged Gram-Schmidt needs A M^-1 to be one linear operator over the
+    // cycle: a fixed preconditioner, no stored Z, no augmentation
+    const bool lagged = S->ortho != KRY_ORTHO_CGS2 && speculate && !flexible && k == 0 &&
+                        m <= DCGS_MAXM;
     for (;;) {
         double beta = 0.0;
         KRY_TRY(true_residual(S, b, x, S->V.p, &beta));
@@ -868,7 +1164,7 @@ static int gmres_solve(SOLVER_ *S, const double *b, double *x) {
         if (nits >= S->maxit) break;
         hipLaunchKernelGGL(k_cycle_start, dim3(1), dim3(64), 0, S->stream, small, L);
         KRY_TRY(vec_scale_copy(S->stream, n, dc(sc + SC_INVBETA), S->V.p, S->V.p));
-        int jend = 0;
+        int jend = 0, last = -1;
         const int steps = m + nstored;
         // step j: z_j = M^-1 v_j (or the stored correction), w = A z_j, CGS2
         // against v_0..v_j with the Hessenberg column and Givens update and
@@ -890,7 +1186,9 @@ static int gmres_solve(SOLVER_ *S, const double *b, double *x) {
                 KRY_HIP(hipMemcpyAsync(zj, S->AUG.p + (size_t)((head + j - m) % k) * S->ldv,
                                        sizeof(double) * n, hipMemcpyDeviceToDevice, S->stream));
             KRY_TRY(spmv_f64(S->stream, S->A, 1.0, zj, 0.0, nullptr, w, 0, nullptr, nullptr, nullptr));
-            KRY_TRY(cgs2_step(S, j, w));
+            if (lagged) KRY_TRY(dcgs_step(S, j));
+            else KRY_TRY(cgs2_step(S, j, w));
+            last = j;
             KRY_HIP(hipMemcpyAsync(S->h_pinned + 8 + 8 * (j & 1), sc + SC_HN, 3 * sizeof(double),
                                    hipMemcpyDeviceToHost, S->stream));
             KRY_HIP(hipEventRecord(S->step_ev[j & 1], S->stream));
@@ -910,6 +1208,13 @@ static int gmres_solve(SOLVER_ *S, const double *b, double *x) {
             if (hn == 0.0) break;                         // lucky breakdown
             if (est <= tol) break;
             if (!ahead && j + 1 < steps) KRY_TRY(issue(j + 1));
+        }
+        // unless step jend was issued ahead, the lagged Gram-Schmidt left
+        // column jend - 1 of H provisional (the least-squares solve takes it
+        // as it is) and column jend of V once projected: normalize it
+        if (lagged && last < jend) {
+            double *vj = S->V.p + (size_t)jend * S->ldv;
+            KRY_TRY(vec_scale_copy(S->stream, n, dc(sc + SC_INVHN), vj, vj));
         }
         hipLaunchKernelGGL(k_ls_solve, dim3(1), dim3(64), 0, S->stream, small, L, jend);
         if (k > 0) {
@@ -1257,6 +1562,13 @@ extern "C" int SolverSetSweepLayout(SOLVER *s, int layout) {
         return set_error(KRY_ERR_ARG, "SolverSetSweepLayout: bad argument");
     s->sweep_layout = layout;
     s->assembled = false;
+    return KRY_OK;
+}
+
+extern "C" int SolverSetOrthog(SOLVER *s, int kind) {
+    if (!s || (kind != KRY_ORTHO_AUTO && kind != KRY_ORTHO_CGS2))
+        return set_error(KRY_ERR_ARG, "SolverSetOrthog: bad argument");
+    s->ortho = kind;
     return KRY_OK;
 }
 

@@ -44,9 +44,11 @@ class GpuSystem:
 
 def make_solver(g, solver, pc, rtol=1e-8, maxit=5000, restart=30, atol=0.0,
                 prec=K.KRY_PREC_F64, cpr=(K.KRY_CPR_PF, 4), layout=K.KRY_SWEEP_AUTO, aug_k=0,
-                ras=(4, 1), amg=(8, 2, 4), cpr_p=K.KRY_CPR_P_ILU0, cpr_f=K.KRY_CPR_F_BILU0):
+                ras=(4, 1), amg=(8, 2, 4), cpr_p=K.KRY_CPR_P_ILU0, cpr_f=K.KRY_CPR_F_BILU0,
+                ortho=K.KRY_ORTHO_AUTO):
     S = K.SolverCreate(solver, pc, g.map)
     K.SolverSetSweepLayout(S, layout)
+    K.SolverSetOrthog(S, ortho)
     K.SolverSetMat(S, g.A)
     K.SolverSetRtol(S, rtol)
     K.SolverSetAtol(S, atol)

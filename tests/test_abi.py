@@ -74,6 +74,9 @@ def test_host_side_argument_errors_without_gpu():
         K.SolverSetCPRPressure(s, 2)
     with pytest.raises(K.KrylovError):
         K.SolverSetCPRFull(s, 2)
+    with pytest.raises(K.KrylovError):
+        K.SolverSetOrthog(s, 2)                  # neither AUTO nor CGS2
+    K.SolverSetOrthog(s, K.KRY_ORTHO_CGS2)
     K.SolverSetRASBoxes(s, 2, 2, 2, 1)
     K.SolverSetAMG(s, 6, 1, 8)
     K.SolverSetCPRPressure(s, K.KRY_CPR_P_AMG)

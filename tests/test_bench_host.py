@@ -64,6 +64,19 @@ def test_cgs2_average_matches_a_step_by_step_count():
                                                                                  rel=1e-15)
 
 
+def test_lagged_cgs2_average_matches_a_step_by_step_count():
+    n, restart = 1000, 30
+    for iters, launches in [(1, 1), (29, 30), (30, 30), (61, 62), (2044, 2045)]:
+        tot = 0
+        for j in range(launches):
+            nc = min(j % restart + 1, restart) if j < iters else min(iters % restart + 1, restart)
+            # pass A reads the nc columns (u the last) and w; pass B reads
+            # them and w again and writes v_j and the next vector
+            tot += ((nc + 1) + (nc + 1 + 2)) * n * 8
+        avg = bench.cgs2_avg_bytes(n, iters, launches, restart, step_bytes=bench.dcgs2_step_bytes)
+        assert avg == pytest.approx(tot / launches, rel=1e-15)
+
+
 def test_traffic_lookup_requires_the_profiled_source(tmp_path, monkeypatch):
     src = tmp_path / "kernel.hip"
     src.write_text("// kernel v1\n")

@@ -1,11 +1,14 @@
-"""GPU pins of the CGS2 Arnoldi step (Algorithm 1's Arnoldi process, with
-classical Gram-Schmidt applied twice in place of modified Gram-Schmidt):
-orthonormality of the basis after a full restart cycle, termination in
+"""GPU pins of the Arnoldi step (Algorithm 1's Arnoldi process, with
+classical Gram-Schmidt applied twice in place of modified Gram-Schmidt:
+CGS2, or for GMRES with a fixed preconditioner its lagged form, whose
+second projection of a step's vector runs in the next step's pass):
+orthonormality of the basis after a full restart cycle for both forms, the
+two forms against each other on a 64^3 black-oil solve, termination in
 k + 1 steps on identity plus rank k, and one-step lucky breakdowns on
 eigenvectors: one where h_{2,1} is rounding noise of the product A v_1,
 and one (A = 4 I) where what the first projection leaves is a rounding
-multiple of v_1, the case in which h_{j+1,j} is taken as an explicit norm
-and a norm at the rounding level of two projections counts as zero."""
+multiple of v_1, the case in which CGS2 takes h_{j+1,j} as an explicit
+norm and a norm at the rounding level of the projections counts as zero."""
 import numpy as np
 import pytest
 
@@ -35,14 +38,16 @@ def _csr(dense):
                 val=np.array(va), bs=1)
 
 
-@pytest.mark.parametrize("solver", ["GMRES", "FGMRES"])
-def test_basis_orthonormal_after_full_cycle_blackoil64(solver):
+@pytest.mark.parametrize("solver,ortho", [("GMRES", "AUTO"), ("GMRES", "CGS2"), ("FGMRES", "AUTO")])
+def test_basis_orthonormal_after_full_cycle_blackoil64(solver, ortho):
     # 64^3 black-oil system, BILU(0), one full cycle of 30 steps (rtol 0):
     # columns 1..30 of V (column 0 holds the next cycle's residual) must be
-    # orthonormal to 1e-12, and every column must be a unit vector
+    # orthonormal to 1e-12, and every column must be a unit vector (GMRES
+    # AUTO: the lagged form, whose end-of-cycle pass normalizes v_30)
     s = ri.blackoil_system(64, 64, 64, seed=0)
     g = GpuSystem(s)
-    S = make_solver(g, getattr(K, f"KRY_{solver}"), K.KRY_PC_BILU0, rtol=0.0, maxit=30)
+    S = make_solver(g, getattr(K, f"KRY_{solver}"), K.KRY_PC_BILU0, rtol=0.0, maxit=30,
+                    ortho=getattr(K, f"KRY_ORTHO_{ortho}"))
     try:
         K.SolverAssemble(S)
         bt, bh = g.vec(s["b"])
@@ -58,6 +63,34 @@ def test_basis_orthonormal_after_full_cycle_blackoil64(solver):
     err = np.abs(G - np.eye(30)).max()
     print(f"max |V^T V - I| over 30 columns: {err:.2e}")
     assert err <= 1e-12
+
+
+@pytest.mark.parametrize("restart", [30, 7])
+def test_lagged_gram_schmidt_agrees_with_cgs2_blackoil64(restart):
+    # GMRES(m) + BILU(0) to 1e-8 on the 64^3 black-oil system with both
+    # forms: the same iteration count, residual estimates equal step by step
+    # to 1e-13 of the initial residual (and 1e-6 of each), iterates to 1e-8
+    # (both are Algorithm 1 in exact arithmetic and differ by rounding,
+    # which restarts carry from cycle to cycle; m = 7 ends many cycles, each
+    # with the lagged form's end-of-cycle pass)
+    s = ri.blackoil_system(64, 64, 64, seed=0)
+    g = GpuSystem(s)
+    try:
+        lag = solve(g, K.KRY_GMRES, K.KRY_PC_BILU0, rtol=1e-8, maxit=3000, restart=restart)
+        cgs = solve(g, K.KRY_GMRES, K.KRY_PC_BILU0, rtol=1e-8, maxit=3000, restart=restart,
+                    ortho=K.KRY_ORTHO_CGS2)
+    finally:
+        g.close()
+    print(f"m={restart}: lagged {lag['iters']} its, relres {lag['relres']:.3e}; "
+          f"CGS2 {cgs['iters']} its, relres {cgs['relres']:.3e}")
+    assert lag["status"] == K.KRY_OK and cgs["status"] == K.KRY_OK
+    assert lag["iters"] == cgs["iters"]
+    hl, hc = np.asarray(lag["hist"]), np.asarray(cgs["hist"])
+    assert hl.shape == hc.shape
+    assert np.max(np.abs(hl - hc)) <= 1e-13 * hc[0]
+    assert np.max(np.abs(hl - hc) / hc) <= 1e-6
+    assert relerr(lag["x"], cgs["x"]) <= 1e-8
+    assert lag["relres"] <= 1e-8
 
 
 def test_identity_plus_rank3_converges_in_four_steps():
