@@ -625,56 +625,62 @@ __global__ __launch_bounds__(256) void k_dcgs_update(int n, double *V, int64_t l
     if (threadIdx.x == 0) partial[(size_t)blockIdx.x * MAXCOL] = nacc;
 }
 
-// finish of step j (one thread) from pass A's sums ab = [a_0..a_j, b_0..b_j]:
-// column j - 1 of H made final (unrotated into Hu, rotated into H, with its
-// Givens rotation and g, replacing its provisional form), the coefficients
-// sa, cu of v_j, the provisional column j (hp) and d of u'
-__global__ void k_dcgs_finish(int j, int m, double *small, SmallLayout L) {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+// finish of step j (one wavefront) from pass A's sums ab = [a_0..a_j,
+// b_0..b_j]: column j - 1 of H made final (unrotated into Hu, rotated into
+// H, with its Givens rotation and g, replacing its provisional form), the
+// coefficients sa, cu of v_j, the provisional column j (hp) and d of u'.
+// Lane k holds the k-th entries (j <= 31 < 64); the rotations run on lane 0
+// over LDS copies.
+__global__ __launch_bounds__(64) void k_dcgs_finish(int j, int m, double *small, SmallLayout L) {
+    __shared__ double col[MAXCOL + 1], cs[MAXCOL], sn[MAXCOL], sh[MAXCOL];
+    const int k = threadIdx.x;
     double *sc = small + L.sc, *Hu = small + L.Hu, *hp = small + L.hp;
-    double *sa = small + L.sa, *dv = small + L.dv;
     const double *a = small + L.ab, *b = a + (j + 1);
     const double eta = sc[SC_ETA];
-    double s[MAXCOL], col[MAXCOL + 1];
-    bool ok = eta > 0.0 && isfinite(eta);
-    double ss = 0.0;
-    for (int k = 0; k < j; k++) {
-        s[k] = ok ? a[k] / eta : 0.0;
-        ss += s[k] * s[k];
-    }
-    const double sig = ok ? a[j] / (eta * eta) : 0.0;
+    const bool eok = eta > 0.0 && isfinite(eta);
+    const double sk = eok && k < j ? a[k] / eta : 0.0;
+    const double ss = wave_sum(sk * sk);
+    const double sig = eok ? a[j] / (eta * eta) : 0.0;
     const double al2 = sig - ss;
-    ok = ok && isfinite(al2) && al2 > 0.5 * sig;
+    const bool ok = eok && isfinite(al2) && al2 > 0.5 * sig;
     const double al = ok ? sqrt(al2) : 0.0;
-    if (!ok)
-        for (int k = 0; k < j; k++) s[k] = 0.0;
-    if (j >= 1) {
-        for (int k = 0; k < j; k++) col[k] = hp[k] + (ok ? eta * s[k] : 0.0);
-        col[j] = ok ? eta * al : 0.0;
-        for (int k = 0; k <= j; k++) Hu[(size_t)(j - 1) * (m + 1) + k] = col[k];
-        small[L.g + j - 1] = sc[SC_GSAVE];   // g_{j-1} before the provisional rotation
-        arnoldi_column(small, L, j - 1, m, col, small + L.cs, small + L.sn, col[j]);
+    const double s_k = ok ? sk : 0.0;
+    if (k < j) {
+        sh[k] = s_k;
+        cs[k] = small[L.cs + k];
+        sn[k] = small[L.sn + k];
     }
-    sc[SC_CU] = ok ? 1.0 / (eta * al) : 0.0;
-    for (int k = 0; k < j; k++) sa[k] = ok ? s[k] / al : 0.0;
+    if (j >= 1) {
+        if (k < j) col[k] = hp[k] + (ok ? eta * s_k : 0.0);
+        if (k == j) col[j] = ok ? eta * al : 0.0;
+        __syncthreads();
+        if (k <= j) Hu[(size_t)(j - 1) * (m + 1) + k] = col[k];
+        __syncthreads();
+        if (k == 0) {
+            small[L.g + j - 1] = sc[SC_GSAVE];   // g_{j-1} before the provisional rotation
+            arnoldi_column(small, L, j - 1, m, col, cs, sn, col[j]);
+        }
+    }
+    __syncthreads();
+    if (k == 0) sc[SC_CU] = ok ? 1.0 / (eta * al) : 0.0;
+    if (k < j) small[L.sa + k] = ok ? s_k / al : 0.0;
     if (!ok) {
-        for (int k = 0; k <= j; k++) hp[k] = dv[k] = 0.0;
-        sc[SC_HH] = 0.0;
+        if (k <= j) small[L.hp + k] = small[L.dv + k] = 0.0;
+        if (k == 0) sc[SC_HH] = 0.0;
         return;
     }
-    double sb = 0.0;
-    for (int k = 0; k < j; k++) sb += s[k] * b[k];
+    const double sb = wave_sum(k < j ? s_k * b[k] : 0.0);
     const double bwj = (b[j] / eta - sb) / al;   // v_j . w
-    double hh = 0.0;
-    for (int i = 0; i <= j; i++) {
-        double hs = 0.0;   // (H s)_i over the final columns k >= i - 1
-        for (int k = i > 0 ? i - 1 : 0; k < j; k++) hs += Hu[(size_t)k * (m + 1) + i] * s[k];
-        const double h = ((i < j ? b[i] : bwj) / eta - hs) / al;
-        hp[i] = h;
-        dv[i] = hs / al + h;
-        hh += h * h;
+    double h = 0.0;
+    if (k <= j) {
+        double hs = 0.0;   // (H s)_k over the final columns q >= k - 1
+        for (int q = k > 0 ? k - 1 : 0; q < j; q++) hs += Hu[(size_t)q * (m + 1) + k] * sh[q];
+        h = ((k < j ? b[k] : bwj) / eta - hs) / al;
+        small[L.hp + k] = h;
+        small[L.dv + k] = hs / al + h;
     }
-    sc[SC_HH] = hh;
+    const double hh = wave_sum(h * h);
+    if (k == 0) sc[SC_HH] = hh;
 }
 
 // norm of step j: eta' from pass B's partials (fixed order), then the
@@ -683,8 +689,14 @@ __global__ void k_dcgs_finish(int j, int m, double *small, SmallLayout L) {
 __global__ __launch_bounds__(256) void k_dcgs_norm(const double *__restrict__ partial, int nblocks,
                                                    int j, int m, double *small, SmallLayout L) {
     __shared__ double red[4];
+    __shared__ double col[MAXCOL + 1], cs[MAXCOL], sn[MAXCOL];
     double s = 0.0;
     for (int b = threadIdx.x; b < nblocks; b += 256) s += partial[(size_t)b * MAXCOL];
+    if ((int)threadIdx.x <= j) col[threadIdx.x] = small[L.hp + threadIdx.x];
+    if ((int)threadIdx.x < j) {
+        cs[threadIdx.x] = small[L.cs + threadIdx.x];
+        sn[threadIdx.x] = small[L.sn + threadIdx.x];
+    }
     s = block_sum<256>(s, red);
     if (threadIdx.x != 0) return;
     double *sc = small + L.sc;
@@ -692,9 +704,7 @@ __global__ __launch_bounds__(256) void k_dcgs_norm(const double *__restrict__ pa
     if (eta <= 8.0 * DBL_EPSILON * (j + 2) * sqrt(sc[SC_HH] + s)) eta = 0.0;
     sc[SC_ETA] = eta;
     sc[SC_GSAVE] = small[L.g + j];
-    double col[MAXCOL + 1];
-    for (int k = 0; k <= j; k++) col[k] = small[L.hp + k];
-    arnoldi_column(small, L, j, m, col, small + L.cs, small + L.sn, eta);
+    arnoldi_column(small, L, j, m, col, cs, sn, eta);
 }
 
 // g = beta e_1 and the first basis vector scale factor
