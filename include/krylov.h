@@ -378,13 +378,16 @@ int LearnedLoad(LEARNED *L, const char *path);
 
 /* ---- per-kernel timing (measurement only) ----------------------------------
  * When enabled, the library brackets every launch of the kernels it times
- * (SpMV, ILU sweeps, CGS2 passes) with HIP events on the launch stream.
+ * (SpMV, ILU sweeps, Gram-Schmidt passes) with HIP events on the launch
+ * stream.
  * KernelTimingQuery synchronizes and returns the launch count and the
  * summed duration in milliseconds of the named kernel family: "spmv_bsr3"
  * and "spmv_csr" (FP64 SpMV), "ilu_fwd_<fmt>_<prec>" and
  * "ilu_bwd_<fmt>_<prec>" (forward / backward sweep, fmt = bsr3 or csr,
- * prec = f64, f32 or bf16 factor storage), "cgs2" (one orthogonalization
- * step: both Gram-Schmidt passes, the norm and the Givens update),
+ * prec = f64, f32 or bf16 factor storage), "cgs2" (one CGS2
+ * orthogonalization step: both Gram-Schmidt passes, the norm and the Givens
+ * update), "dcgs2" (one step of the lagged CGS2: its two passes, the
+ * finish of the previous Hessenberg column, the norm and the estimate),
  * "learned_stage" (one learned-stage apply after the base preconditioner),
  * "conv_l<k>_fwd" (layer k of the network), "conv_wgrad", "conv_dgrad"
  * (weight and input gradients).  Each event adds a few microseconds
