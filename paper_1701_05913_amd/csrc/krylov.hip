@@ -18,6 +18,8 @@
 // its norm taken explicitly, and a follow-up kernel scales it.  All scalars (Hessenberg column,
 // Givens rotations, residual estimate) stay in device memory; the host
 // reads back one estimate per step, which is the only per-step sync.
+// GMRES with a fixed preconditioner takes the lagged form of CGS2 instead
+// (two passes over V per step; see its kernels below).
 // Reductions use fixed grids and fixed summation order, so two runs give
 // bitwise identical iterates.
 #include <cfloat>
@@ -31,6 +33,8 @@ namespace kry {
 
 constexpr int MAXCOL = 64;   // restart length limit (columns of V)
 constexpr int DCGS_MAXM = 31; // longest restart of the lagged Gram-Schmidt
+static_assert(DCGS_MAXM < 64, "the lagged finish holds one column entry per lane of a wavefront");
+static_assert(2 * (DCGS_MAXM + 1) <= MAXCOL, "pass A's sums of a block fit one partial row");
 
 // slots of the small scalar area
 enum {
