@@ -580,6 +580,8 @@ def main():
         "config": {"workload": f"{args.workload}: {wl['desc']}; GMRES(30) + block ILU(0), "
                                f"FP64, rtol {args.rtol:g}, x0 = 0",
                    "headline": HEADLINE, "rtol": args.rtol, "restart": RESTART,
+                   "orthogonalization": "lagged CGS2 (two passes over the basis per "
+                                        "Arnoldi step; the FGMRES variants keep CGS2)",
                    "step": "assemble + solve of the headline configuration"},
         "iters": head["iters"], "true_relres": head["true_relres"],
         "variants": variants, "kernels": head_kernels, "variant_kernels": vkern,
